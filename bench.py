@@ -1,0 +1,139 @@
+#!/usr/bin/env python
+"""Benchmark of the plain FP64 Newton step on one MI355X.
+
+Workload: the gripper scene -- a soft ellipsoid (semi-axes from the seed, voxelised
+on an r^3 grid, E = 5e4 Pa, nu = 0.45) squeezed by two driven affine finger boxes
+closing at 0.05 m/s, gravity, dt = 0.005 s, mu = 0.8, d-hat = 1e-3 m, Newton tolerance
+1e-6 * dt, `--steps` time steps from rest.  Inputs are generated on the host and
+copied to HBM before the timed region; the timed region is the K Newton time steps.
+
+Prints one JSON line with the throughput (sim steps/s), Newton iterations per step,
+the roofline figure of the dominant kernel (PCG sparse matrix-vector product, HIP
+events on the library's stream over the timed region) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sim steps/s + Newton iters/step, learned+batched vs plain at same tol, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+GROUPS = {"spmv": 0, "tet": 1, "contact": 2, "query": 3, "ccd": 4}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene, seconds, max_steps=20):
+    """The oracle as it stands, timed on the host cores: the first steps of the same
+    trajectory until `seconds` of CPU time have been spent (at least one step)."""
+    from oracle import ref
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    used = ref.set_threads(threads)
+    R = ref.RefScene(scene)
+    t = 0.0
+    n = 0
+    newton = 0
+    while n < max_steps and (n == 0 or t < seconds):
+        t0 = time.perf_counter()
+        st = R.step(1)[0]
+        t += time.perf_counter() - t0
+        n += 1
+        newton += st["newton_iters"]
+        log(f"cpu oracle step {n}: {t:.1f} s total, newton {st['newton_iters']}, pcg {st['pcg_iters']}")
+    return {"value": n / t, "unit": "sim steps/s", "cores": used, "kind": "oracle",
+            "sample": f"first {n} steps of the same trajectory ({newton} Newton iterations, {t:.1f} s; "
+                      f"these early steps include the contact-free approach of the fingers)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--res", type=int, default=32)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--timer", default="spmv", choices=sorted(GROUPS))
+    ap.add_argument("--chunk", type=int, default=10, help="steps per library call (progress lines)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import scenegen as sg
+    from paper_2311_05945_amd import zema
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    sc = sg.gripper(args.seed, r=args.res, steps=args.steps)
+    if args.warmup > 0:
+        W = zema.Scene(sc)
+        W.step(args.warmup)
+        del W
+    G = zema.Scene(sc)
+    log(f"scene: {G.n_soft_verts} soft vertices, {G.n_tets} tets, {G.n_dof} DOFs, {G.n_tris} surface triangles")
+    group = GROUPS[args.timer]
+    G.kernel_timer(group, True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.steps:
+        n = min(args.chunk, args.steps - done)
+        stats += G.step(n)
+        done += n
+        log(f"steps {done}/{args.steps}: {time.perf_counter() - t0:.2f} s, newton/step "
+            f"{sum(s['newton_iters'] for s in stats) / len(stats):.2f}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_k, launches, bytes_k = G.kernel_time(group)
+    newton = sum(s["newton_iters"] for s in stats)
+    pcg = sum(s["pcg_iters"] for s in stats)
+    achieved = bytes_k / (ms_k * 1e-3) / 1e9 if ms_k > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "sim steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "form": "plain FP64 GPU (explicit-velocity warm start, unbatched)",
+        "newton_iters_per_step": newton / args.steps,
+        "newton_iters_per_s": newton / elapsed,
+        "pcg_iters_per_newton": pcg / max(newton, 1),
+        "config": {"workload": f"gripper: soft ellipsoid voxelised at r={args.res} (seed {args.seed}) squeezed "
+                               f"by two driven affine fingers, dt=0.005 s, {args.steps} steps",
+                   "seed": args.seed, "res": args.res, "soft_vertices": G.n_soft_verts, "tets": G.n_tets,
+                   "dofs": G.n_dof, "surface_triangles": G.n_tris},
+        "roofline": {"kernel": args.timer, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e3 * ms_k / max(launches, 1), "launches": launches,
+                     "bytes_per_launch": bytes_k / max(launches, 1),
+                     "share_of_step_time": ms_k * 1e-3 / elapsed},
+        "phase_ms_per_step": {k: sum(s[f"ms_{k}"] for s in stats) / args.steps
+                              for k in ("assemble", "pcg", "broad", "ccd", "linesearch")},
+        "failed_steps": sum(1 for s in stats if s["status"] != 0),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sg.gripper(args.seed, r=args.res, steps=args.steps), args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * zema.h -- C interface of the MI355X (gfx950) library for the Newton step of the
+ * soft/affine incremental-potential-contact method of Du et al., "Intersection-free
+ * Robot Manipulation with Soft-Rigid Coupled Incremental Potential Contact"
+ * (arXiv 2311.05945), Sec. III.
+ *
+ * Problem statement followed by every call: soft bodies are tetrahedral meshes with
+ * a diagonal (lumped) mass and a hyper-elastic potential (Sec. III eq. 1, Sec. IV-D:
+ * neo-Hookean with a logarithmic volume term); rigid bodies are affine bodies with
+ * 12 DOFs q_b = (p, a1, a2, a3), x = A x0 + p, mass M_b = int rho J^T J and the
+ * orthogonality potential lambda V |A A^T - I|_F^2 (eq. 2); both are integrated as
+ * one barrier-augmented incremental potential (eqs. 3-5) with lagged smoothed
+ * friction (eqs. 9-10), minimised by projected Newton (eqs. 6-8, 11) with an
+ * intersection-free line search.  Driven bodies follow a kinematic target through
+ * the penalty kappa_A/2 |q - q~|^2 (Sec. IV-C-1, multiplier zero).
+ *
+ * Conventions
+ *   - Status: 0 ok, negative error (ZEMA_E_*).  Outputs are valid only on ok,
+ *     except the required counts returned with ZEMA_E_CAPACITY.
+ *   - The DOF vector y is [soft vertex xyz (3 per vertex, bodies in creation order) |
+ *     q of every non-fixed affine body (12 each, creation order)].  Fixed affine
+ *     bodies are Dirichlet: their DOFs are not in y.
+ *   - Arrays of the hot-path calls (y, ydot, p, grad, xs, pair lists, rhs, sol, v,
+ *     out) are DEVICE pointers on the scene's device; scalar outputs (terms, alpha,
+ *     counts, stats) are HOST pointers.  Scene descriptors are host pointers and
+ *     are copied at creation.  The caller owns every pointer it passes.
+ *   - Positions are row-major (n,3) doubles in SI units; indices int32, zero-based.
+ *   - Surface numbering (used by pair lists): surface vertices = boundary vertices
+ *     of each soft body in ascending vertex order, then every vertex of each affine
+ *     body, bodies in creation order; triangles are rotated so the smallest id comes
+ *     first (orientation kept) and sorted; edges are (min,max) pairs, sorted.
+ *   - A scene is bound to one HIP stream (NULL = default stream); calls on one scene
+ *     are not thread-safe; different scenes are independent.
+ */
+#ifndef ZEMA_H
+#define ZEMA_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ZEMA_OK = 0,
+  ZEMA_E_ARG = -1,        /* bad argument or size */
+  ZEMA_E_MESH = -2,       /* degenerate / inverted tet, open or inward affine surface */
+  ZEMA_E_INTERSECT = -3,  /* a contact pair at zero distance (state not intersection-free) */
+  ZEMA_E_CAPACITY = -4,   /* output buffer too small; required count returned */
+  ZEMA_E_NEWTON = -5,     /* Newton did not converge in newton_max iterations */
+  ZEMA_E_LINESEARCH = -6, /* line-search step fell below 1e-10 */
+  ZEMA_E_PCG = -7,        /* PCG breakdown (p^T H p <= 0) or no convergence */
+  ZEMA_E_NONFINITE = -8,  /* NaN / Inf in the state or a result */
+  ZEMA_E_DEVICE = -9      /* HIP runtime error */
+};
+
+/* flags of zema_ip_assemble */
+enum {
+  ZEMA_GRAD = 1u,       /* write the gradient of the selected terms */
+  ZEMA_HESS = 2u,       /* assemble the PSD-projected Hessian of the selected terms */
+  ZEMA_TERMS_SHIFT = 8u /* bits 8..13 select terms (0 inertia, 1 elastic,
+                           2 orthogonality, 3 kinematic, 4 barrier, 5 friction);
+                           0 selects all */
+};
+
+enum { ZEMA_FREE = 0, ZEMA_FIXED = 1, ZEMA_DRIVEN = 2 };
+enum { ZEMA_FP64 = 0, ZEMA_MIXED = 1 };
+
+typedef struct zema_scene zema_scene;
+
+/* Solver parameters.  dt = h, dhat = barrier distance d-hat (eq. 5), kappa = barrier
+ * stiffness (eq. 4; <= 0 selects the automatic rule: kappa0 = h^2 mbar |g| /
+ * (dhat (ln 2 + 1/2)), doubled after an accepted iterate whose minimum distance
+ * dropped below 1e-3 dhat and decreased), mu = friction coefficient and eps_v =
+ * velocity threshold of eqs. 9-10, gravity (m/s^2), newton_tol (m/s: converged when
+ * the largest vertex displacement of a Newton direction is <= newton_tol * dt),
+ * pcg_rtol (relative residual), ccd_s (ACCD separation fraction, 0.1),
+ * newton_max, pcg_max (<= 0: number of DOFs), precision (ZEMA_FP64 / ZEMA_MIXED),
+ * warm_start (0 explicit velocity). */
+typedef struct {
+  double dt, dhat, kappa, mu, eps_v;
+  double gravity[3];
+  double newton_tol, pcg_rtol, ccd_s;
+  int32_t newton_max, pcg_max, precision, warm_start;
+} zema_params;
+
+/* Soft tetrahedral body (Sec. III eq. 1): rest positions [n_verts][3], tets
+ * [n_tets][4] (positive orientation expected, negative ones are reordered), optional
+ * initial positions / velocities (NULL = rest / zero), Young's modulus E (Pa),
+ * Poisson ratio nu, density rho (kg/m^3). */
+typedef struct {
+  int32_t n_verts, n_tets;
+  const double* rest_pos;
+  const int32_t* tets;
+  const double* pos0;
+  const double* vel0;
+  double E, nu, rho;
+} zema_soft_desc;
+
+/* Affine body (Sec. III eq. 2): closed outward triangle surface in world
+ * coordinates at t = 0 (the rest state), density, orthogonality stiffness lambda
+ * (Pa), initial dq/dt (12), mode, and for driven bodies the kinematic penalty
+ * kappa_A and a target that moves at target_vel (m/s) until target_stop (s). */
+typedef struct {
+  int32_t n_verts, n_tris;
+  const double* rest_pos;
+  const int32_t* tris;
+  double rho, stiffness;
+  double qdot0[12];
+  int32_t mode, pad_;
+  double kappa_A;
+  double target_vel[3];
+  double target_stop;
+} zema_affine_desc;
+
+/* Per-step statistics written by zema_step. */
+typedef struct {
+  int32_t status, newton_iters, pcg_iters, ls_backtracks;
+  int32_t n_pt_active, n_ee_active, n_pt_cand, n_ee_cand;
+  double alpha_ccd_min, kappa, d_min, energy;
+  double ms_total, ms_assemble, ms_pcg, ms_broad, ms_ccd, ms_linesearch;
+} zema_step_stats;
+
+/* Create a scene: copies every input, precomputes rest-shape inverses, volumes,
+ * lumped masses, boundary surfaces, affine mass properties (volume, mass, centre,
+ * second moment) and the static sparsity pattern, and sets the initial state
+ * (rest or pos0, velocities vel0 / qdot0).  hip_stream: a hipStream_t or NULL.
+ * Errors: ZEMA_E_ARG, ZEMA_E_MESH, ZEMA_E_INTERSECT, ZEMA_E_DEVICE. */
+int zema_scene_create(const zema_params* params, const zema_soft_desc* soft, int32_t n_soft,
+                      const zema_affine_desc* affine, int32_t n_affine, void* hip_stream,
+                      zema_scene** out);
+void zema_scene_destroy(zema_scene* s);
+const char* zema_status_string(int status);
+const char* zema_last_error(const zema_scene* s);
+
+/* Sizes: [0] n_dof, [1] soft vertices, [2] tets, [3] surface vertices, [4] surface
+ * triangles, [5] surface edges, [6] non-fixed affine bodies, [7] all bodies. */
+int zema_sizes(const zema_scene* s, int64_t* out8);
+
+/* Set / get the time-step state y^t, dy^t/dt (device, n_dof each), the barrier
+ * stiffness (kappa <= 0 keeps the automatic rule's value) and the step index.
+ * Setting the state recomputes the predictor of eq. 3, the kinematic targets and the
+ * lagged friction table (eqs. 9-10) at y^t. */
+int zema_set_state(zema_scene* s, const double* y, const double* ydot, double kappa, int32_t step);
+int zema_get_state(zema_scene* s, double* y, double* ydot, double* kappa, int32_t* step);
+/* Change kappa without recomputing the lagged friction table. */
+int zema_set_kappa(zema_scene* s, double kappa);
+
+/* Surface vertex positions xs [n_surf][3] (device) of the DOF vector y: soft
+ * vertices copied, affine vertices ((a_k1 x0_1 + a_k2 x0_2) + a_k3 x0_3) + p_k
+ * without fused multiply-add. */
+int zema_surface_positions(zema_scene* s, const double* y, double* xs);
+
+/* Candidate contact pairs (Sec. III: the set C of eq. 4 restricted by a broad
+ * phase): every inter-body (surface vertex, triangle) pair and (edge a, edge b)
+ * pair with a < b, not both on fixed bodies, whose boxes overlap, each box being
+ * [min over the primitive's vertices of min(xs0, xs1)] - r .. [max of max] + r per
+ * axis, closed intervals.  xs1 = NULL means static (xs1 = xs0).  Output pt [n][2]
+ * = (vertex, triangle) sorted lexicographically, ee [n][2] = (a, b) sorted; device
+ * buffers of capacity pt_cap / ee_cap pairs.  The set is also stored in the scene
+ * as the current candidate set.  ZEMA_E_CAPACITY with *n_pt / *n_ee = required. */
+int zema_contact_candidates(zema_scene* s, const double* xs0, const double* xs1, double r,
+                            int32_t* pt, int64_t pt_cap, int64_t* n_pt, int32_t* ee, int64_t ee_cap,
+                            int64_t* n_ee);
+
+/* Incremental potential at y (device, n_dof) on the static candidate set at y
+ * (r = dhat): energy terms (host, 8 doubles: inertia, elastic, orthogonality,
+ * kinematic, barrier, friction, total, minimum candidate distance), the gradient
+ * (device, n_dof; optional) and, with ZEMA_HESS, the PSD-projected Hessian kept in
+ * the scene (eqs. 6-8: x-space pair blocks projected, then mapped through the
+ * affine Jacobian) for zema_hessian_matvec / zema_pcg_solve.  ZEMA_E_INTERSECT if a
+ * tet is inverted or a candidate distance is zero (total = +inf). */
+int zema_ip_assemble(zema_scene* s, const double* y, uint32_t flags, double* terms, double* grad);
+
+/* out = H v for the last assembled Hessian (device vectors, n_dof). */
+int zema_hessian_matvec(zema_scene* s, const double* v, double* out);
+
+/* Block-Jacobi preconditioned CG on the last assembled Hessian: H sol = rhs, start
+ * at 0, stop at |r|_2 <= rtol |rhs|_2 or max_iter (<= 0: n_dof) iterations.
+ * ZEMA_E_PCG on breakdown or no convergence.  rhs, sol device; iters, rel_res host. */
+int zema_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, int32_t max_iter,
+                   int32_t* iters, double* rel_res);
+
+/* Largest step alpha in (0, 1] along p from y (device vectors) that additive CCD
+ * (Li, Kaufman, Jiang 2021, Alg. 1; separation s = ccd_s, zero thickness) certifies
+ * over the swept candidate set of [y, y + p] (r = dhat).  ZEMA_E_INTERSECT if a pair
+ * starts at zero distance. */
+int zema_ccd_max_step(zema_scene* s, const double* y, const double* p, double* alpha);
+
+/* Advance n_steps time steps of the Newton method (warm start, lagged friction,
+ * assemble, PCG, convergence test, swept candidates, CCD bound, backtracking line
+ * search on the energy with an inversion check, kappa rule, velocity update).  On an
+ * error the scene keeps the last accepted state.  stats: host array of n_steps. */
+int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats);
+
+/* Number of lagged friction pairs and their table (host outputs): ids5 [n][5] =
+ * (kind 0 PT / 1 EE, 4 surface vertices), vals8 [n][8] = (lambda, n(3), w(4)). */
+int zema_friction_table(zema_scene* s, int64_t* n, int32_t* ids5, double* vals8, int64_t cap);
+
+/* Launch timing for benchmarks: with enable != 0 the library records HIP events on
+ * the scene's stream around every launch of one kernel group (0 PCG sparse
+ * matrix-vector product, 1 per-tet elastic assembly, 2 contact pair assembly,
+ * 3 broad-phase query, 4 CCD) and accumulates their durations; zema_kernel_time
+ * returns the total milliseconds, the launch count and the algorithmic bytes of
+ * those launches (what the method must move: for the matrix-vector product 76 B per
+ * stored 3x3 block plus four DOF vectors, for the elastic assembly 320 B per tet;
+ * 0 for the other groups) since the timer was enabled.  Both calls synchronise the
+ * stream; bytes may be NULL. */
+int zema_kernel_timer(zema_scene* s, int32_t group, int32_t enable);
+int zema_kernel_time(zema_scene* s, int32_t group, double* ms, int64_t* launches, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

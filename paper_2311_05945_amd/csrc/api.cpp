@@ -1,0 +1,887 @@
+// Host side of the HIP library: scene preprocessing, state, the Newton time step
+// and the C interface declared in include/zema.h.
+//
+// Time step (Sec. III: minimise B_t + D of eq. 11, then the velocity update):
+//   predictor and kinematic targets; lagged friction at y^t (eqs. 9-10);
+//   warm start y^t + a h ydot^t with a the CCD bound of that move (halved while a
+//   tet would invert); then Newton iterations: assemble gradient and projected
+//   Hessian on the active set, PCG for p, stop when the largest vertex displacement
+//   of p is <= newton_tol * h, swept candidates over [y, y + p], CCD bound, halve
+//   the step until no tet inverts and the energy does not increase, accept, and
+//   double the automatic barrier stiffness when the minimum distance fell below
+//   1e-3 dhat and decreased.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "scene.hpp"
+
+using namespace zema;
+
+namespace {
+
+constexpr int BF = 32;
+constexpr int BF_QF = 13;
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct D3h {
+  double x, y, z;
+};
+D3h sub(const double* a, const double* b) { return {a[0] - b[0], a[1] - b[1], a[2] - b[2]}; }
+D3h crs(D3h a, D3h b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+double dt3(D3h a, D3h b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// ------------------------------------------------------------------ preprocessing
+void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const zema_affine_desc* aff, int n_aff) {
+  s->n_soft_bodies = n_soft;
+  s->n_bodies = n_soft + n_aff;
+  std::vector<double> X, x_init, v_init, Dmi_aos, vol, lmu, llam, mass;
+  std::vector<int> tets, vbody;
+  // ---- soft bodies
+  std::vector<std::array<int, 4>> faces;  // packed (a, b, c) outward + body
+  std::vector<unsigned long long> fkey;
+  for (int b = 0; b < n_soft; ++b) {
+    const zema_soft_desc& d = soft[b];
+    if (d.n_verts < 0 || d.n_tets < 0 || (d.n_verts && !d.rest_pos) || (d.n_tets && !d.tets))
+      throw Error(ZEMA_E_ARG, "bad soft body descriptor");
+    int v0 = (int)mass.size();
+    double mu = d.E / (2.0 * (1.0 + d.nu)), la = d.E * d.nu / ((1.0 + d.nu) * (1.0 - 2.0 * d.nu));
+    for (int i = 0; i < d.n_verts; ++i) {
+      for (int k = 0; k < 3; ++k) {
+        X.push_back(d.rest_pos[3 * i + k]);
+        x_init.push_back(d.pos0 ? d.pos0[3 * i + k] : d.rest_pos[3 * i + k]);
+        v_init.push_back(d.vel0 ? d.vel0[3 * i + k] : 0.0);
+      }
+      mass.push_back(0.0);
+      vbody.push_back(b);
+    }
+    for (int e = 0; e < d.n_tets; ++e) {
+      int t[4];
+      for (int a = 0; a < 4; ++a) {
+        int v = d.tets[4 * e + a];
+        if (v < 0 || v >= d.n_verts) throw Error(ZEMA_E_MESH, "tet index out of range");
+        t[a] = v0 + v;
+      }
+      D3h c1 = sub(&X[3 * t[1]], &X[3 * t[0]]), c2 = sub(&X[3 * t[2]], &X[3 * t[0]]),
+          c3 = sub(&X[3 * t[3]], &X[3 * t[0]]);
+      double det = dt3(c1, crs(c2, c3));
+      if (det < 0.0) {  // reorder so that the tet is positive
+        std::swap(t[1], t[2]);
+        std::swap(c1, c2);
+        det = -det;
+      }
+      double L = std::max({std::fabs(c1.x), std::fabs(c1.y), std::fabs(c1.z), std::fabs(c2.x), std::fabs(c2.y),
+                           std::fabs(c2.z), std::fabs(c3.x), std::fabs(c3.y), std::fabs(c3.z)});
+      if (!(det > 1e-14 * L * L * L)) throw Error(ZEMA_E_MESH, "degenerate tet");
+      // Dm = [c1 c2 c3] (columns); inverse rows = (c2 x c3, c3 x c1, c1 x c2) / det
+      D3h r0 = crs(c2, c3), r1 = crs(c3, c1), r2 = crs(c1, c2);
+      double id = 1.0 / det;
+      double Dm[9] = {r0.x * id, r0.y * id, r0.z * id, r1.x * id, r1.y * id, r1.z * id,
+                      r2.x * id, r2.y * id, r2.z * id};
+      for (int k = 0; k < 9; ++k) Dmi_aos.push_back(Dm[k]);
+      double V = det / 6.0;
+      vol.push_back(V);
+      lmu.push_back(mu);
+      llam.push_back(la);
+      for (int a = 0; a < 4; ++a) {
+        tets.push_back(t[a]);
+        mass[t[a]] += 0.25 * d.rho * V;
+      }
+      // outward faces of a positive tet (local index patterns)
+      const int F[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+      for (int f = 0; f < 4; ++f) {
+        int a = t[F[f][0]], bb = t[F[f][1]], c = t[F[f][2]];
+        int lo = std::min({a, bb, c}), hi = std::max({a, bb, c}), mid = a + bb + c - lo - hi;
+        fkey.push_back(((unsigned long long)lo << 42) | ((unsigned long long)mid << 21) | (unsigned long long)hi);
+        faces.push_back({a, bb, c, 0});
+      }
+    }
+  }
+  s->nsv = (int)mass.size();
+  s->nt = (int)vol.size();
+  if (s->nsv >= (1 << 21)) throw Error(ZEMA_E_ARG, "too many soft vertices");
+  // boundary faces: keys occurring once
+  std::vector<int> ford(fkey.size());
+  for (size_t i = 0; i < ford.size(); ++i) ford[i] = (int)i;
+  std::sort(ford.begin(), ford.end(), [&](int a, int b) { return fkey[a] < fkey[b] || (fkey[a] == fkey[b] && a < b); });
+  std::vector<std::array<int, 3>> soft_tris;
+  for (size_t i = 0; i < ford.size();) {
+    size_t j = i;
+    while (j < ford.size() && fkey[ford[j]] == fkey[ford[i]]) ++j;
+    if (j - i == 1) soft_tris.push_back({faces[ford[i]][0], faces[ford[i]][1], faces[ford[i]][2]});
+    i = j;
+  }
+  // ---- surface vertices: soft boundary vertices ascending, then affine vertices
+  std::vector<int> sv_ref, sv_body, soft_sid(s->nsv, -1);
+  std::vector<double> sv_x0;
+  {
+    std::vector<char> on(s->nsv, 0);
+    for (auto& t : soft_tris)
+      for (int k = 0; k < 3; ++k) on[t[k]] = 1;
+    for (int i = 0; i < s->nsv; ++i)
+      if (on[i]) {
+        soft_sid[i] = (int)sv_ref.size();
+        sv_ref.push_back(i);
+        sv_body.push_back(vbody[i]);
+        sv_x0.insert(sv_x0.end(), {0.0, 0.0, 0.0});
+      }
+  }
+  std::vector<std::array<int, 3>> all_tris;
+  for (auto& t : soft_tris) all_tris.push_back({soft_sid[t[0]], soft_sid[t[1]], soft_sid[t[2]]});
+  // ---- affine bodies
+  int dof = 3 * s->nsv, node = s->nsv;
+  s->nfree = 0;
+  for (int b = 0; b < n_aff; ++b) {
+    const zema_affine_desc& d = aff[b];
+    if (d.n_verts <= 0 || d.n_tris <= 0 || !d.rest_pos || !d.tris) throw Error(ZEMA_E_ARG, "bad affine descriptor");
+    if (d.mode < 0 || d.mode > 2) throw Error(ZEMA_E_ARG, "bad affine mode");
+    // closed, consistently oriented: every directed edge has its reverse exactly once
+    std::vector<unsigned long long> de;
+    for (int t = 0; t < d.n_tris; ++t)
+      for (int k = 0; k < 3; ++k) {
+        int a = d.tris[3 * t + k], c = d.tris[3 * t + (k + 1) % 3];
+        if (a < 0 || a >= d.n_verts || c < 0 || c >= d.n_verts) throw Error(ZEMA_E_MESH, "triangle index");
+        de.push_back(((unsigned long long)a << 32) | (unsigned)c);
+      }
+    std::sort(de.begin(), de.end());
+    for (size_t i = 0; i < de.size(); ++i) {
+      if (i + 1 < de.size() && de[i + 1] == de[i]) throw Error(ZEMA_E_MESH, "non-manifold affine surface");
+      unsigned long long rev = ((de[i] & 0xffffffffull) << 32) | (de[i] >> 32);
+      if (!std::binary_search(de.begin(), de.end(), rev)) throw Error(ZEMA_E_MESH, "open affine surface");
+    }
+    Body B;
+    B.mode = d.mode;
+    B.rho = d.rho;
+    B.stiff = d.stiffness;
+    B.kappaA = d.kappa_A;
+    for (int k = 0; k < 3; ++k) B.tvel[k] = d.target_vel[k];
+    B.tstop = d.target_stop;
+    for (int k = 0; k < 12; ++k) B.qdot0[k] = d.qdot0[k];
+    // volume, centre and second moment from signed tets (ref, a, b, c), ref = vertex mean
+    double ref[3] = {0, 0, 0};
+    for (int i = 0; i < d.n_verts; ++i)
+      for (int k = 0; k < 3; ++k) ref[k] += d.rest_pos[3 * i + k] / d.n_verts;
+    double V = 0.0, m1[3] = {0, 0, 0}, m2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int t = 0; t < d.n_tris; ++t) {
+      const double* P[3] = {d.rest_pos + 3 * d.tris[3 * t], d.rest_pos + 3 * d.tris[3 * t + 1],
+                            d.rest_pos + 3 * d.tris[3 * t + 2]};
+      double v[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) v[a][k] = P[a][k] - ref[k];
+      D3h a0{v[0][0], v[0][1], v[0][2]}, a1{v[1][0], v[1][1], v[1][2]}, a2{v[2][0], v[2][1], v[2][2]};
+      double vt = dt3(a0, crs(a1, a2)) / 6.0;
+      V += vt;
+      double sm[3];
+      for (int k = 0; k < 3; ++k) {
+        sm[k] = v[0][k] + v[1][k] + v[2][k];
+        m1[k] += vt * 0.25 * sm[k];
+      }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          m2[i][j] += vt * 0.05 * (v[0][i] * v[0][j] + v[1][i] * v[1][j] + v[2][i] * v[2][j] + sm[i] * sm[j]);
+    }
+    if (!(V > 0.0)) throw Error(ZEMA_E_MESH, "affine surface not outward");
+    B.V = V;
+    B.m = d.rho * V;
+    double cr[3];
+    for (int k = 0; k < 3; ++k) {
+      cr[k] = m1[k] / V;
+      B.c[k] = ref[k] + cr[k];
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) B.S[3 * i + j] = d.rho * (m2[i][j] - V * cr[i] * cr[j]);
+    for (int k = 0; k < 12; ++k) B.qrest[k] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      B.qrest[k] = B.c[k];
+      B.qrest[3 + 4 * k] = 1.0;
+    }
+    B.sv0 = (int)sv_ref.size();
+    B.nsv = d.n_verts;
+    for (int i = 0; i < d.n_verts; ++i) {
+      sv_ref.push_back(-(b + 1));
+      sv_body.push_back(n_soft + b);
+      for (int k = 0; k < 3; ++k) sv_x0.push_back(d.rest_pos[3 * i + k] - B.c[k]);
+    }
+    for (int t = 0; t < d.n_tris; ++t)
+      all_tris.push_back({B.sv0 + d.tris[3 * t], B.sv0 + d.tris[3 * t + 1], B.sv0 + d.tris[3 * t + 2]});
+    if (B.mode != ZEMA_FIXED) {
+      B.dof0 = dof;
+      B.node0 = node;
+      dof += 12;
+      node += 4;
+      s->nfree++;
+    }
+    s->bodies.push_back(B);
+  }
+  s->ndof = dof;
+  s->nnodes = node;
+  s->nsurf = (int)sv_ref.size();
+  // ---- canonical triangles and edges
+  for (auto& t : all_tris) {
+    int k = 0;
+    if (t[1] < t[k]) k = 1;
+    if (t[2] < t[k]) k = 2;
+    t = {t[k], t[(k + 1) % 3], t[(k + 2) % 3]};
+  }
+  std::sort(all_tris.begin(), all_tris.end());
+  std::vector<unsigned long long> ek;
+  for (auto& t : all_tris)
+    for (int k = 0; k < 3; ++k) {
+      unsigned a = (unsigned)std::min(t[k], t[(k + 1) % 3]), c = (unsigned)std::max(t[k], t[(k + 1) % 3]);
+      ek.push_back(((unsigned long long)a << 32) | c);
+    }
+  std::sort(ek.begin(), ek.end());
+  ek.erase(std::unique(ek.begin(), ek.end()), ek.end());
+  s->ntri = (int)all_tris.size();
+  s->nedge = (int)ek.size();
+  std::vector<int> tris_h, edges_h;
+  for (auto& t : all_tris) tris_h.insert(tris_h.end(), {t[0], t[1], t[2]});
+  std::vector<double> elen2;
+  double lsum = 0.0;
+  for (auto e : ek) {
+    int a = (int)(e >> 32), c = (int)(e & 0xffffffffu);
+    edges_h.push_back(a);
+    edges_h.push_back(c);
+    double l2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double pa = sv_ref[a] >= 0 ? X[3 * sv_ref[a] + k] : sv_x0[3 * a + k];
+      double pc = sv_ref[c] >= 0 ? X[3 * sv_ref[c] + k] : sv_x0[3 * c + k];
+      l2 += (pc - pa) * (pc - pa);
+    }
+    elen2.push_back(l2);
+    lsum += std::sqrt(l2);
+  }
+  s->cell = s->nedge ? lsum / s->nedge : 1.0;
+  if (!(s->cell > 0.0)) s->cell = 1.0;
+  // ---- static block pattern: tet node pairs and the 4x4 node blocks of free bodies
+  int nn = s->nnodes;
+  std::vector<unsigned long long> keys;
+  keys.reserve((size_t)16 * s->nt + 16 * s->nfree);
+  for (int e = 0; e < s->nt; ++e)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) keys.push_back((unsigned long long)tets[4 * e + a] * nn + tets[4 * e + b]);
+  for (const Body& B : s->bodies)
+    if (B.node0 >= 0)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) keys.push_back((unsigned long long)(B.node0 + a) * nn + (B.node0 + b));
+  std::vector<unsigned long long> ukeys = keys;
+  std::sort(ukeys.begin(), ukeys.end());
+  ukeys.erase(std::unique(ukeys.begin(), ukeys.end()), ukeys.end());
+  s->nnzb = (int)ukeys.size();
+  std::vector<int> bptr(nn + 1, 0), bcol(s->nnzb), brow(s->nnzb), bdiag(nn, -1);
+  for (int j = 0; j < s->nnzb; ++j) {
+    int r = (int)(ukeys[j] / nn), c = (int)(ukeys[j] % nn);
+    brow[j] = r;
+    bcol[j] = c;
+    bptr[r + 1]++;
+    if (r == c) bdiag[r] = j;
+  }
+  for (int r = 0; r < nn; ++r) bptr[r + 1] += bptr[r];
+  s->bsr_row_soft_end = bptr[s->nsv];
+  std::vector<int> hcnt(s->nnzb + 1, 0), hpos((size_t)16 * s->nt);
+  for (int e = 0; e < s->nt; ++e)
+    for (int q = 0; q < 16; ++q) {
+      unsigned long long k = keys[(size_t)16 * e + q];
+      int j = (int)(std::lower_bound(ukeys.begin(), ukeys.end(), k) - ukeys.begin());
+      hpos[(size_t)16 * e + q] = j;
+      hcnt[j + 1]++;
+    }
+  for (int j = 0; j < s->nnzb; ++j) hcnt[j + 1] += hcnt[j];
+  std::vector<int> hlist(hcnt[s->nnzb]), hfill(hcnt.begin(), hcnt.end() - 1);
+  for (int e = 0; e < s->nt; ++e)
+    for (int q = 0; q < 16; ++q) hlist[hfill[hpos[(size_t)16 * e + q]]++] = 16 * e + q;
+  // vertex -> (tet, slot)
+  std::vector<int> vtp(s->nsv + 1, 0), vtl((size_t)4 * s->nt);
+  for (int e = 0; e < s->nt; ++e)
+    for (int a = 0; a < 4; ++a) vtp[tets[4 * e + a] + 1]++;
+  for (int i = 0; i < s->nsv; ++i) vtp[i + 1] += vtp[i];
+  {
+    std::vector<int> fill(vtp.begin(), vtp.end() - 1);
+    for (int e = 0; e < s->nt; ++e)
+      for (int a = 0; a < 4; ++a) vtl[fill[tets[4 * e + a]]++] = 4 * e + a;
+  }
+  // ---- upload
+  const double h2 = s->P.dt * s->P.dt;
+  std::vector<int4> t4(s->nt);
+  std::vector<double> Dmi_soa((size_t)9 * s->nt), h2vol(s->nt);
+  for (int e = 0; e < s->nt; ++e) {
+    t4[e] = make_int4(tets[4 * e], tets[4 * e + 1], tets[4 * e + 2], tets[4 * e + 3]);
+    for (int k = 0; k < 9; ++k) Dmi_soa[(size_t)k * s->nt + e] = Dmi_aos[(size_t)9 * e + k];
+    h2vol[e] = h2 * vol[e];
+  }
+  s->tets.upload(t4);
+  s->Dmi.upload(Dmi_soa);
+  s->h2vol.upload(h2vol);
+  s->lmu.upload(lmu);
+  s->llam.upload(llam);
+  s->mass.upload(mass);
+  s->mass_h = mass;
+  s->vt_ptr.upload(vtp);
+  s->vt_list.upload(vtl);
+  s->bsr_ptr.upload(bptr);
+  s->bsr_col.upload(bcol);
+  s->bsr_row.upload(brow);
+  s->bsr_diag.upload(bdiag);
+  s->hc_ptr.upload(hcnt);
+  s->hc_list.upload(hlist);
+  s->bsr_val.resize((size_t)9 * s->nnzb + 9);
+  ZCHK(hipMemset(s->bsr_val.p, 0, sizeof(double) * s->bsr_val.n));
+  s->e_tet.resize(s->nt + 1);
+  s->g_tet.resize((size_t)12 * s->nt + 12);
+  s->h_tet.resize((size_t)90 * s->nt + 90);
+  s->e_in.resize(s->nsv + 1);
+  int nb = (int)s->bodies.size();
+  std::vector<double> bf((size_t)BF * std::max(nb, 1), 0.0);
+  std::vector<int> bi((size_t)4 * std::max(nb, 1), 0);
+  std::vector<unsigned char> fixed(std::max(s->n_bodies, 1), 0);
+  for (int b = 0; b < nb; ++b) {
+    const Body& B = s->bodies[b];
+    bf[BF * b + 0] = B.m;
+    bf[BF * b + 1] = B.V;
+    bf[BF * b + 2] = B.stiff;
+    bf[BF * b + 3] = B.kappaA;
+    for (int k = 0; k < 9; ++k) bf[BF * b + 4 + k] = B.S[k];
+    for (int k = 0; k < 12; ++k) bf[BF * b + BF_QF + k] = B.qrest[k];
+    bi[4 * b] = B.mode;
+    bi[4 * b + 1] = B.dof0;
+    bi[4 * b + 2] = B.node0;
+    if (B.mode == ZEMA_FIXED) fixed[n_soft + b] = 1;
+  }
+  s->body_f.upload(bf);
+  s->body_i.upload(bi);
+  s->body_fixed.upload(fixed);
+  s->qtilde.resize((size_t)12 * std::max(nb, 1));
+  s->e_body.resize((size_t)3 * std::max(nb, 1));
+  s->sv_ref.upload(sv_ref);
+  s->sv_body.upload(sv_body);
+  s->sv_x0.upload(sv_x0);
+  s->tris.upload(tris_h);
+  s->edges.upload(edges_h);
+  s->elen2.upload(elen2);
+  size_t ns3 = (size_t)3 * std::max(s->nsurf, 1);
+  s->xs.resize(ns3);
+  s->xs1.resize(ns3);
+  s->dxs.resize(ns3);
+  size_t nd = std::max(s->ndof, 1);
+  for (DBuf<double>* v : {&s->y, &s->ydot, &s->yt, &s->ydt, &s->yhat, &s->ytmp, &s->grad, &s->pdir})
+    v->resize(nd);
+  s->counters.resize(16);
+  s->umin.resize(8);
+  s->red.resize(64 + 8 * 256);
+  s->c_ptr.resize(nn + 1);
+  ZCHK(hipMemset(s->c_ptr.p, 0, sizeof(int) * (nn + 1)));
+  // initial state (device copies)
+  std::vector<double> y0(nd, 0.0), yd0(nd, 0.0);
+  for (int i = 0; i < 3 * s->nsv; ++i) {
+    y0[i] = x_init[i];
+    yd0[i] = v_init[i];
+  }
+  for (const Body& B : s->bodies)
+    if (B.dof0 >= 0)
+      for (int k = 0; k < 12; ++k) {
+        y0[B.dof0 + k] = B.qrest[k];
+        yd0[B.dof0 + k] = B.qdot0[k];
+      }
+  s->ytmp.upload(y0);
+  s->pdir.upload(yd0);
+}
+
+double auto_kappa(const zema_scene* s) {
+  double g = std::sqrt(s->P.gravity[0] * s->P.gravity[0] + s->P.gravity[1] * s->P.gravity[1] +
+                       s->P.gravity[2] * s->P.gravity[2]);
+  if (g == 0.0) g = 9.81;
+  double mbar = 1.0;
+  if (s->nsv) {
+    mbar = 0.0;
+    for (double m : s->mass_h) mbar += m;
+    mbar /= s->nsv;
+  }
+  return s->P.dt * s->P.dt * mbar * g / (s->P.dhat * (std::log(2.0) + 0.5));
+}
+
+// energy terms at y on the current candidate set (surface positions recomputed)
+void eval_energy(zema_scene* s, const double* y, double* T) {
+  k_map_surface(s, y, s->xs.p);
+  k_tet_energy(s, y);
+  k_inertia_energy(s, y, s->e_in.p);
+  k_body_energy(s, y);
+  k_contact_energy(s);
+  int nb = (int)s->bodies.size();
+  const double* P[7] = {s->e_in.p, s->e_tet.p, s->e_body.p, s->e_body.p + nb, s->e_body.p + 2 * nb, s->e_pair.p,
+                        s->e_fric.p};
+  int64_t L[7] = {s->nsv, s->nt, nb, nb, nb, s->npt + s->nee, s->nfric};
+  double out[8];
+  k_sums(s, 7, P, L, out, s->umin.p + 1);
+  double dmin;
+  std::memcpy(&dmin, &out[7], sizeof(double));
+  T[0] = out[0] + out[2];
+  T[1] = out[1];
+  T[2] = out[3];
+  T[3] = out[4];
+  T[4] = out[5];
+  T[5] = out[6];
+  T[6] = T[0] + T[1] + T[2] + T[3] + T[4] + T[5];
+  T[7] = (s->npt + s->nee) ? dmin : INFINITY;
+  if (!std::isfinite(T[1]) || !(T[7] > 0.0)) T[6] = INFINITY;
+}
+
+// energies, gradient (optional) and Hessian (optional) at y on the current candidates
+void assemble(zema_scene* s, const double* y, double* grad, bool hess, unsigned mask, double* T) {
+  eval_energy(s, y, T);
+  if (!std::isfinite(T[6])) return;
+  if (grad || hess) k_tet_assemble(s, y, hess);
+  if (grad) k_gather_grad_soft(s, y, grad, mask);
+  k_body_terms(s, y, grad, hess, mask);
+  if (hess) k_gather_hess_static(s, mask);
+  k_contact_assemble(s, grad, hess, mask);
+  s->hess_valid = hess;
+}
+
+void static_candidates(zema_scene* s, const double* y) {
+  k_map_surface(s, y, s->xs.p);
+  k_candidates(s, s->xs.p, s->xs.p, s->P.dhat);
+}
+
+void swept_candidates(zema_scene* s, const double* y, const double* p) {
+  k_axpy(s, s->ndof, 1.0, p, y, s->ytmp.p);
+  k_map_surface(s, y, s->xs.p);
+  k_map_surface(s, s->ytmp.p, s->xs1.p);
+  k_candidates(s, s->xs.p, s->xs1.p, s->P.dhat);
+}
+
+double min_distance(zema_scene* s, const double* y) {
+  double T[8];
+  eval_energy(s, y, T);
+  return T[7];
+}
+
+// predictor, kinematic targets and the lagged friction table at y^t = s->y
+void begin_step(zema_scene* s) {
+  k_predict(s);
+  int nb = (int)s->bodies.size();
+  std::vector<double> qt((size_t)12 * std::max(nb, 1), 0.0);
+  double tnext = (s->step + 1) * s->P.dt;
+  for (int b = 0; b < nb; ++b) {
+    const Body& B = s->bodies[b];
+    double tt = std::min(tnext, B.tstop);
+    for (int k = 0; k < 12; ++k) qt[12 * b + k] = B.qrest[k];
+    for (int k = 0; k < 3; ++k) qt[12 * b + k] += tt * B.tvel[k];
+  }
+  ZCHK(hipMemcpyAsync(s->qtilde.p, qt.data(), sizeof(double) * qt.size(), hipMemcpyHostToDevice, s->st));
+  s->kappa_lag = s->kappa;
+  static_candidates(s, s->y.p);
+  k_friction_build(s);
+  ZCHK(hipStreamSynchronize(s->st));
+}
+
+int set_state_impl(zema_scene* s, const double* y, const double* ydot, double kappa, int step) {
+  ZCHK(hipMemcpyAsync(s->y.p, y, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+  ZCHK(hipMemcpyAsync(s->ydot.p, ydot, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+  s->step = step;
+  s->kappa = kappa > 0.0 ? kappa : (s->P.kappa > 0.0 ? s->P.kappa : auto_kappa(s));
+  {
+    const double* P[2] = {s->y.p, s->ydot.p};
+    int64_t L[2] = {s->ndof, s->ndof};
+    double out[3];
+    k_sums(s, 2, P, L, out, nullptr);
+    if (!std::isfinite(out[0]) || !std::isfinite(out[1])) throw Error(ZEMA_E_NONFINITE, "non-finite state");
+  }
+  if (k_any_inverted(s, s->y.p)) throw Error(ZEMA_E_MESH, "inverted tet in state");
+  begin_step(s);
+  if (!(min_distance(s, s->y.p) > 0.0)) throw Error(ZEMA_E_INTERSECT, "intersecting state");
+  return 0;
+}
+
+int time_step(zema_scene* s, zema_step_stats* st) {
+  const double h = s->P.dt;
+  const int n = s->ndof;
+  std::memset(st, 0, sizeof(*st));
+  st->alpha_ccd_min = 1.0;
+  double t0 = now_ms(), tb = 0, ta = 0, tp = 0, tc = 0, tl = 0, q;
+  q = now_ms();
+  begin_step(s);
+  tb += now_ms() - q;
+  ZCHK(hipMemcpyAsync(s->yt.p, s->y.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
+  ZCHK(hipMemcpyAsync(s->ydt.p, s->ydot.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
+  // warm start
+  k_scale(s, n, h, s->ydot.p, s->pdir.p);
+  q = now_ms();
+  swept_candidates(s, s->y.p, s->pdir.p);
+  tb += now_ms() - q;
+  double a0;
+  q = now_ms();
+  int rc = k_ccd(s, s->y.p, s->pdir.p, &a0);
+  tc += now_ms() - q;
+  if (rc) throw Error(rc, "intersecting pair at warm-start CCD");
+  for (;;) {
+    k_axpy(s, n, a0, s->pdir.p, s->y.p, s->ytmp.p);
+    if (!k_any_inverted(s, s->ytmp.p)) break;
+    a0 *= 0.5;
+    if (a0 < 1e-10) {
+      ZCHK(hipMemcpyAsync(s->ytmp.p, s->y.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
+      break;
+    }
+  }
+  std::swap(s->y.p, s->ytmp.p);
+  q = now_ms();
+  static_candidates(s, s->y.p);
+  tb += now_ms() - q;
+  double dprev = min_distance(s, s->y.p);
+  const bool auto_k = s->P.kappa <= 0.0;
+  const double tol = s->P.newton_tol * h;
+  const int pcg_max = s->P.pcg_max;
+  bool conv = false;
+  int it = 0;
+  double T[8];
+  for (; it < s->P.newton_max; ++it) {
+    q = now_ms();
+    assemble(s, s->y.p, s->grad.p, true, 0x3fu, T);
+    ta += now_ms() - q;
+    if (!std::isfinite(T[6])) throw Error(ZEMA_E_INTERSECT, "infeasible Newton iterate");
+    st->energy = T[6];
+    st->n_pt_active = s->n_act;  // active barrier pairs (point-triangle and edge-edge)
+    st->n_ee_active = s->nfric;  // lagged friction pairs
+    k_scale(s, n, -1.0, s->grad.p, s->ytmp.p);
+    int pit;
+    double rr;
+    q = now_ms();
+    rc = k_pcg(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, pcg_max, &pit, &rr);
+    tp += now_ms() - q;
+    st->pcg_iters += pit;
+    if (rc) throw Error(rc, "PCG failed");
+    if (k_max_disp(s, s->pdir.p) <= tol) {
+      conv = true;
+      break;
+    }
+    q = now_ms();
+    swept_candidates(s, s->y.p, s->pdir.p);
+    tb += now_ms() - q;
+    st->n_pt_cand = (int)s->npt;
+    st->n_ee_cand = (int)s->nee;
+    double alpha;
+    q = now_ms();
+    rc = k_ccd(s, s->y.p, s->pdir.p, &alpha);
+    tc += now_ms() - q;
+    if (rc) throw Error(rc, "intersecting pair at CCD start");
+    st->alpha_ccd_min = std::min(st->alpha_ccd_min, alpha);
+    q = now_ms();
+    double E0[8], E1[8];
+    eval_energy(s, s->y.p, E0);
+    for (;;) {
+      k_axpy(s, n, alpha, s->pdir.p, s->y.p, s->ytmp.p);
+      eval_energy(s, s->ytmp.p, E1);
+      if (std::isfinite(E1[6]) && E1[6] <= E0[6]) break;
+      alpha *= 0.5;
+      st->ls_backtracks++;
+      if (alpha < 1e-10) throw Error(ZEMA_E_LINESEARCH, "line search failed");
+    }
+    tl += now_ms() - q;
+    std::swap(s->y.p, s->ytmp.p);
+    double dm = E1[7];
+    if (auto_k && dm < 1e-3 * s->P.dhat && dm < dprev) s->kappa *= 2.0;
+    dprev = dm;
+  }
+  st->newton_iters = it;
+  st->kappa = s->kappa;
+  st->d_min = min_distance(s, s->y.p);
+  if (!conv) throw Error(ZEMA_E_NEWTON, "Newton did not converge");
+  k_velocity(s, 1.0 / h);
+  s->step += 1;
+  ZCHK(hipStreamSynchronize(s->st));
+  kt_fold(s);
+  st->ms_total = now_ms() - t0;
+  st->ms_assemble = ta;
+  st->ms_pcg = tp;
+  st->ms_broad = tb;
+  st->ms_ccd = tc;
+  st->ms_linesearch = tl;
+  return 0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launch timing
+namespace zema {
+void kt_begin(zema_scene* s, int g) {
+  KTimer& t = s->kt[g];
+  if (!t.on) return;
+  if (t.used + 2 > t.ev.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      ZCHK(hipEventCreate(&e));
+      t.ev.push_back(e);
+    }
+  }
+  ZCHK(hipEventRecord(t.ev[t.used], s->st));
+}
+void kt_end(zema_scene* s, int g, double bytes) {
+  KTimer& t = s->kt[g];
+  if (!t.on) return;
+  ZCHK(hipEventRecord(t.ev[t.used + 1], s->st));
+  t.used += 2;
+  t.pending.push_back(bytes);
+}
+void kt_fold(zema_scene* s) {
+  for (KTimer& t : s->kt) {
+    for (size_t k = 0; k + 1 < t.used; k += 2) {
+      float ms = 0.0f;
+      ZCHK(hipEventSynchronize(t.ev[k + 1]));
+      ZCHK(hipEventElapsedTime(&ms, t.ev[k], t.ev[k + 1]));
+      t.ms += ms;
+      t.launches++;
+      t.bytes += t.pending[k / 2];
+    }
+    t.used = 0;
+    t.pending.clear();
+  }
+}
+}  // namespace zema
+
+zema_scene::~zema_scene() {
+  for (zema::KTimer& t : kt)
+    for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+}
+
+namespace {
+
+template <class F>
+int guard(zema_scene* s, F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    if (s) s->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    if (s) s->err = e.what();
+    return ZEMA_E_DEVICE;
+  }
+}
+
+}  // namespace
+
+// ================================================================== C interface
+extern "C" {
+
+const char* zema_status_string(int st) {
+  switch (st) {
+    case ZEMA_OK: return "ok";
+    case ZEMA_E_ARG: return "invalid argument";
+    case ZEMA_E_MESH: return "degenerate or inverted mesh";
+    case ZEMA_E_INTERSECT: return "intersecting state";
+    case ZEMA_E_CAPACITY: return "output capacity too small";
+    case ZEMA_E_NEWTON: return "Newton did not converge";
+    case ZEMA_E_LINESEARCH: return "line search failed";
+    case ZEMA_E_PCG: return "PCG breakdown or no convergence";
+    case ZEMA_E_NONFINITE: return "non-finite value";
+    case ZEMA_E_DEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* zema_last_error(const zema_scene* s) { return s ? s->err.c_str() : "null scene"; }
+
+int zema_scene_create(const zema_params* params, const zema_soft_desc* soft, int32_t n_soft,
+                      const zema_affine_desc* affine, int32_t n_affine, void* hip_stream, zema_scene** out) {
+  if (!params || !out || n_soft < 0 || n_affine < 0 || (n_soft && !soft) || (n_affine && !affine)) return ZEMA_E_ARG;
+  if (!(params->dt > 0.0) || !(params->dhat > 0.0)) return ZEMA_E_ARG;
+  zema_scene* s = new zema_scene();
+  s->P = *params;
+  s->st = (hipStream_t)hip_stream;
+  int rc = guard(s, [&]() {
+    build_scene(s, soft, n_soft, affine, n_affine);
+    return set_state_impl(s, s->ytmp.p, s->pdir.p, 0.0, 0);
+  });
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return 0;
+}
+
+void zema_scene_destroy(zema_scene* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->st);
+  delete s;
+}
+
+int zema_sizes(const zema_scene* s, int64_t* o) {
+  if (!s || !o) return ZEMA_E_ARG;
+  o[0] = s->ndof;
+  o[1] = s->nsv;
+  o[2] = s->nt;
+  o[3] = s->nsurf;
+  o[4] = s->ntri;
+  o[5] = s->nedge;
+  o[6] = s->nfree;
+  o[7] = s->n_bodies;
+  return 0;
+}
+
+int zema_set_state(zema_scene* s, const double* y, const double* ydot, double kappa, int32_t step) {
+  if (!s || !y || !ydot) return ZEMA_E_ARG;
+  return guard(s, [&]() { return set_state_impl(s, y, ydot, kappa, step); });
+}
+
+int zema_get_state(zema_scene* s, double* y, double* ydot, double* kappa, int32_t* step) {
+  if (!s) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    if (y) ZCHK(hipMemcpyAsync(y, s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+    if (ydot) ZCHK(hipMemcpyAsync(ydot, s->ydot.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+    ZCHK(hipStreamSynchronize(s->st));
+    if (kappa) *kappa = s->kappa;
+    if (step) *step = s->step;
+    return 0;
+  });
+}
+
+int zema_set_kappa(zema_scene* s, double kappa) {
+  if (!s || !(kappa > 0.0)) return ZEMA_E_ARG;
+  s->kappa = kappa;
+  return 0;
+}
+
+int zema_surface_positions(zema_scene* s, const double* y, double* xs) {
+  if (!s || !y || !xs) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    k_map_surface(s, y, xs);
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
+}
+
+int zema_contact_candidates(zema_scene* s, const double* xs0, const double* xs1, double r, int32_t* pt, int64_t pt_cap,
+                            int64_t* n_pt, int32_t* ee, int64_t ee_cap, int64_t* n_ee) {
+  if (!s || !xs0 || !n_pt || !n_ee || !(r >= 0.0)) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    k_candidates(s, xs0, xs1 ? xs1 : xs0, r);
+    *n_pt = s->npt;
+    *n_ee = s->nee;
+    if (s->npt > pt_cap || s->nee > ee_cap) throw Error(ZEMA_E_CAPACITY, "candidate capacity");
+    if (s->npt) ZCHK(hipMemcpyAsync(pt, s->pt.p, sizeof(int) * 2 * s->npt, hipMemcpyDeviceToDevice, s->st));
+    if (s->nee) ZCHK(hipMemcpyAsync(ee, s->ee.p, sizeof(int) * 2 * s->nee, hipMemcpyDeviceToDevice, s->st));
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
+}
+
+int zema_ip_assemble(zema_scene* s, const double* y, uint32_t flags, double* terms, double* grad) {
+  if (!s || !y || !terms) return ZEMA_E_ARG;
+  if ((flags & ZEMA_GRAD) && !grad) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    unsigned mask = (flags >> ZEMA_TERMS_SHIFT) & 0x3fu;
+    if (!mask) mask = 0x3fu;
+    static_candidates(s, y);
+    double T[8];
+    assemble(s, y, (flags & ZEMA_GRAD) ? s->grad.p : nullptr, (flags & ZEMA_HESS) != 0, mask, T);
+    std::memcpy(terms, T, sizeof(T));
+    if (!std::isfinite(T[6])) throw Error(ZEMA_E_INTERSECT, "infeasible state (inverted tet or zero distance)");
+    if (flags & ZEMA_GRAD)
+      ZCHK(hipMemcpyAsync(grad, s->grad.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
+}
+
+int zema_hessian_matvec(zema_scene* s, const double* v, double* out) {
+  if (!s || !v || !out) return ZEMA_E_ARG;
+  if (!s->hess_valid) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    k_hess_matvec(s, v, out);
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
+}
+
+int zema_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, int32_t max_iter, int32_t* iters,
+                   double* rel_res) {
+  if (!s || !rhs || !sol || !iters || !rel_res || !s->hess_valid) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    int it;
+    double rr;
+    int rc = k_pcg(s, rhs, sol, rtol, max_iter, &it, &rr);
+    *iters = it;
+    *rel_res = rr;
+    if (rc) throw Error(rc, "PCG breakdown or no convergence");
+    return 0;
+  });
+}
+
+int zema_ccd_max_step(zema_scene* s, const double* y, const double* p, double* alpha) {
+  if (!s || !y || !p || !alpha) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    swept_candidates(s, y, p);
+    int rc = k_ccd(s, y, p, alpha);
+    if (rc) throw Error(rc, "intersecting pair at CCD start");
+    return 0;
+  });
+}
+
+int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
+  if (!s || n_steps < 0 || (n_steps && !stats)) return ZEMA_E_ARG;
+  for (int k = 0; k < n_steps; ++k) {
+    // y^t / ydot^t are saved first so a failed step can restore them
+    int rc = guard(s, [&]() {
+      ZCHK(hipMemcpyAsync(s->yt.p, s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+      ZCHK(hipMemcpyAsync(s->ydt.p, s->ydot.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+      return time_step(s, &stats[k]);
+    });
+    stats[k].status = rc;
+    if (rc) {
+      // restore y^t and ydot^t of the failed step
+      (void)hipMemcpyAsync(s->y.p, s->yt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st);
+      (void)hipMemcpyAsync(s->ydot.p, s->ydt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st);
+      (void)hipStreamSynchronize(s->st);
+      return rc;
+    }
+  }
+  return 0;
+}
+
+int zema_kernel_timer(zema_scene* s, int32_t group, int32_t enable) {
+  if (!s || group < 0 || group >= KT_N) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    ZCHK(hipStreamSynchronize(s->st));
+    kt_fold(s);
+    KTimer& t = s->kt[group];
+    t.on = enable != 0;
+    t.ms = 0.0;
+    t.launches = 0;
+    t.bytes = 0.0;
+    return 0;
+  });
+}
+
+int zema_kernel_time(zema_scene* s, int32_t group, double* ms, int64_t* launches, double* bytes) {
+  if (!s || group < 0 || group >= KT_N || !ms || !launches) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    ZCHK(hipStreamSynchronize(s->st));
+    kt_fold(s);
+    *ms = s->kt[group].ms;
+    *launches = s->kt[group].launches;
+    if (bytes) *bytes = s->kt[group].bytes;
+    return 0;
+  });
+}
+
+int zema_friction_table(zema_scene* s, int64_t* n, int32_t* ids5, double* vals8, int64_t cap) {
+  if (!s || !n) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    *n = s->nfric;
+    if (s->nfric > cap) throw Error(ZEMA_E_CAPACITY, "friction table capacity");
+    if (s->nfric) {
+      ZCHK(hipMemcpyAsync(ids5, s->f_ids.p, sizeof(int) * 5 * s->nfric, hipMemcpyDeviceToHost, s->st));
+      ZCHK(hipMemcpyAsync(vals8, s->f_vals.p, sizeof(double) * 8 * s->nfric, hipMemcpyDeviceToHost, s->st));
+    }
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
+}
+
+}  // extern "C"

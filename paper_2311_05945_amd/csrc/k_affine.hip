@@ -1,0 +1,137 @@
+// Affine-body terms (Sec. III eq. 2): inertia 1/2 (q - qhat)^T M_b (q - qhat) with
+// M_b = diag(m I, S, S, S) for a centred rest frame, orthogonality potential
+// h^2 lambda V |A A^T - I|_F^2 (9x9 Hessian projected to PSD), and for driven bodies
+// the kinematic penalty kappa_A/2 |q - q~|^2 of Sec. IV-C-1.  One lane per body.
+#include "geom.hpp"
+#include "scene.hpp"
+
+namespace zema {
+
+constexpr int BF = 32;
+constexpr int BF_M = 0, BF_V = 1, BF_ST = 2, BF_KA = 3, BF_S = 4, BF_QF = 13;
+
+// energies [inertia, orthogonality, kinematic]; optional gradient (12) and Hessian
+__device__ inline void body_terms(const double* q, const double* qh, const double* qt, const double* bf, int mode,
+                                  double h2, double* E3, double* g, double (*H)[12], unsigned mask) {
+  double m = bf[BF_M], V = bf[BF_V], lam = bf[BF_ST], kA = bf[BF_KA];
+  const double* S = bf + BF_S;
+  double dq[12];
+  for (int k = 0; k < 12; ++k) dq[k] = q[k] - qh[k];
+  // inertia
+  double Mdq[12];
+  for (int k = 0; k < 3; ++k) Mdq[k] = m * dq[k];
+  for (int blk = 0; blk < 3; ++blk)
+    for (int i = 0; i < 3; ++i)
+      Mdq[3 + 3 * blk + i] = S[3 * i] * dq[3 + 3 * blk] + S[3 * i + 1] * dq[4 + 3 * blk] + S[3 * i + 2] * dq[5 + 3 * blk];
+  double ein = 0.0;
+  for (int k = 0; k < 12; ++k) ein += 0.5 * dq[k] * Mdq[k];
+  // orthogonality: A rows a_i = q[3+3i .. 5+3i]; R = A A^T - I
+  double A[3][3], R[3][3], AtA[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[i][j] = q[3 + 3 * i + j];
+  double phi = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double acc = A[i][0] * A[j][0] + A[i][1] * A[j][1] + A[i][2] * A[j][2];
+      R[i][j] = acc - (i == j ? 1.0 : 0.0);
+      AtA[i][j] = A[0][i] * A[0][j] + A[1][i] * A[1][j] + A[2][i] * A[2][j];
+      phi += R[i][j] * R[i][j];
+    }
+  double c = h2 * lam * V;
+  double eorth = c * phi;
+  double ekin = 0.0;
+  if (mode == ZEMA_DRIVEN)
+    for (int k = 0; k < 12; ++k) {
+      double d = q[k] - qt[k];
+      ekin += 0.5 * kA * d * d;
+    }
+  E3[0] = ein;
+  E3[1] = eorth;
+  E3[2] = ekin;
+  if (g) {
+    for (int k = 0; k < 12; ++k) g[k] = (mask & 1u) ? Mdq[k] : 0.0;
+    if (mask & 4u)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          g[3 + 3 * i + j] += 4.0 * c * (R[i][0] * A[0][j] + R[i][1] * A[1][j] + R[i][2] * A[2][j]);
+    if ((mask & 8u) && mode == ZEMA_DRIVEN)
+      for (int k = 0; k < 12; ++k) g[k] += kA * (q[k] - qt[k]);
+  }
+  if (H) {
+    for (int i = 0; i < 12; ++i)
+      for (int j = 0; j < 12; ++j) H[i][j] = 0.0;
+    if (mask & 4u) {
+      // d2/dA_ij dA_kl of |A A^T - I|^2 = 4 (delta_ik (A^T A)_lj + A_il A_kj + R_ik delta_jl)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l) {
+              double v = (i == k ? AtA[l][j] : 0.0) + A[i][l] * A[k][j] + (j == l ? R[i][k] : 0.0);
+              H[3 * i + j][3 * k + l] = 4.0 * c * v;
+            }
+      psd_project<9>(H);
+      // move the 9x9 into the a-block (indices 3..11)
+      for (int i = 8; i >= 0; --i)
+        for (int j = 8; j >= 0; --j) H[3 + i][3 + j] = H[i][j];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 12; ++j) {
+          H[i][j] = 0.0;
+          H[j][i] = 0.0;
+        }
+    }
+    if (mask & 1u) {
+      for (int k = 0; k < 3; ++k) H[k][k] += m;
+      for (int blk = 0; blk < 3; ++blk)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) H[3 + 3 * blk + i][3 + 3 * blk + j] += S[3 * i + j];
+    }
+    if ((mask & 8u) && mode == ZEMA_DRIVEN)
+      for (int k = 0; k < 12; ++k) H[k][k] += kA;
+  }
+}
+
+__global__ void body_assemble_kernel(int nb, const double* __restrict__ bf, const int* __restrict__ bi,
+                                     const double* __restrict__ qtilde, const double* __restrict__ y,
+                                     const double* __restrict__ yhat, double* __restrict__ grad,
+                                     double* __restrict__ e_body, const int* __restrict__ bsr_ptr,
+                                     double* __restrict__ val, int nnzb, int want_h, double h2, unsigned mask) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  int mode = bi[4 * b], dof0 = bi[4 * b + 1], node0 = bi[4 * b + 2];
+  if (dof0 < 0) {
+    e_body[b] = e_body[nb + b] = e_body[2 * nb + b] = 0.0;
+    return;
+  }
+  double E3[3], g[12];
+  double H[12][12];
+  body_terms(y + dof0, yhat + dof0, qtilde + 12 * b, bf + BF * b, mode, h2, E3, grad ? g : nullptr,
+             want_h ? H : nullptr, mask);
+  for (int k = 0; k < 3; ++k) e_body[k * nb + b] = E3[k];  // SoA: [inertia | orth | kinematic]
+  if (grad)
+    for (int k = 0; k < 12; ++k) grad[dof0 + k] = g[k];
+  if (want_h)
+    for (int r = 0; r < 4; ++r) {
+      int base = bsr_ptr[node0 + r];
+      for (int c = 0; c < 4; ++c)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) val[(size_t)(3 * i + j) * nnzb + base + c] = H[3 * r + i][3 * c + j];
+    }
+}
+
+void k_body_terms(zema_scene* s, const double* y, double* grad, bool hess, unsigned mask) {
+  int nb = (int)s->bodies.size();
+  if (!nb) return;
+  body_assemble_kernel<<<nblocks(nb, 64), 64, 0, s->st>>>(nb, s->body_f.p, s->body_i.p, s->qtilde.p, y, s->yhat.p,
+                                                          grad, s->e_body.p, s->bsr_ptr.p, s->bsr_val.p, s->nnzb,
+                                                          hess ? 1 : 0, s->P.dt * s->P.dt, mask);
+}
+
+void k_body_energy(zema_scene* s, const double* y) {
+  int nb = (int)s->bodies.size();
+  if (!nb) return;
+  body_assemble_kernel<<<nblocks(nb, 64), 64, 0, s->st>>>(nb, s->body_f.p, s->body_i.p, s->qtilde.p, y, s->yhat.p,
+                                                          nullptr, s->e_body.p, s->bsr_ptr.p, s->bsr_val.p, s->nnzb, 0,
+                                                          s->P.dt * s->P.dt, 0x3fu);
+}
+
+}  // namespace zema

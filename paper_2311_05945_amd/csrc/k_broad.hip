@@ -1,0 +1,331 @@
+// Broad phase: the candidate set of the contact term (Sec. III eq. 4, inter-body
+// point-triangle and edge-edge pairs) is defined by an exact box predicate on the
+// caller's positions -- per axis lo = min over the primitive's vertices of
+// min(xs0, xs1) - r, hi = max of max + r, pairs kept when the closed intervals
+// overlap on all three axes.  A uniform spatial hash (cell size ~ mean surface edge
+// length, hash of Teschner et al. 2003) only accelerates the search: entries are
+// sorted by bucket with the radix sort, every query walks the cells of its box, and a
+// pair is reported only from the cell that contains the componentwise maximum of
+// the two lower corners, which both boxes contain, so each pair appears exactly
+// once.  Boxes spanning more than kBigCells cells skip the table and are tested
+// against every primitive.  The output is sorted by (first, second) id.
+#include <algorithm>
+
+#include "scene.hpp"
+
+namespace zema {
+
+constexpr int kBigCells = 512;
+constexpr int kCellBias = 1 << 20;
+
+struct Grid {
+  double inv_c;
+};
+
+__device__ inline int cell_of(double z, double inv_c) { return (int)floor(__dmul_rn(z, inv_c)); }
+
+__device__ inline unsigned hash3(int ix, int iy, int iz, unsigned mask) {
+  return (((unsigned)ix * 73856093u) ^ ((unsigned)iy * 19349663u) ^ ((unsigned)iz * 83492791u)) & mask;
+}
+
+__device__ inline unsigned long long pack_cell(int ix, int iy, int iz) {
+  return ((unsigned long long)(ix + kCellBias) << 42) | ((unsigned long long)(iy + kCellBias) << 21) |
+         (unsigned long long)(iz + kCellBias);
+}
+
+// boxes of vertices [0, nv), triangles [nv, nv+nt), edges [nv+nt, nv+nt+ne)
+__global__ void boxes_kernel(int nv, int nt, int ne, const int* __restrict__ tris, const int* __restrict__ edges,
+                             const double* __restrict__ xs0, const double* __restrict__ xs1, double r,
+                             double* __restrict__ lo, double* __restrict__ hi) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv + nt + ne) return;
+  int v[3], n;
+  if (i < nv) {
+    v[0] = i;
+    n = 1;
+  } else if (i < nv + nt) {
+    const int* t = tris + 3 * (i - nv);
+    v[0] = t[0];
+    v[1] = t[1];
+    v[2] = t[2];
+    n = 3;
+  } else {
+    const int* e = edges + 2 * (i - nv - nt);
+    v[0] = e[0];
+    v[1] = e[1];
+    n = 2;
+  }
+  for (int k = 0; k < 3; ++k) {
+    double l = INFINITY, h = -INFINITY;
+    for (int a = 0; a < n; ++a) {
+      double p = xs0[3 * v[a] + k], q = xs1[3 * v[a] + k];
+      l = fmin(l, fmin(p, q));
+      h = fmax(h, fmax(p, q));
+    }
+    lo[3 * i + k] = __dsub_rn(l, r);
+    hi[3 * i + k] = __dadd_rn(h, r);
+  }
+}
+
+__device__ inline bool overlap(const double* lo, const double* hi, int a, int b) {
+  for (int k = 0; k < 3; ++k)
+    if (!(lo[3 * a + k] <= hi[3 * b + k] && lo[3 * b + k] <= hi[3 * a + k])) return false;
+  return true;
+}
+
+// cell range of a box; returns the number of cells or -1 when large / out of range
+__device__ inline long long cell_range(const double* lo, const double* hi, int i, double inv_c, int c0[3], int c1[3]) {
+  long long n = 1;
+  for (int k = 0; k < 3; ++k) {
+    double a = __dmul_rn(lo[3 * i + k], inv_c), b = __dmul_rn(hi[3 * i + k], inv_c);
+    if (!(a > -(double)(kCellBias - 2) && b < (double)(kCellBias - 2))) return -1;
+    c0[k] = (int)floor(a);
+    c1[k] = (int)floor(b);
+    n *= (long long)(c1[k] - c0[k] + 1);
+  }
+  return n > kBigCells ? -1 : n;
+}
+
+struct PrimSet {
+  int base;  // index of the first primitive in the box arrays
+  int n;
+};
+
+__device__ inline int prim_body(int kind, int id, const int* tris, const int* edges, const int* sv_body) {
+  if (kind == 0) return sv_body[id];
+  if (kind == 1) return sv_body[tris[3 * id]];
+  return sv_body[edges[2 * id]];
+}
+
+// entries: count cells of every entry primitive (0 for large ones, flagged in big)
+__global__ void entry_count_kernel(PrimSet E, const double* __restrict__ lo, const double* __restrict__ hi,
+                                   double inv_c, int* __restrict__ cnt, int* __restrict__ big_flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= E.n) return;
+  int c0[3], c1[3];
+  long long n = cell_range(lo, hi, E.base + i, inv_c, c0, c1);
+  cnt[i] = n < 0 ? 0 : (int)n;
+  big_flag[i] = n < 0 ? 1 : 0;
+}
+
+__global__ void entry_insert_kernel(PrimSet E, const double* __restrict__ lo, const double* __restrict__ hi,
+                                    double inv_c, const int* __restrict__ offs, unsigned mask,
+                                    unsigned long long* __restrict__ key, int* __restrict__ val,
+                                    unsigned long long* __restrict__ ecell, int* __restrict__ eprim) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= E.n) return;
+  int c0[3], c1[3];
+  if (cell_range(lo, hi, E.base + i, inv_c, c0, c1) < 0) return;
+  int o = offs[i];
+  for (int x = c0[0]; x <= c1[0]; ++x)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int z = c0[2]; z <= c1[2]; ++z, ++o) {
+        key[o] = hash3(x, y, z, mask);
+        val[o] = o;
+        ecell[o] = pack_cell(x, y, z);
+        eprim[o] = i;
+      }
+}
+
+__global__ void bucket_bounds_kernel(int n, const unsigned long long* __restrict__ skey, int* __restrict__ blo,
+                                     int* __restrict__ bhi) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  unsigned h = (unsigned)skey[j];
+  if (j == 0 || (unsigned)skey[j - 1] != h) blo[h] = j;
+  if (j == n - 1 || (unsigned)skey[j + 1] != h) bhi[h] = j + 1;
+}
+
+// gather entry cell / prim into sorted order
+__global__ void entry_permute_kernel(int n, const int* __restrict__ sval, const unsigned long long* __restrict__ ecell,
+                                     const int* __restrict__ eprim, unsigned long long* __restrict__ scell,
+                                     int* __restrict__ sprim) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int o = sval[j];
+  scell[j] = ecell[o];
+  sprim[j] = eprim[o];
+}
+
+struct PairRule {
+  int qkind, ekind;  // 0 vertex, 1 triangle, 2 edge
+  int same_set;      // edge-edge: report (q, e) only when q < e
+};
+
+__device__ inline bool admissible(PairRule R, int q, int e, const int* tris, const int* edges, const int* sv_body,
+                                  const unsigned char* fixed) {
+  if (R.same_set && !(q < e)) return false;
+  int bq = prim_body(R.qkind, q, tris, edges, sv_body), be = prim_body(R.ekind, e, tris, edges, sv_body);
+  if (bq == be) return false;
+  if (fixed[bq] && fixed[be]) return false;
+  return true;
+}
+
+__device__ inline void emit(unsigned long long key, unsigned long long* out, int* counter, int cap) {
+  int k = atomicAdd(counter, 1);
+  if (k < cap) out[k] = key;
+}
+
+__global__ void query_kernel(PrimSet Q, PrimSet E, PairRule R, const double* __restrict__ lo,
+                             const double* __restrict__ hi, double inv_c, unsigned mask, const int* __restrict__ blo,
+                             const int* __restrict__ bhi, const unsigned long long* __restrict__ scell,
+                             const int* __restrict__ sprim, const int* __restrict__ ebig, const int* __restrict__ tris,
+                             const int* __restrict__ edges, const int* __restrict__ sv_body,
+                             const unsigned char* __restrict__ fixed, unsigned long long nE,
+                             unsigned long long* __restrict__ out, int* __restrict__ counter, int cap) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= Q.n) return;
+  int qi = Q.base + q;
+  int c0[3], c1[3];
+  if (cell_range(lo, hi, qi, inv_c, c0, c1) < 0) {
+    // large query box: for a shared set every pair with a large member is reported
+    // by big_entry_kernel; otherwise test every small entry directly
+    if (R.same_set) return;
+    for (int e = 0; e < E.n; ++e) {
+      if (ebig[e]) continue;
+      if (!admissible(R, q, e, tris, edges, sv_body, fixed)) continue;
+      if (overlap(lo, hi, qi, E.base + e)) emit((unsigned long long)q * nE + e, out, counter, cap);
+    }
+    return;
+  }
+  for (int x = c0[0]; x <= c1[0]; ++x)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int z = c0[2]; z <= c1[2]; ++z) {
+        unsigned h = hash3(x, y, z, mask);
+        unsigned long long ck = pack_cell(x, y, z);
+        int j1 = bhi[h];
+        for (int j = blo[h]; j < j1; ++j) {
+          if (scell[j] != ck) continue;
+          int e = sprim[j];
+          if (!admissible(R, q, e, tris, edges, sv_body, fixed)) continue;
+          int ei = E.base + e;
+          if (!overlap(lo, hi, qi, ei)) continue;
+          // report only from the cell holding max(lo_q, lo_e)
+          int m0 = cell_of(fmax(lo[3 * qi], lo[3 * ei]), inv_c);
+          int m1 = cell_of(fmax(lo[3 * qi + 1], lo[3 * ei + 1]), inv_c);
+          int m2 = cell_of(fmax(lo[3 * qi + 2], lo[3 * ei + 2]), inv_c);
+          if (m0 != x || m1 != y || m2 != z) continue;
+          emit((unsigned long long)q * nE + e, out, counter, cap);
+        }
+      }
+}
+
+// large entries: test against every query primitive (for a shared set only pairs
+// not already covered: the other primitive small, or large with a larger id)
+__global__ void big_entry_kernel(PrimSet Q, PrimSet E, PairRule R, const double* __restrict__ lo,
+                                 const double* __restrict__ hi, const int* __restrict__ ebig,
+                                 const int* __restrict__ tris, const int* __restrict__ edges,
+                                 const int* __restrict__ sv_body, const unsigned char* __restrict__ fixed,
+                                 unsigned long long nE, unsigned long long* __restrict__ out, int* __restrict__ counter,
+                                 int cap) {
+  for (int e = blockIdx.x; e < E.n; e += gridDim.x) {
+  if (!ebig[e]) continue;
+  for (int q = threadIdx.x; q < Q.n; q += blockDim.x) {
+    if (R.same_set) {
+      if (q == e) continue;
+      int a = q < e ? q : e, b = q < e ? e : q;
+      if (ebig[q] && !(e < q)) continue;  // both large: reported by the smaller id
+      if (!admissible(R, a, b, tris, edges, sv_body, fixed)) continue;
+      if (overlap(lo, hi, Q.base + q, E.base + e)) emit((unsigned long long)a * nE + b, out, counter, cap);
+    } else {
+      if (!admissible(R, q, e, tris, edges, sv_body, fixed)) continue;
+      if (overlap(lo, hi, Q.base + q, E.base + e)) emit((unsigned long long)q * nE + e, out, counter, cap);
+    }
+  }
+  }
+}
+
+__global__ void decode_pairs_kernel(int n, const unsigned long long* __restrict__ k, unsigned long long nE,
+                                    int* __restrict__ out) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  out[2 * j] = (int)(k[j] / nE);
+  out[2 * j + 1] = (int)(k[j] % nE);
+}
+
+static int bits_for(unsigned long long v) {
+  int b = 0;
+  while (b < 64 && (v >> b)) ++b;
+  return b;
+}
+
+// One candidate search (PT or EE); result sorted into out (n x 2 ints).
+static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>& out) {
+  if (Q.n == 0 || E.n == 0) {
+    out.resize(0);
+    return 0;
+  }
+  const double inv_c = 1.0 / s->cell;
+  s->cnt.reserve(E.n + 1);
+  s->offs.reserve(E.n + 1);
+  s->big_list.reserve(E.n + 1);
+  entry_count_kernel<<<nblocks(E.n), kBlock, 0, s->st>>>(E, s->bb_lo.p, s->bb_hi.p, inv_c, s->cnt.p, s->big_list.p);
+  int64_t total = k_exclusive_scan(s, s->cnt.p, s->offs.p, E.n);
+  unsigned tsize = 1024;
+  while (tsize < 2 * total) tsize <<= 1;
+  unsigned mask = tsize - 1;
+  SortBufs& sb = s->sort;
+  sb.k0.reserve(total + 1);
+  sb.v0.reserve(total + 1);
+  s->ent_cell.reserve(2 * total + 2);
+  s->ent_prim.reserve(2 * total + 2);
+  s->bucket_lo.reserve(tsize);
+  s->bucket_hi.reserve(tsize);
+  if (total > 0) {
+    entry_insert_kernel<<<nblocks(E.n), kBlock, 0, s->st>>>(E, s->bb_lo.p, s->bb_hi.p, inv_c, s->offs.p, mask,
+                                                            sb.k0.p, sb.v0.p, s->ent_cell.p, s->ent_prim.p);
+    k_radix_sort(s, sb, total, bits_for(mask));
+    // sorted copies live in the second halves of ent_cell / ent_prim
+    entry_permute_kernel<<<nblocks(total), kBlock, 0, s->st>>>((int)total, sb.v0.p, s->ent_cell.p, s->ent_prim.p,
+                                                               s->ent_cell.p + total, s->ent_prim.p + total);
+  }
+  ZCHK(hipMemsetAsync(s->bucket_lo.p, 0, sizeof(int) * tsize, s->st));
+  ZCHK(hipMemsetAsync(s->bucket_hi.p, 0, sizeof(int) * tsize, s->st));
+  if (total > 0)
+    bucket_bounds_kernel<<<nblocks(total), kBlock, 0, s->st>>>((int)total, sb.k0.p, s->bucket_lo.p, s->bucket_hi.p);
+  unsigned long long nE = (unsigned long long)E.n;
+  int* counter = s->counters.p;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    int cap = (int)std::min<size_t>(s->pair_keys.cap, (size_t)INT32_MAX);
+    ZCHK(hipMemsetAsync(counter, 0, sizeof(int), s->st));
+    kt_begin(s, KT_QUERY);
+    query_kernel<<<nblocks(Q.n, 128), 128, 0, s->st>>>(
+        Q, E, R, s->bb_lo.p, s->bb_hi.p, inv_c, mask, s->bucket_lo.p, s->bucket_hi.p, s->ent_cell.p + total,
+        s->ent_prim.p + total, s->big_list.p, s->tris.p, s->edges.p, s->sv_body.p, s->body_fixed.p, nE,
+        s->pair_keys.p, counter, cap);
+    kt_end(s, KT_QUERY);
+    big_entry_kernel<<<std::min(E.n, 1024), kBlock, 0, s->st>>>(Q, E, R, s->bb_lo.p, s->bb_hi.p, s->big_list.p, s->tris.p, s->edges.p,
+                                                s->sv_body.p, s->body_fixed.p, nE, s->pair_keys.p, counter, cap);
+    int n;
+    ZCHK(hipMemcpyAsync(&n, counter, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    ZCHK(hipStreamSynchronize(s->st));
+    if (n <= cap) {
+      // sort the pair keys (values unused)
+      sb.k0.reserve(n + 1);
+      sb.v0.reserve(n + 1);
+      if (n > 0) ZCHK(hipMemcpyAsync(sb.k0.p, s->pair_keys.p, sizeof(unsigned long long) * n,
+                                     hipMemcpyDeviceToDevice, s->st));
+      k_radix_sort(s, sb, n, bits_for((unsigned long long)Q.n * nE));
+      out.resize((size_t)2 * n);
+      if (n > 0) decode_pairs_kernel<<<nblocks(n), kBlock, 0, s->st>>>(n, sb.k0.p, nE, out.p);
+      return n;
+    }
+    s->pair_keys.reserve((size_t)n + n / 4 + 1024);
+  }
+  throw Error(ZEMA_E_CAPACITY, "candidate buffer growth failed");
+}
+
+void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r) {
+  int nv = s->nsurf, nt = s->ntri, ne = s->nedge;
+  int np = nv + nt + ne;
+  s->bb_lo.reserve(3 * (size_t)np);
+  s->bb_hi.reserve(3 * (size_t)np);
+  if (s->pair_keys.cap < 4096) s->pair_keys.reserve(1 << 16);
+  if (np)
+    boxes_kernel<<<nblocks(np), kBlock, 0, s->st>>>(nv, nt, ne, s->tris.p, s->edges.p, xs0, xs1 ? xs1 : xs0, r,
+                                                    s->bb_lo.p, s->bb_hi.p);
+  s->npt = search(s, PrimSet{0, nv}, PrimSet{nv, nt}, PairRule{0, 1, 0}, s->pt);
+  s->nee = search(s, PrimSet{nv + nt, ne}, PrimSet{nv + nt, ne}, PairRule{2, 2, 1}, s->ee);
+}
+
+}  // namespace zema

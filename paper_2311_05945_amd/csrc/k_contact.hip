@@ -1,0 +1,560 @@
+// Contact terms of the incremental potential: log-barrier pairs (Sec. III eqs.
+// 4-5, edge-edge pairs mollified) and lagged smoothed friction (eqs. 9-10), with the
+// soft-affine chain rule of eqs. 6-8: the 12x12 pair Hessian is projected to PSD in
+// x-space and then mapped through the affine Jacobian J(x0) = [I | e_r x0^T].
+//
+// Assembly is deterministic: every active pair writes its y-space contributions as
+// (row node, column node, 3x3 block) triplets and (node, 3-vector) gradient entries
+// at scanned offsets; the triplets are radix-sorted by key and summed per key in
+// sorted order into a CSR contact matrix over the 3-DOF nodes.
+#include "geom.hpp"
+#include "scene.hpp"
+
+namespace zema {
+
+__device__ inline void pair_slots(int k, int npt, const int* __restrict__ pt, const int* __restrict__ ee,
+                                  const int* __restrict__ tris, const int* __restrict__ edges, int& kind, int sv[4],
+                                  int& ea, int& eb) {
+  if (k < npt) {
+    kind = 0;
+    int v = pt[2 * k], t = pt[2 * k + 1];
+    sv[0] = v;
+    sv[1] = tris[3 * t];
+    sv[2] = tris[3 * t + 1];
+    sv[3] = tris[3 * t + 2];
+    ea = eb = -1;
+  } else {
+    kind = 1;
+    int j = k - npt;
+    ea = ee[2 * j];
+    eb = ee[2 * j + 1];
+    sv[0] = edges[2 * ea];
+    sv[1] = edges[2 * ea + 1];
+    sv[2] = edges[2 * eb];
+    sv[3] = edges[2 * eb + 1];
+  }
+}
+
+// ------------------------------------------------------------------ energies (line search)
+__global__ void contact_energy_kernel(int npt, int nee, const int* __restrict__ pt, const int* __restrict__ ee,
+                                      const int* __restrict__ tris, const int* __restrict__ edges,
+                                      const double* __restrict__ elen2, const double* __restrict__ xs, double kappa,
+                                      double dhat, double* __restrict__ e_pair, double* __restrict__ d_pair,
+                                      unsigned long long* __restrict__ dmin) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  double d = INFINITY;
+  if (k < npt + nee) {
+    int kind, sv[4], ea, eb;
+    pair_slots(k, npt, pt, ee, tris, edges, kind, sv, ea, eb);
+    V3 x[4];
+    for (int a = 0; a < 4; ++a) x[a] = ld3(xs + 3 * sv[a]);
+    double eps = kind == 1 ? 1e-3 * elen2[ea] * elen2[eb] : 0.0;
+    e_pair[k] = pair_barrier_energy(kind, x, eps, kappa, dhat, &d);
+    d_pair[k] = d;
+  }
+  for (int o = 32; o > 0; o >>= 1) d = fmin(d, __shfl_xor(d, o, 64));
+  if ((threadIdx.x & 63) == 0 && d < INFINITY) atomicMin(dmin, dbits(d));
+}
+
+// friction: f0 and the coefficients of the 3x3 core  alpha Pi - beta u u^T
+__device__ inline double friction_core(double y, double ys, double& f1y, double& alpha, double& beta) {
+  if (y < ys) {
+    f1y = 2.0 / ys - y / (ys * ys);
+    alpha = f1y;
+    beta = y > 0.0 ? 1.0 / (ys * ys * y) : 0.0;
+    return -y * y * y / (3.0 * ys * ys) + y * y / ys + ys / 3.0;
+  }
+  f1y = 1.0 / y;
+  alpha = 1.0 / y;
+  beta = 1.0 / (y * y * y);
+  return y;
+}
+
+__device__ inline V3 friction_u(const double* __restrict__ fv, const double* __restrict__ xt, const V3* x) {
+  V3 D = v3(0, 0, 0);
+  for (int a = 0; a < 4; ++a) D = D + fv[4 + a] * (x[a] - ld3(xt + 3 * a));
+  V3 n = ld3(fv + 1);
+  return D - dot(n, D) * n;
+}
+
+__global__ void friction_energy_kernel(int nf, const int* __restrict__ fids, const double* __restrict__ fvals,
+                                       const double* __restrict__ fxt, const double* __restrict__ xs, double mu,
+                                       double ys, double* __restrict__ e) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  V3 x[4];
+  for (int a = 0; a < 4; ++a) x[a] = ld3(xs + 3 * fids[5 * f + 1 + a]);
+  V3 u = friction_u(fvals + 8 * f, fxt + 12 * f, x);
+  double y = sqrt(dot(u, u)), f1y, al, be;
+  double f0 = friction_core(y, ys, f1y, al, be);
+  e[f] = mu * fvals[8 * f] * f0;
+}
+
+// ------------------------------------------------------------------ lagged friction table
+__global__ void friction_flag_kernel(int npt, int nee, const int* __restrict__ pt, const int* __restrict__ ee,
+                                     const int* __restrict__ tris, const int* __restrict__ edges,
+                                     const double* __restrict__ xs, double dhat, int* __restrict__ flag) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npt + nee) return;
+  int kind, sv[4], ea, eb;
+  pair_slots(k, npt, pt, ee, tris, edges, kind, sv, ea, eb);
+  V3 x[4];
+  for (int a = 0; a < 4; ++a) x[a] = ld3(xs + 3 * sv[a]);
+  double d = pair_dist(kind, x, nullptr);
+  flag[k] = (d < dhat && d > 0.0) ? 1 : 0;
+}
+
+// lambda = kappa m |b'(d)| (normal force in IP units), n = unit vector between the
+// closest points, w = closest-point weights (PT: 1, -beta_i; EE: 1-ga, ga, -(1-gb), -gb)
+__global__ void friction_fill_kernel(int npt, int nee, const int* __restrict__ pt, const int* __restrict__ ee,
+                                     const int* __restrict__ tris, const int* __restrict__ edges,
+                                     const double* __restrict__ elen2, const double* __restrict__ xs, double kappa,
+                                     double dhat, const int* __restrict__ flag, const int* __restrict__ offs,
+                                     int* __restrict__ fids, double* __restrict__ fvals, double* __restrict__ fxt) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npt + nee || !flag[k]) return;
+  int f = offs[k];
+  int kind, sv[4], ea, eb;
+  pair_slots(k, npt, pt, ee, tris, edges, kind, sv, ea, eb);
+  V3 x[4];
+  for (int a = 0; a < 4; ++a) x[a] = ld3(xs + 3 * sv[a]);
+  double w[4];
+  V3 c0, c1;
+  double m = 1.0;
+  if (kind == 0) {
+    int t = pt_type(x[0], x[1], x[2], x[3]);
+    double b[3] = {0, 0, 0};
+    if (t <= 2) {
+      b[t] = 1.0;
+    } else if (t <= 5) {
+      int i = t - 3, j = (i + 1) % 3;
+      V3 e = x[1 + j] - x[1 + i];
+      double s = dot(x[0] - x[1 + i], e) / dot(e, e);
+      s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+      b[i] = 1.0 - s;
+      b[j] = s;
+    } else {
+      V3 u = x[2] - x[1], v = x[3] - x[1], ww = x[0] - x[1];
+      V3 n = cross(u, v);
+      double nn = dot(n, n);
+      b[1] = dot(cross(ww, v), n) / nn;
+      b[2] = dot(cross(u, ww), n) / nn;
+      b[0] = 1.0 - b[1] - b[2];
+    }
+    w[0] = 1.0;
+    w[1] = -b[0];
+    w[2] = -b[1];
+    w[3] = -b[2];
+    c0 = x[0];
+    c1 = b[0] * x[1] + b[1] * x[2] + b[2] * x[3];
+  } else {
+    double sa, tb;
+    ee_type(x[0], x[1], x[2], x[3], &sa, &tb);
+    w[0] = 1.0 - sa;
+    w[1] = sa;
+    w[2] = -(1.0 - tb);
+    w[3] = -tb;
+    c0 = (1.0 - sa) * x[0] + sa * x[1];
+    c1 = (1.0 - tb) * x[2] + tb * x[3];
+    V3 n = cross(x[1] - x[0], x[3] - x[2]);
+    double m1, m2;
+    mollifier(dot(n, n), 1e-3 * elen2[ea] * elen2[eb], m, m1, m2);
+  }
+  double d = pair_dist(kind, x, nullptr);
+  double b, b1, b2;
+  barrier3(d, dhat, b, b1, b2);
+  V3 n = c0 - c1;
+  double nn = sqrt(dot(n, n));
+  n = nn > 0.0 ? (1.0 / nn) * n : v3(0, 0, 0);
+  fids[5 * f] = kind;
+  for (int a = 0; a < 4; ++a) fids[5 * f + 1 + a] = sv[a];
+  fvals[8 * f] = nn > 0.0 ? kappa * m * fabs(b1) : 0.0;
+  fvals[8 * f + 1] = n.x;
+  fvals[8 * f + 2] = n.y;
+  fvals[8 * f + 3] = n.z;
+  for (int a = 0; a < 4; ++a) fvals[8 * f + 4 + a] = w[a];
+  for (int a = 0; a < 4; ++a) {
+    fxt[12 * f + 3 * a] = x[a].x;
+    fxt[12 * f + 3 * a + 1] = x[a].y;
+    fxt[12 * f + 3 * a + 2] = x[a].z;
+  }
+}
+
+// ------------------------------------------------------------------ entities and emission
+struct Ent {
+  int n;            // number of entities
+  int id[4];        // soft vertex id or -(body+1)
+  int node0[4];     // first node
+  int nn[4];        // nodes per entity (1 soft, 4 affine)
+  int of_slot[4];   // entity of each slot, -1 for fixed
+};
+
+__device__ inline void entities(const int sv[4], const int* __restrict__ sv_ref, const int* __restrict__ bi, Ent& E) {
+  E.n = 0;
+  for (int a = 0; a < 4; ++a) {
+    int r = sv_ref[sv[a]];
+    int node0, nn;
+    if (r >= 0) {
+      node0 = r;
+      nn = 1;
+    } else {
+      node0 = bi[4 * (-r - 1) + 2];
+      nn = 4;
+      if (node0 < 0) {
+        E.of_slot[a] = -1;
+        continue;
+      }
+    }
+    int found = -1;
+    for (int k = 0; k < E.n; ++k)
+      if (E.id[k] == r) found = k;
+    if (found < 0) {
+      found = E.n++;
+      E.id[found] = r;
+      E.node0[found] = node0;
+      E.nn[found] = nn;
+    }
+    E.of_slot[a] = found;
+  }
+}
+
+__device__ inline int ent_dofs(const Ent& E) {
+  int t = 0;
+  for (int k = 0; k < E.n; ++k) t += E.nn[k];
+  return t;
+}
+
+// 3x3 Jacobian of slot position w.r.t. node j of its entity: I, or e_{j-1} x0^T
+__device__ inline void node_jac(int nn, int j, V3 x0, double J[3][3]) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) J[r][c] = 0.0;
+  if (nn == 1 || j == 0) {
+    J[0][0] = J[1][1] = J[2][2] = 1.0;
+  } else {
+    J[j - 1][0] = x0.x;
+    J[j - 1][1] = x0.y;
+    J[j - 1][2] = x0.z;
+  }
+}
+
+// Write gradient entries and (optionally) all node-pair Hessian blocks of one item.
+__device__ inline void emit_item(const Ent& E, const int sv[4], const double* __restrict__ sv_x0, const double* g12,
+                                 double (*H)[12], int nn_total, unsigned long long* __restrict__ key,
+                                 double* __restrict__ val, int o) {
+  V3 x0[4];
+  for (int a = 0; a < 4; ++a) x0[a] = ld3(sv_x0 + 3 * sv[a]);
+  unsigned long long W = (unsigned long long)nn_total + 1;
+  // gradient
+  for (int e = 0; e < E.n; ++e)
+    for (int j = 0; j < E.nn[e]; ++j) {
+      double acc[3] = {0, 0, 0};
+      for (int a = 0; a < 4; ++a) {
+        if (E.of_slot[a] != e) continue;
+        double J[3][3];
+        node_jac(E.nn[e], j, x0[a], J);
+        for (int c = 0; c < 3; ++c)
+          for (int r = 0; r < 3; ++r) acc[c] += J[r][c] * g12[3 * a + r];
+      }
+      key[o] = (unsigned long long)(E.node0[e] + j) * W + (unsigned long long)nn_total;
+      for (int c = 0; c < 3; ++c) val[(size_t)9 * o + c] = acc[c];
+      for (int c = 3; c < 9; ++c) val[(size_t)9 * o + c] = 0.0;
+      ++o;
+    }
+  if (!H) return;
+  for (int e = 0; e < E.n; ++e)
+    for (int j = 0; j < E.nn[e]; ++j)
+      for (int f = 0; f < E.n; ++f)
+        for (int l = 0; l < E.nn[f]; ++l) {
+          double K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+          for (int a = 0; a < 4; ++a) {
+            if (E.of_slot[a] != e) continue;
+            double Ja[3][3];
+            node_jac(E.nn[e], j, x0[a], Ja);
+            for (int b = 0; b < 4; ++b) {
+              if (E.of_slot[b] != f) continue;
+              double Jb[3][3];
+              node_jac(E.nn[f], l, x0[b], Jb);
+              // K += Ja^T P_ab Jb
+              double PJ[3][3];
+              for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                  PJ[r][c] = H[3 * a + r][3 * b] * Jb[0][c] + H[3 * a + r][3 * b + 1] * Jb[1][c] +
+                             H[3 * a + r][3 * b + 2] * Jb[2][c];
+              for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) K[r][c] += Ja[0][r] * PJ[0][c] + Ja[1][r] * PJ[1][c] + Ja[2][r] * PJ[2][c];
+            }
+          }
+          key[o] = (unsigned long long)(E.node0[e] + j) * W + (unsigned long long)(E.node0[f] + l);
+          for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) val[(size_t)9 * o + 3 * r + c] = K[r][c];
+          ++o;
+        }
+}
+
+// item i < n_act: barrier pair act_idx[i]; else friction pair i - n_act
+struct ItemArgs {
+  int npt, nee, n_act, nfric;
+  const int *pt, *ee, *tris, *edges, *act, *sv_ref, *bi, *fids;
+  const double *elen2, *xs, *sv_x0, *fvals, *fxt;
+  double kappa, dhat, mu, ys;
+  int nn_total, hess;
+};
+
+__device__ inline void item_slots(const ItemArgs& A, int i, int& kind, int sv[4], int& ea, int& eb, bool& fric) {
+  if (i < A.n_act) {
+    fric = false;
+    pair_slots(A.act[i], A.npt, A.pt, A.ee, A.tris, A.edges, kind, sv, ea, eb);
+  } else {
+    fric = true;
+    int f = i - A.n_act;
+    kind = A.fids[5 * f];
+    for (int a = 0; a < 4; ++a) sv[a] = A.fids[5 * f + 1 + a];
+    ea = eb = -1;
+  }
+}
+
+__global__ void active_flag_kernel(int n, const double* __restrict__ d_pair, double dhat, int* __restrict__ flag) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) flag[k] = d_pair[k] < dhat ? 1 : 0;
+}
+
+__global__ void compact_kernel(int n, const int* __restrict__ flag, const int* __restrict__ offs, int* __restrict__ out) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && flag[k]) out[offs[k]] = k;
+}
+
+__global__ void item_count_kernel(ItemArgs A, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_act + A.nfric) return;
+  int kind, sv[4], ea, eb;
+  bool fric;
+  item_slots(A, i, kind, sv, ea, eb, fric);
+  Ent E;
+  entities(sv, A.sv_ref, A.bi, E);
+  int nd = ent_dofs(E);
+  cnt[i] = nd + (A.hess ? nd * nd : 0);
+}
+
+__global__ void __launch_bounds__(64) item_emit_kernel(ItemArgs A, const int* __restrict__ offs,
+                                                       unsigned long long* __restrict__ key, double* __restrict__ val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_act + A.nfric) return;
+  int kind, sv[4], ea, eb;
+  bool fric;
+  item_slots(A, i, kind, sv, ea, eb, fric);
+  V3 x[4];
+  for (int a = 0; a < 4; ++a) x[a] = ld3(A.xs + 3 * sv[a]);
+  double g[12];
+  double H[12][12];
+  if (!fric) {
+    double eps = kind == 1 ? 1e-3 * A.elen2[ea] * A.elen2[eb] : 0.0;
+    double E, d;
+    pair_barrier(kind, x, eps, A.kappa, A.dhat, E, g, H, &d);
+    if (A.hess) psd_project<12>(H);
+  } else {
+    int f = i - A.n_act;
+    const double* fv = A.fvals + 8 * f;
+    V3 u = friction_u(fv, A.fxt + 12 * f, x);
+    double y = sqrt(dot(u, u)), f1y, al, be;
+    friction_core(y, A.ys, f1y, al, be);
+    double c = A.mu * fv[0];
+    V3 n = ld3(fv + 1);
+    double U[3] = {u.x, u.y, u.z}, N[3] = {n.x, n.y, n.z};
+    for (int a = 0; a < 4; ++a)
+      for (int r = 0; r < 3; ++r) g[3 * a + r] = c * f1y * fv[4 + a] * U[r];
+    double core[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int s = 0; s < 3; ++s) core[r][s] = al * ((r == s ? 1.0 : 0.0) - N[r] * N[s]) - be * U[r] * U[s];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        for (int r = 0; r < 3; ++r)
+          for (int s = 0; s < 3; ++s) H[3 * a + r][3 * b + s] = c * fv[4 + a] * fv[4 + b] * core[r][s];
+  }
+  Ent E;
+  entities(sv, A.sv_ref, A.bi, E);
+  emit_item(E, sv, A.sv_x0, g, A.hess ? H : nullptr, A.nn_total, key, val, offs[i]);
+}
+
+// segment heads of sorted keys: head[j] = 1 if key differs from the previous one;
+// hess_head additionally requires a Hessian key (column < nn)
+__global__ void heads_kernel(int n, const unsigned long long* __restrict__ k, unsigned long long W, int* __restrict__ head,
+                             int* __restrict__ hhead) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  bool h = (j == 0) || (k[j] != k[j - 1]);
+  head[j] = h ? 1 : 0;
+  hhead[j] = (h && (k[j] % W) != W - 1) ? 1 : 0;
+}
+
+__global__ void seg_start_kernel(int n, const int* __restrict__ head, const int* __restrict__ sid,
+                                 int* __restrict__ start) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n && head[j]) start[sid[j]] = j;
+}
+
+// one lane per segment: sum in sorted order; gradient keys add into grad, Hessian
+// keys become CSR entries
+__global__ void seg_reduce_kernel(int nseg, int n, const int* __restrict__ start, const unsigned long long* __restrict__ k,
+                                  const int* __restrict__ perm, const double* __restrict__ val, unsigned long long W,
+                                  const int* __restrict__ hid, double* __restrict__ grad, int* __restrict__ crow,
+                                  int* __restrict__ ccol, double* __restrict__ cval, int nnzc) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nseg) return;
+  int j0 = start[u], j1 = u + 1 < nseg ? start[u + 1] : n;
+  unsigned long long key = k[j0];
+  int row = (int)(key / W), col = (int)(key % W);
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  bool is_grad = (unsigned long long)col == W - 1;
+  int nq = is_grad ? 3 : 9;
+  for (int j = j0; j < j1; ++j) {
+    const double* v = val + (size_t)9 * perm[j];
+    for (int q = 0; q < nq; ++q) acc[q] += v[q];
+  }
+  if (is_grad) {
+    if (grad)
+      for (int q = 0; q < 3; ++q) grad[3 * row + q] += acc[q];
+  } else {
+    int h = hid[j0];
+    crow[h] = row;
+    ccol[h] = col;
+    for (int q = 0; q < 9; ++q) cval[(size_t)q * nnzc + h] = acc[q];
+  }
+}
+
+__global__ void row_ptr_kernel(int nrows, int nnzc, const int* __restrict__ crow, int* __restrict__ cptr) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > nrows) return;
+  int lo = 0, hi = nnzc;  // first index with crow >= r
+  while (lo < hi) {
+    int m = (lo + hi) >> 1;
+    if (crow[m] < r)
+      lo = m + 1;
+    else
+      hi = m;
+  }
+  cptr[r] = lo;
+}
+
+// ------------------------------------------------------------------ launchers
+static int bits_for(unsigned long long v) {
+  int b = 0;
+  while (b < 64 && (v >> b)) ++b;
+  return b;
+}
+
+void k_contact_energy(zema_scene* s) {
+  int nc = (int)(s->npt + s->nee);
+  s->e_pair.reserve(nc + 1);
+  s->d_pair.reserve(nc + 1);
+  unsigned long long inf_bits = 0x7ff0000000000000ull;
+  ZCHK(hipMemcpyAsync(s->umin.p + 1, &inf_bits, sizeof(inf_bits), hipMemcpyHostToDevice, s->st));
+  if (nc)
+    contact_energy_kernel<<<nblocks(nc), kBlock, 0, s->st>>>((int)s->npt, (int)s->nee, s->pt.p, s->ee.p, s->tris.p,
+                                                             s->edges.p, s->elen2.p, s->xs.p, s->kappa, s->P.dhat,
+                                                             s->e_pair.p, s->d_pair.p, s->umin.p + 1);
+  s->e_fric.reserve(s->nfric + 1);
+  if (s->nfric)
+    friction_energy_kernel<<<nblocks(s->nfric), kBlock, 0, s->st>>>(s->nfric, s->f_ids.p, s->f_vals.p, s->f_xt.p,
+                                                                     s->xs.p, s->P.mu, s->P.eps_v * s->P.dt,
+                                                                     s->e_fric.p);
+}
+
+void k_friction_build(zema_scene* s) {
+  int nc = (int)(s->npt + s->nee);
+  s->nfric = 0;
+  if (!nc) return;
+  s->cnt.reserve(nc + 1);
+  s->offs.reserve(nc + 1);
+  friction_flag_kernel<<<nblocks(nc), kBlock, 0, s->st>>>((int)s->npt, (int)s->nee, s->pt.p, s->ee.p, s->tris.p,
+                                                          s->edges.p, s->xs.p, s->P.dhat, s->cnt.p);
+  int64_t nf = k_exclusive_scan(s, s->cnt.p, s->offs.p, nc);
+  s->nfric = (int)nf;
+  s->f_ids.reserve(5 * nf + 5);
+  s->f_vals.reserve(8 * nf + 8);
+  s->f_xt.reserve(12 * nf + 12);
+  if (nf)
+    friction_fill_kernel<<<nblocks(nc), kBlock, 0, s->st>>>((int)s->npt, (int)s->nee, s->pt.p, s->ee.p, s->tris.p,
+                                                            s->edges.p, s->elen2.p, s->xs.p, s->kappa, s->P.dhat,
+                                                            s->cnt.p, s->offs.p, s->f_ids.p, s->f_vals.p, s->f_xt.p);
+}
+
+void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
+  int nc = (int)(s->npt + s->nee);
+  // active barrier pairs (distances come from k_contact_energy at the same xs)
+  s->n_act = 0;
+  if ((mask & 16u) && nc) {
+    s->cnt.reserve(nc + 1);
+    s->offs.reserve(nc + 1);
+    active_flag_kernel<<<nblocks(nc), kBlock, 0, s->st>>>(nc, s->d_pair.p, s->P.dhat, s->cnt.p);
+    s->n_act = (int)k_exclusive_scan(s, s->cnt.p, s->offs.p, nc);
+    s->act_idx.reserve(s->n_act + 1);
+    compact_kernel<<<nblocks(nc), kBlock, 0, s->st>>>(nc, s->cnt.p, s->offs.p, s->act_idx.p);
+  }
+  int nfr = (mask & 32u) ? s->nfric : 0;
+  int nitems = s->n_act + nfr;
+  s->nnzc = 0;
+  s->c_ptr.reserve(s->nnodes + 1);
+  if (nitems == 0) {
+    ZCHK(hipMemsetAsync(s->c_ptr.p, 0, sizeof(int) * (s->nnodes + 1), s->st));
+    return;
+  }
+  ItemArgs A;
+  A.npt = (int)s->npt;
+  A.nee = (int)s->nee;
+  A.n_act = s->n_act;
+  A.nfric = nfr;
+  A.pt = s->pt.p;
+  A.ee = s->ee.p;
+  A.tris = s->tris.p;
+  A.edges = s->edges.p;
+  A.act = s->act_idx.p;
+  A.sv_ref = s->sv_ref.p;
+  A.bi = s->body_i.p;
+  A.fids = s->f_ids.p;
+  A.elen2 = s->elen2.p;
+  A.xs = s->xs.p;
+  A.sv_x0 = s->sv_x0.p;
+  A.fvals = s->f_vals.p;
+  A.fxt = s->f_xt.p;
+  A.kappa = s->kappa;
+  A.dhat = s->P.dhat;
+  A.mu = s->P.mu;
+  A.ys = s->P.eps_v * s->P.dt;
+  A.nn_total = s->nnodes;
+  A.hess = hess ? 1 : 0;
+  s->trip_cnt.reserve(nitems + 1);
+  s->trip_off.reserve(nitems + 1);
+  item_count_kernel<<<nblocks(nitems), kBlock, 0, s->st>>>(A, s->trip_cnt.p);
+  int64_t ntrip = k_exclusive_scan(s, s->trip_cnt.p, s->trip_off.p, nitems);
+  SortBufs& sb = s->sort;
+  sb.k0.reserve(ntrip + 1);
+  sb.v0.reserve(ntrip + 1);
+  s->trip_val.reserve((size_t)9 * ntrip + 9);
+  kt_begin(s, KT_CONTACT);
+  item_emit_kernel<<<nblocks(nitems, 64), 64, 0, s->st>>>(A, s->trip_off.p, sb.k0.p, s->trip_val.p);
+  kt_end(s, KT_CONTACT);
+  k_iota(s, sb.v0.p, ntrip);  // sort values = triplet ids
+  unsigned long long W = (unsigned long long)s->nnodes + 1;
+  k_radix_sort(s, sb, ntrip, bits_for((unsigned long long)s->nnodes * W + W));
+  // segments
+  s->cnt.reserve(ntrip + 1);
+  s->offs.reserve(ntrip + 1);
+  s->trip_cnt.reserve(ntrip + 1);
+  s->seg_start.reserve(ntrip + 1);
+  int* head = s->cnt.p;
+  int* hhead = s->trip_cnt.p;
+  heads_kernel<<<nblocks(ntrip), kBlock, 0, s->st>>>((int)ntrip, sb.k0.p, W, head, hhead);
+  int64_t nseg = k_exclusive_scan(s, head, s->offs.p, ntrip);
+  seg_start_kernel<<<nblocks(ntrip), kBlock, 0, s->st>>>((int)ntrip, head, s->offs.p, s->seg_start.p);
+  int64_t nh = k_exclusive_scan(s, hhead, hhead, ntrip);  // Hessian segment ids
+  s->nnzc = (int)nh;
+  s->c_col.reserve(nh + 1);
+  s->c_val.reserve((size_t)9 * nh + 9);
+  s->seg_row.reserve(nh + 1);
+  seg_reduce_kernel<<<nblocks(nseg), kBlock, 0, s->st>>>((int)nseg, (int)ntrip, s->seg_start.p, sb.k0.p, sb.v0.p,
+                                                         s->trip_val.p, W, hhead, grad, s->seg_row.p, s->c_col.p,
+                                                         s->c_val.p, (int)nh);
+  row_ptr_kernel<<<nblocks(s->nnodes + 1), kBlock, 0, s->st>>>(s->nnodes, (int)nh, s->seg_row.p, s->c_ptr.p);
+}
+
+}  // namespace zema

@@ -1,0 +1,242 @@
+// Vector kernels of the Newton step: affine vertex map (Sec. III eq. 2,
+// x = A x0 + p), predictor (eq. 3), velocity update (text after eq. 11),
+// convergence norm, deterministic multi-segment sums and inversion count.
+#include <cstring>
+
+#include "scene.hpp"
+
+namespace zema {
+
+constexpr int BF = 32;  // doubles per body record: m, V, stiff, kappa_A, S[9], qfix[12]
+constexpr int BF_M = 0, BF_V = 1, BF_ST = 2, BF_KA = 3, BF_S = 4, BF_QF = 13;
+
+__device__ inline const double* body_q(const double* y, const double* bf, const int* bi, int b) {
+  int dof0 = bi[4 * b + 1];
+  return dof0 >= 0 ? y + dof0 : bf + BF * b + BF_QF;
+}
+
+// ((a_k1 x0_1 + a_k2 x0_2) + a_k3 x0_3) + p_k, each operation rounded separately
+__global__ void map_surface_kernel(int nsurf, const int* __restrict__ ref, const double* __restrict__ x0,
+                                   const double* __restrict__ y, const double* __restrict__ bf,
+                                   const int* __restrict__ bi, double* __restrict__ xs) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsurf) return;
+  int r = ref[i];
+  if (r >= 0) {
+    xs[3 * i] = y[3 * r];
+    xs[3 * i + 1] = y[3 * r + 1];
+    xs[3 * i + 2] = y[3 * r + 2];
+    return;
+  }
+  const double* q = body_q(y, bf, bi, -r - 1);
+  double a = x0[3 * i], b = x0[3 * i + 1], c = x0[3 * i + 2];
+  for (int k = 0; k < 3; ++k) {
+    double s = __dmul_rn(q[3 + 3 * k], a);
+    s = __dadd_rn(s, __dmul_rn(q[4 + 3 * k], b));
+    s = __dadd_rn(s, __dmul_rn(q[5 + 3 * k], c));
+    xs[3 * i + k] = __dadd_rn(s, q[k]);
+  }
+}
+
+__global__ void surface_disp_kernel(int nsurf, const int* __restrict__ ref, const double* __restrict__ x0,
+                                    const double* __restrict__ p, const int* __restrict__ bi,
+                                    double* __restrict__ dx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsurf) return;
+  int r = ref[i];
+  if (r >= 0) {
+    dx[3 * i] = p[3 * r];
+    dx[3 * i + 1] = p[3 * r + 1];
+    dx[3 * i + 2] = p[3 * r + 2];
+    return;
+  }
+  int dof0 = bi[4 * (-r - 1) + 1];
+  if (dof0 < 0) {
+    dx[3 * i] = dx[3 * i + 1] = dx[3 * i + 2] = 0.0;
+    return;
+  }
+  const double* q = p + dof0;
+  double a = x0[3 * i], b = x0[3 * i + 1], c = x0[3 * i + 2];
+  for (int k = 0; k < 3; ++k) dx[3 * i + k] = q[3 + 3 * k] * a + q[4 + 3 * k] * b + q[5 + 3 * k] * c + q[k];
+}
+
+__global__ void axpy_kernel(int n, double a, const double* __restrict__ x, const double* __restrict__ y,
+                            double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = y[i] + a * x[i];
+}
+
+__global__ void scale_kernel(int n, double a, const double* __restrict__ x, double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i];
+}
+
+__global__ void iota_kernel(int64_t n, int* __restrict__ p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int)i;
+}
+
+__global__ void velocity_kernel(int n, double inv_h, const double* __restrict__ y, const double* __restrict__ yt,
+                                double* __restrict__ v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (y[i] - yt[i]) * inv_h;
+}
+
+// xhat = x + h v + h^2 g; qhat = q + h qdot + h^2 (g, 0, 0, 0)
+__global__ void predict_kernel(int nsoft3, int ndof, double h, double gx, double gy, double gz,
+                               const double* __restrict__ y, const double* __restrict__ v, double* __restrict__ yhat) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndof) return;
+  double g = 0.0;
+  int k;
+  if (i < nsoft3)
+    k = i % 3;
+  else
+    k = (i - nsoft3) % 12;
+  if (k < 3) g = k == 0 ? gx : (k == 1 ? gy : gz);
+  yhat[i] = y[i] + h * v[i] + h * h * g;
+}
+
+__global__ void max_disp_kernel(int nsv, int nsurf, const int* __restrict__ ref, const double* __restrict__ x0,
+                                const double* __restrict__ p, const int* __restrict__ bi,
+                                unsigned long long* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double m = 0.0;
+  if (i < nsv) {
+    double a = p[3 * i], b = p[3 * i + 1], c = p[3 * i + 2];
+    m = sqrt(a * a + b * b + c * c);
+  } else if (i < nsv + nsurf) {
+    int j = i - nsv;
+    int r = ref[j];
+    if (r < 0) {
+      int dof0 = bi[4 * (-r - 1) + 1];
+      if (dof0 >= 0) {
+        const double* q = p + dof0;
+        double s2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          double d = q[3 + 3 * k] * x0[3 * j] + q[4 + 3 * k] * x0[3 * j + 1] + q[5 + 3 * k] * x0[3 * j + 2] + q[k];
+          s2 += d * d;
+        }
+        m = sqrt(s2);
+      }
+    }
+  }
+  // wave maximum, then one atomic per wave (non-negative doubles order as integers)
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, dbits(m));
+}
+
+constexpr int kSumGrid = 256;
+
+struct SegTab {
+  const double* p[8];
+  int64_t n[8];
+};
+
+__global__ void sums_l1(SegTab tab, double* __restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  int k = blockIdx.y;
+  const double* a = tab.p[k];
+  int64_t n = tab.n[k];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)kSumGrid * kBlock) acc += a[i];
+  double r = block_sum<kBlock>(acc, sh);
+  if (threadIdx.x == 0) part[k * kSumGrid + blockIdx.x] = r;
+}
+
+__global__ void sums_l2(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[kBlock / 64];
+  int k = blockIdx.x;
+  double r = block_sum<kBlock>(part[k * kSumGrid + threadIdx.x], sh);
+  if (threadIdx.x == 0) out[k] = r;
+}
+
+__global__ void inverted_kernel(int nt, const int4* __restrict__ tets, const double* __restrict__ y,
+                                unsigned int* __restrict__ cnt) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  int bad = 0;
+  if (e < nt) {
+    int4 t = tets[e];
+    V3 x0 = ld3(y + 3 * t.x), x1 = ld3(y + 3 * t.y), x2 = ld3(y + 3 * t.z), x3 = ld3(y + 3 * t.w);
+    double J = dot(x1 - x0, cross(x2 - x0, x3 - x0));
+    bad = !(J > 0.0);
+  }
+  unsigned long long b = __ballot(bad);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(cnt, (unsigned int)__popcll(b));
+}
+
+// ------------------------------------------------------------------ launchers
+void k_map_surface(zema_scene* s, const double* y, double* xs) {
+  if (!s->nsurf) return;
+  map_surface_kernel<<<nblocks(s->nsurf), kBlock, 0, s->st>>>(s->nsurf, s->sv_ref.p, s->sv_x0.p, y, s->body_f.p,
+                                                              s->body_i.p, xs);
+}
+
+void k_surface_disp(zema_scene* s, const double* p, double* dx) {
+  if (!s->nsurf) return;
+  surface_disp_kernel<<<nblocks(s->nsurf), kBlock, 0, s->st>>>(s->nsurf, s->sv_ref.p, s->sv_x0.p, p, s->body_i.p, dx);
+}
+
+void k_axpy(zema_scene* s, int n, double a, const double* x, const double* y, double* out) {
+  if (n) axpy_kernel<<<nblocks(n), kBlock, 0, s->st>>>(n, a, x, y, out);
+}
+
+void k_scale(zema_scene* s, int n, double a, const double* x, double* out) {
+  if (n) scale_kernel<<<nblocks(n), kBlock, 0, s->st>>>(n, a, x, out);
+}
+
+void k_iota(zema_scene* s, int* p, int64_t n) {
+  if (n > 0) iota_kernel<<<nblocks(n), kBlock, 0, s->st>>>(n, p);
+}
+
+void k_velocity(zema_scene* s, double inv_h) {
+  if (s->ndof) velocity_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(s->ndof, inv_h, s->y.p, s->yt.p, s->ydot.p);
+}
+
+void k_predict(zema_scene* s) {
+  if (s->ndof)
+    predict_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(3 * s->nsv, s->ndof, s->P.dt, s->P.gravity[0],
+                                                           s->P.gravity[1], s->P.gravity[2], s->y.p, s->ydot.p,
+                                                           s->yhat.p);
+}
+
+double k_max_disp(zema_scene* s, const double* p) {
+  ZCHK(hipMemsetAsync(s->umin.p, 0, sizeof(unsigned long long), s->st));
+  int n = s->nsv + s->nsurf;
+  if (n) max_disp_kernel<<<nblocks(n), kBlock, 0, s->st>>>(s->nsv, s->nsurf, s->sv_ref.p, s->sv_x0.p, p, s->body_i.p,
+                                                           s->umin.p);
+  unsigned long long u;
+  ZCHK(hipMemcpyAsync(&u, s->umin.p, sizeof(u), hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+  double d;
+  std::memcpy(&d, &u, sizeof(d));
+  return d;
+}
+
+void k_sums(zema_scene* s, int nseg, const double* const* ptr, const int64_t* len, double* out_host,
+            const void* extra) {
+  SegTab tab;
+  for (int k = 0; k < 8; ++k) {
+    tab.p[k] = k < nseg ? ptr[k] : nullptr;
+    tab.n[k] = k < nseg ? len[k] : 0;
+  }
+  s->red.reserve(32 + 8 * kSumGrid);
+  sums_l1<<<dim3(kSumGrid, nseg), kBlock, 0, s->st>>>(tab, s->red.p + 32);
+  sums_l2<<<nseg, kBlock, 0, s->st>>>(s->red.p + 32, s->red.p);
+  ZCHK(hipMemcpyAsync(out_host, s->red.p, nseg * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  if (extra) ZCHK(hipMemcpyAsync(out_host + nseg, extra, sizeof(double), hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+}
+
+bool k_any_inverted(zema_scene* s, const double* y) {
+  if (!s->nt) return false;
+  unsigned int* c = reinterpret_cast<unsigned int*>(s->counters.p + 8);
+  ZCHK(hipMemsetAsync(c, 0, sizeof(unsigned int), s->st));
+  inverted_kernel<<<nblocks(s->nt), kBlock, 0, s->st>>>(s->nt, s->tets.p, y, c);
+  unsigned int h;
+  ZCHK(hipMemcpyAsync(&h, c, sizeof(h), hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+  return h != 0;
+}
+
+}  // namespace zema

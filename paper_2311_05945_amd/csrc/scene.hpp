@@ -1,0 +1,191 @@
+// Scene state of the HIP library and the launchers of its kernels.
+//
+// HBM layout (one scene):
+//   y, ydot, y^t, ydot^t, yhat    AoS DOF vectors [3*nsv | 12*nfree] (double)
+//   tets                          int4 [nt]                  (16 B, one load per tet)
+//   Dm^-1                         SoA double [9][nt]         (coalesced planes)
+//   h^2 V, mu, lambda             SoA double [nt] each
+//   element Hessians              AoS double [nt][90]        (10 upper 3x3 blocks)
+//   static BSR                    row_ptr [nodes+1], col [nnzb], val SoA [9][nnzb]
+//   contact matrix (dynamic)      CSR over the same nodes, val SoA [9][nnz_c]
+//   surface                       xs AoS [nsurf][3]; tris int [ntri][3]; edges int [ne][2]
+// Nodes of the block system: soft vertex i -> node i; free affine body k -> nodes
+// nsv + 4k + {0: p, 1: a1, 2: a2, 3: a3} (3 DOFs each), so every block is 3x3.
+#pragma once
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/zema.h"
+#include "common.hpp"
+
+namespace zema {
+
+struct Body {
+  int mode = 0;
+  int dof0 = -1, node0 = -1;       // -1 for fixed bodies
+  int sv0 = 0, nsv = 0;            // surface vertex range
+  double rho = 0, stiff = 0, kappaA = 0;
+  double V = 0, m = 0, c[3] = {0, 0, 0}, S[9] = {0};
+  double qrest[12], qdot0[12];
+  double tvel[3] = {0, 0, 0}, tstop = 0;
+};
+
+// Launch timing of one kernel group with HIP events on the scene's stream.
+enum { KT_SPMV = 0, KT_TET = 1, KT_CONTACT = 2, KT_QUERY = 3, KT_CCD = 4, KT_N = 5 };
+struct KTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  size_t used = 0;
+  double ms = 0.0;
+  long long launches = 0;
+  double bytes = 0.0;           // algorithmic bytes of the timed launches
+  std::vector<double> pending;  // bytes of launches not folded yet
+};
+
+// Buffers for one radix sort of (key, value) pairs.
+struct SortBufs {
+  DBuf<unsigned long long> k0, k1;
+  DBuf<int> v0, v1;
+  DBuf<int> hist;
+};
+
+}  // namespace zema
+
+struct zema_scene {
+  zema_params P;
+  hipStream_t st = nullptr;
+  std::string err;
+  int n_soft_bodies = 0, n_bodies = 0;
+  int nsv = 0, nt = 0, nsurf = 0, ntri = 0, nedge = 0, nfree = 0, ndof = 0, nnodes = 0;
+  std::vector<zema::Body> bodies;  // affine bodies, creation order
+  std::vector<double> mass_h;
+  double cell = 0.0;               // hash cell size
+
+  // ---- soft (device)
+  zema::DBuf<int4> tets;
+  zema::DBuf<double> Dmi, h2vol, lmu, llam, mass;
+  zema::DBuf<int> vt_ptr, vt_list;       // vertex -> (tet*4 + slot)
+  zema::DBuf<double> e_tet, g_tet, h_tet, e_in;  // per-tet energy, gradient [nt][12], Hessian [nt][90]
+  // ---- static BSR
+  int nnzb = 0, bsr_row_soft_end = 0;
+  zema::DBuf<int> bsr_ptr, bsr_col, bsr_row, bsr_diag, hc_ptr, hc_list;
+  zema::DBuf<double> bsr_val;
+  // ---- affine (device): per body packed
+  zema::DBuf<double> body_f;  // [nb][32]: m, V, stiff, kappaA, S(9), qfix(12) ...
+  zema::DBuf<int> body_i;     // [nb][4]: mode, dof0, node0, pad
+  zema::DBuf<double> qtilde;  // [nb][12]
+  zema::DBuf<double> e_body;  // [nb][3] inertia, orth, kinematic
+  // ---- surface (device)
+  zema::DBuf<int> sv_ref;      // >= 0 soft vertex, < 0 : -(body+1)
+  zema::DBuf<int> sv_body;     // global body id (soft bodies first)
+  zema::DBuf<double> sv_x0;    // [nsurf][3]
+  zema::DBuf<int> tris, edges;
+  zema::DBuf<double> elen2;
+  zema::DBuf<unsigned char> body_fixed;  // per global body
+  zema::DBuf<double> xs, xs1, dxs;      // surface positions / displacements
+  // ---- state
+  zema::DBuf<double> y, ydot, yt, ydt, yhat, ytmp, grad, pdir;
+  double kappa = 0.0, kappa_lag = 0.0;
+  int step = 0;
+  // ---- candidates (current set)
+  zema::DBuf<int> pt, ee;       // [n][2]
+  int64_t npt = 0, nee = 0;
+  // broad phase work
+  zema::DBuf<double> bb_lo, bb_hi;       // boxes of all primitives
+  zema::DBuf<int> cnt, offs;
+  zema::DBuf<unsigned long long> ent_cell;
+  zema::DBuf<int> ent_prim, bucket_lo, bucket_hi, big_list;
+  zema::DBuf<unsigned long long> pair_keys;
+  zema::DBuf<int> counters;              // small device counters
+  zema::SortBufs sort;
+  std::vector<std::unique_ptr<zema::DBuf<int>>> scan_tmp;
+  // ---- contact evaluation
+  zema::DBuf<int> act_idx;               // compacted active candidate ids
+  zema::DBuf<int> trip_cnt, trip_off;
+  zema::DBuf<unsigned long long> trip_key;
+  zema::DBuf<double> trip_val;           // [ntrip][9]
+  zema::DBuf<double> e_pair, d_pair;     // per candidate energy / distance
+  int n_act = 0;
+  // contact matrix (CSR over nodes)
+  int nnzc = 0;
+  zema::DBuf<int> c_ptr, c_col, seg_start, seg_row;
+  zema::DBuf<double> c_val;
+  // ---- friction (lagged)
+  int nfric = 0;
+  zema::DBuf<int> f_ids;       // [n][5]
+  zema::DBuf<double> f_vals;   // [n][8] lambda, n, w
+  zema::DBuf<double> f_xt;     // [n][12]
+  zema::DBuf<double> e_fric;
+  // ---- PCG
+  zema::DBuf<double> minv_soft;  // [9][nsv]
+  zema::DBuf<double> minv_body;  // [nfree][144]
+  zema::DBuf<double> pr, pz, pp0, pp1, pq, px;
+  zema::DBuf<double> partial;    // block partial sums
+  zema::DBuf<double> scal;       // PCG scalars
+  zema::DBuf<unsigned int> ticket;
+  // ---- reductions / readback
+  zema::DBuf<double> red;        // reduction results
+  zema::DBuf<unsigned long long> umin;
+  double* host_pinned = nullptr;  // small pinned readback area
+  bool hess_valid = false;
+  zema::KTimer kt[zema::KT_N];
+  ~zema_scene();
+};
+
+namespace zema {
+
+// -------- launch timing (api.cpp)
+void kt_begin(zema_scene* s, int g);
+void kt_end(zema_scene* s, int g, double bytes = 0.0);
+void kt_fold(zema_scene* s);  // after a stream synchronisation: accumulate elapsed times
+
+// -------- map / vectors (k_misc.hip)
+void k_map_surface(zema_scene* s, const double* y, double* xs);
+void k_surface_disp(zema_scene* s, const double* p, double* dx);
+void k_axpy(zema_scene* s, int n, double a, const double* x, const double* y, double* out);  // out = y + a x
+void k_scale(zema_scene* s, int n, double a, const double* x, double* out);
+void k_iota(zema_scene* s, int* p, int64_t n);  // p[i] = i
+void k_velocity(zema_scene* s, double inv_h);   // ydot = (y - yt) * inv_h
+void k_predict(zema_scene* s);                  // yhat from y^t, ydot^t
+double k_max_disp(zema_scene* s, const double* p);  // max vertex displacement of direction p
+// multi-segment deterministic sums: out[k] = sum of seg k (host results)
+// (extra: optional device word copied to out_host[nseg] in the same synchronisation)
+void k_sums(zema_scene* s, int nseg, const double* const* ptr, const int64_t* len, double* out_host,
+            const void* extra);
+bool k_any_inverted(zema_scene* s, const double* y);
+
+// -------- elastic (k_elastic.hip)
+void k_tet_assemble(zema_scene* s, const double* y, bool hess);  // e_tet, g_tet, h_tet
+void k_tet_energy(zema_scene* s, const double* y);               // e_tet only (inf if inverted)
+void k_gather_grad_soft(zema_scene* s, const double* y, double* grad, unsigned mask);
+void k_gather_hess_static(zema_scene* s, unsigned mask);
+void k_inertia_energy(zema_scene* s, const double* y, double* e_out);
+
+// -------- affine (k_affine.hip)
+void k_body_terms(zema_scene* s, const double* y, double* grad, bool hess, unsigned mask);
+void k_body_energy(zema_scene* s, const double* y);
+
+// -------- contact (k_contact.hip)
+// evaluate the current candidate set at xs: energies / distances; with derivatives,
+// builds the contact matrix (CSR) and adds gradient contributions into grad.
+void k_contact_energy(zema_scene* s);                 // e_pair, d_pair, e_fric at xs
+void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask);
+void k_friction_build(zema_scene* s);                 // lagged table from current candidates at xs
+
+// -------- broad phase (k_broad.hip)
+void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r);
+
+// -------- sort / scan (k_sort.hip)
+int64_t k_exclusive_scan(zema_scene* s, const int* in, int* out, int64_t n, bool want_total = true);
+void k_radix_sort(zema_scene* s, SortBufs& b, int64_t n, int key_bits);  // sorts (b.k0, b.v0) in place
+
+// -------- sparse / PCG (k_sparse.hip)
+void k_hess_matvec(zema_scene* s, const double* v, double* out);
+void k_build_precond(zema_scene* s);
+int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres);
+
+// -------- CCD (k_ccd.hip)
+int k_ccd(zema_scene* s, const double* y, const double* p, double* alpha);
+
+}  // namespace zema

@@ -1,0 +1,278 @@
+"""Python binding of libzema.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts scene descriptions
+to the C structs of include/zema.h and passes torch device tensors as raw pointers.
+Importing it without the built library raises immediately: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzema.so")
+
+D, I32, I64 = C.c_double, C.c_int32, C.c_int64
+PD, PI32, PI64 = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+VP = C.c_void_p
+
+OK, E_ARG, E_MESH, E_INTERSECT, E_CAPACITY, E_NEWTON, E_LINESEARCH, E_PCG, E_NONFINITE, E_DEVICE = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+GRAD, HESS, TERMS_SHIFT = 1, 2, 8
+TERM_NAMES = ("inertia", "elastic", "orthogonality", "kinematic", "barrier", "friction", "total", "min_distance")
+
+
+class Params(C.Structure):
+    _fields_ = [("dt", D), ("dhat", D), ("kappa", D), ("mu", D), ("eps_v", D), ("gravity", D * 3),
+                ("newton_tol", D), ("pcg_rtol", D), ("ccd_s", D), ("newton_max", I32), ("pcg_max", I32),
+                ("precision", I32), ("warm_start", I32)]
+
+
+class SoftDesc(C.Structure):
+    _fields_ = [("n_verts", I32), ("n_tets", I32), ("rest_pos", PD), ("tets", PI32), ("pos0", PD), ("vel0", PD),
+                ("E", D), ("nu", D), ("rho", D)]
+
+
+class AffineDesc(C.Structure):
+    _fields_ = [("n_verts", I32), ("n_tris", I32), ("rest_pos", PD), ("tris", PI32), ("rho", D),
+                ("stiffness", D), ("qdot0", D * 12), ("mode", I32), ("pad_", I32), ("kappa_A", D),
+                ("target_vel", D * 3), ("target_stop", D)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("status", I32), ("newton_iters", I32), ("pcg_iters", I32), ("ls_backtracks", I32),
+                ("n_pt_active", I32), ("n_ee_active", I32), ("n_pt_cand", I32), ("n_ee_cand", I32),
+                ("alpha_ccd_min", D), ("kappa", D), ("d_min", D), ("energy", D), ("ms_total", D),
+                ("ms_assemble", D), ("ms_pcg", D), ("ms_broad", D), ("ms_ccd", D), ("ms_linesearch", D)]
+
+
+_LIB = None
+
+# (name, argtypes) of every entry point of include/zema.h
+SIGNATURES = [
+    ("zema_scene_create", [C.POINTER(Params), C.POINTER(SoftDesc), I32, C.POINTER(AffineDesc), I32, VP,
+                           C.POINTER(VP)]),
+    ("zema_scene_destroy", [VP]),
+    ("zema_status_string", [C.c_int]),
+    ("zema_last_error", [VP]),
+    ("zema_sizes", [VP, PI64]),
+    ("zema_set_state", [VP, VP, VP, D, I32]),
+    ("zema_get_state", [VP, VP, VP, PD, PI32]),
+    ("zema_set_kappa", [VP, D]),
+    ("zema_surface_positions", [VP, VP, VP]),
+    ("zema_contact_candidates", [VP, VP, VP, D, VP, I64, PI64, VP, I64, PI64]),
+    ("zema_ip_assemble", [VP, VP, C.c_uint32, PD, VP]),
+    ("zema_hessian_matvec", [VP, VP, VP]),
+    ("zema_pcg_solve", [VP, VP, VP, D, I32, PI32, PD]),
+    ("zema_ccd_max_step", [VP, VP, VP, PD]),
+    ("zema_step", [VP, I32, C.POINTER(StepStats)]),
+    ("zema_friction_table", [VP, PI64, PI32, PD, I64]),
+    ("zema_kernel_timer", [VP, I32, I32]),
+    ("zema_kernel_time", [VP, I32, PD, PI64, PD]),
+]
+KT_SPMV, KT_TET, KT_CONTACT, KT_QUERY, KT_CCD = range(5)
+
+
+def lib():
+    """Load libzema.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2311_05945_amd/build.py "
+                               "(or __graft_entry__.build()); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        for name, args in SIGNATURES:
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.zema_scene_destroy.restype = None
+        L.zema_status_string.restype = C.c_char_p
+        L.zema_last_error.restype = C.c_char_p
+        _LIB = L
+    return _LIB
+
+
+class ZemaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"zema status {code}: {msg}")
+        self.code = code
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _pd(a):
+    return None if a is None else a.ctypes.data_as(PD)
+
+
+def _ptr(t):
+    """Raw device pointer of a torch tensor (None for None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def params_struct(p) -> Params:
+    return Params(p.dt, p.dhat, p.kappa, p.mu, p.eps_v, (D * 3)(*p.gravity), p.newton_tol, p.pcg_rtol, p.ccd_s,
+                  p.newton_max, p.pcg_max, p.precision, p.warm_start)
+
+
+class Scene:
+    """A scene of libzema bound to one torch (HIP) stream."""
+
+    def __init__(self, scene, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        L = lib()
+        self._keep = []
+        softs = (SoftDesc * max(1, len(scene.softs)))()
+        for k, b in enumerate(scene.softs):
+            rp = _f64(b.rest_pos); tt = np.ascontiguousarray(b.tets, dtype=np.int32)
+            p0 = _f64(b.pos0) if b.pos0 is not None else None
+            v0 = _f64(b.vel0) if b.vel0 is not None else None
+            self._keep += [rp, tt, p0, v0]
+            softs[k] = SoftDesc(len(rp), len(tt), _pd(rp), tt.ctypes.data_as(PI32), _pd(p0), _pd(v0), b.E, b.nu, b.rho)
+        affs = (AffineDesc * max(1, len(scene.affines)))()
+        for k, b in enumerate(scene.affines):
+            rp = _f64(b.rest_pos); tt = np.ascontiguousarray(b.tris, dtype=np.int32)
+            self._keep += [rp, tt]
+            affs[k] = AffineDesc(len(rp), len(tt), _pd(rp), tt.ctypes.data_as(PI32), b.rho, b.stiffness,
+                                 (D * 12)(*np.asarray(b.qdot0, dtype=float)), b.mode, 0, b.kappa_A,
+                                 (D * 3)(*np.asarray(b.target_vel, dtype=float)), b.target_stop)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        P = params_struct(scene.params)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = L.zema_scene_create(C.byref(P), softs, len(scene.softs), affs, len(scene.affines),
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise ZemaError(rc, L.zema_status_string(rc).decode())
+        self.h = h
+        s = np.zeros(8, dtype=np.int64)
+        L.zema_sizes(self.h, s.ctypes.data_as(PI64))
+        (self.n_dof, self.n_soft_verts, self.n_tets, self.n_surf, self.n_tris, self.n_edges,
+         self.n_free_bodies, self.n_bodies) = [int(x) for x in s]
+        self.params = scene.params
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().zema_scene_destroy(self.h)
+            self.h = None
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise ZemaError(rc, lib().zema_last_error(self.h).decode())
+
+    def _dev(self, a, dtype=None):
+        t = self.torch
+        dtype = dtype or t.float64
+        if isinstance(a, t.Tensor):
+            return a.to(device=self.device, dtype=dtype).contiguous()
+        return t.as_tensor(np.asarray(a), dtype=dtype, device=self.device).contiguous()
+
+    def zeros(self, *shape, dtype=None):
+        return self.torch.zeros(*shape, dtype=dtype or self.torch.float64, device=self.device)
+
+    # ---- state
+    def set_state(self, y, ydot, kappa=0.0, step=0):
+        y = self._dev(y); yd = self._dev(ydot)
+        self._chk(lib().zema_set_state(self.h, _ptr(y), _ptr(yd), float(kappa), int(step)))
+
+    def get_state(self):
+        y = self.zeros(self.n_dof); yd = self.zeros(self.n_dof); k = D(); st = I32()
+        self._chk(lib().zema_get_state(self.h, _ptr(y), _ptr(yd), C.byref(k), C.byref(st)))
+        return y, yd, k.value, st.value
+
+    def set_kappa(self, kappa):
+        self._chk(lib().zema_set_kappa(self.h, float(kappa)))
+
+    def surface_positions(self, y):
+        y = self._dev(y)
+        xs = self.zeros(self.n_surf, 3)
+        self._chk(lib().zema_surface_positions(self.h, _ptr(y), _ptr(xs)))
+        return xs
+
+    # ---- hot path
+    def contact_candidates(self, xs0, xs1=None, r=None):
+        r = self.params.dhat if r is None else r
+        xs0 = self._dev(xs0); xs1 = self._dev(xs1) if xs1 is not None else None
+        npt, nee = I64(), I64()
+        cap = 1024
+        while True:
+            pt = self.torch.zeros((cap, 2), dtype=self.torch.int32, device=self.device)
+            ee = self.torch.zeros((cap, 2), dtype=self.torch.int32, device=self.device)
+            rc = lib().zema_contact_candidates(self.h, _ptr(xs0), _ptr(xs1), float(r), _ptr(pt), cap,
+                                               C.byref(npt), _ptr(ee), cap, C.byref(nee))
+            if rc == E_CAPACITY:
+                cap = max(npt.value, nee.value, 1)
+                continue
+            self._chk(rc)
+            return pt[:npt.value], ee[:nee.value]
+
+    def ip_assemble(self, y, grad=True, hess=True, mask=0):
+        y = self._dev(y)
+        terms = np.zeros(8)
+        g = self.zeros(self.n_dof) if grad else None
+        flags = (GRAD if grad else 0) | (HESS if hess else 0) | ((int(mask) & 0x3F) << TERMS_SHIFT)
+        self._chk(lib().zema_ip_assemble(self.h, _ptr(y), flags, _pd(terms), _ptr(g)))
+        return terms, g
+
+    def hessian_matvec(self, v):
+        v = self._dev(v)
+        out = self.zeros(self.n_dof)
+        self._chk(lib().zema_hessian_matvec(self.h, _ptr(v), _ptr(out)))
+        return out
+
+    def pcg_solve(self, rhs, rtol=None, max_iter=0):
+        rtol = self.params.pcg_rtol if rtol is None else rtol
+        rhs = self._dev(rhs)
+        sol = self.zeros(self.n_dof); it = I32(); rr = D()
+        self._chk(lib().zema_pcg_solve(self.h, _ptr(rhs), _ptr(sol), float(rtol), int(max_iter), C.byref(it),
+                                       C.byref(rr)))
+        return sol, it.value, rr.value
+
+    def ccd_max_step(self, y, p):
+        y = self._dev(y); p = self._dev(p)
+        a = D()
+        self._chk(lib().zema_ccd_max_step(self.h, _ptr(y), _ptr(p), C.byref(a)))
+        return a.value
+
+    def step(self, n=1):
+        st = (StepStats * max(n, 1))()
+        rc = lib().zema_step(self.h, n, st)
+        out = [{f[0]: getattr(s, f[0]) for f in StepStats._fields_} for s in st[:n]]
+        if rc != 0:
+            raise ZemaError(rc, lib().zema_last_error(self.h).decode())
+        return out
+
+    def friction_table(self):
+        n = I64()
+        cap = 0
+        while True:
+            ids = np.zeros((max(cap, 1), 5), dtype=np.int32); vals = np.zeros((max(cap, 1), 8))
+            rc = lib().zema_friction_table(self.h, C.byref(n), ids.ctypes.data_as(PI32), _pd(vals), cap)
+            if rc == E_CAPACITY:
+                cap = n.value
+                continue
+            self._chk(rc)
+            return ids[:n.value], vals[:n.value]
+
+
+    def kernel_timer(self, group, enable=True):
+        self._chk(lib().zema_kernel_timer(self.h, int(group), 1 if enable else 0))
+
+    def kernel_time(self, group):
+        """(total ms, launches, algorithmic bytes) of a timed kernel group."""
+        ms = D(); n = I64(); b = D()
+        self._chk(lib().zema_kernel_time(self.h, int(group), C.byref(ms), C.byref(n), C.byref(b)))
+        return ms.value, n.value, b.value
+
+
+def scene_create(scene, device="cuda:0", stream=None) -> Scene:
+    return Scene(scene, device, stream)

@@ -242,7 +242,9 @@ def cube_drop(n_cells: int = 4, steps: int = 20) -> Scene:
     L = 0.1
     H = L / n_cells
     mask = np.ones((n_cells,) * 3, dtype=bool)
-    verts, tets = voxel_mesh(mask, (-L / 2, 0.005, -L / 2), H)
+    # the cube is shifted off the slab's top diagonal (x = z) so that no vertex sits
+    # exactly on a feature boundary of the slab's triangles
+    verts, tets = voxel_mesh(mask, (-L / 2 + 0.0123, 0.005, -L / 2 - 0.0071), H)
     slab_v, slab_t = box_surface((0.0, -0.025, 0.0), (0.25, 0.025, 0.25), 1)
     p = Params(dt=0.01, dhat=1e-3, kappa=0.0, mu=0.5, eps_v=1e-3, newton_tol=1e-6)
     soft = SoftBody(verts, tets, E=1e5, nu=0.4, rho=1000.0)
@@ -267,7 +269,8 @@ def _gripper_fingers(obj_verts, dhat, speed, rot=None, offset=0.0, obj_center=No
     fingers = []
     stop = (2 * dhat + travel_frac * x_ext) / speed
     for side in (-1.0, 1.0):
-        cen_local = np.array([side * (x_ext + 2 * dhat + fx / 2), offset, 0.0])
+        # small fixed shift so finger grid lines do not coincide with voxel grid lines
+        cen_local = np.array([side * (x_ext + 2 * dhat + fx / 2), offset + 7.1e-4, -3.7e-4])
         v, t = box_surface(cen_local, (fx / 2, fy / 2, fz / 2), (quads, quads, quads))
         v = v @ R.T + c
         vel = R @ np.array([-side * speed, 0.0, 0.0])

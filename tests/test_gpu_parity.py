@@ -1,0 +1,311 @@
+"""GPU parity: the HIP library against the CPU oracle on identical seeded states.
+
+Gates (per Newton iterate of oracle trajectories, and at a full-size gripper contact
+state):
+  * candidate pair sets bit-identical (same sorted int32 lists);
+  * each energy term within 1e-9 relative (floor 1e-12 of the total energy);
+  * each term's gradient within 1e-9 of that term's largest gradient entry;
+  * Hessian products H v within 1e-9 of |H v| (per term and total);
+  * PCG: the GPU solution meets the residual bound on the oracle's Hessian;
+  * zero intersections (exact rational check) after every GPU step;
+  * bitwise determinism of assembly.
+"""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import exact, ref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TERMS = ("inertia", "elastic", "orthogonality", "kinematic", "barrier", "friction")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def zema():
+    _need_gpu()
+    from paper_2311_05945_amd import zema as z
+    return z
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def energy_floor(sc, R):
+    """Absolute rounding floor of the energy terms: 64 eps times the elastic energy of
+    unit strain, h^2 V (mu + lambda), V the total soft volume.  Forming Psi from O(1)
+    invariants loses about eps * mu per element, so terms below this are noise."""
+    V = R.lumped_mass().sum() / sc.softs[0].rho if sc.softs else 0.0
+    b = sc.softs[0] if sc.softs else None
+    ml = (b.E / (2 * (1 + b.nu)) + b.E * b.nu / ((1 + b.nu) * (1 - 2 * b.nu))) if b else 0.0
+    return 64 * np.finfo(float).eps * sc.params.dt ** 2 * V * ml
+
+
+def check_terms(tg, tr, ctx="", floor=0.0):
+    for k in range(6):
+        tol = 1e-9 * abs(tr[k]) + max(1e-12 * abs(tr[6]), floor)
+        assert abs(tg[k] - tr[k]) <= tol, f"{ctx} term {TERMS[k]}: gpu {tg[k]!r} oracle {tr[k]!r}"
+    assert tg[7] == pytest.approx(tr[7], rel=1e-9, abs=0), f"{ctx} min distance"
+
+
+def check_grad_terms(G, R, y, ctx=""):
+    """Per-term gradients: |g_gpu - g_ref|_inf <= 1e-9 max(|g_term|_inf, 1e-3 S), S the
+    largest term gradient |g_k|_inf; the total gradient to 1e-9 S.
+
+    The floor matters only where a term's gradient is rounding noise (the elastic
+    gradient of an unstrained body) or where the terms cancel (a converged iterate)."""
+    ref_g = [R.ip_assemble(y, hess=False, mask=1 << k)[1] for k in range(6)]
+    S = max(np.abs(g).max() for g in ref_g)
+    _, g_all = R.ip_assemble(y, hess=False)
+    _, gg_all = G.ip_assemble(y, hess=False)
+    rel_all = np.abs(gg_all.cpu().numpy() - g_all).max() / S
+    assert rel_all <= 1e-9, f"{ctx} total gradient err {rel_all:.3e} of the largest term"
+    worst = rel_all
+    for k in range(6):
+        gr = ref_g[k]
+        _, gg = G.ip_assemble(y, hess=False, mask=1 << k)
+        gg = gg.cpu().numpy()
+        scale = max(np.abs(gr).max(), 1e-3 * S)
+        err = np.abs(gg - gr).max()
+        if scale == 0.0:
+            assert err == 0.0, f"{ctx} {TERMS[k]} gradient should vanish"
+            continue
+        rel = err / scale
+        worst = max(worst, rel)
+        assert rel <= 1e-9, f"{ctx} {TERMS[k]} gradient rel err {rel:.3e}"
+    return worst
+
+
+def check_hv(G, R, y, seed, ctx="", masks=(0,) + tuple(1 << k for k in range(6))):
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for m in masks:
+        R.ip_assemble(y, mask=m)
+        G.ip_assemble(y, mask=m)
+        for _ in range(2):
+            v = rng.normal(size=R.n_dof)
+            hr = R.hessian_matvec(v)
+            hg = G.hessian_matvec(v).cpu().numpy()
+            scale = np.abs(hr).max()
+            if scale == 0.0:
+                assert np.abs(hg).max() == 0.0
+                continue
+            rel = np.abs(hg - hr).max() / scale
+            worst = max(worst, rel)
+            assert rel <= 1e-9, f"{ctx} mask {m}: H v rel err {rel:.3e}"
+    return worst
+
+
+@pytest.fixture(scope="module")
+def cube_records():
+    sc = sg.cube_drop()
+    R = ref.RefScene(sc)
+    R.record(True)
+    R.step(8)
+    return sc, R.records()
+
+
+def test_candidates_bit_exact_cube(zema, cube_records):
+    sc, recs = cube_records
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    n = 0
+    for i, rc in enumerate(recs[::3]):
+        xs = R.surface_positions(rc["y_k"])
+        log(f"candidates cube rec {i}")
+        for r in (sc.params.dhat, 0.0, 3e-3):
+            pr, er = R.candidates(xs, None, r)
+            pg, eg = G.contact_candidates(xs, None, r)
+            assert np.array_equal(pg.cpu().numpy(), pr) and np.array_equal(eg.cpu().numpy(), er)
+            n += len(pr) + len(er)
+        # swept
+        xs1 = xs + np.random.default_rng(i).normal(scale=2e-3, size=xs.shape)
+        pr, er = R.candidates(xs, xs1, sc.params.dhat)
+        pg, eg = G.contact_candidates(xs, xs1, sc.params.dhat)
+        assert np.array_equal(pg.cpu().numpy(), pr) and np.array_equal(eg.cpu().numpy(), er)
+    assert n > 0
+
+
+def test_energy_gradient_per_iterate_cube(zema, cube_records):
+    sc, recs = cube_records
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    worst = 0.0
+    for i, rc in enumerate(recs):
+        log(f"iterate {i}/{len(recs)} step {rc['step']}")
+        R.set_state(rc["y_t"], rc["ydot_t"], rc["kappa_lag"], rc["step"])
+        G.set_state(rc["y_t"], rc["ydot_t"], rc["kappa_lag"], rc["step"])
+        R.set_kappa(rc["kappa"])
+        G.set_kappa(rc["kappa"])
+        tr, _ = R.ip_assemble(rc["y_k"], hess=False)
+        tg, _ = G.ip_assemble(rc["y_k"], hess=False)
+        check_terms(tg, tr, f"iterate {i}", energy_floor(sc, R))
+        worst = max(worst, check_grad_terms(G, R, rc["y_k"], f"iterate {i}"))
+    log(f"worst per-term gradient rel err {worst:.2e} over {len(recs)} iterates")
+
+
+def test_friction_table_cube(zema, cube_records):
+    sc, recs = cube_records
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    rc = recs[-1]
+    R.set_state(rc["y_t"], rc["ydot_t"], rc["kappa_lag"], rc["step"])
+    G.set_state(rc["y_t"], rc["ydot_t"], rc["kappa_lag"], rc["step"])
+    ir, vr = R.friction_table()
+    ig, vg = G.friction_table()
+    assert len(ir) > 0 and np.array_equal(ir, ig)
+    assert np.abs(vg[:, 0] - vr[:, 0]).max() <= 1e-9 * np.abs(vr[:, 0]).max()
+    assert np.abs(vg[:, 1:] - vr[:, 1:]).max() <= 1e-9
+
+
+def test_hessian_products_cube(zema, cube_records):
+    sc, recs = cube_records
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    worst = 0.0
+    for i, rc in enumerate(recs[::4]):
+        log(f"H v iterate {i}")
+        R.set_state(rc["y_t"], rc["ydot_t"], rc["kappa_lag"], rc["step"])
+        G.set_state(rc["y_t"], rc["ydot_t"], rc["kappa_lag"], rc["step"])
+        R.set_kappa(rc["kappa"])
+        G.set_kappa(rc["kappa"])
+        worst = max(worst, check_hv(G, R, rc["y_k"], i, f"iterate {i}"))
+    log(f"worst H v rel err {worst:.2e}")
+
+
+def test_pcg_residual_cube(zema, cube_records):
+    sc, recs = cube_records
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    rc = recs[len(recs) // 2]
+    R.set_state(rc["y_t"], rc["ydot_t"], rc["kappa_lag"], rc["step"])
+    G.set_state(rc["y_t"], rc["ydot_t"], rc["kappa_lag"], rc["step"])
+    R.set_kappa(rc["kappa"]); G.set_kappa(rc["kappa"])
+    _, g = R.ip_assemble(rc["y_k"])
+    G.ip_assemble(rc["y_k"])
+    for rtol in (1e-4, 1e-10):
+        xg, itg, rrg = G.pcg_solve(-g, rtol=rtol)
+        xr, itr, rrr = R.pcg_solve(-g, rtol=rtol)
+        xg = xg.cpu().numpy()
+        res = np.linalg.norm(R.hessian_matvec(xg) + g) / np.linalg.norm(g)
+        log(f"pcg rtol {rtol}: gpu iters {itg} rel {rrg:.2e} true {res:.2e}; oracle iters {itr}")
+        assert rrg <= rtol and res <= 1.01 * rtol + 1e-13
+        assert abs(itg - itr) <= max(2, itr // 10)
+        if rtol < 1e-8:
+            assert np.linalg.norm(xg - xr) <= 1e-6 * np.linalg.norm(xr)
+
+
+def test_ccd_bound_cube(zema, cube_records):
+    sc, recs = cube_records
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    tris, edges, vb = R.surface()
+    rng = np.random.default_rng(0)
+    for i, rc in enumerate(recs[1::5]):
+        y = rc["y_k"]
+        p = np.zeros_like(y)
+        p[1::3] = -4e-3                      # push the cube down into the slab
+        p += rng.normal(scale=1e-4, size=p.shape)
+        ar = R.ccd_max_step(y, p)
+        ag = G.ccd_max_step(y, p)
+        log(f"ccd {i}: gpu {ag:.6f} oracle {ar:.6f}")
+        assert 0 < ag <= 1 and abs(ag - ar) <= 1e-6
+        xs = R.surface_positions(y + ag * p)
+        assert exact.count_intersections(xs, tris, edges, vb) == 0
+
+
+def test_steps_cube_intersection_free(zema):
+    sc = sg.cube_drop()
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    tris, edges, vb = R.surface()
+    soft = sc.softs[0]
+    for k in range(20):
+        st = G.step(1)[0]
+        R.step(1)
+        y = G.get_state()[0].cpu().numpy()
+        xs = R.surface_positions(y)
+        n_int = exact.count_intersections(xs, tris, edges, vb)
+        n_inv = exact.count_inverted(y[:3 * R.n_soft_verts].reshape(-1, 3), soft.tets)
+        dy = np.abs(y - R.get_state()[0]).max()
+        log(f"step {k}: newton {st['newton_iters']} pcg {st['pcg_iters']} dmin {st['d_min']:.3e} "
+            f"|y_gpu - y_oracle| {dy:.2e} intersections {n_int} inverted {n_inv}")
+        assert st["status"] == 0 and n_int == 0 and n_inv == 0
+        assert dy < 1e-5
+
+
+def test_assembly_deterministic(zema, cube_records):
+    sc, recs = cube_records
+    G = zema.Scene(sc)
+    rc = recs[-1]
+    G.set_state(rc["y_t"], rc["ydot_t"], rc["kappa_lag"], rc["step"])
+    t1, g1 = G.ip_assemble(rc["y_k"])
+    v = torch.randn(G.n_dof, dtype=torch.float64, device="cuda")
+    h1 = G.hessian_matvec(v)
+    t2, g2 = G.ip_assemble(rc["y_k"])
+    h2 = G.hessian_matvec(v)
+    assert np.array_equal(t1, t2) and torch.equal(g1, g2) and torch.equal(h1, h2)
+
+
+# ------------------------------------------------------------------ full-size gripper
+
+def gripper_contact_state(sc, R, squeeze=0.5, noise=3e-5, seed=0):
+    """Rest state of the gripper scene with both fingers moved inward until their
+    inner faces are `squeeze` * dhat from the object's extreme vertices, plus a small
+    seeded perturbation of the soft vertices."""
+    y, yd, _, _ = R.get_state()
+    y = y.copy()
+    n3 = 3 * R.n_soft_verts
+    y[:n3] += np.random.default_rng(seed).normal(scale=noise, size=n3)
+    x_ext = sc.meta["x_ext"]
+    dh = sc.params.dhat
+    for k, f in enumerate(sc.affines):
+        side = -1.0 if f.rest_pos[:, 0].mean() < 0 else 1.0
+        y[n3 + 12 * k] -= side * (2 * dh - squeeze * dh)
+    return y, yd
+
+
+@pytest.fixture(scope="module")
+def gripper_full():
+    sc = sg.gripper(0)
+    R = ref.RefScene(sc)
+    y, yd = gripper_contact_state(sc, R)
+    R.set_state(y, yd)
+    return sc, R, y, yd
+
+
+def test_gripper_full_size_candidates(zema, gripper_full):
+    sc, R, y, yd = gripper_full
+    G = zema.Scene(sc)
+    xs = R.surface_positions(y)
+    log(f"gripper: {R.n_tets} tets, {R.n_surf} surface vertices, {R.n_tris} tris, {R.n_edges} edges")
+    pr, er = R.candidates(xs, None, sc.params.dhat)
+    pg, eg = G.contact_candidates(xs, None, sc.params.dhat)
+    log(f"static: {len(pr)} PT, {len(er)} EE")
+    assert len(pr) > 100 and np.array_equal(pg.cpu().numpy(), pr) and np.array_equal(eg.cpu().numpy(), er)
+    xs1 = xs.copy()
+    xs1[:, 1] -= 2e-3                              # a swept box per primitive
+    pr, er = R.candidates(xs, xs1, sc.params.dhat)
+    pg, eg = G.contact_candidates(xs, xs1, sc.params.dhat)
+    assert np.array_equal(pg.cpu().numpy(), pr) and np.array_equal(eg.cpu().numpy(), er)
+
+
+def test_gripper_full_size_energy_gradient_hv(zema, gripper_full):
+    sc, R, y, yd = gripper_full
+    G = zema.Scene(sc)
+    G.set_state(y, yd)
+    tr, _ = R.ip_assemble(y, hess=False)
+    tg, _ = G.ip_assemble(y, hess=False)
+    log(f"gripper terms gpu {tg} oracle {tr}")
+    assert tr[4] > 0
+    check_terms(tg, tr, "gripper", energy_floor(sc, R))
+    worst = check_grad_terms(G, R, y, "gripper")
+    worst_h = check_hv(G, R, y, 7, "gripper", masks=(0, 1 << 1, 1 << 4))
+    log(f"gripper worst grad {worst:.2e} worst Hv {worst_h:.2e}")

@@ -184,7 +184,10 @@ class RefScene:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().zref_scene_destroy(self.h)
+            try:
+                lib().zref_scene_destroy(self.h)
+            except Exception:  # interpreter shutdown: module globals already gone
+                pass
             self.h = None
 
     def _chk(self, rc):

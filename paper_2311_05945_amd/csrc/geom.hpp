@@ -37,11 +37,15 @@ __host__ __device__ inline int pt_type(V3 p, V3 a, V3 b, V3 c) {
 }
 
 // Closest features of two segments (Ericson, Sec. 5.1.9) mapped to a type; nearly
-// parallel segments (|a x b|^2 <= 1e-20 |a|^2 |b|^2) take the endpoint branch.
+// parallel segments (|a x b|^2 <= 1e-20 |a|^2 |b|^2) take the endpoint branch, so the
+// interior-interior type always has |a x b| > 0.
 __host__ __device__ inline int ee_type(V3 a0, V3 a1, V3 b0, V3 b1, double* sp, double* tp) {
   V3 d1 = a1 - a0, d2 = b1 - b0, r = a0 - b0;
   double A = dot(d1, d1), E = dot(d2, d2), f = dot(d2, r), c = dot(d1, r), bb = dot(d1, d2);
-  double den = A * E - bb * bb;
+  // |d1 x d2|^2 from the cross product: exactly zero for parallel axis-aligned edges,
+  // where A E - bb^2 would round to a small non-zero value
+  V3 nx = cross(d1, d2);
+  double den = dot(nx, nx);
   double s = 0.0, t;
   if (den > 1e-20 * A * E) {
     s = (bb * f - c * E) / den;

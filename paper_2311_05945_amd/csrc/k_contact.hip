@@ -50,6 +50,7 @@ __global__ void contact_energy_kernel(int npt, int nee, const int* __restrict__ 
     for (int a = 0; a < 4; ++a) x[a] = ld3(xs + 3 * sv[a]);
     double eps = kind == 1 ? 1e-3 * elen2[ea] * elen2[eb] : 0.0;
     e_pair[k] = pair_barrier_energy(kind, x, eps, kappa, dhat, &d);
+    if (d != d) d = 0.0;  // a non-finite distance makes the state infeasible, never inactive
     d_pair[k] = d;
   }
   for (int o = 32; o > 0; o >>= 1) d = fmin(d, __shfl_xor(d, o, 64));

@@ -162,7 +162,10 @@ class Scene:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().zema_scene_destroy(self.h)
+            try:
+                lib().zema_scene_destroy(self.h)
+            except Exception:  # interpreter shutdown: module globals already gone
+                pass
             self.h = None
 
     def _chk(self, rc):

@@ -64,8 +64,10 @@ enum {
 
 enum { ZEMA_FREE = 0, ZEMA_FIXED = 1, ZEMA_DRIVEN = 2 };
 enum { ZEMA_FP64 = 0, ZEMA_MIXED = 1 };
+enum { ZEMA_WARM_EXPLICIT = 0, ZEMA_WARM_LEARNED = 1 };
 
 typedef struct zema_scene zema_scene;
+typedef struct zema_mlp zema_mlp;
 
 /* Solver parameters.  dt = h, dhat = barrier distance d-hat (eq. 5), kappa = barrier
  * stiffness (eq. 4; <= 0 selects the automatic rule: kappa0 = h^2 mbar |g| /
@@ -74,8 +76,13 @@ typedef struct zema_scene zema_scene;
  * velocity threshold of eqs. 9-10, gravity (m/s^2), newton_tol (m/s: converged when
  * the largest vertex displacement of a Newton direction is <= newton_tol * dt),
  * pcg_rtol (relative residual), ccd_s (ACCD separation fraction, 0.1),
- * newton_max, pcg_max (<= 0: number of DOFs), precision (ZEMA_FP64 / ZEMA_MIXED),
- * warm_start (0 explicit velocity). */
+ * newton_max, pcg_max (<= 0: number of DOFs), precision (ZEMA_FP64: every array
+ * FP64; ZEMA_MIXED: Hessian blocks, their products and the block-Jacobi
+ * preconditioner in FP32, energies, gradients, line search, CCD and the convergence
+ * test FP64), warm_start (ZEMA_WARM_EXPLICIT: y^t + alpha h ydot^t; ZEMA_WARM_LEARNED:
+ * the network attached by zema_scene_set_mlp proposes the soft-vertex displacement,
+ * filtered by the same CCD bound and kept only if its energy is not higher than the
+ * explicit start's). */
 typedef struct {
   double dt, dhat, kappa, mu, eps_v;
   double gravity[3];
@@ -116,8 +123,9 @@ typedef struct {
 typedef struct {
   int32_t status, newton_iters, pcg_iters, ls_backtracks;
   int32_t n_pt_active, n_ee_active, n_pt_cand, n_ee_cand;
+  int32_t warm_learned, reserved_;  /* 1 if the learned initial guess was kept */
   double alpha_ccd_min, kappa, d_min, energy;
-  double ms_total, ms_assemble, ms_pcg, ms_broad, ms_ccd, ms_linesearch;
+  double ms_total, ms_assemble, ms_pcg, ms_broad, ms_ccd, ms_linesearch, ms_warm;
 } zema_step_stats;
 
 /* Create a scene: copies every input, precomputes rest-shape inverses, volumes,
@@ -196,6 +204,16 @@ int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats);
  * (kind 0 PT / 1 EE, 4 surface vertices), vals8 [n][8] = (lambda, n(3), w(4)). */
 int zema_friction_table(zema_scene* s, int64_t* n, int32_t* ids5, double* vals8, int64_t cap);
 
+/* Validation of the intersection-free guarantee: at y (device), the number of
+ * inter-body (surface edge, surface triangle) pairs whose closed segment and closed
+ * triangle intersect, the number of tets with non-positive volume, and the number of
+ * pairs / tets whose orientation signs the FP64 filter (static error bound of
+ * orient3d) cannot certify.  The first min(n_uncertain, cap) uncertain (edge,
+ * triangle) pairs are written to uncertain_pairs (device, [cap][2]) for an exact
+ * check by the caller; uncertain tets are only counted.  Counts are host outputs. */
+int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect, int64_t* n_inverted,
+                            int64_t* n_uncertain, int32_t* uncertain_pairs, int64_t cap);
+
 /* Launch timing for benchmarks: with enable != 0 the library records HIP events on
  * the scene's stream around every launch of one kernel group (0 PCG sparse
  * matrix-vector product, 1 per-tet elastic assembly, 2 contact pair assembly,
@@ -207,6 +225,59 @@ int zema_friction_table(zema_scene* s, int64_t* n, int32_t* ids5, double* vals8,
  * stream; bytes may be NULL. */
 int zema_kernel_timer(zema_scene* s, int32_t group, int32_t enable);
 int zema_kernel_time(zema_scene* s, int32_t group, double* ms, int64_t* launches, double* bytes);
+
+/* ---------------------------------------------------------------- learned initial guess
+ * Not part of the paper's method: a per-soft-vertex network proposes the Newton
+ * initial guess of a time step; the step itself (tolerance, CCD filter, line
+ * search) is unchanged, so the result is judged by the same Newton loop.
+ *
+ * Network: 16 -> 64 -> 64 -> 64 -> 3, ReLU, weight matrices used in bfloat16 (round to
+ * nearest even from the FP32 master copy), biases FP32, FP32 accumulation on the
+ * matrix cores.  Parameters: ZEMA_MLP_PARAMS floats in the order W1 [64][16], b1,
+ * W2 [64][64], b2, W3 [64][64], b3, W4 [3][64], b4 (W row-major [out][in]).
+ *
+ * Features of soft vertex i (ZEMA_MLP_FEATURES floats; s = dt * 0.05 m/s):
+ *   0-2 dt v_i / s;  3-5 dt (v_i - v_i of the previous step) / s;
+ *   6   min(d_i, 4 dhat) / dhat, d_i the distance to the nearest triangle of another
+ *       body (surface vertices; 4 for interior ones and none in range);
+ *   7-9 unit vector to the closest point of that triangle; 10-12 dt (velocity of that
+ *       point) / s; 13-15 dt (kinematic target velocity - velocity) / s of the driven
+ *       body owning it (0 otherwise).  Entries 7-15 are 0 when no triangle is in range.
+ * Output: the correction of dt v_i in units of s.  Training target of a step:
+ * ((x_i^{t+1} - x_i^t) - dt v_i^t) / s. */
+#define ZEMA_MLP_PARAMS 9603
+#define ZEMA_MLP_FEATURES 16
+
+/* Network object bound to hip_stream (NULL: the default stream); weights zero until
+ * set.  Errors: ZEMA_E_ARG, ZEMA_E_DEVICE. */
+int zema_mlp_create(void* hip_stream, zema_mlp** out);
+void zema_mlp_destroy(zema_mlp* m);
+const char* zema_mlp_last_error(const zema_mlp* m);
+/* Host [ZEMA_MLP_PARAMS] FP32 parameters in / out; set also clears the Adam state. */
+int zema_mlp_set_weights(zema_mlp* m, const float* theta);
+int zema_mlp_get_weights(zema_mlp* m, float* theta);
+/* out [n][3] = network(feat [n][16]); device pointers. */
+int zema_mlp_forward(zema_mlp* m, const float* feat, int64_t n, float* out);
+/* Mean-squared-error loss (1 / 3n) sum |out - target|^2 over rows 0..n-1 of feat and
+ * target [n][3] (device) and its gradient grad [ZEMA_MLP_PARAMS] (device); loss is a
+ * host output.  No update. */
+int zema_mlp_grad(zema_mlp* m, const float* feat, const float* target, int64_t n, float* grad, double* loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, learning rate lr)
+ * on the batch of rows idx [batch] (device int32, each in [0, n_rows); rows out of
+ * range are skipped) of feat / target [n_rows]; loss of the batch before the step is
+ * a host output. */
+int zema_mlp_train_step(zema_mlp* m, const float* feat, const float* target, int64_t n_rows, const int32_t* idx,
+                        int64_t batch, float lr, double* loss);
+
+/* Network used by zema_step when params.warm_start == ZEMA_WARM_LEARNED (NULL
+ * detaches).  The scene reads the weights on its own stream at every step; the
+ * caller must not update them concurrently. */
+int zema_scene_set_mlp(zema_scene* s, zema_mlp* m);
+/* Features [n_soft_verts][16] (device) at the current state.  Replaces the stored
+ * candidate set with the one at radius 4 dhat. */
+int zema_scene_features(zema_scene* s, float* feat);
+/* Training target [n_soft_verts][3] (device) of the last step taken by zema_step. */
+int zema_scene_warm_target(zema_scene* s, float* target);
 
 #ifdef __cplusplus
 }

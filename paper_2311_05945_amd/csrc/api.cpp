@@ -15,6 +15,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <new>
 #include <vector>
 
 #include "scene.hpp"
@@ -330,11 +332,18 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   s->bsr_diag.upload(bdiag);
   s->hc_ptr.upload(hcnt);
   s->hc_list.upload(hlist);
-  s->bsr_val.resize((size_t)9 * s->nnzb + 9);
+  // the mixed-precision form keeps Hessian blocks and their products in FP32; only
+  // the buffers of the chosen form are allocated at full size
+  s->mixed = s->P.precision == ZEMA_MIXED;
+  size_t nbv = (size_t)9 * s->nnzb + 9, nht = (size_t)90 * s->nt + 90;
+  s->bsr_val.resize(s->mixed ? 9 : nbv);
   ZCHK(hipMemset(s->bsr_val.p, 0, sizeof(double) * s->bsr_val.n));
+  s->bsr_val32.resize(s->mixed ? nbv : 9);
+  ZCHK(hipMemset(s->bsr_val32.p, 0, sizeof(float) * s->bsr_val32.n));
   s->e_tet.resize(s->nt + 1);
   s->g_tet.resize((size_t)12 * s->nt + 12);
-  s->h_tet.resize((size_t)90 * s->nt + 90);
+  s->h_tet.resize(s->mixed ? 90 : nht);
+  s->h_tet32.resize(s->mixed ? nht : 90);
   s->e_in.resize(s->nsv + 1);
   int nb = (int)s->bodies.size();
   std::vector<double> bf((size_t)BF * std::max(nb, 1), 0.0);
@@ -359,6 +368,9 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   s->qtilde.resize((size_t)12 * std::max(nb, 1));
   s->e_body.resize((size_t)3 * std::max(nb, 1));
   s->sv_ref.upload(sv_ref);
+  s->soft_sv.upload(soft_sid.empty() ? std::vector<int>{-1} : soft_sid);
+  s->body_tv.resize((size_t)3 * std::max<size_t>(s->bodies.size(), 1));
+  ZCHK(hipMemset(s->body_tv.p, 0, sizeof(double) * s->body_tv.n));
   s->sv_body.upload(sv_body);
   s->sv_x0.upload(sv_x0);
   s->tris.upload(tris_h);
@@ -369,7 +381,7 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   s->xs1.resize(ns3);
   s->dxs.resize(ns3);
   size_t nd = std::max(s->ndof, 1);
-  for (DBuf<double>* v : {&s->y, &s->ydot, &s->yt, &s->ydt, &s->yhat, &s->ytmp, &s->grad, &s->pdir})
+  for (DBuf<double>* v : {&s->y, &s->ydot, &s->yt, &s->ydt, &s->yhat, &s->ytmp, &s->grad, &s->pdir, &s->yd_prev})
     v->resize(nd);
   s->counters.resize(16);
   s->umin.resize(8);
@@ -474,6 +486,16 @@ void begin_step(zema_scene* s) {
     for (int k = 0; k < 3; ++k) qt[12 * b + k] += tt * B.tvel[k];
   }
   ZCHK(hipMemcpyAsync(s->qtilde.p, qt.data(), sizeof(double) * qt.size(), hipMemcpyHostToDevice, s->st));
+  // translational target velocity of each driven body over this step (learned guess input)
+  s->body_tv_h.assign((size_t)3 * std::max(nb, 1), 0.0);
+  for (int b = 0; b < nb; ++b) {
+    const Body& B = s->bodies[b];
+    if (B.mode != ZEMA_DRIVEN) continue;
+    double span = std::min(tnext, B.tstop) - std::min(tnext - s->P.dt, B.tstop);
+    for (int k = 0; k < 3; ++k) s->body_tv_h[3 * b + k] = B.tvel[k] * span / s->P.dt;
+  }
+  ZCHK(hipMemcpyAsync(s->body_tv.p, s->body_tv_h.data(), sizeof(double) * s->body_tv_h.size(),
+                      hipMemcpyHostToDevice, s->st));
   s->kappa_lag = s->kappa;
   static_candidates(s, s->y.p);
   k_friction_build(s);
@@ -483,7 +505,9 @@ void begin_step(zema_scene* s) {
 int set_state_impl(zema_scene* s, const double* y, const double* ydot, double kappa, int step) {
   ZCHK(hipMemcpyAsync(s->y.p, y, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
   ZCHK(hipMemcpyAsync(s->ydot.p, ydot, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+  ZCHK(hipMemcpyAsync(s->yd_prev.p, ydot, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
   s->step = step;
+  s->stepped = false;
   s->kappa = kappa > 0.0 ? kappa : (s->P.kappa > 0.0 ? s->P.kappa : auto_kappa(s));
   {
     const double* P[2] = {s->y.p, s->ydot.p};
@@ -498,34 +522,68 @@ int set_state_impl(zema_scene* s, const double* y, const double* ydot, double ka
   return 0;
 }
 
+// y_out = y^t + a p, a the ACCD bound of the sweep along p, halved until no tet inverts
+void filtered_start(zema_scene* s, const double* p, double* y_out, double& tb, double& tc) {
+  double q = now_ms();
+  swept_candidates(s, s->y.p, p);
+  tb += now_ms() - q;
+  double a0;
+  q = now_ms();
+  int rc = k_ccd(s, s->y.p, p, &a0);
+  tc += now_ms() - q;
+  if (rc) throw Error(rc, "intersecting pair at warm-start CCD");
+  for (;;) {
+    k_axpy(s, s->ndof, a0, p, s->y.p, y_out);
+    if (!k_any_inverted(s, y_out)) break;
+    a0 *= 0.5;
+    if (a0 < 1e-10) {
+      ZCHK(hipMemcpyAsync(y_out, s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+      break;
+    }
+  }
+}
+
 int time_step(zema_scene* s, zema_step_stats* st) {
   const double h = s->P.dt;
   const int n = s->ndof;
   std::memset(st, 0, sizeof(*st));
   st->alpha_ccd_min = 1.0;
-  double t0 = now_ms(), tb = 0, ta = 0, tp = 0, tc = 0, tl = 0, q;
+  double t0 = now_ms(), tb = 0, ta = 0, tp = 0, tc = 0, tl = 0, tw = 0, q;
+  int rc;
   q = now_ms();
   begin_step(s);
   tb += now_ms() - q;
   ZCHK(hipMemcpyAsync(s->yt.p, s->y.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
   ZCHK(hipMemcpyAsync(s->ydt.p, s->ydot.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
-  // warm start
+  // initial guess: y^t + a h ydot^t with a the CCD bound of that sweep; with the
+  // learned form also the network's proposal, filtered the same way and kept only
+  // if its energy is not higher (swept_candidates uses ytmp, so the learned start
+  // is formed first, into ywarm)
   k_scale(s, n, h, s->ydot.p, s->pdir.p);
-  q = now_ms();
-  swept_candidates(s, s->y.p, s->pdir.p);
-  tb += now_ms() - q;
-  double a0;
-  q = now_ms();
-  int rc = k_ccd(s, s->y.p, s->pdir.p, &a0);
-  tc += now_ms() - q;
-  if (rc) throw Error(rc, "intersecting pair at warm-start CCD");
-  for (;;) {
-    k_axpy(s, n, a0, s->pdir.p, s->y.p, s->ytmp.p);
-    if (!k_any_inverted(s, s->ytmp.p)) break;
-    a0 *= 0.5;
-    if (a0 < 1e-10) {
-      ZCHK(hipMemcpyAsync(s->ytmp.p, s->y.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
-      break;
+  const bool learned = s->P.warm_start == ZEMA_WARM_LEARNED;
+  if (learned) {
+    q = now_ms();
+    s->feat.reserve((size_t)16 * s->nsv + 16);
+    s->mlp_out.reserve((size_t)3 * s->nsv + 3);
+    s->ywarm.reserve(n);
+    k_features(s, s->feat.p);
+    mlp_forward(s->mlp, s->st, s->feat.p, s->nsv, s->mlp_out.p);
+    k_warm_dir(s, s->mlp_out.p, s->grad.p);
+    tw += now_ms() - q;
+    filtered_start(s, s->grad.p, s->ywarm.p, tb, tc);
+  }
+  filtered_start(s, s->pdir.p, s->ytmp.p, tb, tc);
+  if (learned) {
+    q = now_ms();
+    double Tp[8], Tl[8];
+    static_candidates(s, s->ytmp.p);
+    eval_energy(s, s->ytmp.p, Tp);
+    static_candidates(s, s->ywarm.p);
+    eval_energy(s, s->ywarm.p, Tl);
+    tw += now_ms() - q;
+    if (std::isfinite(Tl[6]) && Tl[6] <= Tp[6]) {
+      std::swap(s->ytmp.p, s->ywarm.p);
+      st->warm_learned = 1;
     }
   }
   std::swap(s->y.p, s->ytmp.p);
@@ -591,6 +649,7 @@ int time_step(zema_scene* s, zema_step_stats* st) {
   st->kappa = s->kappa;
   st->d_min = min_distance(s, s->y.p);
   if (!conv) throw Error(ZEMA_E_NEWTON, "Newton did not converge");
+  ZCHK(hipMemcpyAsync(s->yd_prev.p, s->ydt.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
   k_velocity(s, 1.0 / h);
   s->step += 1;
   ZCHK(hipStreamSynchronize(s->st));
@@ -601,6 +660,7 @@ int time_step(zema_scene* s, zema_step_stats* st) {
   st->ms_broad = tb;
   st->ms_ccd = tc;
   st->ms_linesearch = tl;
+  st->ms_warm = tw;
   return 0;
 }
 
@@ -690,6 +750,8 @@ int zema_scene_create(const zema_params* params, const zema_soft_desc* soft, int
                       const zema_affine_desc* affine, int32_t n_affine, void* hip_stream, zema_scene** out) {
   if (!params || !out || n_soft < 0 || n_affine < 0 || (n_soft && !soft) || (n_affine && !affine)) return ZEMA_E_ARG;
   if (!(params->dt > 0.0) || !(params->dhat > 0.0)) return ZEMA_E_ARG;
+  if (params->precision != ZEMA_FP64 && params->precision != ZEMA_MIXED) return ZEMA_E_ARG;
+  if (params->warm_start != ZEMA_WARM_EXPLICIT && params->warm_start != ZEMA_WARM_LEARNED) return ZEMA_E_ARG;
   zema_scene* s = new zema_scene();
   s->P = *params;
   s->st = (hipStream_t)hip_stream;
@@ -825,6 +887,10 @@ int zema_ccd_max_step(zema_scene* s, const double* y, const double* p, double* a
 
 int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
   if (!s || n_steps < 0 || (n_steps && !stats)) return ZEMA_E_ARG;
+  if (s->P.warm_start == ZEMA_WARM_LEARNED && !s->mlp) {
+    s->err = "learned initial guess selected but no network attached";
+    return ZEMA_E_ARG;
+  }
   for (int k = 0; k < n_steps; ++k) {
     // y^t / ydot^t are saved first so a failed step can restore them
     int rc = guard(s, [&]() {
@@ -833,6 +899,7 @@ int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
       return time_step(s, &stats[k]);
     });
     stats[k].status = rc;
+    s->stepped = rc == 0;
     if (rc) {
       // restore y^t and ydot^t of the failed step
       (void)hipMemcpyAsync(s->y.p, s->yt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st);
@@ -842,6 +909,21 @@ int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
     }
   }
   return 0;
+}
+
+int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect, int64_t* n_inverted,
+                            int64_t* n_uncertain, int32_t* uncertain_pairs, int64_t cap) {
+  if (!s || !y || !n_intersect || !n_inverted || !n_uncertain || (cap > 0 && !uncertain_pairs)) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    s->unc_pairs.reserve((size_t)2 * std::max<int64_t>(cap, 1));
+    k_intersections(s, y, n_intersect, n_inverted, n_uncertain, s->unc_pairs);
+    int64_t nu_pairs = std::min<int64_t>(*n_uncertain, cap);
+    if (nu_pairs > 0)
+      ZCHK(hipMemcpyAsync(uncertain_pairs, s->unc_pairs.p, sizeof(int) * 2 * nu_pairs, hipMemcpyDeviceToDevice,
+                          s->st));
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
 }
 
 int zema_kernel_timer(zema_scene* s, int32_t group, int32_t enable) {
@@ -879,6 +961,128 @@ int zema_friction_table(zema_scene* s, int64_t* n, int32_t* ids5, double* vals8,
       ZCHK(hipMemcpyAsync(ids5, s->f_ids.p, sizeof(int) * 5 * s->nfric, hipMemcpyDeviceToHost, s->st));
       ZCHK(hipMemcpyAsync(vals8, s->f_vals.p, sizeof(double) * 8 * s->nfric, hipMemcpyDeviceToHost, s->st));
     }
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
+}
+
+
+// ---------------------------------------------------------------- learned initial guess
+
+static int mguard(zema_mlp* m, const std::function<int()>& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    if (m) m->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    if (m) m->err = e.what();
+    return ZEMA_E_DEVICE;
+  }
+}
+
+int zema_mlp_create(void* hip_stream, zema_mlp** out) {
+  if (!out) return ZEMA_E_ARG;
+  *out = nullptr;
+  zema_mlp* m = new (std::nothrow) zema_mlp();
+  if (!m) return ZEMA_E_DEVICE;
+  m->st = (hipStream_t)hip_stream;
+  int rc = mguard(m, [&]() {
+    for (DBuf<float>* b : {&m->theta, &m->mom, &m->vel, &m->grad}) {
+      b->resize(kMlpParams);
+      ZCHK(hipMemset(b->p, 0, sizeof(float) * kMlpParams));
+    }
+    m->loss.resize(1);
+    return 0;
+  });
+  if (rc) {
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return 0;
+}
+
+void zema_mlp_destroy(zema_mlp* m) {
+  if (m && m->st) (void)hipStreamSynchronize(m->st);
+  delete m;
+}
+
+const char* zema_mlp_last_error(const zema_mlp* m) { return m ? m->err.c_str() : "null network"; }
+
+int zema_mlp_set_weights(zema_mlp* m, const float* theta) {
+  if (!m || !theta) return ZEMA_E_ARG;
+  return mguard(m, [&]() {
+    ZCHK(hipMemcpyAsync(m->theta.p, theta, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, m->st));
+    ZCHK(hipMemsetAsync(m->mom.p, 0, sizeof(float) * kMlpParams, m->st));
+    ZCHK(hipMemsetAsync(m->vel.p, 0, sizeof(float) * kMlpParams, m->st));
+    ZCHK(hipStreamSynchronize(m->st));
+    m->step = 0;
+    return 0;
+  });
+}
+
+int zema_mlp_get_weights(zema_mlp* m, float* theta) {
+  if (!m || !theta) return ZEMA_E_ARG;
+  return mguard(m, [&]() {
+    ZCHK(hipMemcpyAsync(theta, m->theta.p, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost, m->st));
+    ZCHK(hipStreamSynchronize(m->st));
+    return 0;
+  });
+}
+
+int zema_mlp_forward(zema_mlp* m, const float* feat, int64_t n, float* out) {
+  if (!m || n < 0 || (n && (!feat || !out))) return ZEMA_E_ARG;
+  return mguard(m, [&]() {
+    mlp_forward(m, m->st, feat, (long)n, out);
+    ZCHK(hipGetLastError());
+    ZCHK(hipStreamSynchronize(m->st));
+    return 0;
+  });
+}
+
+int zema_mlp_grad(zema_mlp* m, const float* feat, const float* target, int64_t n, float* grad, double* loss) {
+  if (!m || n <= 0 || !feat || !target || !grad || !loss) return ZEMA_E_ARG;
+  return mguard(m, [&]() {
+    *loss = mlp_grad(m, feat, target, nullptr, (long)n, (long)n, false, 0.0f);
+    ZCHK(hipMemcpyAsync(grad, m->grad.p, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, m->st));
+    ZCHK(hipStreamSynchronize(m->st));
+    return 0;
+  });
+}
+
+int zema_mlp_train_step(zema_mlp* m, const float* feat, const float* target, int64_t n_rows, const int32_t* idx,
+                        int64_t batch, float lr, double* loss) {
+  if (!m || n_rows <= 0 || batch <= 0 || !feat || !target || !idx || !loss || !(lr > 0.0f)) return ZEMA_E_ARG;
+  return mguard(m, [&]() {
+    *loss = mlp_grad(m, feat, target, idx, (long)n_rows, (long)batch, true, lr);
+    return 0;
+  });
+}
+
+int zema_scene_set_mlp(zema_scene* s, zema_mlp* m) {
+  if (!s) return ZEMA_E_ARG;
+  s->mlp = m;
+  return 0;
+}
+
+int zema_scene_features(zema_scene* s, float* feat) {
+  if (!s || (s->nsv && !feat)) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    k_features(s, feat);
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
+}
+
+int zema_scene_warm_target(zema_scene* s, float* target) {
+  if (!s || (s->nsv && !target)) return ZEMA_E_ARG;
+  if (!s->stepped) {
+    s->err = "no completed step since the state was set";
+    return ZEMA_E_ARG;
+  }
+  return guard(s, [&]() {
+    k_warm_target(s, target);
     ZCHK(hipStreamSynchronize(s->st));
     return 0;
   });

@@ -104,6 +104,30 @@ __host__ __device__ inline double ee_d2(const V3* x, int type) {
   return d2_triple_val(x[2] - x[0], x[1] - x[0], x[3] - x[2]);
 }
 
+// barycentric weights of the closest point of triangle (x1, x2, x3) to x0, on the
+// feature pt_type selects (vertex, clamped edge parameter, or face projection)
+__host__ __device__ inline void pt_closest_bary(const V3* x, double b[3]) {
+  int t = pt_type(x[0], x[1], x[2], x[3]);
+  b[0] = b[1] = b[2] = 0.0;
+  if (t <= 2) {
+    b[t] = 1.0;
+  } else if (t <= 5) {
+    int i = t - 3, j = (i + 1) % 3;
+    V3 e = x[1 + j] - x[1 + i];
+    double s = dot(x[0] - x[1 + i], e) / dot(e, e);
+    s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+    b[i] = 1.0 - s;
+    b[j] = s;
+  } else {
+    V3 u = x[2] - x[1], v = x[3] - x[1], ww = x[0] - x[1];
+    V3 n = cross(u, v);
+    double nn = dot(n, n);
+    b[1] = dot(cross(ww, v), n) / nn;
+    b[2] = dot(cross(u, ww), n) / nn;
+    b[0] = 1.0 - b[1] - b[2];
+  }
+}
+
 __host__ __device__ inline double pair_dist(int kind, const V3* x, int* type_out) {
   int t;
   double D;

@@ -90,11 +90,12 @@ __device__ inline void body_terms(const double* q, const double* qh, const doubl
   }
 }
 
+template <class T>
 __global__ void body_assemble_kernel(int nb, const double* __restrict__ bf, const int* __restrict__ bi,
                                      const double* __restrict__ qtilde, const double* __restrict__ y,
                                      const double* __restrict__ yhat, double* __restrict__ grad,
                                      double* __restrict__ e_body, const int* __restrict__ bsr_ptr,
-                                     double* __restrict__ val, int nnzb, int want_h, double h2, unsigned mask) {
+                                     T* __restrict__ val, int nnzb, int want_h, double h2, unsigned mask) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nb) return;
   int mode = bi[4 * b], dof0 = bi[4 * b + 1], node0 = bi[4 * b + 2];
@@ -114,24 +115,31 @@ __global__ void body_assemble_kernel(int nb, const double* __restrict__ bf, cons
       int base = bsr_ptr[node0 + r];
       for (int c = 0; c < 4; ++c)
         for (int i = 0; i < 3; ++i)
-          for (int j = 0; j < 3; ++j) val[(size_t)(3 * i + j) * nnzb + base + c] = H[3 * r + i][3 * c + j];
+          for (int j = 0; j < 3; ++j) val[(size_t)(3 * i + j) * nnzb + base + c] = T(H[3 * r + i][3 * c + j]);
     }
 }
 
 void k_body_terms(zema_scene* s, const double* y, double* grad, bool hess, unsigned mask) {
   int nb = (int)s->bodies.size();
   if (!nb) return;
-  body_assemble_kernel<<<nblocks(nb, 64), 64, 0, s->st>>>(nb, s->body_f.p, s->body_i.p, s->qtilde.p, y, s->yhat.p,
-                                                          grad, s->e_body.p, s->bsr_ptr.p, s->bsr_val.p, s->nnzb,
-                                                          hess ? 1 : 0, s->P.dt * s->P.dt, mask);
+  if (s->mixed)
+    body_assemble_kernel<float><<<nblocks(nb, 64), 64, 0, s->st>>>(nb, s->body_f.p, s->body_i.p, s->qtilde.p, y,
+                                                                   s->yhat.p, grad, s->e_body.p, s->bsr_ptr.p,
+                                                                   s->bsr_val32.p, s->nnzb, hess ? 1 : 0,
+                                                                   s->P.dt * s->P.dt, mask);
+  else
+    body_assemble_kernel<double><<<nblocks(nb, 64), 64, 0, s->st>>>(nb, s->body_f.p, s->body_i.p, s->qtilde.p, y,
+                                                                    s->yhat.p, grad, s->e_body.p, s->bsr_ptr.p,
+                                                                    s->bsr_val.p, s->nnzb, hess ? 1 : 0,
+                                                                    s->P.dt * s->P.dt, mask);
 }
 
 void k_body_energy(zema_scene* s, const double* y) {
   int nb = (int)s->bodies.size();
   if (!nb) return;
-  body_assemble_kernel<<<nblocks(nb, 64), 64, 0, s->st>>>(nb, s->body_f.p, s->body_i.p, s->qtilde.p, y, s->yhat.p,
-                                                          nullptr, s->e_body.p, s->bsr_ptr.p, s->bsr_val.p, s->nnzb, 0,
-                                                          s->P.dt * s->P.dt, 0x3fu);
+  body_assemble_kernel<double><<<nblocks(nb, 64), 64, 0, s->st>>>(nb, s->body_f.p, s->body_i.p, s->qtilde.p, y,
+                                                                  s->yhat.p, nullptr, s->e_body.p, s->bsr_ptr.p,
+                                                                  s->bsr_val.p, s->nnzb, 0, s->P.dt * s->P.dt, 0x3fu);
 }
 
 }  // namespace zema

@@ -108,15 +108,18 @@ __global__ void entry_count_kernel(PrimSet E, const double* __restrict__ lo, con
   big_flag[i] = n < 0 ? 1 : 0;
 }
 
-__global__ void entry_insert_kernel(PrimSet E, const double* __restrict__ lo, const double* __restrict__ hi,
+__global__ void entry_insert_kernel(PrimSet E, int ekind, const double* __restrict__ lo, const double* __restrict__ hi,
                                     double inv_c, const int* __restrict__ offs, unsigned mask,
                                     unsigned long long* __restrict__ key, int* __restrict__ val,
-                                    unsigned long long* __restrict__ ecell, int* __restrict__ eprim) {
+                                    unsigned long long* __restrict__ ecell, int* __restrict__ eprim,
+                                    int* __restrict__ ebody, const int* __restrict__ tris,
+                                    const int* __restrict__ edges, const int* __restrict__ sv_body) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E.n) return;
   int c0[3], c1[3];
   if (cell_range(lo, hi, E.base + i, inv_c, c0, c1) < 0) return;
   int o = offs[i];
+  int body = prim_body(ekind, i, tris, edges, sv_body);
   for (int x = c0[0]; x <= c1[0]; ++x)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int z = c0[2]; z <= c1[2]; ++z, ++o) {
@@ -124,6 +127,7 @@ __global__ void entry_insert_kernel(PrimSet E, const double* __restrict__ lo, co
         val[o] = o;
         ecell[o] = pack_cell(x, y, z);
         eprim[o] = i;
+        ebody[o] = body;
       }
 }
 
@@ -138,13 +142,15 @@ __global__ void bucket_bounds_kernel(int n, const unsigned long long* __restrict
 
 // gather entry cell / prim into sorted order
 __global__ void entry_permute_kernel(int n, const int* __restrict__ sval, const unsigned long long* __restrict__ ecell,
-                                     const int* __restrict__ eprim, unsigned long long* __restrict__ scell,
-                                     int* __restrict__ sprim) {
+                                     const int* __restrict__ eprim, const int* __restrict__ ebody,
+                                     unsigned long long* __restrict__ scell, int* __restrict__ sprim,
+                                     int* __restrict__ sbody) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   int o = sval[j];
   scell[j] = ecell[o];
   sprim[j] = eprim[o];
+  sbody[j] = ebody[o];
 }
 
 struct PairRule {
@@ -169,7 +175,8 @@ __device__ inline void emit(unsigned long long key, unsigned long long* out, int
 __global__ void query_kernel(PrimSet Q, PrimSet E, PairRule R, const double* __restrict__ lo,
                              const double* __restrict__ hi, double inv_c, unsigned mask, const int* __restrict__ blo,
                              const int* __restrict__ bhi, const unsigned long long* __restrict__ scell,
-                             const int* __restrict__ sprim, const int* __restrict__ ebig, const int* __restrict__ tris,
+                             const int* __restrict__ sprim, const int* __restrict__ sbody,
+                             const int* __restrict__ ebig, const int* __restrict__ tris,
                              const int* __restrict__ edges, const int* __restrict__ sv_body,
                              const unsigned char* __restrict__ fixed, unsigned long long nE,
                              unsigned long long* __restrict__ out, int* __restrict__ counter, int cap) {
@@ -188,6 +195,7 @@ __global__ void query_kernel(PrimSet Q, PrimSet E, PairRule R, const double* __r
     }
     return;
   }
+  const int bq = prim_body(R.qkind, q, tris, edges, sv_body);
   for (int x = c0[0]; x <= c1[0]; ++x)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int z = c0[2]; z <= c1[2]; ++z) {
@@ -195,6 +203,7 @@ __global__ void query_kernel(PrimSet Q, PrimSet E, PairRule R, const double* __r
         unsigned long long ck = pack_cell(x, y, z);
         int j1 = bhi[h];
         for (int j = blo[h]; j < j1; ++j) {
+          if (sbody[j] == bq) continue;  // same body: never a candidate
           if (scell[j] != ck) continue;
           int e = sprim[j];
           if (!admissible(R, q, e, tris, edges, sv_body, fixed)) continue;
@@ -269,15 +278,18 @@ static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>
   sb.v0.reserve(total + 1);
   s->ent_cell.reserve(2 * total + 2);
   s->ent_prim.reserve(2 * total + 2);
+  s->ent_body.reserve(2 * total + 2);
   s->bucket_lo.reserve(tsize);
   s->bucket_hi.reserve(tsize);
   if (total > 0) {
-    entry_insert_kernel<<<nblocks(E.n), kBlock, 0, s->st>>>(E, s->bb_lo.p, s->bb_hi.p, inv_c, s->offs.p, mask,
-                                                            sb.k0.p, sb.v0.p, s->ent_cell.p, s->ent_prim.p);
+    entry_insert_kernel<<<nblocks(E.n), kBlock, 0, s->st>>>(E, R.ekind, s->bb_lo.p, s->bb_hi.p, inv_c, s->offs.p,
+                                                            mask, sb.k0.p, sb.v0.p, s->ent_cell.p, s->ent_prim.p,
+                                                            s->ent_body.p, s->tris.p, s->edges.p, s->sv_body.p);
     k_radix_sort(s, sb, total, bits_for(mask));
     // sorted copies live in the second halves of ent_cell / ent_prim
     entry_permute_kernel<<<nblocks(total), kBlock, 0, s->st>>>((int)total, sb.v0.p, s->ent_cell.p, s->ent_prim.p,
-                                                               s->ent_cell.p + total, s->ent_prim.p + total);
+                                                               s->ent_body.p, s->ent_cell.p + total,
+                                                               s->ent_prim.p + total, s->ent_body.p + total);
   }
   ZCHK(hipMemsetAsync(s->bucket_lo.p, 0, sizeof(int) * tsize, s->st));
   ZCHK(hipMemsetAsync(s->bucket_hi.p, 0, sizeof(int) * tsize, s->st));
@@ -291,7 +303,7 @@ static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>
     kt_begin(s, KT_QUERY);
     query_kernel<<<nblocks(Q.n, 128), 128, 0, s->st>>>(
         Q, E, R, s->bb_lo.p, s->bb_hi.p, inv_c, mask, s->bucket_lo.p, s->bucket_hi.p, s->ent_cell.p + total,
-        s->ent_prim.p + total, s->big_list.p, s->tris.p, s->edges.p, s->sv_body.p, s->body_fixed.p, nE,
+        s->ent_prim.p + total, s->ent_body.p + total, s->big_list.p, s->tris.p, s->edges.p, s->sv_body.p, s->body_fixed.p, nE,
         s->pair_keys.p, counter, cap);
     kt_end(s, KT_QUERY);
     big_entry_kernel<<<std::min(E.n, 1024), kBlock, 0, s->st>>>(Q, E, R, s->bb_lo.p, s->bb_hi.p, s->big_list.p, s->tris.p, s->edges.p,
@@ -313,6 +325,19 @@ static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>
     s->pair_keys.reserve((size_t)n + n / 4 + 1024);
   }
   throw Error(ZEMA_E_CAPACITY, "candidate buffer growth failed");
+}
+
+// inter-body (edge, triangle) pairs whose exact (uninflated) boxes overlap at xs
+int64_t k_edge_tri_pairs(zema_scene* s, const double* xs, DBuf<int>& out) {
+  int nv = s->nsurf, nt = s->ntri, ne = s->nedge;
+  int np = nv + nt + ne;
+  s->bb_lo.reserve(3 * (size_t)np);
+  s->bb_hi.reserve(3 * (size_t)np);
+  if (s->pair_keys.cap < 4096) s->pair_keys.reserve(1 << 16);
+  if (np)
+    boxes_kernel<<<nblocks(np), kBlock, 0, s->st>>>(nv, nt, ne, s->tris.p, s->edges.p, xs, xs, 0.0, s->bb_lo.p,
+                                                    s->bb_hi.p);
+  return search(s, PrimSet{nv + nt, ne}, PrimSet{nv, nt}, PairRule{2, 1, 0}, out);
 }
 
 void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r) {

@@ -123,25 +123,8 @@ __global__ void friction_fill_kernel(int npt, int nee, const int* __restrict__ p
   V3 c0, c1;
   double m = 1.0;
   if (kind == 0) {
-    int t = pt_type(x[0], x[1], x[2], x[3]);
-    double b[3] = {0, 0, 0};
-    if (t <= 2) {
-      b[t] = 1.0;
-    } else if (t <= 5) {
-      int i = t - 3, j = (i + 1) % 3;
-      V3 e = x[1 + j] - x[1 + i];
-      double s = dot(x[0] - x[1 + i], e) / dot(e, e);
-      s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
-      b[i] = 1.0 - s;
-      b[j] = s;
-    } else {
-      V3 u = x[2] - x[1], v = x[3] - x[1], ww = x[0] - x[1];
-      V3 n = cross(u, v);
-      double nn = dot(n, n);
-      b[1] = dot(cross(ww, v), n) / nn;
-      b[2] = dot(cross(u, ww), n) / nn;
-      b[0] = 1.0 - b[1] - b[2];
-    }
+    double b[3];
+    pt_closest_bary(x, b);
     w[0] = 1.0;
     w[1] = -b[0];
     w[2] = -b[1];
@@ -225,73 +208,6 @@ __device__ inline int ent_dofs(const Ent& E) {
   return t;
 }
 
-// 3x3 Jacobian of slot position w.r.t. node j of its entity: I, or e_{j-1} x0^T
-__device__ inline void node_jac(int nn, int j, V3 x0, double J[3][3]) {
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) J[r][c] = 0.0;
-  if (nn == 1 || j == 0) {
-    J[0][0] = J[1][1] = J[2][2] = 1.0;
-  } else {
-    J[j - 1][0] = x0.x;
-    J[j - 1][1] = x0.y;
-    J[j - 1][2] = x0.z;
-  }
-}
-
-// Write gradient entries and (optionally) all node-pair Hessian blocks of one item.
-__device__ inline void emit_item(const Ent& E, const int sv[4], const double* __restrict__ sv_x0, const double* g12,
-                                 double (*H)[12], int nn_total, unsigned long long* __restrict__ key,
-                                 double* __restrict__ val, int o) {
-  V3 x0[4];
-  for (int a = 0; a < 4; ++a) x0[a] = ld3(sv_x0 + 3 * sv[a]);
-  unsigned long long W = (unsigned long long)nn_total + 1;
-  // gradient
-  for (int e = 0; e < E.n; ++e)
-    for (int j = 0; j < E.nn[e]; ++j) {
-      double acc[3] = {0, 0, 0};
-      for (int a = 0; a < 4; ++a) {
-        if (E.of_slot[a] != e) continue;
-        double J[3][3];
-        node_jac(E.nn[e], j, x0[a], J);
-        for (int c = 0; c < 3; ++c)
-          for (int r = 0; r < 3; ++r) acc[c] += J[r][c] * g12[3 * a + r];
-      }
-      key[o] = (unsigned long long)(E.node0[e] + j) * W + (unsigned long long)nn_total;
-      for (int c = 0; c < 3; ++c) val[(size_t)9 * o + c] = acc[c];
-      for (int c = 3; c < 9; ++c) val[(size_t)9 * o + c] = 0.0;
-      ++o;
-    }
-  if (!H) return;
-  for (int e = 0; e < E.n; ++e)
-    for (int j = 0; j < E.nn[e]; ++j)
-      for (int f = 0; f < E.n; ++f)
-        for (int l = 0; l < E.nn[f]; ++l) {
-          double K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-          for (int a = 0; a < 4; ++a) {
-            if (E.of_slot[a] != e) continue;
-            double Ja[3][3];
-            node_jac(E.nn[e], j, x0[a], Ja);
-            for (int b = 0; b < 4; ++b) {
-              if (E.of_slot[b] != f) continue;
-              double Jb[3][3];
-              node_jac(E.nn[f], l, x0[b], Jb);
-              // K += Ja^T P_ab Jb
-              double PJ[3][3];
-              for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c)
-                  PJ[r][c] = H[3 * a + r][3 * b] * Jb[0][c] + H[3 * a + r][3 * b + 1] * Jb[1][c] +
-                             H[3 * a + r][3 * b + 2] * Jb[2][c];
-              for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) K[r][c] += Ja[0][r] * PJ[0][c] + Ja[1][r] * PJ[1][c] + Ja[2][r] * PJ[2][c];
-            }
-          }
-          key[o] = (unsigned long long)(E.node0[e] + j) * W + (unsigned long long)(E.node0[f] + l);
-          for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) val[(size_t)9 * o + 3 * r + c] = K[r][c];
-          ++o;
-        }
-}
-
 // item i < n_act: barrier pair act_idx[i]; else friction pair i - n_act
 struct ItemArgs {
   int npt, nee, n_act, nfric;
@@ -336,8 +252,11 @@ __global__ void item_count_kernel(ItemArgs A, int* __restrict__ cnt) {
   cnt[i] = nd + (A.hess ? nd * nd : 0);
 }
 
-__global__ void __launch_bounds__(64) item_emit_kernel(ItemArgs A, const int* __restrict__ offs,
-                                                       unsigned long long* __restrict__ key, double* __restrict__ val) {
+// K1: one lane per item: gradient (12) and full 12x12 Hessian in x-space.  Barrier
+// pairs store the unprojected Hessian (projected by K2); friction Hessians are PSD by
+// construction.
+__global__ void __launch_bounds__(64) pair_deriv_kernel(ItemArgs A, double* __restrict__ hout,
+                                                        double* __restrict__ gout) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n_act + A.nfric) return;
   int kind, sv[4], ea, eb;
@@ -351,7 +270,6 @@ __global__ void __launch_bounds__(64) item_emit_kernel(ItemArgs A, const int* __
     double eps = kind == 1 ? 1e-3 * A.elen2[ea] * A.elen2[eb] : 0.0;
     double E, d;
     pair_barrier(kind, x, eps, A.kappa, A.dhat, E, g, H, &d);
-    if (A.hess) psd_project<12>(H);
   } else {
     int f = i - A.n_act;
     const double* fv = A.fvals + 8 * f;
@@ -365,15 +283,182 @@ __global__ void __launch_bounds__(64) item_emit_kernel(ItemArgs A, const int* __
       for (int r = 0; r < 3; ++r) g[3 * a + r] = c * f1y * fv[4 + a] * U[r];
     double core[3][3];
     for (int r = 0; r < 3; ++r)
-      for (int s = 0; s < 3; ++s) core[r][s] = al * ((r == s ? 1.0 : 0.0) - N[r] * N[s]) - be * U[r] * U[s];
+      for (int q = 0; q < 3; ++q) core[r][q] = al * ((r == q ? 1.0 : 0.0) - N[r] * N[q]) - be * U[r] * U[q];
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b)
         for (int r = 0; r < 3; ++r)
-          for (int s = 0; s < 3; ++s) H[3 * a + r][3 * b + s] = c * fv[4 + a] * fv[4 + b] * core[r][s];
+          for (int q = 0; q < 3; ++q) H[3 * a + r][3 * b + q] = c * fv[4 + a] * fv[4 + b] * core[r][q];
   }
+  for (int k = 0; k < 12; ++k) gout[(size_t)12 * i + k] = g[k];
+  if (A.hess)
+    for (int r = 0; r < 12; ++r)
+      for (int q = 0; q < 12; ++q) hout[(size_t)144 * i + 12 * r + q] = H[r][q];
+}
+
+// Round-robin (circle) ordering of the 66 index pairs of a 12x12 matrix: in round r
+// the six pairs (L_k, L_{11-k}) are disjoint, L_0 = 0, L_i = ((i - 1 + r) mod 11) + 1.
+__device__ inline int rr_index(int r, int i) { return i == 0 ? 0 : ((i - 1 + r) % 11) + 1; }
+
+// K2: one wavefront (block of 64) per item.  Barrier Hessians are projected to PSD by
+// parallel cyclic Jacobi in LDS (six disjoint rotations per round, the update
+// A <- J^T A J and V <- V J applied to all 144 entries by the 64 lanes); then the
+// item's node-pair blocks J_a^T P_ab J_b and gradient entries J_a^T g_a are emitted
+// with the lanes splitting the blocks.
+constexpr int LDA = 13;
+__global__ void __launch_bounds__(64) project_emit_kernel(ItemArgs A, const double* __restrict__ hin,
+                                                          const double* __restrict__ gin,
+                                                          const int* __restrict__ offs,
+                                                          unsigned long long* __restrict__ key,
+                                                          double* __restrict__ val) {
+  __shared__ double M[12 * LDA], Vm[12 * LDA], G[12], X0[12];
+  __shared__ double cs[12][2];  // per index: c and the signed partner coefficient
+  __shared__ int partner[12];
+  const int i = blockIdx.x, lane = threadIdx.x;
+  if (i >= A.n_act + A.nfric) return;
+  int kind, sv[4], ea, eb;
+  bool fric;
+  item_slots(A, i, kind, sv, ea, eb, fric);
+  if (lane < 12) {
+    G[lane] = gin[(size_t)12 * i + lane];
+    X0[lane] = A.sv_x0[3 * sv[lane / 3] + lane % 3];
+  }
+  if (A.hess) {
+    for (int e = lane; e < 144; e += 64) {
+      int r = e / 12, c = e % 12;
+      M[r * LDA + c] = hin[(size_t)144 * i + e];
+      Vm[r * LDA + c] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (!fric) {
+      double fro = 0.0;
+      for (int e = lane; e < 144; e += 64) fro += M[(e / 12) * LDA + e % 12] * M[(e / 12) * LDA + e % 12];
+      fro = wave_sum(fro);
+      for (int sweep = 0; sweep < 20; ++sweep) {
+        double off = 0.0;
+        for (int e = lane; e < 144; e += 64) {
+          int r = e / 12, c = e % 12;
+          if (r < c) off += M[r * LDA + c] * M[r * LDA + c];
+        }
+        off = wave_sum(off);
+        if (!(off > 1e-34 * fro)) break;
+        for (int rd = 0; rd < 11; ++rd) {
+          if (lane < 6) {
+            int p = rr_index(rd, lane), q = rr_index(rd, 11 - lane);
+            double apq = M[p * LDA + q], c = 1.0, sn = 0.0;
+            if (apq != 0.0) {
+              double th = (M[q * LDA + q] - M[p * LDA + p]) / (2.0 * apq);
+              double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+              c = 1.0 / sqrt(t * t + 1.0);
+              sn = t * c;
+            }
+            // column p of J: (p: c, q: -s); column q of J: (p: s, q: c)
+            partner[p] = q;
+            partner[q] = p;
+            cs[p][0] = c;
+            cs[p][1] = -sn;
+            cs[q][0] = c;
+            cs[q][1] = sn;
+          }
+          __syncthreads();
+          double na[3], nv[3];
+          int cnt = 0;
+          for (int e = lane; e < 144; e += 64, ++cnt) {
+            int r = e / 12, c = e % 12;
+            int rp = partner[r], cp = partner[c];
+            double jrr = cs[r][0], jpr = cs[r][1];  // J[r][r], J[rp][r]
+            double jcc = cs[c][0], jpc = cs[c][1];  // J[c][c], J[cp][c]
+            // (A J)[k][c] for k in {r, rp}
+            double arc = M[r * LDA + c] * jcc + M[r * LDA + cp] * jpc;
+            double apc = M[rp * LDA + c] * jcc + M[rp * LDA + cp] * jpc;
+            na[cnt] = jrr * arc + jpr * apc;
+            nv[cnt] = Vm[r * LDA + c] * jcc + Vm[r * LDA + cp] * jpc;
+          }
+          __syncthreads();
+          cnt = 0;
+          for (int e = lane; e < 144; e += 64, ++cnt) {
+            M[(e / 12) * LDA + e % 12] = na[cnt];
+            Vm[(e / 12) * LDA + e % 12] = nv[cnt];
+          }
+          __syncthreads();
+        }
+      }
+      // P = V max(Lambda, 0) V^T
+      double pv[3];
+      int cnt = 0;
+      for (int e = lane; e < 144; e += 64, ++cnt) {
+        int r = e / 12, c = e % 12;
+        double acc = 0.0;
+        for (int k = 0; k < 12; ++k) {
+          double l = M[k * LDA + k];
+          if (l > 0.0) acc += l * Vm[r * LDA + k] * Vm[c * LDA + k];
+        }
+        pv[cnt] = acc;
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int e = lane; e < 144; e += 64, ++cnt) M[(e / 12) * LDA + e % 12] = pv[cnt];
+    }
+  }
+  __syncthreads();
+  // node list of the item: entities (soft vertex: one node; free affine body: p, a1..a3)
   Ent E;
   entities(sv, A.sv_ref, A.bi, E);
-  emit_item(E, sv, A.sv_x0, g, A.hess ? H : nullptr, A.nn_total, key, val, offs[i]);
+  int nd = ent_dofs(E);
+  int ntot = nd + (A.hess ? nd * nd : 0);
+  unsigned long long W = (unsigned long long)A.nn_total + 1;
+  int o0 = offs[i];
+  for (int t = lane; t < ntot; t += 64) {
+    int o = o0 + t;
+    if (t < nd) {
+      int e = 0, j = t;
+      while (j >= E.nn[e]) j -= E.nn[e++];
+      double acc[3] = {0, 0, 0};
+      for (int a = 0; a < 4; ++a) {
+        if (E.of_slot[a] != e) continue;
+        if (E.nn[e] == 1 || j == 0) {
+          for (int c = 0; c < 3; ++c) acc[c] += G[3 * a + c];
+        } else {
+          double gr = G[3 * a + j - 1];
+          for (int c = 0; c < 3; ++c) acc[c] += X0[3 * a + c] * gr;
+        }
+      }
+      key[o] = (unsigned long long)(E.node0[e] + j) * W + (unsigned long long)A.nn_total;
+      for (int c = 0; c < 3; ++c) val[(size_t)9 * o + c] = acc[c];
+      for (int c = 3; c < 9; ++c) val[(size_t)9 * o + c] = 0.0;
+    } else {
+      int bidx = t - nd, n = bidx / nd, m = bidx % nd;
+      int e = 0, j = n, f = 0, l = m;
+      while (j >= E.nn[e]) j -= E.nn[e++];
+      while (l >= E.nn[f]) l -= E.nn[f++];
+      bool Ij = (E.nn[e] == 1 || j == 0), Il = (E.nn[f] == 1 || l == 0);
+      double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int a = 0; a < 4; ++a) {
+        if (E.of_slot[a] != e) continue;
+        for (int b = 0; b < 4; ++b) {
+          if (E.of_slot[b] != f) continue;
+          const double* P = M + (3 * a) * LDA + 3 * b;  // P_ab[r][c] = P[r * LDA + c]
+          if (Ij && Il) {
+            for (int r = 0; r < 3; ++r)
+              for (int c = 0; c < 3; ++c) K[3 * r + c] += P[r * LDA + c];
+          } else if (Ij) {  // P_ab e_s x0_b^T
+            int sI = l - 1;
+            for (int r = 0; r < 3; ++r)
+              for (int c = 0; c < 3; ++c) K[3 * r + c] += P[r * LDA + sI] * X0[3 * b + c];
+          } else if (Il) {  // x0_a e_r^T P_ab
+            int rI = j - 1;
+            for (int r = 0; r < 3; ++r)
+              for (int c = 0; c < 3; ++c) K[3 * r + c] += X0[3 * a + r] * P[rI * LDA + c];
+          } else {  // P_ab[r][s] x0_a x0_b^T
+            double prs = P[(j - 1) * LDA + (l - 1)];
+            for (int r = 0; r < 3; ++r)
+              for (int c = 0; c < 3; ++c) K[3 * r + c] += prs * X0[3 * a + r] * X0[3 * b + c];
+          }
+        }
+      }
+      key[o] = (unsigned long long)(E.node0[e] + j) * W + (unsigned long long)(E.node0[f] + l);
+      for (int q = 0; q < 9; ++q) val[(size_t)9 * o + q] = K[q];
+    }
+  }
 }
 
 // segment heads of sorted keys: head[j] = 1 if key differs from the previous one;
@@ -393,24 +478,27 @@ __global__ void seg_start_kernel(int n, const int* __restrict__ head, const int*
   if (j < n && head[j]) start[sid[j]] = j;
 }
 
-// one lane per segment: sum in sorted order; gradient keys add into grad, Hessian
-// keys become CSR entries
+// one wavefront per segment: lanes sum strided entries in sorted order, then a fixed
+// shuffle tree; gradient keys add into grad, Hessian keys become CSR entries
+template <class T>
 __global__ void seg_reduce_kernel(int nseg, int n, const int* __restrict__ start, const unsigned long long* __restrict__ k,
                                   const int* __restrict__ perm, const double* __restrict__ val, unsigned long long W,
                                   const int* __restrict__ hid, double* __restrict__ grad, int* __restrict__ crow,
-                                  int* __restrict__ ccol, double* __restrict__ cval, int nnzc) {
-  int u = blockIdx.x * blockDim.x + threadIdx.x;
+                                  int* __restrict__ ccol, T* __restrict__ cval, int nnzc) {
+  int u = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
   if (u >= nseg) return;
   int j0 = start[u], j1 = u + 1 < nseg ? start[u + 1] : n;
   unsigned long long key = k[j0];
   int row = (int)(key / W), col = (int)(key % W);
-  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   bool is_grad = (unsigned long long)col == W - 1;
-  int nq = is_grad ? 3 : 9;
-  for (int j = j0; j < j1; ++j) {
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = j0 + lane; j < j1; j += 64) {
     const double* v = val + (size_t)9 * perm[j];
-    for (int q = 0; q < nq; ++q) acc[q] += v[q];
+    for (int q = 0; q < 9; ++q) acc[q] += v[q];
   }
+  for (int q = 0; q < 9; ++q) acc[q] = wave_sum(acc[q]);
+  if (lane != 0) return;
   if (is_grad) {
     if (grad)
       for (int q = 0; q < 3; ++q) grad[3 * row + q] += acc[q];
@@ -418,7 +506,7 @@ __global__ void seg_reduce_kernel(int nseg, int n, const int* __restrict__ start
     int h = hid[j0];
     crow[h] = row;
     ccol[h] = col;
-    for (int q = 0; q < 9; ++q) cval[(size_t)q * nnzc + h] = acc[q];
+    for (int q = 0; q < 9; ++q) cval[(size_t)q * nnzc + h] = T(acc[q]);
   }
 }
 
@@ -527,12 +615,19 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   s->trip_off.reserve(nitems + 1);
   item_count_kernel<<<nblocks(nitems), kBlock, 0, s->st>>>(A, s->trip_cnt.p);
   int64_t ntrip = k_exclusive_scan(s, s->trip_cnt.p, s->trip_off.p, nitems);
+  if (ntrip == 0) {  // every item touches only fixed bodies
+    ZCHK(hipMemsetAsync(s->c_ptr.p, 0, sizeof(int) * (s->nnodes + 1), s->st));
+    return;
+  }
   SortBufs& sb = s->sort;
   sb.k0.reserve(ntrip + 1);
   sb.v0.reserve(ntrip + 1);
   s->trip_val.reserve((size_t)9 * ntrip + 9);
+  s->item_h.reserve((size_t)144 * nitems + 144);
+  s->item_g.reserve((size_t)12 * nitems + 12);
+  pair_deriv_kernel<<<nblocks(nitems, 64), 64, 0, s->st>>>(A, s->item_h.p, s->item_g.p);
   kt_begin(s, KT_CONTACT);
-  item_emit_kernel<<<nblocks(nitems, 64), 64, 0, s->st>>>(A, s->trip_off.p, sb.k0.p, s->trip_val.p);
+  project_emit_kernel<<<nitems, 64, 0, s->st>>>(A, s->item_h.p, s->item_g.p, s->trip_off.p, sb.k0.p, s->trip_val.p);
   kt_end(s, KT_CONTACT);
   k_iota(s, sb.v0.p, ntrip);  // sort values = triplet ids
   unsigned long long W = (unsigned long long)s->nnodes + 1;
@@ -552,9 +647,16 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   s->c_col.reserve(nh + 1);
   s->c_val.reserve((size_t)9 * nh + 9);
   s->seg_row.reserve(nh + 1);
-  seg_reduce_kernel<<<nblocks(nseg), kBlock, 0, s->st>>>((int)nseg, (int)ntrip, s->seg_start.p, sb.k0.p, sb.v0.p,
-                                                         s->trip_val.p, W, hhead, grad, s->seg_row.p, s->c_col.p,
-                                                         s->c_val.p, (int)nh);
+  if (s->mixed) {
+    s->c_val32.reserve((size_t)9 * nh + 9);
+    seg_reduce_kernel<float><<<nblocks(nseg, 4), kBlock, 0, s->st>>>((int)nseg, (int)ntrip, s->seg_start.p, sb.k0.p,
+                                                                     sb.v0.p, s->trip_val.p, W, hhead, grad,
+                                                                     s->seg_row.p, s->c_col.p, s->c_val32.p, (int)nh);
+  } else {
+    seg_reduce_kernel<double><<<nblocks(nseg, 4), kBlock, 0, s->st>>>((int)nseg, (int)ntrip, s->seg_start.p, sb.k0.p,
+                                                                      sb.v0.p, s->trip_val.p, W, hhead, grad,
+                                                                      s->seg_row.p, s->c_col.p, s->c_val.p, (int)nh);
+  }
   row_ptr_kernel<<<nblocks(s->nnodes + 1), kBlock, 0, s->st>>>(s->nnodes, (int)nh, s->seg_row.p, s->c_ptr.p);
 }
 

@@ -29,13 +29,14 @@ __device__ inline void load_tet(int e, int nt, const int4* __restrict__ tets, co
       F[i][j] = (x[1][i] - x[0][i]) * D[0][j] + (x[2][i] - x[0][i]) * D[1][j] + (x[3][i] - x[0][i]) * D[2][j];
 }
 
+template <class T>
 __global__ void __launch_bounds__(128) tet_assemble_kernel(int nt, const int4* __restrict__ tets,
                                                             const double* __restrict__ Dmi,
                                                             const double* __restrict__ h2vol,
                                                             const double* __restrict__ lmu,
                                                             const double* __restrict__ llam,
                                                             const double* __restrict__ y, double* __restrict__ e_out,
-                                                            double* __restrict__ g_out, double* __restrict__ h_out,
+                                                            double* __restrict__ g_out, T* __restrict__ h_out,
                                                             int want_h) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nt) return;
@@ -43,10 +44,10 @@ __global__ void __launch_bounds__(128) tet_assemble_kernel(int nt, const int4* _
   int4 t;
   load_tet(e, nt, tets, Dmi, y, F, G, t);
   double g[12];
-  double* hb = want_h ? h_out + (size_t)90 * e : nullptr;
-  double E = nh_element(F, G, lmu[e], llam[e], h2vol[e], g, hb);
+  double E = nh_element(F, G, lmu[e], llam[e], h2vol[e], g, nullptr);
   e_out[e] = E;
   for (int k = 0; k < 12; ++k) g_out[(size_t)12 * e + k] = g[k];
+  if (want_h && E < INFINITY) nh_hess_blocks<T>(F, G, lmu[e], llam[e], h2vol[e], h_out + (size_t)90 * e);
 }
 
 __global__ void tet_energy_kernel(int nt, const int4* __restrict__ tets, const double* __restrict__ Dmi,
@@ -97,30 +98,31 @@ __device__ inline int upper_index(int a, int b) {
 
 // static BSR blocks of soft rows: sum of tet blocks (list order = tet order) and
 // the inertia mass on the diagonal
+template <class T>
 __global__ void gather_hess_kernel(int nnzb_soft, const int* __restrict__ brow, const int* __restrict__ bcol,
                                    const int* __restrict__ hc_ptr, const int* __restrict__ hc_list,
-                                   const double* __restrict__ h_tet, const double* __restrict__ mass,
-                                   double* __restrict__ val, int nnzb, unsigned mask) {
+                                   const T* __restrict__ h_tet, const double* __restrict__ mass,
+                                   T* __restrict__ val, int nnzb, unsigned mask) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nnzb_soft) return;
-  double acc[9];
-  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  T acc[9];
+  for (int k = 0; k < 9; ++k) acc[k] = T(0);
   if (mask & 2u)
     for (int k = hc_ptr[j]; k < hc_ptr[j + 1]; ++k) {
       int ent = hc_list[k];
       int e = ent >> 4, a = (ent >> 2) & 3, b = ent & 3;
       if (a <= b) {
-        const double* h = h_tet + (size_t)90 * e + 9 * upper_index(a, b);
+        const T* h = h_tet + (size_t)90 * e + 9 * upper_index(a, b);
         for (int q = 0; q < 9; ++q) acc[q] += h[q];
       } else {
-        const double* h = h_tet + (size_t)90 * e + 9 * upper_index(b, a);
+        const T* h = h_tet + (size_t)90 * e + 9 * upper_index(b, a);
         for (int r = 0; r < 3; ++r)
           for (int c = 0; c < 3; ++c) acc[3 * r + c] += h[3 * c + r];
       }
     }
   int row = brow[j];
   if ((mask & 1u) && bcol[j] == row) {
-    double m = mass[row];
+    T m = T(mass[row]);
     acc[0] += m;
     acc[4] += m;
     acc[8] += m;
@@ -139,10 +141,15 @@ __global__ void inertia_energy_kernel(int nsv, const double* __restrict__ mass, 
 void k_tet_assemble(zema_scene* s, const double* y, bool hess) {
   if (!s->nt) return;
   kt_begin(s, KT_TET);
-  tet_assemble_kernel<<<nblocks(s->nt, 128), 128, 0, s->st>>>(s->nt, s->tets.p, s->Dmi.p, s->h2vol.p, s->lmu.p,
-                                                              s->llam.p, y, s->e_tet.p, s->g_tet.p, s->h_tet.p,
-                                                              hess ? 1 : 0);
-  kt_end(s, KT_TET, 320.0 * s->nt);
+  if (s->mixed)
+    tet_assemble_kernel<float><<<nblocks(s->nt, 128), 128, 0, s->st>>>(s->nt, s->tets.p, s->Dmi.p, s->h2vol.p,
+                                                                       s->lmu.p, s->llam.p, y, s->e_tet.p,
+                                                                       s->g_tet.p, s->h_tet32.p, hess ? 1 : 0);
+  else
+    tet_assemble_kernel<double><<<nblocks(s->nt, 128), 128, 0, s->st>>>(s->nt, s->tets.p, s->Dmi.p, s->h2vol.p,
+                                                                        s->lmu.p, s->llam.p, y, s->e_tet.p,
+                                                                        s->g_tet.p, s->h_tet.p, hess ? 1 : 0);
+  kt_end(s, KT_TET, (s->mixed ? 170.0 : 320.0) * s->nt);
 }
 
 void k_tet_energy(zema_scene* s, const double* y) {
@@ -158,13 +165,17 @@ void k_gather_grad_soft(zema_scene* s, const double* y, double* grad, unsigned m
 }
 
 void k_gather_hess_static(zema_scene* s, unsigned mask) {
-  int nsoft_blocks = 0;
   // soft rows come first in node order
-  nsoft_blocks = s->nsv ? s->bsr_row_soft_end : 0;
+  int nsoft_blocks = s->nsv ? s->bsr_row_soft_end : 0;
   if (!nsoft_blocks) return;
-  gather_hess_kernel<<<nblocks(nsoft_blocks), kBlock, 0, s->st>>>(nsoft_blocks, s->bsr_row.p, s->bsr_col.p,
-                                                                  s->hc_ptr.p, s->hc_list.p, s->h_tet.p, s->mass.p,
-                                                                  s->bsr_val.p, s->nnzb, mask);
+  if (s->mixed)
+    gather_hess_kernel<float><<<nblocks(nsoft_blocks), kBlock, 0, s->st>>>(nsoft_blocks, s->bsr_row.p, s->bsr_col.p,
+                                                                          s->hc_ptr.p, s->hc_list.p, s->h_tet32.p,
+                                                                          s->mass.p, s->bsr_val32.p, s->nnzb, mask);
+  else
+    gather_hess_kernel<double><<<nblocks(nsoft_blocks), kBlock, 0, s->st>>>(nsoft_blocks, s->bsr_row.p, s->bsr_col.p,
+                                                                           s->hc_ptr.p, s->hc_list.p, s->h_tet.p,
+                                                                           s->mass.p, s->bsr_val.p, s->nnzb, mask);
 }
 
 void k_inertia_energy(zema_scene* s, const double* y, double* e_out) {

@@ -14,92 +14,105 @@ namespace zema {
 
 constexpr int RG = 16;  // lanes per soft row
 
+// matrix with block values of type V (double, or float for the mixed-precision
+// form, where products also accumulate in float)
+template <class V>
 struct Mat {
   int nsv, nnodes, nnzb, nnzc;
   const int *bp, *bc, *cp, *cc;
-  const double *bv, *cv;
+  const V *bv, *cv;
 };
 
-struct Vec {
-  const double* a;  // value = a + beta * b (b may be null)
-  const double* b;
-  const double* beta;
-  __device__ inline V3 at(int j) const {
-    V3 v = ld3(a + 3 * j);
-    if (b) {
-      double be = *beta;
-      V3 w = ld3(b + 3 * j);
-      v = v + be * w;
-    }
-    return v;
+template <class V>
+struct Acc3 {
+  V x, y, z;
+};
+
+// x = a + beta b at node c (DOF vectors stay FP64; converted to V for the product)
+template <class V>
+__device__ inline void blk_acc(const V* __restrict__ v, int stride, int j, const double* a, const double* b,
+                               double beta, int c, Acc3<V>& acc) {
+  double u0 = a[3 * c], u1 = a[3 * c + 1], u2 = a[3 * c + 2];
+  if (b) {
+    u0 += beta * b[3 * c];
+    u1 += beta * b[3 * c + 1];
+    u2 += beta * b[3 * c + 2];
   }
-};
-
-__device__ inline V3 blk_mul(const double* v, int stride, int j, V3 x) {
-  return v3(v[j] * x.x + v[stride + j] * x.y + v[2 * stride + j] * x.z,
-            v[3 * stride + j] * x.x + v[4 * stride + j] * x.y + v[5 * stride + j] * x.z,
-            v[6 * stride + j] * x.x + v[7 * stride + j] * x.y + v[8 * stride + j] * x.z);
+  V x0 = V(u0), x1 = V(u1), x2 = V(u2);
+  acc.x += v[j] * x0 + v[stride + j] * x1 + v[2 * stride + j] * x2;
+  acc.y += v[3 * stride + j] * x0 + v[4 * stride + j] * x1 + v[5 * stride + j] * x2;
+  acc.z += v[6 * stride + j] * x0 + v[7 * stride + j] * x1 + v[8 * stride + j] * x2;
 }
 
-__device__ inline V3 row_partial(const Mat& M, int row, int lane, int nl, const Vec& x) {
-  V3 acc = v3(0, 0, 0);
-  for (int j = M.bp[row] + lane; j < M.bp[row + 1]; j += nl) acc = acc + blk_mul(M.bv, M.nnzb, j, x.at(M.bc[j]));
+template <class V>
+__device__ inline Acc3<V> row_partial(const Mat<V>& M, int row, int lane, int nl, const double* a, const double* b,
+                                      double beta) {
+  Acc3<V> acc{V(0), V(0), V(0)};
+  for (int j = M.bp[row] + lane; j < M.bp[row + 1]; j += nl) blk_acc(M.bv, M.nnzb, j, a, b, beta, M.bc[j], acc);
   if (M.cp)
-    for (int j = M.cp[row] + lane; j < M.cp[row + 1]; j += nl) acc = acc + blk_mul(M.cv, M.nnzc, j, x.at(M.cc[j]));
+    for (int j = M.cp[row] + lane; j < M.cp[row + 1]; j += nl) blk_acc(M.cv, M.nnzc, j, a, b, beta, M.cc[j], acc);
   return acc;
 }
 
-// out = H x; optionally writes xo = x (own rows) and block partials of x.out
-__global__ void spmv_kernel(Mat M, Vec x, double* __restrict__ out, double* __restrict__ xo,
-                            double* __restrict__ partial, const double* __restrict__ done) {
-  if (done && *done != 0.0) return;
-  __shared__ double sh[kBlock / 64];
-  __shared__ double red[3][kBlock / 64];
+// q = H x with x = a + beta b.  Writes xo = x for the rows it owns and the block
+// partial of x . q when those pointers are given.  Soft rows: 16 lanes each; affine
+// rows: one block each.
+template <class V>
+__device__ inline double spmv_rows(const Mat<V>& M, const double* a, const double* b, double beta, double* q,
+                                   double* xo, double* sh_red /* 3 * waves */) {
   int nsoft_blocks = (M.nsv + (kBlock / RG) - 1) / (kBlock / RG);
   double dotv = 0.0;
   if ((int)blockIdx.x < nsoft_blocks) {
     int row = blockIdx.x * (kBlock / RG) + threadIdx.x / RG;
     int lane = threadIdx.x % RG;
-    V3 acc = v3(0, 0, 0);
-    if (row < M.nsv) acc = row_partial(M, row, lane, RG, x);
+    Acc3<V> acc{V(0), V(0), V(0)};
+    if (row < M.nsv) acc = row_partial(M, row, lane, RG, a, b, beta);
     for (int o = RG / 2; o > 0; o >>= 1) {
       acc.x += __shfl_xor(acc.x, o, RG);
       acc.y += __shfl_xor(acc.y, o, RG);
       acc.z += __shfl_xor(acc.z, o, RG);
     }
     if (lane == 0 && row < M.nsv) {
-      st3(out + 3 * row, acc);
-      V3 xv = x.at(row);
+      V3 qv = v3(double(acc.x), double(acc.y), double(acc.z));
+      st3(q + 3 * row, qv);
+      V3 xv = ld3(a + 3 * row);
+      if (b) xv = xv + beta * ld3(b + 3 * row);
       if (xo) st3(xo + 3 * row, xv);
-      dotv = dot(xv, acc);
+      dotv = dot(xv, qv);
     }
   } else {
     int row = M.nsv + (blockIdx.x - nsoft_blocks);
-    V3 acc = row_partial(M, row, threadIdx.x, kBlock, x);
-    acc.x = wave_sum(acc.x);
-    acc.y = wave_sum(acc.y);
-    acc.z = wave_sum(acc.z);
+    Acc3<V> acc = row_partial(M, row, threadIdx.x, kBlock, a, b, beta);
+    for (int o = 32; o > 0; o >>= 1) {
+      acc.x += __shfl_xor(acc.x, o, 64);
+      acc.y += __shfl_xor(acc.y, o, 64);
+      acc.z += __shfl_xor(acc.z, o, 64);
+    }
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) {
-      red[0][w] = acc.x;
-      red[1][w] = acc.y;
-      red[2][w] = acc.z;
+      sh_red[3 * w] = double(acc.x);
+      sh_red[3 * w + 1] = double(acc.y);
+      sh_red[3 * w + 2] = double(acc.z);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      V3 s = v3(0, 0, 0);
-      for (int k = 0; k < kBlock / 64; ++k) s = s + v3(red[0][k], red[1][k], red[2][k]);
-      st3(out + 3 * row, s);
-      V3 xv = x.at(row);
+      V3 sq = v3(0, 0, 0);
+      for (int k = 0; k < kBlock / 64; ++k) sq = sq + v3(sh_red[3 * k], sh_red[3 * k + 1], sh_red[3 * k + 2]);
+      st3(q + 3 * row, sq);
+      V3 xv = ld3(a + 3 * row);
+      if (b) xv = xv + beta * ld3(b + 3 * row);
       if (xo) st3(xo + 3 * row, xv);
-      dotv = dot(xv, s);
+      dotv = dot(xv, sq);
     }
     __syncthreads();
   }
-  if (partial) {
-    double r = block_sum<kBlock>(dotv, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
-  }
+  return dotv;
+}
+
+template <class V>
+__global__ void spmv_kernel(Mat<V> M, const double* __restrict__ x, double* __restrict__ out) {
+  __shared__ double red[3 * (kBlock / 64)];
+  spmv_rows(M, x, nullptr, 0.0, out, nullptr, red);
 }
 
 // ------------------------------------------------------------------ preconditioner
@@ -114,18 +127,19 @@ __device__ inline int find_col(const int* cc, int j0, int j1, int col) {
   return j0;
 }
 
-__device__ inline void add_block(const Mat& M, int row, int col, double* D, int ld, int r0, int c0) {
+template <class V>
+__device__ inline void add_block(const Mat<V>& M, int row, int col, double* D, int ld, int r0, int c0) {
   // static
   int j0 = M.bp[row], j1 = M.bp[row + 1];
   int j = find_col(M.bc, j0, j1, col);
   if (j < j1 && M.bc[j] == col)
-    for (int q = 0; q < 9; ++q) D[(r0 + q / 3) * ld + c0 + q % 3] += M.bv[(size_t)q * M.nnzb + j];
+    for (int q = 0; q < 9; ++q) D[(r0 + q / 3) * ld + c0 + q % 3] += double(M.bv[(size_t)q * M.nnzb + j]);
   if (M.cp) {
     j0 = M.cp[row];
     j1 = M.cp[row + 1];
     j = find_col(M.cc, j0, j1, col);
     if (j < j1 && M.cc[j] == col)
-      for (int q = 0; q < 9; ++q) D[(r0 + q / 3) * ld + c0 + q % 3] += M.cv[(size_t)q * M.nnzc + j];
+      for (int q = 0; q < 9; ++q) D[(r0 + q / 3) * ld + c0 + q % 3] += double(M.cv[(size_t)q * M.nnzc + j]);
   }
 }
 
@@ -146,7 +160,8 @@ __host__ __device__ inline bool inv3(const double* a, double* o) {
   return true;
 }
 
-__global__ void precond_soft_kernel(Mat M, double* __restrict__ minv, int* __restrict__ bad) {
+template <class V>
+__global__ void precond_soft_kernel(Mat<V> M, double* __restrict__ minv, int* __restrict__ bad) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M.nsv) return;
   double D[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, I[9];
@@ -158,55 +173,62 @@ __global__ void precond_soft_kernel(Mat M, double* __restrict__ minv, int* __res
   for (int q = 0; q < 9; ++q) minv[(size_t)q * M.nsv + i] = I[q];
 }
 
-// 12x12 inverse by Gauss-Jordan with partial pivoting, one lane per affine body
-__global__ void precond_body_kernel(Mat M, int nfree, double* __restrict__ minv, int* __restrict__ bad) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
+// 12x12 inverse of an affine body's diagonal block by Gauss-Jordan with partial
+// pivoting: one wavefront per body, the augmented matrix [D | I] in LDS.
+template <class V>
+__global__ void __launch_bounds__(64) precond_body_kernel(Mat<V> M, int nfree, double* __restrict__ minv,
+                                                          int* __restrict__ bad) {
+  __shared__ double Aug[12][25];
+  __shared__ int piv_row;
+  int k = blockIdx.x, lane = threadIdx.x;
   if (k >= nfree) return;
   int node0 = M.nsv + 4 * k;
-  double A[144], I[144];
-  for (int q = 0; q < 144; ++q) {
-    A[q] = 0.0;
-    I[q] = (q % 13 == 0) ? 1.0 : 0.0;
+  for (int e = lane; e < 12 * 24; e += 64) {
+    int r = e / 24, c = e % 24;
+    Aug[r][c] = c >= 12 ? (c - 12 == r ? 1.0 : 0.0) : 0.0;
   }
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) add_block(M, node0 + r, node0 + c, A, 12, 3 * r, 3 * c);
+  __syncthreads();
+  if (lane < 16) add_block(M, node0 + lane / 4, node0 + lane % 4, &Aug[0][0], 25, 3 * (lane / 4), 3 * (lane % 4));
+  __syncthreads();
   for (int c = 0; c < 12; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < 12; ++r)
-      if (fabs(A[r * 12 + c]) > fabs(A[piv * 12 + c])) piv = r;
-    if (A[piv * 12 + c] == 0.0) {
-      atomicAdd(bad, 1);
+    if (lane == 0) {
+      int pr = c;
+      for (int r = c + 1; r < 12; ++r)
+        if (fabs(Aug[r][c]) > fabs(Aug[pr][c])) pr = r;
+      piv_row = pr;
+    }
+    __syncthreads();
+    int pr = piv_row;
+    if (Aug[pr][c] == 0.0) {
+      if (lane == 0) atomicAdd(bad, 1);
       return;
     }
-    if (piv != c)
-      for (int q = 0; q < 12; ++q) {
-        double t = A[c * 12 + q];
-        A[c * 12 + q] = A[piv * 12 + q];
-        A[piv * 12 + q] = t;
-        t = I[c * 12 + q];
-        I[c * 12 + q] = I[piv * 12 + q];
-        I[piv * 12 + q] = t;
-      }
-    double d = 1.0 / A[c * 12 + c];
-    for (int q = 0; q < 12; ++q) {
-      A[c * 12 + q] *= d;
-      I[c * 12 + q] *= d;
+    if (pr != c && lane < 24) {
+      double t = Aug[c][lane];
+      Aug[c][lane] = Aug[pr][lane];
+      Aug[pr][lane] = t;
     }
-    for (int r = 0; r < 12; ++r) {
-      if (r == c) continue;
-      double f = A[r * 12 + c];
-      if (f == 0.0) continue;
-      for (int q = 0; q < 12; ++q) {
-        A[r * 12 + q] -= f * A[c * 12 + q];
-        I[r * 12 + q] -= f * I[c * 12 + q];
-      }
+    __syncthreads();
+    double d = 1.0 / Aug[c][c];
+    __syncthreads();
+    if (lane < 24) Aug[c][lane] *= d;
+    __syncthreads();
+    // eliminate column c from every other row (factors read before any update)
+    double f[12];
+    for (int r = 0; r < 12; ++r) f[r] = Aug[r][c];
+    __syncthreads();
+    for (int e = lane; e < 12 * 24; e += 64) {
+      int r = e / 24, cc = e % 24;
+      if (r != c) Aug[r][cc] -= f[r] * Aug[c][cc];
     }
+    __syncthreads();
   }
-  for (int q = 0; q < 144; ++q) minv[(size_t)144 * k + q] = I[q];
+  for (int e = lane; e < 144; e += 64) minv[(size_t)144 * k + e] = Aug[e / 12][12 + e % 12];
 }
 
 // ------------------------------------------------------------------ PCG kernels
-// scalars: 0 rz, 1 pq, 2 alpha, 3 beta, 4 rr, 5 bb, 6 done, 7 iters, 8 breakdown, 9 tol2
+// scalars: 0/1 rz (ping-pong by iteration parity), 2 alpha, 4 rr, 5 bb, 6 done,
+// 7 iters, 8 breakdown, 9 tol^2 = rtol^2 bb
 __device__ inline void apply_minv(int i, int nsv, const double* __restrict__ ms, const double* __restrict__ mb,
                                   const double* __restrict__ r, double* __restrict__ z) {
   if (i < nsv) {
@@ -225,6 +247,26 @@ __device__ inline void apply_minv(int i, int nsv, const double* __restrict__ ms,
       zz[a] = acc;
     }
   }
+}
+
+// every block sums the same partials in the same order (deterministic, identical)
+__device__ inline void reduce_partials2(const double* __restrict__ partial, int nb, double* sh, double& a, double& b) {
+  double x = 0.0, y = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) {
+    x += partial[2 * i];
+    y += partial[2 * i + 1];
+  }
+  a = block_sum<kBlock>(x, sh);
+  b = block_sum<kBlock>(y, sh);
+  __shared__ double bc[2];
+  if (threadIdx.x == 0) {
+    bc[0] = a;
+    bc[1] = b;
+  }
+  __syncthreads();
+  a = bc[0];
+  b = bc[1];
+  __syncthreads();
 }
 
 __global__ void pcg_init_kernel(int nsv, int nfree, const double* __restrict__ b, const double* __restrict__ ms,
@@ -256,16 +298,11 @@ __global__ void pcg_init_kernel(int nsv, int nfree, const double* __restrict__ b
 
 __global__ void pcg_init_fin(int nb, const double* __restrict__ partial, double* __restrict__ sc, double rtol) {
   __shared__ double sh[kBlock / 64];
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kBlock) {
-    a += partial[2 * i];
-    b += partial[2 * i + 1];
-  }
-  double rz = block_sum<kBlock>(a, sh);
-  double bb = block_sum<kBlock>(b, sh);
+  double rz, bb;
+  reduce_partials2(partial, nb, sh, rz, bb);
   if (threadIdx.x == 0) {
     sc[0] = rz;
-    sc[3] = 0.0;
+    sc[1] = rz;
     sc[4] = bb;
     sc[5] = bb;
     sc[6] = bb == 0.0 ? 1.0 : 0.0;
@@ -275,107 +312,142 @@ __global__ void pcg_init_fin(int nb, const double* __restrict__ partial, double*
   }
 }
 
-__global__ void pcg_alpha_kernel(int nb, const double* __restrict__ partial, double* __restrict__ sc) {
+// Iteration k, first half: (k > 0) reduce the previous update's partials into
+// rz_k, rr_k, stop if converged, beta = rz_k / rz_{k-1}; then q = H p_k with
+// p_k = z + beta p_{k-1} formed in the gathers, p_k stored, partials of p_k . q.
+template <class V>
+__global__ void pcg_spmv_kernel(Mat<V> M, int k, int nbu, const double* __restrict__ upart,
+                                const double* __restrict__ z, const double* __restrict__ pold,
+                                double* __restrict__ pnew, double* __restrict__ q, double* __restrict__ spart,
+                                double* __restrict__ sc) {
   if (sc[6] != 0.0) return;
   __shared__ double sh[kBlock / 64];
-  double a = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kBlock) a += partial[i];
-  double pq = block_sum<kBlock>(a, sh);
-  if (threadIdx.x == 0) {
-    sc[1] = pq;
-    if (!(pq > 0.0)) {
-      sc[8] = 1.0;
-      sc[6] = 1.0;
-    } else {
-      sc[2] = sc[0] / pq;
+  __shared__ double red[3 * (kBlock / 64)];
+  __shared__ double beta_s;
+  if (k > 0) {
+    double rz, rr;
+    reduce_partials2(upart, nbu, sh, rz, rr);
+    bool conv = rr <= sc[9];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[7] = k;
+      sc[4] = rr;
+      sc[k & 1] = rz;
+      if (conv) sc[6] = 1.0;
     }
+    if (conv) return;
+    if (threadIdx.x == 0) beta_s = rz / sc[(k - 1) & 1];
+    __syncthreads();
+  } else {
+    if (threadIdx.x == 0) beta_s = 0.0;
+    __syncthreads();
   }
+  double dotv = spmv_rows(M, z, pold, beta_s, q, pnew, red);
+  double r = block_sum<kBlock>(dotv, sh);
+  if (threadIdx.x == 0) spart[blockIdx.x] = r;
 }
 
-__global__ void pcg_update_kernel(int nsv, int nfree, const double* __restrict__ p, const double* __restrict__ q,
+// Iteration k, second half: pq from the spmv partials, alpha = rz_k / pq (breakdown
+// if pq <= 0), x += alpha p, r -= alpha q, z = M^-1 r, partials of r.z and r.r.
+__global__ void pcg_update_kernel(int nsv, int nfree, int k, int nbs, const double* __restrict__ spart,
+                                  const double* __restrict__ p, const double* __restrict__ q,
                                   const double* __restrict__ ms, const double* __restrict__ mb, double* __restrict__ x,
-                                  double* __restrict__ r, double* __restrict__ z, const double* __restrict__ sc,
-                                  double* __restrict__ partial) {
+                                  double* __restrict__ r, double* __restrict__ z, double* __restrict__ sc,
+                                  double* __restrict__ upart) {
   if (sc[6] != 0.0) return;
   __shared__ double sh[kBlock / 64];
+  __shared__ double pq_s;
+  {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nbs; i += kBlock) a += spart[i];
+    double t = block_sum<kBlock>(a, sh);
+    if (threadIdx.x == 0) pq_s = t;
+    __syncthreads();
+  }
+  const double pq = pq_s;
+  if (!(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[8] = 1.0;
+      sc[6] = 1.0;
+    }
+    return;
+  }
+  const double alpha = sc[k & 1] / pq;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double alpha = sc[2];
   double rz = 0.0, rr = 0.0;
   if (i < nsv + nfree) {
     int o = i < nsv ? 3 * i : 3 * nsv + 12 * (i - nsv), n = i < nsv ? 3 : 12;
-    for (int k = 0; k < n; ++k) {
-      x[o + k] += alpha * p[o + k];
-      r[o + k] -= alpha * q[o + k];
+    for (int kk = 0; kk < n; ++kk) {
+      x[o + kk] += alpha * p[o + kk];
+      r[o + kk] -= alpha * q[o + kk];
     }
     apply_minv(i, nsv, ms, mb, r, z);
-    for (int k = 0; k < n; ++k) {
-      rz += r[o + k] * z[o + k];
-      rr += r[o + k] * r[o + k];
+    for (int kk = 0; kk < n; ++kk) {
+      rz += r[o + kk] * z[o + kk];
+      rr += r[o + kk] * r[o + kk];
     }
   }
   double s1 = block_sum<kBlock>(rz, sh);
   double s2 = block_sum<kBlock>(rr, sh);
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = s1;
-    partial[2 * blockIdx.x + 1] = s2;
+    upart[2 * blockIdx.x] = s1;
+    upart[2 * blockIdx.x + 1] = s2;
   }
 }
 
-__global__ void pcg_beta_kernel(int nb, const double* __restrict__ partial, double* __restrict__ sc) {
+// after the last update: residual and convergence of iteration k
+__global__ void pcg_final_kernel(int k, int nbu, const double* __restrict__ upart, double* __restrict__ sc) {
   if (sc[6] != 0.0) return;
   __shared__ double sh[kBlock / 64];
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kBlock) {
-    a += partial[2 * i];
-    b += partial[2 * i + 1];
-  }
-  double rz = block_sum<kBlock>(a, sh);
-  double rr = block_sum<kBlock>(b, sh);
+  double rz, rr;
+  reduce_partials2(upart, nbu, sh, rz, rr);
   if (threadIdx.x == 0) {
-    sc[7] += 1.0;
+    sc[7] = k;
     sc[4] = rr;
-    if (rr <= sc[9]) {
-      sc[6] = 1.0;
-    } else {
-      sc[3] = rz / sc[0];
-      sc[0] = rz;
-    }
+    if (rr <= sc[9]) sc[6] = 1.0;
   }
 }
 
-static Mat make_mat(zema_scene* s) {
-  Mat M;
+template <class V>
+static Mat<V> make_mat(zema_scene* s, const V* bv, const V* cv) {
+  Mat<V> M;
   M.nsv = s->nsv;
   M.nnodes = s->nnodes;
   M.nnzb = s->nnzb;
   M.nnzc = s->nnzc;
   M.bp = s->bsr_ptr.p;
   M.bc = s->bsr_col.p;
-  M.bv = s->bsr_val.p;
-  bool has_c = s->nnzc > 0;
-  M.cp = has_c ? s->c_ptr.p : nullptr;
+  M.bv = bv;
+  M.cp = s->nnzc > 0 ? s->c_ptr.p : nullptr;
   M.cc = s->c_col.p;
-  M.cv = s->c_val.p;
+  M.cv = cv;
   return M;
 }
 
 static int spmv_grid(zema_scene* s) { return (s->nsv + (kBlock / RG) - 1) / (kBlock / RG) + 4 * s->nfree; }
 
 void k_hess_matvec(zema_scene* s, const double* v, double* out) {
-  Mat M = make_mat(s);
-  Vec x{v, nullptr, nullptr};
   int g = spmv_grid(s);
-  if (g) spmv_kernel<<<g, kBlock, 0, s->st>>>(M, x, out, nullptr, nullptr, nullptr);
+  if (!g) return;
+  if (s->mixed)
+    spmv_kernel<float><<<g, kBlock, 0, s->st>>>(make_mat<float>(s, s->bsr_val32.p, s->c_val32.p), v, out);
+  else
+    spmv_kernel<double><<<g, kBlock, 0, s->st>>>(make_mat<double>(s, s->bsr_val.p, s->c_val.p), v, out);
 }
 
 void k_build_precond(zema_scene* s) {
-  Mat M = make_mat(s);
   s->minv_soft.reserve((size_t)9 * s->nsv + 9);
   s->minv_body.reserve((size_t)144 * s->nfree + 144);
   int* bad = s->counters.p + 4;
   ZCHK(hipMemsetAsync(bad, 0, sizeof(int), s->st));
-  if (s->nsv) precond_soft_kernel<<<nblocks(s->nsv), kBlock, 0, s->st>>>(M, s->minv_soft.p, bad);
-  if (s->nfree) precond_body_kernel<<<nblocks(s->nfree, 64), 64, 0, s->st>>>(M, s->nfree, s->minv_body.p, bad);
+  if (s->mixed) {
+    auto M = make_mat<float>(s, s->bsr_val32.p, s->c_val32.p);
+    if (s->nsv) precond_soft_kernel<float><<<nblocks(s->nsv), kBlock, 0, s->st>>>(M, s->minv_soft.p, bad);
+    if (s->nfree) precond_body_kernel<float><<<s->nfree, 64, 0, s->st>>>(M, s->nfree, s->minv_body.p, bad);
+  } else {
+    auto M = make_mat<double>(s, s->bsr_val.p, s->c_val.p);
+    if (s->nsv) precond_soft_kernel<double><<<nblocks(s->nsv), kBlock, 0, s->st>>>(M, s->minv_soft.p, bad);
+    if (s->nfree) precond_body_kernel<double><<<s->nfree, 64, 0, s->st>>>(M, s->nfree, s->minv_body.p, bad);
+  }
 }
 
 int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres) {
@@ -390,30 +462,35 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   int nunits = s->nsv + s->nfree;
   int nbv = nblocks(nunits);
   int g = spmv_grid(s);
-  s->partial.reserve(2 * (size_t)std::max(nbv, g) + 2);
+  s->partial.reserve(2 * (size_t)nbv + (size_t)g + 4);
+  double* upart = s->partial.p;
+  double* spart = s->partial.p + 2 * (size_t)nbv + 2;
   s->scal.reserve(16);
   double* sc = s->scal.p;
-  Mat M = make_mat(s);
+  auto M64 = make_mat<double>(s, s->bsr_val.p, s->c_val.p);
+  auto M32 = make_mat<float>(s, s->bsr_val32.p, s->c_val32.p);
   pcg_init_kernel<<<nbv, kBlock, 0, s->st>>>(s->nsv, s->nfree, rhs, s->minv_soft.p, s->minv_body.p, sol, s->pr.p,
-                                             s->pz.p, s->pp0.p, s->partial.p);
-  pcg_init_fin<<<1, kBlock, 0, s->st>>>(nbv, s->partial.p, sc, rtol);
+                                             s->pz.p, s->pp0.p, upart);
+  pcg_init_fin<<<1, kBlock, 0, s->st>>>(nbv, upart, sc, rtol);
   double* pold = s->pp0.p;
   double* pnew = s->pp1.p;
-  const int chunk = 8;
+  const int chunk = 16;
   double hs[10];
   int it = 0;
   for (;;) {
-    for (int k = 0; k < chunk && it < max_iter; ++k, ++it) {
-      Vec x{s->pz.p, pold, sc + 3};
+    for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
       kt_begin(s, KT_SPMV);
-      spmv_kernel<<<g, kBlock, 0, s->st>>>(M, x, s->pq.p, pnew, s->partial.p, sc + 6);
-      kt_end(s, KT_SPMV, 76.0 * (s->nnzb + s->nnzc) + 32.0 * s->ndof);
-      pcg_alpha_kernel<<<1, kBlock, 0, s->st>>>(g, s->partial.p, sc);
-      pcg_update_kernel<<<nbv, kBlock, 0, s->st>>>(s->nsv, s->nfree, pnew, s->pq.p, s->minv_soft.p, s->minv_body.p,
-                                                   sol, s->pr.p, s->pz.p, sc, s->partial.p);
-      pcg_beta_kernel<<<1, kBlock, 0, s->st>>>(nbv, s->partial.p, sc);
+      if (s->mixed)
+        pcg_spmv_kernel<float><<<g, kBlock, 0, s->st>>>(M32, it, nbv, upart, s->pz.p, pold, pnew, s->pq.p, spart, sc);
+      else
+        pcg_spmv_kernel<double><<<g, kBlock, 0, s->st>>>(M64, it, nbv, upart, s->pz.p, pold, pnew, s->pq.p, spart,
+                                                         sc);
+      kt_end(s, KT_SPMV, (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 32.0 * s->ndof);
+      pcg_update_kernel<<<nbv, kBlock, 0, s->st>>>(s->nsv, s->nfree, it, g, spart, pnew, s->pq.p, s->minv_soft.p,
+                                                   s->minv_body.p, sol, s->pr.p, s->pz.p, sc, upart);
       std::swap(pold, pnew);
     }
+    if (it >= max_iter) pcg_final_kernel<<<1, kBlock, 0, s->st>>>(it, nbv, upart, sc);
     ZCHK(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s->st));
     ZCHK(hipStreamSynchronize(s->st));
     if (hs[6] != 0.0 || it >= max_iter) break;

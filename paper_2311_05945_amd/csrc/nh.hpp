@@ -12,32 +12,34 @@ namespace zema {
 
 // symmetric 3x3 eigen-decomposition by cyclic Jacobi: A overwritten by its
 // eigenvalues on the diagonal, V columns are eigenvectors
-__host__ __device__ inline void eig3(double A[3][3], double V[3][3]) {
+template <class T>
+__host__ __device__ inline void eig3(T A[3][3], T V[3][3]) {
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+    for (int j = 0; j < 3; ++j) V[i][j] = i == j ? T(1) : T(0);
   for (int sweep = 0; sweep < 12; ++sweep) {
-    double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
-    double dg = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
-    if (off <= 1e-34 * dg || off == 0.0) break;
+    T off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    T dg = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    const T rel = sizeof(T) == 8 ? T(1e-34) : T(1e-15);
+    if (off <= rel * dg || off == T(0)) break;
     for (int p = 0; p < 2; ++p)
       for (int q = p + 1; q < 3; ++q) {
-        double apq = A[p][q];
-        if (apq == 0.0) continue;
-        double th = (A[q][q] - A[p][p]) / (2.0 * apq);
-        double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        T apq = A[p][q];
+        if (apq == T(0)) continue;
+        T th = (A[q][q] - A[p][p]) / (T(2) * apq);
+        T t = (th >= T(0) ? T(1) : T(-1)) / (fabs(th) + sqrt(th * th + T(1)));
+        T c = T(1) / sqrt(t * t + T(1)), s = t * c;
         for (int k = 0; k < 3; ++k) {
-          double akp = A[k][p], akq = A[k][q];
+          T akp = A[k][p], akq = A[k][q];
           A[k][p] = c * akp - s * akq;
           A[k][q] = s * akp + c * akq;
         }
         for (int k = 0; k < 3; ++k) {
-          double apk = A[p][k], aqk = A[q][k];
+          T apk = A[p][k], aqk = A[q][k];
           A[p][k] = c * apk - s * aqk;
           A[q][k] = s * apk + c * aqk;
         }
         for (int k = 0; k < 3; ++k) {
-          double vkp = V[k][p], vkq = V[k][q];
+          T vkp = V[k][p], vkq = V[k][q];
           V[k][p] = c * vkp - s * vkq;
           V[k][q] = s * vkp + c * vkq;
         }
@@ -115,6 +117,83 @@ __host__ __device__ inline double nh_energy(const double F[3][3], double mu, dou
   return c * (0.5 * mu * (I - 3.0) - mu * L + 0.5 * lam * L * L);
 }
 
+// index of (i, j), i <= j, in the packed upper triangle of a 9x9 matrix
+__host__ __device__ inline int up9(int i, int j) { return i * 9 - (i * (i - 1)) / 2 + (j - i); }
+
+// The 10 upper 3x3 blocks (order (0,0),(0,1),(0,2),(0,3),(1,1),(1,2),(1,3),(2,2),
+// (2,3),(3,3)) of h^2 V B^T P9 B, P9 the PSD projection of d2Psi/dF2, computed in
+// arithmetic type T (double, or float for the mixed-precision form).  P9 is
+// accumulated mode by mode from the analytic eigensystem, then contracted with the
+// rows of G (F = sum_a x_a G_a^T).
+template <class T>
+__host__ __device__ inline void nh_hess_blocks(const double F[3][3], const double Gd[4][3], double mu_d, double lam_d,
+                                               double c_d, T* hblk) {
+  double J = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+             F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+  const T mu = T(mu_d), lam = T(lam_d), L = T(log(J));
+  double Ud[3][3], sd[3], Vd[3][3];
+  svd3(F, Ud, sd, Vd);
+  T U[3][3], V[3][3], s[3], G[4][3];
+  for (int i = 0; i < 3; ++i) {
+    s[i] = T(sd[i]);
+    for (int j = 0; j < 3; ++j) {
+      U[i][j] = T(Ud[i][j]);
+      V[i][j] = T(Vd[i][j]);
+    }
+  }
+  for (int a = 0; a < 4; ++a)
+    for (int j = 0; j < 3; ++j) G[a][j] = T(Gd[a][j]);
+  T A[3][3], Ev[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      A[i][j] = i == j ? mu + (mu + lam - lam * L) / (s[i] * s[i]) : lam / (s[i] * s[j]);
+  eig3<T>(A, Ev);
+  T P[45];
+  for (int k = 0; k < 45; ++k) P[k] = T(0);
+  T q[9];
+  // scaling modes: U diag(e_m) V^T
+  for (int m = 0; m < 3; ++m) {
+    T lm = A[m][m];
+    if (!(lm > T(0))) continue;
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc)
+        q[3 * r + cc] = Ev[0][m] * U[r][0] * V[cc][0] + Ev[1][m] * U[r][1] * V[cc][1] + Ev[2][m] * U[r][2] * V[cc][2];
+    for (int i = 0; i < 9; ++i)
+      for (int j = i; j < 9; ++j) P[up9(i, j)] += lm * q[i] * q[j];
+  }
+  // twist (antisymmetric) and flip (symmetric) modes of each pair of singular values
+  const T is2 = T(0.70710678118654752440);
+  const int pi[3] = {0, 1, 0}, pj[3] = {1, 2, 2};
+  for (int t = 0; t < 3; ++t) {
+    int i = pi[t], j = pj[t];
+    T qq = (lam * L - mu) / (s[i] * s[j]);
+    for (int mode = 0; mode < 2; ++mode) {
+      T lm = mode == 0 ? mu + qq : mu - qq;
+      if (!(lm > T(0))) continue;
+      T sg = mode == 0 ? T(-1) : T(1);
+      for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) q[3 * r + cc] = is2 * (U[r][i] * V[cc][j] + sg * U[r][j] * V[cc][i]);
+      for (int a = 0; a < 9; ++a)
+        for (int b = a; b < 9; ++b) P[up9(a, b)] += lm * q[a] * q[b];
+    }
+  }
+  const T c = T(c_d);
+  int blk = 0;
+  for (int a = 0; a < 4; ++a)
+    for (int bb = a; bb < 4; ++bb, ++blk)
+      for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) {
+          T acc = T(0);
+          for (int j = 0; j < 3; ++j)
+            for (int l = 0; l < 3; ++l) {
+              int x = 3 * r + j, y = 3 * cc + l;
+              T pv = x <= y ? P[up9(x, y)] : P[up9(y, x)];
+              acc += G[a][j] * G[bb][l] * pv;
+            }
+          hblk[9 * blk + 3 * r + cc] = c * acc;
+        }
+}
+
 // Gradient (12) and optionally the 10 upper 3x3 blocks of the projected Hessian
 // (order (0,0),(0,1),(0,2),(0,3),(1,1),(1,2),(1,3),(2,2),(2,3),(3,3), row-major 3x3).
 __host__ __device__ inline double nh_element(const double F[3][3], const double G[4][3], double mu, double lam, double c,
@@ -149,51 +228,7 @@ __host__ __device__ inline double nh_element(const double F[3][3], const double 
     for (int j = 0; j < 3; ++j) P[i][j] = mu * F[i][j] + k * cof[i][j];
   for (int a = 0; a < 4; ++a)
     for (int r = 0; r < 3; ++r) g[3 * a + r] = c * (P[r][0] * G[a][0] + P[r][1] * G[a][1] + P[r][2] * G[a][2]);
-  if (!hblk) return E;
-  double U[3][3], s[3], V[3][3];
-  svd3(F, U, s, V);
-  // 3x3 Hessian in the singular values (scaling modes)
-  double A[3][3], Ev[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      A[i][j] = i == j ? mu + (mu + lam - lam * L) / (s[i] * s[i]) : lam / (s[i] * s[j]);
-  eig3(A, Ev);
-  double lamk[9];
-  double Q[9][3][3];
-  for (int m = 0; m < 3; ++m) {
-    lamk[m] = A[m][m];
-    for (int r = 0; r < 3; ++r)
-      for (int cc = 0; cc < 3; ++cc)
-        Q[m][r][cc] = Ev[0][m] * U[r][0] * V[cc][0] + Ev[1][m] * U[r][1] * V[cc][1] + Ev[2][m] * U[r][2] * V[cc][2];
-  }
-  const double is2 = 0.70710678118654752440;
-  int pi[3] = {0, 1, 0}, pj[3] = {1, 2, 2};
-  for (int t = 0; t < 3; ++t) {
-    int i = pi[t], j = pj[t];
-    double q = (lam * L - mu) / (s[i] * s[j]);
-    lamk[3 + t] = mu + q;  // twist
-    lamk[6 + t] = mu - q;  // flip
-    for (int r = 0; r < 3; ++r)
-      for (int cc = 0; cc < 3; ++cc) {
-        double a1 = U[r][i] * V[cc][j], a2 = U[r][j] * V[cc][i];
-        Q[3 + t][r][cc] = is2 * (a1 - a2);
-        Q[6 + t][r][cc] = is2 * (a1 + a2);
-      }
-  }
-  double b[9][12];
-  for (int m = 0; m < 9; ++m)
-    for (int a = 0; a < 4; ++a)
-      for (int r = 0; r < 3; ++r) b[m][3 * a + r] = Q[m][r][0] * G[a][0] + Q[m][r][1] * G[a][1] + Q[m][r][2] * G[a][2];
-  int blk = 0;
-  for (int a = 0; a < 4; ++a)
-    for (int bb = a; bb < 4; ++bb, ++blk)
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc) {
-          double acc = 0.0;
-          for (int m = 0; m < 9; ++m)
-            if (lamk[m] > 0.0) acc += lamk[m] * b[m][3 * a + r] * b[m][3 * bb + cc];
-          hblk[9 * blk + 3 * r + cc] = c * acc;
-        }
+  if (hblk) nh_hess_blocks<double>(F, G, mu, lam, c, hblk);
   return E;
 }
 

@@ -18,6 +18,7 @@
 
 #include "../../include/zema.h"
 #include "common.hpp"
+#include "mlp.hpp"
 
 namespace zema {
 
@@ -67,10 +68,13 @@ struct zema_scene {
   zema::DBuf<double> Dmi, h2vol, lmu, llam, mass;
   zema::DBuf<int> vt_ptr, vt_list;       // vertex -> (tet*4 + slot)
   zema::DBuf<double> e_tet, g_tet, h_tet, e_in;  // per-tet energy, gradient [nt][12], Hessian [nt][90]
+  zema::DBuf<float> h_tet32;                      // element Hessian blocks, mixed precision
   // ---- static BSR
   int nnzb = 0, bsr_row_soft_end = 0;
   zema::DBuf<int> bsr_ptr, bsr_col, bsr_row, bsr_diag, hc_ptr, hc_list;
   zema::DBuf<double> bsr_val;
+  zema::DBuf<float> bsr_val32;           // static block values, mixed precision
+  bool mixed = false;                    // FP32 Hessian storage / products
   // ---- affine (device): per body packed
   zema::DBuf<double> body_f;  // [nb][32]: m, V, stiff, kappaA, S(9), qfix(12) ...
   zema::DBuf<int> body_i;     // [nb][4]: mode, dof0, node0, pad
@@ -84,18 +88,29 @@ struct zema_scene {
   zema::DBuf<double> elen2;
   zema::DBuf<unsigned char> body_fixed;  // per global body
   zema::DBuf<double> xs, xs1, dxs;      // surface positions / displacements
+  // ---- learned initial guess
+  zema_mlp* mlp = nullptr;               // network used when P.warm_start == 1 (not owned)
+  bool stepped = false;                  // a step completed since the state was set
+  zema::DBuf<int> soft_sv;               // soft vertex -> surface vertex or -1
+  zema::DBuf<double> yd_prev, body_tv;   // velocity before the last step; target velocity [nb][3]
+  std::vector<double> body_tv_h;
+  zema::DBuf<unsigned long long> fdmin;  // per surface vertex: nearest other-body triangle distance
+  zema::DBuf<int> fpick;                 // ... and the PT pair realising it
+  zema::DBuf<float> feat, mlp_out;       // [nsv][16], [nsv][3]
+  zema::DBuf<double> ywarm;              // learned initial guess [ndof]
   // ---- state
   zema::DBuf<double> y, ydot, yt, ydt, yhat, ytmp, grad, pdir;
   double kappa = 0.0, kappa_lag = 0.0;
   int step = 0;
   // ---- candidates (current set)
   zema::DBuf<int> pt, ee;       // [n][2]
+  zema::DBuf<int> et_pairs, unc_pairs;  // intersection check work
   int64_t npt = 0, nee = 0;
   // broad phase work
   zema::DBuf<double> bb_lo, bb_hi;       // boxes of all primitives
   zema::DBuf<int> cnt, offs;
   zema::DBuf<unsigned long long> ent_cell;
-  zema::DBuf<int> ent_prim, bucket_lo, bucket_hi, big_list;
+  zema::DBuf<int> ent_prim, ent_body, bucket_lo, bucket_hi, big_list;
   zema::DBuf<unsigned long long> pair_keys;
   zema::DBuf<int> counters;              // small device counters
   zema::SortBufs sort;
@@ -105,12 +120,14 @@ struct zema_scene {
   zema::DBuf<int> trip_cnt, trip_off;
   zema::DBuf<unsigned long long> trip_key;
   zema::DBuf<double> trip_val;           // [ntrip][9]
+  zema::DBuf<double> item_h, item_g;     // per contact item: 12x12 Hessian, gradient
   zema::DBuf<double> e_pair, d_pair;     // per candidate energy / distance
   int n_act = 0;
   // contact matrix (CSR over nodes)
   int nnzc = 0;
   zema::DBuf<int> c_ptr, c_col, seg_start, seg_row;
   zema::DBuf<double> c_val;
+  zema::DBuf<float> c_val32;
   // ---- friction (lagged)
   int nfric = 0;
   zema::DBuf<int> f_ids;       // [n][5]
@@ -175,6 +192,16 @@ void k_friction_build(zema_scene* s);                 // lagged table from curre
 
 // -------- broad phase (k_broad.hip)
 void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r);
+void k_features(zema_scene* s, float* feat);
+void k_warm_dir(zema_scene* s, const float* out, double* p);
+void k_warm_target(zema_scene* s, float* target);
+int64_t k_edge_tri_pairs(zema_scene* s, const double* xs, DBuf<int>& out);
+
+// -------- intersection count (k_intersect.hip)
+// counts of intersecting inter-body (edge, triangle) pairs, tets with J <= 0 and
+// pairs / tets whose sign the floating-point filter cannot decide (listed in unc)
+void k_intersections(zema_scene* s, const double* y, int64_t* n_int, int64_t* n_inv, int64_t* n_unc,
+                     DBuf<int>& unc);
 
 // -------- sort / scan (k_sort.hip)
 int64_t k_exclusive_scan(zema_scene* s, const int* in, int* out, int64_t n, bool want_total = true);

@@ -44,8 +44,10 @@ class AffineDesc(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("status", I32), ("newton_iters", I32), ("pcg_iters", I32), ("ls_backtracks", I32),
                 ("n_pt_active", I32), ("n_ee_active", I32), ("n_pt_cand", I32), ("n_ee_cand", I32),
+                ("warm_learned", I32), ("reserved_", I32),
                 ("alpha_ccd_min", D), ("kappa", D), ("d_min", D), ("energy", D), ("ms_total", D),
-                ("ms_assemble", D), ("ms_pcg", D), ("ms_broad", D), ("ms_ccd", D), ("ms_linesearch", D)]
+                ("ms_assemble", D), ("ms_pcg", D), ("ms_broad", D), ("ms_ccd", D), ("ms_linesearch", D),
+                ("ms_warm", D)]
 
 
 _LIB = None
@@ -69,9 +71,24 @@ SIGNATURES = [
     ("zema_ccd_max_step", [VP, VP, VP, PD]),
     ("zema_step", [VP, I32, C.POINTER(StepStats)]),
     ("zema_friction_table", [VP, PI64, PI32, PD, I64]),
+    ("zema_intersection_count", [VP, VP, PI64, PI64, PI64, VP, I64]),
     ("zema_kernel_timer", [VP, I32, I32]),
     ("zema_kernel_time", [VP, I32, PD, PI64, PD]),
+    ("zema_mlp_create", [VP, C.POINTER(VP)]),
+    ("zema_mlp_destroy", [VP]),
+    ("zema_mlp_last_error", [VP]),
+    ("zema_mlp_set_weights", [VP, C.POINTER(C.c_float)]),
+    ("zema_mlp_get_weights", [VP, C.POINTER(C.c_float)]),
+    ("zema_mlp_forward", [VP, VP, I64, VP]),
+    ("zema_mlp_grad", [VP, VP, VP, I64, VP, PD]),
+    ("zema_mlp_train_step", [VP, VP, VP, I64, VP, I64, C.c_float, PD]),
+    ("zema_scene_set_mlp", [VP, VP]),
+    ("zema_scene_features", [VP, VP]),
+    ("zema_scene_warm_target", [VP, VP]),
 ]
+MLP_PARAMS = 9603
+MLP_FEATURES = 16
+WARM_EXPLICIT, WARM_LEARNED = 0, 1
 KT_SPMV, KT_TET, KT_CONTACT, KT_QUERY, KT_CCD = range(5)
 
 
@@ -88,8 +105,10 @@ def lib():
             f.argtypes = args
             f.restype = C.c_int
         L.zema_scene_destroy.restype = None
+        L.zema_mlp_destroy.restype = None
         L.zema_status_string.restype = C.c_char_p
         L.zema_last_error.restype = C.c_char_p
+        L.zema_mlp_last_error.restype = C.c_char_p
         _LIB = L
     return _LIB
 
@@ -267,6 +286,15 @@ class Scene:
             return ids[:n.value], vals[:n.value]
 
 
+    def intersection_count(self, y, cap=1024):
+        """(intersecting edge-triangle pairs, inverted tets, uncertain, uncertain pairs)."""
+        y = self._dev(y)
+        ni, nv, nu = I64(), I64(), I64()
+        unc = self.torch.zeros((max(cap, 1), 2), dtype=self.torch.int32, device=self.device)
+        self._chk(lib().zema_intersection_count(self.h, _ptr(y), C.byref(ni), C.byref(nv), C.byref(nu), _ptr(unc),
+                                                cap))
+        return ni.value, nv.value, nu.value, unc[:min(nu.value, cap)]
+
     def kernel_timer(self, group, enable=True):
         self._chk(lib().zema_kernel_timer(self.h, int(group), 1 if enable else 0))
 
@@ -275,6 +303,89 @@ class Scene:
         ms = D(); n = I64(); b = D()
         self._chk(lib().zema_kernel_time(self.h, int(group), C.byref(ms), C.byref(n), C.byref(b)))
         return ms.value, n.value, b.value
+
+
+    # ---- learned initial guess
+    def set_mlp(self, mlp):
+        self._mlp = mlp                      # keep the network alive while attached
+        self._chk(lib().zema_scene_set_mlp(self.h, mlp.h if mlp is not None else None))
+
+    def features(self):
+        f = self.torch.zeros((self.n_soft_verts, MLP_FEATURES), dtype=self.torch.float32, device=self.device)
+        self._chk(lib().zema_scene_features(self.h, _ptr(f)))
+        return f
+
+    def warm_target(self):
+        t = self.torch.zeros((self.n_soft_verts, 3), dtype=self.torch.float32, device=self.device)
+        self._chk(lib().zema_scene_warm_target(self.h, _ptr(t)))
+        return t
+
+
+class Mlp:
+    """The warm-start network of libzema (weights on the device, FP32 master copy)."""
+
+    def __init__(self, theta=None, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = lib().zema_mlp_create(C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise ZemaError(rc, lib().zema_status_string(rc).decode())
+        self.h = h
+        if theta is not None:
+            self.set_weights(theta)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                lib().zema_mlp_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise ZemaError(rc, lib().zema_mlp_last_error(self.h).decode())
+
+    def _dev32(self, a):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(device=self.device, dtype=t.float32).contiguous()
+        return t.as_tensor(np.asarray(a), dtype=t.float32, device=self.device).contiguous()
+
+    def set_weights(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.shape != (MLP_PARAMS,):
+            raise ValueError(f"expected {MLP_PARAMS} parameters")
+        self._chk(lib().zema_mlp_set_weights(self.h, th.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def get_weights(self):
+        th = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._chk(lib().zema_mlp_get_weights(self.h, th.ctypes.data_as(C.POINTER(C.c_float))))
+        return th
+
+    def forward(self, feat):
+        f = self._dev32(feat)
+        out = self.torch.zeros((f.shape[0], 3), dtype=self.torch.float32, device=self.device)
+        self._chk(lib().zema_mlp_forward(self.h, _ptr(f), f.shape[0], _ptr(out)))
+        return out
+
+    def grad(self, feat, target):
+        f = self._dev32(feat); t = self._dev32(target)
+        g = self.torch.zeros(MLP_PARAMS, dtype=self.torch.float32, device=self.device)
+        loss = D()
+        self._chk(lib().zema_mlp_grad(self.h, _ptr(f), _ptr(t), f.shape[0], _ptr(g), C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, feat, target, idx, lr):
+        """One Adam step on rows idx (device int32 tensor) of feat / target (device)."""
+        loss = D()
+        self._chk(lib().zema_mlp_train_step(self.h, _ptr(feat), _ptr(target), feat.shape[0], _ptr(idx),
+                                            idx.shape[0], float(lr), C.byref(loss)))
+        return loss.value
 
 
 def scene_create(scene, device="cuda:0", stream=None) -> Scene:

@@ -331,3 +331,35 @@ def two_tets_scene() -> Scene:
 def random_state_perturbation(n: int, scale: float, seed: int) -> np.ndarray:
     """Seeded Gaussian perturbation (n,3) used to build deformed test states."""
     return np.random.default_rng(seed).normal(0.0, scale, (n, 3))
+
+
+# ------------------------------------------------------------------ warm-start network inputs
+
+MLP_SHAPES = [(64, 16), (64,), (64, 64), (64,), (64, 64), (64,), (3, 64), (3,)]
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial parameters of the 16-64-64-64-3 warm-start network as one flat FP32
+    vector (W1, b1, W2, b2, W3, b3, W4, b4; W row-major [out][in]): He-uniform weights
+    in +-sqrt(6 / fan_in), zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            lim = np.sqrt(6.0 / shape[1])
+            parts.append(rng.uniform(-lim, lim, size=shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_batch(seed: int, n: int):
+    """Seeded synthetic network inputs of the feature ranges: velocity-like entries
+    N(0, 1), a clearance in [0, 4], a unit direction, and targets N(0, 0.3)."""
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, 16))
+    x[:, 6] = rng.uniform(0.0, 4.0, size=n)
+    d = rng.normal(size=(n, 3))
+    x[:, 7:10] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    t = rng.normal(scale=0.3, size=(n, 3))
+    return x.astype(np.float32), t.astype(np.float32)

@@ -1,0 +1,225 @@
+"""GPU parity of the learned initial guess: network kernels, features, target, step.
+
+Gates:
+  * forward output and loss within 1e-2 relative (norm over the tensor) of the FP64
+    reference on the same bf16-rounded weights and inputs: the kernels also round the
+    hidden activations to bf16 (relative 2^-9 each), which the reference does not;
+  * gradient within 1e-2 relative per parameter tensor (deltas rounded to bf16 before
+    the weight-gradient products);
+  * Adam: parameters whose reference gradient is not tiny move by -lr sign(g) within
+    5 percent after one step (m-hat = g, v-hat = g^2 at step 1); no parameter moves by
+    more than lr;
+  * determinism: two gradient evaluations are bitwise equal;
+  * features within 1e-6 (absolute, and relative to 1) of the FP64 reference; target
+    of a step within 1e-4 (units of s = h * 0.05 m/s) of the oracle's step;
+  * a learned step with a zero network reproduces the explicit step bitwise, and a
+    trained network keeps every step intersection-free and converged.
+"""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import exact, mlp as omlp, ref, warm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SIZES = [(n, s) for n, s in zip(("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"),
+                                (1024, 64, 4096, 64, 4096, 64, 192, 3))]
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def zema():
+    _need_gpu()
+    from paper_2311_05945_amd import zema as z
+    return z
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def split(theta):
+    out, o = {}, 0
+    for name, n in SIZES:
+        out[name] = theta[o:o + n]
+        o += n
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 17, 1000])
+def test_forward_matches_reference(zema, n):
+    th = sg.mlp_init(1)
+    th[1024:1088] = 0.05                                   # nonzero biases
+    x, _ = sg.mlp_batch(2, n)
+    M = zema.Mlp(th)
+    y = M.forward(x).cpu().numpy()
+    yr = omlp.predict(th, x)
+    r = rel(y, yr)
+    log(f"n={n}: forward rel err {r:.2e}")
+    assert r <= 1e-2
+    assert np.abs(y - yr).max() <= 5e-2 * max(np.abs(yr).max(), 1e-3)
+
+
+def test_gradient_matches_reference(zema):
+    th = sg.mlp_init(3)
+    x, t = sg.mlp_batch(4, 1000)                            # 62.5 tiles: a ragged tail
+    M = zema.Mlp(th)
+    loss, g = M.grad(x, t)
+    lr_, gr = omlp.loss_and_grad(th, x, t)
+    g = g.cpu().numpy()
+    assert loss == pytest.approx(lr_, rel=1e-2)
+    G, Gr = split(g), split(gr)
+    for name, _ in SIZES:
+        r = rel(G[name], Gr[name])
+        log(f"grad {name}: rel err {r:.2e}")
+        assert r <= 1e-2, name
+    loss2, g2 = M.grad(x, t)
+    assert loss2 == loss and torch.equal(g2.cpu(), torch.from_numpy(g))
+
+
+def test_adam_step(zema):
+    th = sg.mlp_init(5)
+    x, t = sg.mlp_batch(6, 512)
+    M = zema.Mlp(th)
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(x).to(dev)
+    T = torch.from_numpy(t).to(dev)
+    idx = torch.arange(512, dtype=torch.int32, device=dev)
+    lr = 1e-3
+    loss = M.train_step(X, T, idx, lr)
+    th1 = M.get_weights()
+    _, gr = omlp.loss_and_grad(th, x, t)
+    d = th1.astype(np.float64) - th
+    assert loss == pytest.approx(omlp.loss(omlp.predict(th, x), t), rel=1e-2)
+    assert np.abs(d).max() <= lr * (1 + 1e-5) + 1e-9
+    strong = np.abs(gr) > 0.05 * np.abs(gr).max()
+    assert strong.sum() > 100
+    assert np.allclose(d[strong], -lr * np.sign(gr[strong]), rtol=0.05, atol=2e-8)
+
+
+def test_training_reduces_loss(zema):
+    """A learnable target (a fixed random teacher network of the same shape): 300 Adam
+    steps of batch 4096 cut the loss by 10x."""
+    teacher = sg.mlp_init(11)
+    x, _ = sg.mlp_batch(12, 20000)
+    t = omlp.predict(teacher, x).astype(np.float32)
+    M = zema.Mlp(sg.mlp_init(13))
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(x).to(dev)
+    T = torch.from_numpy(t).to(dev)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    losses = []
+    for it in range(300):
+        idx = torch.randint(0, 20000, (4096,), generator=g, dtype=torch.int64).to(torch.int32).to(dev)
+        losses.append(M.train_step(X, T, idx, 1e-3))
+    log(f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.1 * losses[0]
+
+
+def test_features_match_reference(zema):
+    from test_gpu_parity import gripper_contact_state
+    from test_oracle_warm import lowered_cube
+    cases = []
+    sc = lowered_cube()
+    R = ref.RefScene(sc)
+    y, yd, _, _ = R.get_state()
+    yd = np.random.default_rng(0).normal(size=y.shape) * 0.1
+    cases.append(("cube", sc, R, y, yd))
+    sc2 = sg.gripper(0, r=16)
+    R2 = ref.RefScene(sc2)
+    y2, yd2 = gripper_contact_state(sc2, R2, squeeze=1.5, noise=2e-5)
+    yd2 = yd2.copy()
+    yd2[:3 * R2.n_soft_verts] = np.random.default_rng(1).normal(size=3 * R2.n_soft_verts) * 0.02
+    cases.append(("gripper", sc2, R2, y2, yd2))
+    for name, sc, R, y, yd in cases:
+        G = zema.Scene(sc)
+        G.set_state(y, yd)
+        f = G.features().cpu().numpy().astype(np.float64)
+        fr = warm.features(sc, R, y, yd, yd, 0)
+        err = np.abs(f - fr) / np.maximum(1.0, np.abs(fr))
+        log(f"{name}: {int((fr[:, 6] < 4).sum())} vertices with a triangle in range, worst feature err "
+            f"{err.max():.2e}")
+        assert err.max() <= 1e-6
+
+
+def test_target_matches_oracle_step(zema):
+    sc = sg.cube_drop()
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    y0, yd0, _, _ = R.get_state()
+    for k in range(3):
+        G.step(1)
+        R.step(1)
+    yb, ydb, _, _ = R.get_state()
+    R.step(1)
+    G.step(1)
+    ya, _, _, _ = R.get_state()
+    t = G.warm_target().cpu().numpy()
+    tr = warm.warm_target(sc, ya, yb, ydb, R.n_soft_verts)
+    log(f"target max |gpu - oracle| {np.abs(t - tr).max():.2e}, max |target| {np.abs(tr).max():.3f}")
+    assert np.abs(t - tr).max() <= 1e-4
+
+
+def test_zero_network_reproduces_explicit_steps(zema):
+    sa = sg.gripper(0, r=12)
+    sb = sg.gripper(0, r=12)
+    sb.params.warm_start = 1
+    A = zema.Scene(sa)
+    B = zema.Scene(sb)
+    M = zema.Mlp(np.zeros(9603, dtype=np.float32))
+    B.set_mlp(M)
+    for k in range(6):
+        st_a = A.step(1)[0]
+        st_b = B.step(1)[0]
+        assert st_b["warm_learned"] == 1                 # equal proposals: energies equal
+        assert st_a["newton_iters"] == st_b["newton_iters"]
+        assert torch.equal(A.get_state()[0], B.get_state()[0])
+
+
+def test_learned_steps_intersection_free(zema):
+    """Train briefly on explicit-start trajectories of one small scene, then step a
+    second seed with the learned start: every step converges at the same tolerance
+    and is intersection-free."""
+    dev = torch.device("cuda:0")
+    feats, targs = [], []
+    sc = sg.gripper(1, r=12)
+    G = zema.Scene(sc)
+    for k in range(30):
+        feats.append(G.features())
+        G.step(1)
+        targs.append(G.warm_target())
+    X = torch.cat(feats).contiguous()
+    T = torch.cat(targs).contiguous()
+    M = zema.Mlp(sg.mlp_init(7))
+    gen = torch.Generator(device="cpu").manual_seed(1)
+    l0 = l1 = None
+    for it in range(200):
+        idx = torch.randint(0, X.shape[0], (4096,), generator=gen, dtype=torch.int64).to(torch.int32).to(dev)
+        l1 = M.train_step(X, T, idx, 1e-3)
+        l0 = l0 if l0 is not None else l1
+    log(f"training loss {l0:.4f} -> {l1:.4f} on {X.shape[0]} vertex-steps")
+    sc2 = sg.gripper(2, r=12)
+    sc2.params.warm_start = 1
+    B = zema.Scene(sc2)
+    B.set_mlp(M)
+    R = ref.RefScene(sc2)
+    tris, edges, vb = R.surface()
+    used = 0
+    for k in range(10):
+        st = B.step(1)[0]
+        assert st["status"] == 0
+        used += st["warm_learned"]
+        y = B.get_state()[0].cpu().numpy()
+        assert exact.count_intersections(R.surface_positions(y), tris, edges, vb) == 0
+    log(f"learned start kept in {used}/10 steps")

@@ -240,7 +240,9 @@ def test_steps_cube_intersection_free(zema):
         dy = np.abs(y - R.get_state()[0]).max()
         log(f"step {k}: newton {st['newton_iters']} pcg {st['pcg_iters']} dmin {st['d_min']:.3e} "
             f"|y_gpu - y_oracle| {dy:.2e} intersections {n_int} inverted {n_inv}")
+        gi, gv, gu, _ = G.intersection_count(y)
         assert st["status"] == 0 and n_int == 0 and n_inv == 0
+        assert gi == 0 and gv == 0
         assert dy < 1e-5
 
 
@@ -312,3 +314,26 @@ def test_gripper_full_size_energy_gradient_hv(zema, gripper_full):
     worst = check_grad_terms(G, R, y, "gripper")
     worst_h = check_hv(G, R, y, 7, "gripper", masks=(0, 1 << 1, 1 << 4))
     log(f"gripper worst grad {worst:.2e} worst Hv {worst_h:.2e}")
+
+
+def test_intersection_count_matches_exact(zema):
+    """GPU intersection count (filtered FP64, uncertain pairs resolved exactly) equals
+    the exact rational count on free, touching (coplanar), crossing and deep states."""
+    sc = sg.cube_drop()
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    tris, edges, vb = R.surface()
+    y = R.get_state()[0]
+    n3 = 3 * R.n_soft_verts
+    for shift in (0.0, -0.005, -0.0075, -0.02):
+        y1 = y.copy()
+        y1[1:n3:3] += shift
+        ni, nv, nu, unc = G.intersection_count(y1, cap=4096)
+        xs = R.surface_positions(y1)
+        n_exact = exact.count_intersections(xs, tris, edges, vb)
+        resolved = sum(exact.seg_tri_intersect(xs[edges[e, 0]], xs[edges[e, 1]], xs[tris[t, 0]], xs[tris[t, 1]],
+                                               xs[tris[t, 2]]) for e, t in unc.cpu().numpy())
+        log(f"shift {shift}: gpu certain {ni}, uncertain {nu} ({resolved} intersect), exact {n_exact}, inverted {nv}")
+        assert nu <= 4096 and ni + resolved == n_exact
+        assert nv == exact.count_inverted(y1[:n3].reshape(-1, 3), sc.softs[0].tets)
+    assert n_exact > 0

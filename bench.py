@@ -52,6 +52,67 @@ def cpu_baseline(scene, seconds, max_steps=20):
                       f"these early steps include the contact-free approach of the fingers)"}
 
 
+def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5):
+    """Steps every scene `steps` times; returns (wall seconds, stats list, intersections)."""
+    import torch
+    for sc in scenes:
+        sc.params.precision = 1 if mixed else 0
+        sc.params.warm_start = 1 if learned is not None else 0
+    objs = [zema.Scene.batch(scenes)] if batched else [zema.Scene(sc) for sc in scenes]
+    for o in objs:
+        if learned is not None:
+            o.set_mlp(learned)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for o in objs:
+        done = 0
+        while done < steps:
+            n = min(chunk, steps - done)
+            stats += o.step(n)
+            done += n
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    inter = 0
+    for o in objs:
+        ni, nv, nu, _ = o.intersection_count(o.get_state()[0], cap=0)
+        inter += ni + nv + nu
+    return t, stats, inter
+
+
+def forms(args, zema):
+    """The batched, learned and mixed-precision forms against the plain form, on a
+    sample of uneven grasp scenes at the same Newton tolerance."""
+    import numpy as np
+
+    import scenegen as sg
+    seeds = list(range(args.form_seed, args.form_seed + args.form_scenes))
+    mk = lambda: [sg.batch_scene(s, steps=args.form_steps) for s in seeds]
+    mlp = None
+    if os.path.exists(args.mlp):
+        mlp = zema.Mlp(np.load(args.mlp))
+    out = {"sample": f"{len(seeds)} uneven grasp scenes (seeds {seeds[0]}-{seeds[-1]}), {args.form_steps} steps "
+                     f"each from rest, dt=0.005 s, Newton tol 1e-6 dt",
+           "network": os.path.basename(args.mlp) if mlp is not None else None}
+    cases = [("plain", False, None, False), ("batched", True, None, False)]
+    if mlp is not None:
+        cases += [("learned", False, mlp, False), ("batched_learned", True, mlp, False),
+                  ("batched_learned_mixed", True, mlp, True)]
+    total = len(seeds) * args.form_steps
+    for name, batched, learned, mixed in cases:
+        t, st, inter = run_form(zema, mk(), args.form_steps, batched, learned, mixed)
+        newton = sum(x["newton_iters"] for x in st)
+        out[name] = {"steps_per_s": total / t, "newton_iters_per_step": newton / total,
+                     "wall_s": t, "intersections": inter,
+                     "learned_start_kept": (sum(x["warm_learned"] for x in st) / total) if learned else None}
+        log(f"form {name}: {total / t:.2f} scene-steps/s, newton/step {newton / total:.2f}, "
+            f"intersections {inter}")
+    base = out["plain"]["steps_per_s"]
+    for name, *_ in cases[1:]:
+        out[name]["speedup_vs_plain"] = out[name]["steps_per_s"] / base
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +124,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--timer", default="spmv", choices=sorted(GROUPS))
     ap.add_argument("--chunk", type=int, default=10, help="steps per library call (progress lines)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched / learned / mixed comparison")
+    ap.add_argument("--form-scenes", type=int, default=8)
+    ap.add_argument("--form-steps", type=int, default=16)
+    ap.add_argument("--form-seed", type=int, default=10000)
+    ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_05945_amd", "warm_mlp.npy"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -130,6 +196,8 @@ def main():
                               for k in ("assemble", "pcg", "broad", "ccd", "linesearch")},
         "failed_steps": sum(1 for s in stats if s["status"] != 0),
     }
+    if not args.no_forms:
+        out["forms"] = forms(args, zema)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sg.gripper(args.seed, r=args.res, steps=args.steps), args.cpu_seconds)
     print(json.dumps(out))

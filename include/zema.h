@@ -197,8 +197,33 @@ int zema_ccd_max_step(zema_scene* s, const double* y, const double* p, double* a
 /* Advance n_steps time steps of the Newton method (warm start, lagged friction,
  * assemble, PCG, convergence test, swept candidates, CCD bound, backtracking line
  * search on the energy with an inversion check, kappa rule, velocity update).  On an
- * error the scene keeps the last accepted state.  stats: host array of n_steps. */
+ * error the scene keeps the last accepted state.  stats: host array of
+ * n_steps * n_scenes entries, step-major (n_scenes = 1 for a single scene). */
 int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats);
+
+/* ---------------------------------------------------------------- batches
+ * Independent scenes stepped together (the paper evaluates grasps in parallel): one
+ * object holds the concatenation of every scene's bodies, each phase of a step is one
+ * launch over all of them, and every scene keeps its own Newton iteration, PCG
+ * scalars, CCD bound, line search and barrier stiffness; a scene that has converged
+ * stops moving until all have.  Scene k owns soft bodies [soft_off[k], soft_off[k+1])
+ * and affine bodies [aff_off[k], aff_off[k+1]) of the descriptor arrays (offsets:
+ * host [n_scenes + 1], starting at 0); params[k] (host [n_scenes]) must agree on every
+ * field except mu.  Candidate pairs never join two scenes.
+ * y (zema_get_state / zema_set_state) is [soft vertices of all scenes, scene by
+ * scene | free affine bodies of all scenes, scene by scene]; surface vertices are
+ * numbered scene by scene.  zema_step fills n_steps * n_scenes statistics; the
+ * single-scene hot-path calls (ip_assemble, pcg_solve, ccd_max_step) return
+ * ZEMA_E_ARG on a batch, zema_set_kappa sets every scene and zema_get_state reports
+ * scene 0's kappa.  Errors: as zema_scene_create. */
+int zema_batch_create(const zema_params* params, int32_t n_scenes, const zema_soft_desc* soft,
+                      const int32_t* soft_off, const zema_affine_desc* affine, const int32_t* aff_off,
+                      void* hip_stream, zema_scene** out);
+/* Number of scenes and, when ranges is not NULL, per scene (host [n_scenes][8]):
+ * soft vertex range, free affine body range, tet range, surface vertex range, each
+ * [begin, end).  A scene's DOFs are 3 v0 .. 3 v1 and 3 n_soft_verts + 12 f0 ..
+ * 3 n_soft_verts + 12 f1. */
+int zema_batch_layout(const zema_scene* s, int32_t* n_scenes, int64_t* ranges);
 
 /* Number of lagged friction pairs and their table (host outputs): ids5 [n][5] =
  * (kind 0 PT / 1 EE, 4 surface vertices), vals8 [n][8] = (lambda, n(3), w(4)). */

@@ -40,9 +40,25 @@ D3h crs(D3h a, D3h b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.
 double dt3(D3h a, D3h b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
 // ------------------------------------------------------------------ preprocessing
-void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const zema_affine_desc* aff, int n_aff) {
+// Scene k of a batch owns soft bodies [soft_off[k], soft_off[k+1]) and affine bodies
+// [aff_off[k], aff_off[k+1]); one scene: offsets {0, n_soft} and {0, n_aff}.
+void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const zema_affine_desc* aff, int n_aff,
+                 const int* soft_off, const int* aff_off, int ns, const double* mu_sc) {
   s->n_soft_bodies = n_soft;
   s->n_bodies = n_soft + n_aff;
+  s->ns = ns;
+  s->scn.assign(ns, SceneRange());
+  for (int k = 0; k < ns; ++k) {
+    if (soft_off[k + 1] < soft_off[k] || aff_off[k + 1] < aff_off[k]) throw Error(ZEMA_E_ARG, "scene offsets");
+    s->scn[k].mu = mu_sc[k];
+  }
+  if (soft_off[0] != 0 || aff_off[0] != 0 || soft_off[ns] != n_soft || aff_off[ns] != n_aff)
+    throw Error(ZEMA_E_ARG, "scene offsets");
+  std::vector<int> body_scene(std::max(n_soft + n_aff, 1), 0);
+  for (int k = 0; k < ns; ++k) {
+    for (int b = soft_off[k]; b < soft_off[k + 1]; ++b) body_scene[b] = k;
+    for (int b = aff_off[k]; b < aff_off[k + 1]; ++b) body_scene[n_soft + b] = k;
+  }
   std::vector<double> X, x_init, v_init, Dmi_aos, vol, lmu, llam, mass;
   std::vector<int> tets, vbody;
   // ---- soft bodies
@@ -50,6 +66,11 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   std::vector<unsigned long long> fkey;
   for (int b = 0; b < n_soft; ++b) {
     const zema_soft_desc& d = soft[b];
+    SceneRange& R = s->scn[body_scene[b]];
+    if (b == soft_off[body_scene[b]]) {
+      R.v0 = R.v1 = (int)mass.size();
+      R.t0 = R.t1 = (int)vol.size();
+    }
     if (d.n_verts < 0 || d.n_tets < 0 || (d.n_verts && !d.rest_pos) || (d.n_tets && !d.tets))
       throw Error(ZEMA_E_ARG, "bad soft body descriptor");
     int v0 = (int)mass.size();
@@ -104,9 +125,19 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
         faces.push_back({a, bb, c, 0});
       }
     }
+    R.v1 = (int)mass.size();
+    R.t1 = (int)vol.size();
   }
   s->nsv = (int)mass.size();
   s->nt = (int)vol.size();
+  for (int k = 0, v = 0, t = 0; k < ns; ++k) {  // scenes without soft bodies: empty ranges in order
+    if (soft_off[k + 1] == soft_off[k]) {
+      s->scn[k].v0 = s->scn[k].v1 = v;
+      s->scn[k].t0 = s->scn[k].t1 = t;
+    }
+    v = s->scn[k].v1;
+    t = s->scn[k].t1;
+  }
   if (s->nsv >= (1 << 21)) throw Error(ZEMA_E_ARG, "too many soft vertices");
   // boundary faces: keys occurring once
   std::vector<int> ford(fkey.size());
@@ -119,23 +150,6 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
     if (j - i == 1) soft_tris.push_back({faces[ford[i]][0], faces[ford[i]][1], faces[ford[i]][2]});
     i = j;
   }
-  // ---- surface vertices: soft boundary vertices ascending, then affine vertices
-  std::vector<int> sv_ref, sv_body, soft_sid(s->nsv, -1);
-  std::vector<double> sv_x0;
-  {
-    std::vector<char> on(s->nsv, 0);
-    for (auto& t : soft_tris)
-      for (int k = 0; k < 3; ++k) on[t[k]] = 1;
-    for (int i = 0; i < s->nsv; ++i)
-      if (on[i]) {
-        soft_sid[i] = (int)sv_ref.size();
-        sv_ref.push_back(i);
-        sv_body.push_back(vbody[i]);
-        sv_x0.insert(sv_x0.end(), {0.0, 0.0, 0.0});
-      }
-  }
-  std::vector<std::array<int, 3>> all_tris;
-  for (auto& t : soft_tris) all_tris.push_back({soft_sid[t[0]], soft_sid[t[1]], soft_sid[t[2]]});
   // ---- affine bodies
   int dof = 3 * s->nsv, node = s->nsv;
   s->nfree = 0;
@@ -203,15 +217,7 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
       B.qrest[k] = B.c[k];
       B.qrest[3 + 4 * k] = 1.0;
     }
-    B.sv0 = (int)sv_ref.size();
     B.nsv = d.n_verts;
-    for (int i = 0; i < d.n_verts; ++i) {
-      sv_ref.push_back(-(b + 1));
-      sv_body.push_back(n_soft + b);
-      for (int k = 0; k < 3; ++k) sv_x0.push_back(d.rest_pos[3 * i + k] - B.c[k]);
-    }
-    for (int t = 0; t < d.n_tris; ++t)
-      all_tris.push_back({B.sv0 + d.tris[3 * t], B.sv0 + d.tris[3 * t + 1], B.sv0 + d.tris[3 * t + 2]});
     if (B.mode != ZEMA_FIXED) {
       B.dof0 = dof;
       B.node0 = node;
@@ -223,6 +229,46 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   }
   s->ndof = dof;
   s->nnodes = node;
+  // ---- surface vertices, scene by scene: the scene's soft boundary vertices
+  // ascending, then every vertex of its affine bodies in body order
+  std::vector<int> sv_ref, sv_body, soft_sid(s->nsv, -1);
+  std::vector<double> sv_x0;
+  std::vector<std::array<int, 3>> all_tris;
+  {
+    std::vector<char> on(s->nsv, 0);
+    for (auto& t : soft_tris)
+      for (int k = 0; k < 3; ++k) on[t[k]] = 1;
+    for (int k = 0, f = 0; k < ns; ++k) {
+      SceneRange& R = s->scn[k];
+      R.s0 = (int)sv_ref.size();
+      for (int i = R.v0; i < R.v1; ++i)
+        if (on[i]) {
+          soft_sid[i] = (int)sv_ref.size();
+          sv_ref.push_back(i);
+          sv_body.push_back(vbody[i]);
+          sv_x0.insert(sv_x0.end(), {0.0, 0.0, 0.0});
+        }
+      R.b0 = aff_off[k];
+      R.b1 = aff_off[k + 1];
+      R.f0 = f;
+      for (int b = R.b0; b < R.b1; ++b) {
+        Body& B = s->bodies[b];
+        const zema_affine_desc& d = aff[b];
+        B.sv0 = (int)sv_ref.size();
+        for (int i = 0; i < d.n_verts; ++i) {
+          sv_ref.push_back(-(b + 1));
+          sv_body.push_back(n_soft + b);
+          for (int q = 0; q < 3; ++q) sv_x0.push_back(d.rest_pos[3 * i + q] - B.c[q]);
+        }
+        for (int t = 0; t < d.n_tris; ++t)
+          all_tris.push_back({B.sv0 + d.tris[3 * t], B.sv0 + d.tris[3 * t + 1], B.sv0 + d.tris[3 * t + 2]});
+        if (B.mode != ZEMA_FIXED) ++f;
+      }
+      R.f1 = f;
+      R.s1 = (int)sv_ref.size();
+    }
+    for (auto& t : soft_tris) all_tris.push_back({soft_sid[t[0]], soft_sid[t[1]], soft_sid[t[2]]});
+  }
   s->nsurf = (int)sv_ref.size();
   // ---- canonical triangles and edges
   for (auto& t : all_tris) {
@@ -261,6 +307,21 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   }
   s->cell = s->nedge ? lsum / s->nedge : 1.0;
   if (!(s->cell > 0.0)) s->cell = 1.0;
+  std::vector<int> sv_scene(std::max(s->nsurf, 1), 0);
+  for (int i = 0; i < s->nsurf; ++i) sv_scene[i] = body_scene[sv_body[i]];
+  {
+    std::vector<double> csum(ns, 0.0);
+    std::vector<int> ccnt(ns, 0);
+    for (int e = 0; e < s->nedge; ++e) {
+      int k = sv_scene[edges_h[2 * e]];
+      csum[k] += std::sqrt(elen2[e]);
+      ccnt[k]++;
+    }
+    for (int k = 0; k < ns; ++k) {
+      double c = ccnt[k] ? csum[k] / ccnt[k] : s->cell;
+      s->scn[k].cell = c > 0.0 ? c : 1.0;
+    }
+  }
   // ---- static block pattern: tet node pairs and the 4x4 node blocks of free bodies
   int nn = s->nnodes;
   std::vector<unsigned long long> keys;
@@ -372,6 +433,41 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   s->body_tv.resize((size_t)3 * std::max<size_t>(s->bodies.size(), 1));
   ZCHK(hipMemset(s->body_tv.p, 0, sizeof(double) * s->body_tv.n));
   s->sv_body.upload(sv_body);
+  // ---- scene table
+  s->body_scene.upload(body_scene);
+  s->sv_scene.upload(sv_scene);
+  {
+    std::vector<int> vs(std::max(s->nsv, 1), 0), fs(std::max(s->nfree, 1), 0), rng((size_t)8 * ns);
+    for (int k = 0; k < ns; ++k) {
+      const SceneRange& R = s->scn[k];
+      for (int i = R.v0; i < R.v1; ++i) vs[i] = k;
+      for (int f = R.f0; f < R.f1; ++f) fs[f] = k;
+      int r[8] = {R.v0, R.v1, R.t0, R.t1, R.b0, R.b1, R.f0, R.f1};
+      for (int q = 0; q < 8; ++q) rng[(size_t)8 * k + q] = r[q];
+      double m = 0.0;
+      for (int i = R.v0; i < R.v1; ++i) m += mass[i];
+      s->scn[k].mbar = R.v1 > R.v0 ? m / (R.v1 - R.v0) : 1.0;
+    }
+    s->v_scene.upload(vs);
+    s->f_scene.upload(fs);
+    s->scn_rng.upload(rng);
+    std::vector<double> ic(ns), mu(ns);
+    for (int k = 0; k < ns; ++k) {
+      ic[k] = 1.0 / s->scn[k].cell;
+      mu[k] = s->scn[k].mu;
+    }
+    s->icell_sc.upload(ic);
+    s->mu_sc.upload(mu);
+    s->kappa_sc.resize(ns);
+    s->sc_u64.resize(ns);
+    s->sc_dmin.resize(ns);
+    s->sc_tmin.resize(ns);
+    s->sc_alpha.resize(ns);
+    s->sc_sum.resize((size_t)8 * ns);
+    s->sc_mask.resize(ns);
+    s->sc_rng.resize((size_t)8 * ns);
+    s->sc_cnt.resize(ns);
+  }
   s->sv_x0.upload(sv_x0);
   s->tris.upload(tris_h);
   s->edges.upload(edges_h);
@@ -404,55 +500,70 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   s->pdir.upload(yd0);
 }
 
-double auto_kappa(const zema_scene* s) {
+double auto_kappa(const zema_scene* s, int k) {
   double g = std::sqrt(s->P.gravity[0] * s->P.gravity[0] + s->P.gravity[1] * s->P.gravity[1] +
                        s->P.gravity[2] * s->P.gravity[2]);
   if (g == 0.0) g = 9.81;
-  double mbar = 1.0;
-  if (s->nsv) {
-    mbar = 0.0;
-    for (double m : s->mass_h) mbar += m;
-    mbar /= s->nsv;
-  }
-  return s->P.dt * s->P.dt * mbar * g / (s->P.dhat * (std::log(2.0) + 0.5));
+  return s->P.dt * s->P.dt * s->scn[k].mbar * g / (s->P.dhat * (std::log(2.0) + 0.5));
 }
 
-// energy terms at y on the current candidate set (surface positions recomputed)
+// host staging arrays of per-scene uploads live in the scene, so they outlive the copy
+void upload_kappa(zema_scene* s) {
+  s->kappa_h.resize(s->ns);
+  for (int k = 0; k < s->ns; ++k) s->kappa_h[k] = s->scn[k].kappa;
+  ZCHK(hipMemcpyAsync(s->kappa_sc.p, s->kappa_h.data(), sizeof(double) * s->ns, hipMemcpyHostToDevice, s->st));
+}
+
+// energy terms at y on the current candidate set (surface positions recomputed), per
+// scene: T[8 k + 0..5] the terms, 6 the total (+inf when infeasible), 7 the minimum
+// distance (+inf without pairs)
 void eval_energy(zema_scene* s, const double* y, double* T) {
   k_map_surface(s, y, s->xs.p);
   k_tet_energy(s, y);
   k_inertia_energy(s, y, s->e_in.p);
   k_body_energy(s, y);
   k_contact_energy(s);
-  int nb = (int)s->bodies.size();
-  const double* P[7] = {s->e_in.p, s->e_tet.p, s->e_body.p, s->e_body.p + nb, s->e_body.p + 2 * nb, s->e_pair.p,
-                        s->e_fric.p};
-  int64_t L[7] = {s->nsv, s->nt, nb, nb, nb, s->npt + s->nee, s->nfric};
-  double out[8];
-  k_sums(s, 7, P, L, out, s->umin.p + 1);
-  double dmin;
-  std::memcpy(&dmin, &out[7], sizeof(double));
-  T[0] = out[0] + out[2];
-  T[1] = out[1];
-  T[2] = out[3];
-  T[3] = out[4];
-  T[4] = out[5];
-  T[5] = out[6];
-  T[6] = T[0] + T[1] + T[2] + T[3] + T[4] + T[5];
-  T[7] = (s->npt + s->nee) ? dmin : INFINITY;
-  if (!std::isfinite(T[1]) || !(T[7] > 0.0)) T[6] = INFINITY;
+  if (s->ns == 1) {
+    int nb = (int)s->bodies.size();
+    const double* P[7] = {s->e_in.p, s->e_tet.p, s->e_body.p, s->e_body.p + nb, s->e_body.p + 2 * nb, s->e_pair.p,
+                          s->e_fric.p};
+    int64_t L[7] = {s->nsv, s->nt, nb, nb, nb, s->npt + s->nee, s->nfric};
+    double out[8];
+    k_sums(s, 7, P, L, out, s->sc_dmin.p);
+    unsigned long long du;
+    std::memcpy(&du, &out[7], sizeof(du));
+    double dmin;
+    std::memcpy(&dmin, &out[7], sizeof(double));
+    T[0] = out[0] + out[2];
+    T[1] = out[1];
+    T[2] = out[3];
+    T[3] = out[4];
+    T[4] = out[5];
+    T[5] = out[6];
+    T[6] = T[0] + T[1] + T[2] + T[3] + T[4] + T[5];
+    T[7] = (s->npt + s->nee) && du != ~0ull ? dmin : INFINITY;
+  } else {
+    k_scene_sums(s, T);
+  }
+  for (int k = 0; k < s->ns; ++k) {
+    double* t = T + 8 * k;
+    if (!std::isfinite(t[1]) || !(t[7] > 0.0)) t[6] = INFINITY;
+  }
 }
 
-// energies, gradient (optional) and Hessian (optional) at y on the current candidates
-void assemble(zema_scene* s, const double* y, double* grad, bool hess, unsigned mask, double* T) {
+// energies, gradient (optional) and Hessian (optional) at y on the current candidates;
+// false (and nothing assembled) when a scene's state is infeasible
+bool assemble(zema_scene* s, const double* y, double* grad, bool hess, unsigned mask, double* T) {
   eval_energy(s, y, T);
-  if (!std::isfinite(T[6])) return;
+  for (int k = 0; k < s->ns; ++k)
+    if (!std::isfinite(T[8 * k + 6])) return false;
   if (grad || hess) k_tet_assemble(s, y, hess);
   if (grad) k_gather_grad_soft(s, y, grad, mask);
   k_body_terms(s, y, grad, hess, mask);
   if (hess) k_gather_hess_static(s, mask);
   k_contact_assemble(s, grad, hess, mask);
   s->hess_valid = hess;
+  return true;
 }
 
 void static_candidates(zema_scene* s, const double* y) {
@@ -467,10 +578,12 @@ void swept_candidates(zema_scene* s, const double* y, const double* p) {
   k_candidates(s, s->xs.p, s->xs1.p, s->P.dhat);
 }
 
-double min_distance(zema_scene* s, const double* y) {
-  double T[8];
-  eval_energy(s, y, T);
-  return T[7];
+// per-scene minimum distances at y on the current candidates
+std::vector<double> min_distance(zema_scene* s, const double* y) {
+  std::vector<double> T((size_t)8 * s->ns), d(s->ns);
+  eval_energy(s, y, T.data());
+  for (int k = 0; k < s->ns; ++k) d[k] = T[8 * k + 7];
+  return d;
 }
 
 // predictor, kinematic targets and the lagged friction table at y^t = s->y
@@ -496,7 +609,8 @@ void begin_step(zema_scene* s) {
   }
   ZCHK(hipMemcpyAsync(s->body_tv.p, s->body_tv_h.data(), sizeof(double) * s->body_tv_h.size(),
                       hipMemcpyHostToDevice, s->st));
-  s->kappa_lag = s->kappa;
+  for (SceneRange& R : s->scn) R.kappa_lag = R.kappa;
+  upload_kappa(s);
   static_candidates(s, s->y.p);
   k_friction_build(s);
   ZCHK(hipStreamSynchronize(s->st));
@@ -508,7 +622,9 @@ int set_state_impl(zema_scene* s, const double* y, const double* ydot, double ka
   ZCHK(hipMemcpyAsync(s->yd_prev.p, ydot, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
   s->step = step;
   s->stepped = false;
-  s->kappa = kappa > 0.0 ? kappa : (s->P.kappa > 0.0 ? s->P.kappa : auto_kappa(s));
+  for (int k = 0; k < s->ns; ++k)
+    s->scn[k].kappa = kappa > 0.0 ? kappa : (s->P.kappa > 0.0 ? s->P.kappa : auto_kappa(s, k));
+  upload_kappa(s);
   {
     const double* P[2] = {s->y.p, s->ydot.p};
     int64_t L[2] = {s->ndof, s->ndof};
@@ -518,47 +634,53 @@ int set_state_impl(zema_scene* s, const double* y, const double* ydot, double ka
   }
   if (k_any_inverted(s, s->y.p)) throw Error(ZEMA_E_MESH, "inverted tet in state");
   begin_step(s);
-  if (!(min_distance(s, s->y.p) > 0.0)) throw Error(ZEMA_E_INTERSECT, "intersecting state");
+  for (double d : min_distance(s, s->y.p))
+    if (!(d > 0.0)) throw Error(ZEMA_E_INTERSECT, "intersecting state");
   return 0;
 }
 
-// y_out = y^t + a p, a the ACCD bound of the sweep along p, halved until no tet inverts
+// y_out = y^t + a p per scene, a the ACCD bound of that scene's sweep along p, halved
+// for a scene until none of its tets inverts
 void filtered_start(zema_scene* s, const double* p, double* y_out, double& tb, double& tc) {
+  const int ns = s->ns;
   double q = now_ms();
   swept_candidates(s, s->y.p, p);
   tb += now_ms() - q;
-  double a0;
+  std::vector<double> a0(ns);
+  std::vector<int> inv(ns);
   q = now_ms();
-  int rc = k_ccd(s, s->y.p, p, &a0);
+  int rc = k_ccd(s, s->y.p, p, a0.data());
   tc += now_ms() - q;
   if (rc) throw Error(rc, "intersecting pair at warm-start CCD");
   for (;;) {
-    k_axpy(s, s->ndof, a0, p, s->y.p, y_out);
-    if (!k_any_inverted(s, y_out)) break;
-    a0 *= 0.5;
-    if (a0 < 1e-10) {
-      ZCHK(hipMemcpyAsync(y_out, s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
-      break;
-    }
+    k_axpy_scene(s, a0.data(), p, s->y.p, y_out);
+    if (!k_inverted(s, y_out, inv.data())) break;
+    for (int k = 0; k < ns; ++k)
+      if (inv[k]) a0[k] = a0[k] * 0.5 < 1e-10 ? 0.0 : a0[k] * 0.5;
   }
 }
 
+// One time step of every scene (Sec. III: Newton on the incremental potential with
+// the intersection-free line search); scenes iterate in lockstep, a converged scene
+// stops moving (its right-hand side is zeroed) until every scene has converged.
 int time_step(zema_scene* s, zema_step_stats* st) {
   const double h = s->P.dt;
-  const int n = s->ndof;
-  std::memset(st, 0, sizeof(*st));
-  st->alpha_ccd_min = 1.0;
+  const int n = s->ndof, ns = s->ns;
+  for (int k = 0; k < ns; ++k) {
+    std::memset(&st[k], 0, sizeof(st[k]));
+    st[k].alpha_ccd_min = 1.0;
+  }
   double t0 = now_ms(), tb = 0, ta = 0, tp = 0, tc = 0, tl = 0, tw = 0, q;
-  int rc;
   q = now_ms();
   begin_step(s);
   tb += now_ms() - q;
   ZCHK(hipMemcpyAsync(s->yt.p, s->y.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
   ZCHK(hipMemcpyAsync(s->ydt.p, s->ydot.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
+  std::vector<double> T((size_t)8 * ns), T1((size_t)8 * ns), E0((size_t)8 * ns);
   // initial guess: y^t + a h ydot^t with a the CCD bound of that sweep; with the
-  // learned form also the network's proposal, filtered the same way and kept only
-  // if its energy is not higher (swept_candidates uses ytmp, so the learned start
-  // is formed first, into ywarm)
+  // learned form also the network's proposal, filtered the same way and kept per
+  // scene only if its energy is not higher (swept_candidates uses ytmp, so the
+  // learned start is formed first, into ywarm)
   k_scale(s, n, h, s->ydot.p, s->pdir.p);
   const bool learned = s->P.warm_start == ZEMA_WARM_LEARNED;
   if (learned) {
@@ -575,92 +697,150 @@ int time_step(zema_scene* s, zema_step_stats* st) {
   filtered_start(s, s->pdir.p, s->ytmp.p, tb, tc);
   if (learned) {
     q = now_ms();
-    double Tp[8], Tl[8];
     static_candidates(s, s->ytmp.p);
-    eval_energy(s, s->ytmp.p, Tp);
+    eval_energy(s, s->ytmp.p, T.data());
     static_candidates(s, s->ywarm.p);
-    eval_energy(s, s->ywarm.p, Tl);
-    tw += now_ms() - q;
-    if (std::isfinite(Tl[6]) && Tl[6] <= Tp[6]) {
-      std::swap(s->ytmp.p, s->ywarm.p);
-      st->warm_learned = 1;
+    eval_energy(s, s->ywarm.p, T1.data());
+    s->mask_h.assign(ns, 0);
+    for (int k = 0; k < ns; ++k) {
+      s->mask_h[k] = std::isfinite(T1[8 * k + 6]) && T1[8 * k + 6] <= T[8 * k + 6];
+      st[k].warm_learned = s->mask_h[k];
     }
+    k_select_scene(s, s->mask_h.data(), s->ywarm.p, s->ytmp.p, s->grad.p);  // grad is free here
+    std::swap(s->ytmp.p, s->grad.p);
+    tw += now_ms() - q;
   }
   std::swap(s->y.p, s->ytmp.p);
   q = now_ms();
   static_candidates(s, s->y.p);
   tb += now_ms() - q;
-  double dprev = min_distance(s, s->y.p);
+  std::vector<double> dprev = min_distance(s, s->y.p);
   const bool auto_k = s->P.kappa <= 0.0;
   const double tol = s->P.newton_tol * h;
   const int pcg_max = s->P.pcg_max;
-  bool conv = false;
-  int it = 0;
-  double T[8];
-  for (; it < s->P.newton_max; ++it) {
+  std::vector<int> active(ns, 1), done(ns, 0), pit(ns), pst(ns);
+  std::vector<double> alpha(ns), disp(ns), rr(ns);
+  int n_active = ns;
+  for (int it = 0; it < s->P.newton_max && n_active > 0; ++it) {
     q = now_ms();
-    assemble(s, s->y.p, s->grad.p, true, 0x3fu, T);
+    bool ok = assemble(s, s->y.p, s->grad.p, true, 0x3fu, T.data());
     ta += now_ms() - q;
-    if (!std::isfinite(T[6])) throw Error(ZEMA_E_INTERSECT, "infeasible Newton iterate");
-    st->energy = T[6];
-    st->n_pt_active = s->n_act;  // active barrier pairs (point-triangle and edge-edge)
-    st->n_ee_active = s->nfric;  // lagged friction pairs
+    if (!ok) throw Error(ZEMA_E_INTERSECT, "infeasible Newton iterate");
+    for (int k = 0; k < ns; ++k)
+      if (active[k]) {
+        st[k].energy = T[8 * k + 6];
+        st[k].newton_iters = it;
+      }
+    if (ns == 1) {
+      st[0].n_pt_active = s->n_act;  // active barrier pairs (point-triangle and edge-edge)
+      st[0].n_ee_active = s->nfric;  // lagged friction pairs
+    }
     k_scale(s, n, -1.0, s->grad.p, s->ytmp.p);
-    int pit;
-    double rr;
     q = now_ms();
-    rc = k_pcg(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, pcg_max, &pit, &rr);
+    if (ns == 1) {
+      double r1;
+      int rc = k_pcg(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, pcg_max, &pit[0], &r1);
+      pst[0] = rc;
+    } else {
+      k_pcg_batch(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, pcg_max, active.data(), pit.data(), rr.data(),
+                  pst.data());
+    }
     tp += now_ms() - q;
-    st->pcg_iters += pit;
-    if (rc) throw Error(rc, "PCG failed");
-    if (k_max_disp(s, s->pdir.p) <= tol) {
-      conv = true;
-      break;
+    for (int k = 0; k < ns; ++k)
+      if (active[k]) {
+        st[k].pcg_iters += pit[k];
+        if (pst[k]) throw Error(pst[k], "PCG failed");
+      }
+    k_max_disp(s, s->pdir.p, disp.data());
+    for (int k = 0; k < ns; ++k)
+      if (active[k] && disp[k] <= tol) {
+        active[k] = 0;
+        done[k] = 1;
+        --n_active;
+      }
+    if (n_active == 0) break;
+    // finished scenes take no step: their direction is zero (they were not solved)
+    if (ns > 1) {
+      s->scale_h.resize(ns);
+      for (int k = 0; k < ns; ++k) s->scale_h[k] = active[k] ? 1.0 : 0.0;
+      k_scale_scene(s, s->scale_h.data(), s->pdir.p);
     }
     q = now_ms();
     swept_candidates(s, s->y.p, s->pdir.p);
     tb += now_ms() - q;
-    st->n_pt_cand = (int)s->npt;
-    st->n_ee_cand = (int)s->nee;
-    double alpha;
+    if (ns == 1) {
+      st[0].n_pt_cand = (int)s->npt;
+      st[0].n_ee_cand = (int)s->nee;
+    }
     q = now_ms();
-    rc = k_ccd(s, s->y.p, s->pdir.p, &alpha);
+    int rc = k_ccd(s, s->y.p, s->pdir.p, alpha.data());
     tc += now_ms() - q;
     if (rc) throw Error(rc, "intersecting pair at CCD start");
-    st->alpha_ccd_min = std::min(st->alpha_ccd_min, alpha);
+    for (int k = 0; k < ns; ++k) {
+      if (!active[k]) alpha[k] = 0.0;
+      else st[k].alpha_ccd_min = std::min(st[k].alpha_ccd_min, alpha[k]);
+    }
     q = now_ms();
-    double E0[8], E1[8];
-    eval_energy(s, s->y.p, E0);
+    eval_energy(s, s->y.p, E0.data());
+    std::vector<int> acc(ns);
+    for (int k = 0; k < ns; ++k) acc[k] = !active[k];
     for (;;) {
-      k_axpy(s, n, alpha, s->pdir.p, s->y.p, s->ytmp.p);
-      eval_energy(s, s->ytmp.p, E1);
-      if (std::isfinite(E1[6]) && E1[6] <= E0[6]) break;
-      alpha *= 0.5;
-      st->ls_backtracks++;
-      if (alpha < 1e-10) throw Error(ZEMA_E_LINESEARCH, "line search failed");
+      k_axpy_scene(s, alpha.data(), s->pdir.p, s->y.p, s->ytmp.p);
+      eval_energy(s, s->ytmp.p, T1.data());
+      bool all = true;
+      for (int k = 0; k < ns; ++k) {
+        if (acc[k]) continue;
+        if (std::isfinite(T1[8 * k + 6]) && T1[8 * k + 6] <= E0[8 * k + 6]) {
+          acc[k] = 1;
+          continue;
+        }
+        all = false;
+        alpha[k] *= 0.5;
+        st[k].ls_backtracks++;
+        if (alpha[k] < 1e-10) throw Error(ZEMA_E_LINESEARCH, "line search failed");
+      }
+      if (all) break;
     }
     tl += now_ms() - q;
     std::swap(s->y.p, s->ytmp.p);
-    double dm = E1[7];
-    if (auto_k && dm < 1e-3 * s->P.dhat && dm < dprev) s->kappa *= 2.0;
-    dprev = dm;
+    bool kchg = false;
+    for (int k = 0; k < ns; ++k) {
+      if (!active[k]) continue;
+      double dm = T1[8 * k + 7];
+      if (auto_k && dm < 1e-3 * s->P.dhat && dm < dprev[k]) {
+        s->scn[k].kappa *= 2.0;
+        kchg = true;
+      }
+      dprev[k] = dm;
+    }
+    if (kchg) upload_kappa(s);
   }
-  st->newton_iters = it;
-  st->kappa = s->kappa;
-  st->d_min = min_distance(s, s->y.p);
-  if (!conv) throw Error(ZEMA_E_NEWTON, "Newton did not converge");
+  std::vector<double> dfin = min_distance(s, s->y.p);
+  for (int k = 0; k < ns; ++k) {
+    if (active[k]) st[k].newton_iters = s->P.newton_max;
+    st[k].kappa = s->scn[k].kappa;
+    st[k].d_min = dfin[k];
+  }
+  if (n_active > 0) {
+    for (int k = 0; k < ns; ++k)
+      if (active[k]) st[k].status = ZEMA_E_NEWTON;
+    throw Error(ZEMA_E_NEWTON, "Newton did not converge");
+  }
   ZCHK(hipMemcpyAsync(s->yd_prev.p, s->ydt.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
   k_velocity(s, 1.0 / h);
   s->step += 1;
   ZCHK(hipStreamSynchronize(s->st));
   kt_fold(s);
-  st->ms_total = now_ms() - t0;
-  st->ms_assemble = ta;
-  st->ms_pcg = tp;
-  st->ms_broad = tb;
-  st->ms_ccd = tc;
-  st->ms_linesearch = tl;
-  st->ms_warm = tw;
+  double tt = now_ms() - t0;
+  for (int k = 0; k < ns; ++k) {
+    st[k].ms_total = tt;
+    st[k].ms_assemble = ta;
+    st[k].ms_pcg = tp;
+    st[k].ms_broad = tb;
+    st[k].ms_ccd = tc;
+    st[k].ms_linesearch = tl;
+    st[k].ms_warm = tw;
+  }
   return 0;
 }
 
@@ -756,7 +936,9 @@ int zema_scene_create(const zema_params* params, const zema_soft_desc* soft, int
   s->P = *params;
   s->st = (hipStream_t)hip_stream;
   int rc = guard(s, [&]() {
-    build_scene(s, soft, n_soft, affine, n_affine);
+    int so[2] = {0, n_soft}, ao[2] = {0, n_affine};
+    double mu = params->mu;
+    build_scene(s, soft, n_soft, affine, n_affine, so, ao, 1, &mu);
     return set_state_impl(s, s->ytmp.p, s->pdir.p, 0.0, 0);
   });
   if (rc) {
@@ -764,6 +946,56 @@ int zema_scene_create(const zema_params* params, const zema_soft_desc* soft, int
     return rc;
   }
   *out = s;
+  return 0;
+}
+
+int zema_batch_create(const zema_params* params, int32_t n_scenes, const zema_soft_desc* soft,
+                      const int32_t* soft_off, const zema_affine_desc* affine, const int32_t* aff_off,
+                      void* hip_stream, zema_scene** out) {
+  if (!params || !out || n_scenes <= 0 || !soft_off || !aff_off) return ZEMA_E_ARG;
+  *out = nullptr;
+  const zema_params& P0 = params[0];
+  for (int k = 0; k < n_scenes; ++k) {
+    const zema_params& P = params[k];
+    if (!(P.dt > 0.0) || !(P.dhat > 0.0)) return ZEMA_E_ARG;
+    if (P.precision != ZEMA_FP64 && P.precision != ZEMA_MIXED) return ZEMA_E_ARG;
+    if (P.warm_start != ZEMA_WARM_EXPLICIT && P.warm_start != ZEMA_WARM_LEARNED) return ZEMA_E_ARG;
+    // everything but the friction coefficient is shared by the scenes of a batch
+    bool same = P.dt == P0.dt && P.dhat == P0.dhat && P.kappa == P0.kappa && P.eps_v == P0.eps_v &&
+                P.gravity[0] == P0.gravity[0] && P.gravity[1] == P0.gravity[1] && P.gravity[2] == P0.gravity[2] &&
+                P.newton_tol == P0.newton_tol && P.pcg_rtol == P0.pcg_rtol && P.ccd_s == P0.ccd_s &&
+                P.newton_max == P0.newton_max && P.pcg_max == P0.pcg_max && P.precision == P0.precision &&
+                P.warm_start == P0.warm_start;
+    if (!same) return ZEMA_E_ARG;
+  }
+  int n_soft = soft_off[n_scenes], n_aff = aff_off[n_scenes];
+  if (n_soft < 0 || n_aff < 0 || (n_soft && !soft) || (n_aff && !affine)) return ZEMA_E_ARG;
+  zema_scene* s = new zema_scene();
+  s->P = P0;
+  s->st = (hipStream_t)hip_stream;
+  int rc = guard(s, [&]() {
+    std::vector<double> mu(n_scenes);
+    for (int k = 0; k < n_scenes; ++k) mu[k] = params[k].mu;
+    build_scene(s, soft, n_soft, affine, n_aff, soft_off, aff_off, n_scenes, mu.data());
+    return set_state_impl(s, s->ytmp.p, s->pdir.p, 0.0, 0);
+  });
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return 0;
+}
+
+int zema_batch_layout(const zema_scene* s, int32_t* n_scenes, int64_t* ranges) {
+  if (!s || !n_scenes) return ZEMA_E_ARG;
+  *n_scenes = s->ns;
+  if (ranges)
+    for (int k = 0; k < s->ns; ++k) {
+      const SceneRange& R = s->scn[k];
+      int64_t r[8] = {R.v0, R.v1, R.f0, R.f1, R.t0, R.t1, R.s0, R.s1};
+      for (int q = 0; q < 8; ++q) ranges[8 * k + q] = r[q];
+    }
   return 0;
 }
 
@@ -797,7 +1029,7 @@ int zema_get_state(zema_scene* s, double* y, double* ydot, double* kappa, int32_
     if (y) ZCHK(hipMemcpyAsync(y, s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
     if (ydot) ZCHK(hipMemcpyAsync(ydot, s->ydot.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
     ZCHK(hipStreamSynchronize(s->st));
-    if (kappa) *kappa = s->kappa;
+    if (kappa) *kappa = s->scn[0].kappa;
     if (step) *step = s->step;
     return 0;
   });
@@ -805,8 +1037,12 @@ int zema_get_state(zema_scene* s, double* y, double* ydot, double* kappa, int32_
 
 int zema_set_kappa(zema_scene* s, double kappa) {
   if (!s || !(kappa > 0.0)) return ZEMA_E_ARG;
-  s->kappa = kappa;
-  return 0;
+  return guard(s, [&]() {
+    for (SceneRange& R : s->scn) R.kappa = kappa;
+    upload_kappa(s);
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
 }
 
 int zema_surface_positions(zema_scene* s, const double* y, double* xs) {
@@ -834,7 +1070,7 @@ int zema_contact_candidates(zema_scene* s, const double* xs0, const double* xs1,
 }
 
 int zema_ip_assemble(zema_scene* s, const double* y, uint32_t flags, double* terms, double* grad) {
-  if (!s || !y || !terms) return ZEMA_E_ARG;
+  if (!s || !y || !terms || s->ns != 1) return ZEMA_E_ARG;
   if ((flags & ZEMA_GRAD) && !grad) return ZEMA_E_ARG;
   return guard(s, [&]() {
     unsigned mask = (flags >> ZEMA_TERMS_SHIFT) & 0x3fu;
@@ -863,7 +1099,7 @@ int zema_hessian_matvec(zema_scene* s, const double* v, double* out) {
 
 int zema_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, int32_t max_iter, int32_t* iters,
                    double* rel_res) {
-  if (!s || !rhs || !sol || !iters || !rel_res || !s->hess_valid) return ZEMA_E_ARG;
+  if (!s || !rhs || !sol || !iters || !rel_res || !s->hess_valid || s->ns != 1) return ZEMA_E_ARG;
   return guard(s, [&]() {
     int it;
     double rr;
@@ -876,7 +1112,7 @@ int zema_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, i
 }
 
 int zema_ccd_max_step(zema_scene* s, const double* y, const double* p, double* alpha) {
-  if (!s || !y || !p || !alpha) return ZEMA_E_ARG;
+  if (!s || !y || !p || !alpha || s->ns != 1) return ZEMA_E_ARG;
   return guard(s, [&]() {
     swept_candidates(s, y, p);
     int rc = k_ccd(s, y, p, alpha);
@@ -896,9 +1132,9 @@ int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
     int rc = guard(s, [&]() {
       ZCHK(hipMemcpyAsync(s->yt.p, s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
       ZCHK(hipMemcpyAsync(s->ydt.p, s->ydot.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
-      return time_step(s, &stats[k]);
+      return time_step(s, &stats[(size_t)k * s->ns]);
     });
-    stats[k].status = rc;
+    for (int j = 0; j < s->ns; ++j) stats[(size_t)k * s->ns + j].status = rc;
     s->stepped = rc == 0;
     if (rc) {
       // restore y^t and ydot^t of the failed step

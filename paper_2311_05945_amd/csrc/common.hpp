@@ -96,6 +96,31 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Per-scene extremum of non-negative doubles (ordered as their bits): one atomic per
+// wavefront when all its lanes belong to the same scene, else one per lane.  sc < 0
+// contributes nothing.  Min and max are order-independent, so the result is exact.
+template <bool MAX>
+__device__ inline void scene_atomic_ext(unsigned long long* out, int sc, double v) {
+  int sc0 = __shfl(sc, 0, 64);
+  if (__all(sc == sc0)) {
+    for (int o = 32; o > 0; o >>= 1) {
+      double w = __shfl_xor(v, o, 64);
+      v = MAX ? fmax(v, w) : fmin(v, w);
+    }
+    if ((threadIdx.x & 63) == 0 && sc0 >= 0) {
+      if (MAX)
+        atomicMax(out + sc0, dbits(v));
+      else
+        atomicMin(out + sc0, dbits(v));
+    }
+  } else if (sc >= 0) {
+    if (MAX)
+      atomicMax(out + sc, dbits(v));
+    else
+      atomicMin(out + sc, dbits(v));
+  }
+}
+
 // Deterministic block sum (fixed tree), result valid in thread 0.
 template <int B>
 __device__ inline double block_sum(double v, double* sh) {

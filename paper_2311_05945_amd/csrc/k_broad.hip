@@ -18,14 +18,13 @@ namespace zema {
 constexpr int kBigCells = 512;
 constexpr int kCellBias = 1 << 20;
 
-struct Grid {
-  double inv_c;
-};
-
 __device__ inline int cell_of(double z, double inv_c) { return (int)floor(__dmul_rn(z, inv_c)); }
 
-__device__ inline unsigned hash3(int ix, int iy, int iz, unsigned mask) {
-  return (((unsigned)ix * 73856093u) ^ ((unsigned)iy * 19349663u) ^ ((unsigned)iz * 83492791u)) & mask;
+// cells of different scenes of a batch hash apart (scene 0 leaves the hash unchanged)
+__device__ inline unsigned hash3(int ix, int iy, int iz, int sc, unsigned mask) {
+  return (((unsigned)ix * 73856093u) ^ ((unsigned)iy * 19349663u) ^ ((unsigned)iz * 83492791u) ^
+          ((unsigned)sc * 2654435761u)) &
+         mask;
 }
 
 __device__ inline unsigned long long pack_cell(int ix, int iy, int iz) {
@@ -97,33 +96,45 @@ __device__ inline int prim_body(int kind, int id, const int* tris, const int* ed
   return sv_body[edges[2 * id]];
 }
 
+// scene tables of the search: per surface vertex and per body scene, per-scene 1/cell
+struct SceneTab {
+  const int *sv_body, *body_scene;
+  const double* icell;
+};
+
+__device__ inline int prim_scene(int kind, int id, const int* tris, const int* edges, const SceneTab& S) {
+  return S.body_scene[prim_body(kind, id, tris, edges, S.sv_body)];
+}
+
 // entries: count cells of every entry primitive (0 for large ones, flagged in big)
-__global__ void entry_count_kernel(PrimSet E, const double* __restrict__ lo, const double* __restrict__ hi,
-                                   double inv_c, int* __restrict__ cnt, int* __restrict__ big_flag) {
+__global__ void entry_count_kernel(PrimSet E, int ekind, const double* __restrict__ lo, const double* __restrict__ hi,
+                                   SceneTab S, const int* __restrict__ tris, const int* __restrict__ edges,
+                                   int* __restrict__ cnt, int* __restrict__ big_flag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E.n) return;
   int c0[3], c1[3];
-  long long n = cell_range(lo, hi, E.base + i, inv_c, c0, c1);
+  long long n = cell_range(lo, hi, E.base + i, S.icell[prim_scene(ekind, i, tris, edges, S)], c0, c1);
   cnt[i] = n < 0 ? 0 : (int)n;
   big_flag[i] = n < 0 ? 1 : 0;
 }
 
 __global__ void entry_insert_kernel(PrimSet E, int ekind, const double* __restrict__ lo, const double* __restrict__ hi,
-                                    double inv_c, const int* __restrict__ offs, unsigned mask,
+                                    SceneTab S, const int* __restrict__ offs, unsigned mask,
                                     unsigned long long* __restrict__ key, int* __restrict__ val,
                                     unsigned long long* __restrict__ ecell, int* __restrict__ eprim,
                                     int* __restrict__ ebody, const int* __restrict__ tris,
-                                    const int* __restrict__ edges, const int* __restrict__ sv_body) {
+                                    const int* __restrict__ edges) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= E.n) return;
   int c0[3], c1[3];
-  if (cell_range(lo, hi, E.base + i, inv_c, c0, c1) < 0) return;
+  int body = prim_body(ekind, i, tris, edges, S.sv_body);
+  int sc = S.body_scene[body];
+  if (cell_range(lo, hi, E.base + i, S.icell[sc], c0, c1) < 0) return;
   int o = offs[i];
-  int body = prim_body(ekind, i, tris, edges, sv_body);
   for (int x = c0[0]; x <= c1[0]; ++x)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int z = c0[2]; z <= c1[2]; ++z, ++o) {
-        key[o] = hash3(x, y, z, mask);
+        key[o] = hash3(x, y, z, sc, mask);
         val[o] = o;
         ecell[o] = pack_cell(x, y, z);
         eprim[o] = i;
@@ -158,11 +169,13 @@ struct PairRule {
   int same_set;      // edge-edge: report (q, e) only when q < e
 };
 
-__device__ inline bool admissible(PairRule R, int q, int e, const int* tris, const int* edges, const int* sv_body,
+// inter-body pairs of one scene, not both on fixed bodies
+__device__ inline bool admissible(PairRule R, int q, int e, const int* tris, const int* edges, const SceneTab& S,
                                   const unsigned char* fixed) {
   if (R.same_set && !(q < e)) return false;
-  int bq = prim_body(R.qkind, q, tris, edges, sv_body), be = prim_body(R.ekind, e, tris, edges, sv_body);
+  int bq = prim_body(R.qkind, q, tris, edges, S.sv_body), be = prim_body(R.ekind, e, tris, edges, S.sv_body);
   if (bq == be) return false;
+  if (S.body_scene[bq] != S.body_scene[be]) return false;
   if (fixed[bq] && fixed[be]) return false;
   return true;
 }
@@ -173,40 +186,42 @@ __device__ inline void emit(unsigned long long key, unsigned long long* out, int
 }
 
 __global__ void query_kernel(PrimSet Q, PrimSet E, PairRule R, const double* __restrict__ lo,
-                             const double* __restrict__ hi, double inv_c, unsigned mask, const int* __restrict__ blo,
+                             const double* __restrict__ hi, SceneTab S, unsigned mask, const int* __restrict__ blo,
                              const int* __restrict__ bhi, const unsigned long long* __restrict__ scell,
                              const int* __restrict__ sprim, const int* __restrict__ sbody,
                              const int* __restrict__ ebig, const int* __restrict__ tris,
-                             const int* __restrict__ edges, const int* __restrict__ sv_body,
-                             const unsigned char* __restrict__ fixed, unsigned long long nE,
-                             unsigned long long* __restrict__ out, int* __restrict__ counter, int cap) {
+                             const int* __restrict__ edges, const unsigned char* __restrict__ fixed,
+                             unsigned long long nE, unsigned long long* __restrict__ out, int* __restrict__ counter,
+                             int cap) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= Q.n) return;
   int qi = Q.base + q;
   int c0[3], c1[3];
+  const int bq = prim_body(R.qkind, q, tris, edges, S.sv_body);
+  const int sq = S.body_scene[bq];
+  const double inv_c = S.icell[sq];
   if (cell_range(lo, hi, qi, inv_c, c0, c1) < 0) {
     // large query box: for a shared set every pair with a large member is reported
     // by big_entry_kernel; otherwise test every small entry directly
     if (R.same_set) return;
     for (int e = 0; e < E.n; ++e) {
       if (ebig[e]) continue;
-      if (!admissible(R, q, e, tris, edges, sv_body, fixed)) continue;
+      if (!admissible(R, q, e, tris, edges, S, fixed)) continue;
       if (overlap(lo, hi, qi, E.base + e)) emit((unsigned long long)q * nE + e, out, counter, cap);
     }
     return;
   }
-  const int bq = prim_body(R.qkind, q, tris, edges, sv_body);
   for (int x = c0[0]; x <= c1[0]; ++x)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int z = c0[2]; z <= c1[2]; ++z) {
-        unsigned h = hash3(x, y, z, mask);
+        unsigned h = hash3(x, y, z, sq, mask);
         unsigned long long ck = pack_cell(x, y, z);
         int j1 = bhi[h];
         for (int j = blo[h]; j < j1; ++j) {
           if (sbody[j] == bq) continue;  // same body: never a candidate
           if (scell[j] != ck) continue;
           int e = sprim[j];
-          if (!admissible(R, q, e, tris, edges, sv_body, fixed)) continue;
+          if (!admissible(R, q, e, tris, edges, S, fixed)) continue;
           int ei = E.base + e;
           if (!overlap(lo, hi, qi, ei)) continue;
           // report only from the cell holding max(lo_q, lo_e)
@@ -223,8 +238,8 @@ __global__ void query_kernel(PrimSet Q, PrimSet E, PairRule R, const double* __r
 // not already covered: the other primitive small, or large with a larger id)
 __global__ void big_entry_kernel(PrimSet Q, PrimSet E, PairRule R, const double* __restrict__ lo,
                                  const double* __restrict__ hi, const int* __restrict__ ebig,
-                                 const int* __restrict__ tris, const int* __restrict__ edges,
-                                 const int* __restrict__ sv_body, const unsigned char* __restrict__ fixed,
+                                 const int* __restrict__ tris, const int* __restrict__ edges, SceneTab S,
+                                 const unsigned char* __restrict__ fixed,
                                  unsigned long long nE, unsigned long long* __restrict__ out, int* __restrict__ counter,
                                  int cap) {
   for (int e = blockIdx.x; e < E.n; e += gridDim.x) {
@@ -234,10 +249,10 @@ __global__ void big_entry_kernel(PrimSet Q, PrimSet E, PairRule R, const double*
       if (q == e) continue;
       int a = q < e ? q : e, b = q < e ? e : q;
       if (ebig[q] && !(e < q)) continue;  // both large: reported by the smaller id
-      if (!admissible(R, a, b, tris, edges, sv_body, fixed)) continue;
+      if (!admissible(R, a, b, tris, edges, S, fixed)) continue;
       if (overlap(lo, hi, Q.base + q, E.base + e)) emit((unsigned long long)a * nE + b, out, counter, cap);
     } else {
-      if (!admissible(R, q, e, tris, edges, sv_body, fixed)) continue;
+      if (!admissible(R, q, e, tris, edges, S, fixed)) continue;
       if (overlap(lo, hi, Q.base + q, E.base + e)) emit((unsigned long long)q * nE + e, out, counter, cap);
     }
   }
@@ -264,11 +279,12 @@ static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>
     out.resize(0);
     return 0;
   }
-  const double inv_c = 1.0 / s->cell;
+  const SceneTab S{s->sv_body.p, s->body_scene.p, s->icell_sc.p};
   s->cnt.reserve(E.n + 1);
   s->offs.reserve(E.n + 1);
   s->big_list.reserve(E.n + 1);
-  entry_count_kernel<<<nblocks(E.n), kBlock, 0, s->st>>>(E, s->bb_lo.p, s->bb_hi.p, inv_c, s->cnt.p, s->big_list.p);
+  entry_count_kernel<<<nblocks(E.n), kBlock, 0, s->st>>>(E, R.ekind, s->bb_lo.p, s->bb_hi.p, S, s->tris.p, s->edges.p,
+                                                         s->cnt.p, s->big_list.p);
   int64_t total = k_exclusive_scan(s, s->cnt.p, s->offs.p, E.n);
   unsigned tsize = 1024;
   while (tsize < 2 * total) tsize <<= 1;
@@ -282,9 +298,9 @@ static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>
   s->bucket_lo.reserve(tsize);
   s->bucket_hi.reserve(tsize);
   if (total > 0) {
-    entry_insert_kernel<<<nblocks(E.n), kBlock, 0, s->st>>>(E, R.ekind, s->bb_lo.p, s->bb_hi.p, inv_c, s->offs.p,
-                                                            mask, sb.k0.p, sb.v0.p, s->ent_cell.p, s->ent_prim.p,
-                                                            s->ent_body.p, s->tris.p, s->edges.p, s->sv_body.p);
+    entry_insert_kernel<<<nblocks(E.n), kBlock, 0, s->st>>>(E, R.ekind, s->bb_lo.p, s->bb_hi.p, S, s->offs.p, mask,
+                                                            sb.k0.p, sb.v0.p, s->ent_cell.p, s->ent_prim.p,
+                                                            s->ent_body.p, s->tris.p, s->edges.p);
     k_radix_sort(s, sb, total, bits_for(mask));
     // sorted copies live in the second halves of ent_cell / ent_prim
     entry_permute_kernel<<<nblocks(total), kBlock, 0, s->st>>>((int)total, sb.v0.p, s->ent_cell.p, s->ent_prim.p,
@@ -301,13 +317,14 @@ static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>
     int cap = (int)std::min<size_t>(s->pair_keys.cap, (size_t)INT32_MAX);
     ZCHK(hipMemsetAsync(counter, 0, sizeof(int), s->st));
     kt_begin(s, KT_QUERY);
-    query_kernel<<<nblocks(Q.n, 128), 128, 0, s->st>>>(
-        Q, E, R, s->bb_lo.p, s->bb_hi.p, inv_c, mask, s->bucket_lo.p, s->bucket_hi.p, s->ent_cell.p + total,
-        s->ent_prim.p + total, s->ent_body.p + total, s->big_list.p, s->tris.p, s->edges.p, s->sv_body.p, s->body_fixed.p, nE,
-        s->pair_keys.p, counter, cap);
+    query_kernel<<<nblocks(Q.n, 128), 128, 0, s->st>>>(Q, E, R, s->bb_lo.p, s->bb_hi.p, S, mask, s->bucket_lo.p,
+                                                        s->bucket_hi.p, s->ent_cell.p + total, s->ent_prim.p + total,
+                                                        s->ent_body.p + total, s->big_list.p, s->tris.p, s->edges.p,
+                                                        s->body_fixed.p, nE, s->pair_keys.p, counter, cap);
     kt_end(s, KT_QUERY);
-    big_entry_kernel<<<std::min(E.n, 1024), kBlock, 0, s->st>>>(Q, E, R, s->bb_lo.p, s->bb_hi.p, s->big_list.p, s->tris.p, s->edges.p,
-                                                s->sv_body.p, s->body_fixed.p, nE, s->pair_keys.p, counter, cap);
+    big_entry_kernel<<<std::min(E.n, 1024), kBlock, 0, s->st>>>(Q, E, R, s->bb_lo.p, s->bb_hi.p, s->big_list.p,
+                                                                s->tris.p, s->edges.p, S, s->body_fixed.p, nE,
+                                                                s->pair_keys.p, counter, cap);
     int n;
     ZCHK(hipMemcpyAsync(&n, counter, sizeof(int), hipMemcpyDeviceToHost, s->st));
     ZCHK(hipStreamSynchronize(s->st));

@@ -4,6 +4,7 @@
 // linearly in the step size because x = A x0 + p is linear in q, so linear CCD is
 // exact for them too.  The global bound is min(1, min_k t_k).
 #include <cstring>
+#include <vector>
 
 #include "geom.hpp"
 #include "scene.hpp"
@@ -12,10 +13,11 @@ namespace zema {
 
 __global__ void accd_kernel(int npt, int nee, const int* __restrict__ pt, const int* __restrict__ ee,
                             const int* __restrict__ tris, const int* __restrict__ edges, const double* __restrict__ xs,
-                            const double* __restrict__ dx, double s_sep, unsigned long long* __restrict__ tmin,
-                            int* __restrict__ bad) {
+                            const double* __restrict__ dx, double s_sep, const int* __restrict__ sv_scene,
+                            unsigned long long* __restrict__ tmin, int* __restrict__ bad) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   double t = 1.0;
+  int sc = -1;
   if (k < npt + nee) {
     int kind, sv[4];
     if (k < npt) {
@@ -33,6 +35,7 @@ __global__ void accd_kernel(int npt, int nee, const int* __restrict__ pt, const 
       sv[2] = edges[2 * eb];
       sv[3] = edges[2 * eb + 1];
     }
+    sc = sv_scene[sv[0]];
     V3 x[4], p[4];
     for (int a = 0; a < 4; ++a) {
       x[a] = ld3(xs + 3 * sv[a]);
@@ -69,33 +72,34 @@ __global__ void accd_kernel(int npt, int nee, const int* __restrict__ pt, const 
       }
     }
   }
-  for (int o = 32; o > 0; o >>= 1) t = fmin(t, __shfl_xor(t, o, 64));
-  if ((threadIdx.x & 63) == 0) atomicMin(tmin, dbits(t));
+  scene_atomic_ext<false>(tmin, sc, t);
 }
 
-// alpha_max over the current candidate set for the move y -> y + p
+// per scene: alpha_max over the current candidate set for the move y -> y + p
+// (alpha [ns], host); a pair already at zero distance fails the call
 int k_ccd(zema_scene* s, const double* y, const double* p, double* alpha) {
   k_map_surface(s, y, s->xs.p);
   k_surface_disp(s, p, s->dxs.p);
   int n = (int)(s->npt + s->nee);
-  unsigned long long one_bits = 0x3ff0000000000000ull;  // 1.0
-  ZCHK(hipMemcpyAsync(s->umin.p + 2, &one_bits, sizeof(one_bits), hipMemcpyHostToDevice, s->st));
+  ZCHK(hipMemsetAsync(s->sc_tmin.p, 0xff, sizeof(unsigned long long) * s->ns, s->st));  // no pair: 1
   int* bad = s->counters.p + 5;
   ZCHK(hipMemsetAsync(bad, 0, sizeof(int), s->st));
   if (n) {
     kt_begin(s, KT_CCD);
     accd_kernel<<<nblocks(n), kBlock, 0, s->st>>>((int)s->npt, (int)s->nee, s->pt.p, s->ee.p, s->tris.p, s->edges.p,
-                                                  s->xs.p, s->dxs.p, s->P.ccd_s, s->umin.p + 2, bad);
+                                                  s->xs.p, s->dxs.p, s->P.ccd_s, s->sv_scene.p, s->sc_tmin.p, bad);
     kt_end(s, KT_CCD);
   }
-  unsigned long long u;
+  std::vector<unsigned long long> u(s->ns);
   int b;
-  ZCHK(hipMemcpyAsync(&u, s->umin.p + 2, sizeof(u), hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipMemcpyAsync(u.data(), s->sc_tmin.p, sizeof(unsigned long long) * s->ns, hipMemcpyDeviceToHost, s->st));
   ZCHK(hipMemcpyAsync(&b, bad, sizeof(b), hipMemcpyDeviceToHost, s->st));
   ZCHK(hipStreamSynchronize(s->st));
-  double t;
-  std::memcpy(&t, &u, sizeof(t));
-  *alpha = t < 1.0 ? t : 1.0;
+  for (int k = 0; k < s->ns; ++k) {
+    double t = 1.0;
+    if (u[k] != ~0ull) std::memcpy(&t, &u[k], sizeof(t));
+    alpha[k] = t < 1.0 ? t : 1.0;
+  }
   return b ? ZEMA_E_INTERSECT : 0;
 }
 

@@ -36,25 +36,28 @@ __device__ inline void pair_slots(int k, int npt, const int* __restrict__ pt, co
 }
 
 // ------------------------------------------------------------------ energies (line search)
+// barrier energy and distance of every candidate pair; per-scene minimum distance
 __global__ void contact_energy_kernel(int npt, int nee, const int* __restrict__ pt, const int* __restrict__ ee,
                                       const int* __restrict__ tris, const int* __restrict__ edges,
-                                      const double* __restrict__ elen2, const double* __restrict__ xs, double kappa,
+                                      const double* __restrict__ elen2, const double* __restrict__ xs,
+                                      const double* __restrict__ kappa_sc, const int* __restrict__ sv_scene,
                                       double dhat, double* __restrict__ e_pair, double* __restrict__ d_pair,
                                       unsigned long long* __restrict__ dmin) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   double d = INFINITY;
+  int sc = -1;
   if (k < npt + nee) {
     int kind, sv[4], ea, eb;
     pair_slots(k, npt, pt, ee, tris, edges, kind, sv, ea, eb);
+    sc = sv_scene[sv[0]];
     V3 x[4];
     for (int a = 0; a < 4; ++a) x[a] = ld3(xs + 3 * sv[a]);
     double eps = kind == 1 ? 1e-3 * elen2[ea] * elen2[eb] : 0.0;
-    e_pair[k] = pair_barrier_energy(kind, x, eps, kappa, dhat, &d);
+    e_pair[k] = pair_barrier_energy(kind, x, eps, kappa_sc[sc], dhat, &d);
     if (d != d) d = 0.0;  // a non-finite distance makes the state infeasible, never inactive
     d_pair[k] = d;
   }
-  for (int o = 32; o > 0; o >>= 1) d = fmin(d, __shfl_xor(d, o, 64));
-  if ((threadIdx.x & 63) == 0 && d < INFINITY) atomicMin(dmin, dbits(d));
+  scene_atomic_ext<false>(dmin, sc, d);
 }
 
 // friction: f0 and the coefficients of the 3x3 core  alpha Pi - beta u u^T
@@ -79,10 +82,12 @@ __device__ inline V3 friction_u(const double* __restrict__ fv, const double* __r
 }
 
 __global__ void friction_energy_kernel(int nf, const int* __restrict__ fids, const double* __restrict__ fvals,
-                                       const double* __restrict__ fxt, const double* __restrict__ xs, double mu,
-                                       double ys, double* __restrict__ e) {
+                                       const double* __restrict__ fxt, const double* __restrict__ xs,
+                                       const double* __restrict__ mu_sc, const int* __restrict__ sv_scene, double ys,
+                                       double* __restrict__ e) {
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
+  const double mu = mu_sc[sv_scene[fids[5 * f + 1]]];
   V3 x[4];
   for (int a = 0; a < 4; ++a) x[a] = ld3(xs + 3 * fids[5 * f + 1 + a]);
   V3 u = friction_u(fvals + 8 * f, fxt + 12 * f, x);
@@ -109,7 +114,8 @@ __global__ void friction_flag_kernel(int npt, int nee, const int* __restrict__ p
 // closest points, w = closest-point weights (PT: 1, -beta_i; EE: 1-ga, ga, -(1-gb), -gb)
 __global__ void friction_fill_kernel(int npt, int nee, const int* __restrict__ pt, const int* __restrict__ ee,
                                      const int* __restrict__ tris, const int* __restrict__ edges,
-                                     const double* __restrict__ elen2, const double* __restrict__ xs, double kappa,
+                                     const double* __restrict__ elen2, const double* __restrict__ xs,
+                                     const double* __restrict__ kappa_sc, const int* __restrict__ sv_scene,
                                      double dhat, const int* __restrict__ flag, const int* __restrict__ offs,
                                      int* __restrict__ fids, double* __restrict__ fvals, double* __restrict__ fxt) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -117,6 +123,7 @@ __global__ void friction_fill_kernel(int npt, int nee, const int* __restrict__ p
   int f = offs[k];
   int kind, sv[4], ea, eb;
   pair_slots(k, npt, pt, ee, tris, edges, kind, sv, ea, eb);
+  const double kappa = kappa_sc[sv_scene[sv[0]]];
   V3 x[4];
   for (int a = 0; a < 4; ++a) x[a] = ld3(xs + 3 * sv[a]);
   double w[4];
@@ -213,7 +220,9 @@ struct ItemArgs {
   int npt, nee, n_act, nfric;
   const int *pt, *ee, *tris, *edges, *act, *sv_ref, *bi, *fids;
   const double *elen2, *xs, *sv_x0, *fvals, *fxt;
-  double kappa, dhat, mu, ys;
+  const double *kappa_sc, *mu_sc;
+  const int* sv_scene;
+  double dhat, ys;
   int nn_total, hess;
 };
 
@@ -269,14 +278,14 @@ __global__ void __launch_bounds__(64) pair_deriv_kernel(ItemArgs A, double* __re
   if (!fric) {
     double eps = kind == 1 ? 1e-3 * A.elen2[ea] * A.elen2[eb] : 0.0;
     double E, d;
-    pair_barrier(kind, x, eps, A.kappa, A.dhat, E, g, H, &d);
+    pair_barrier(kind, x, eps, A.kappa_sc[A.sv_scene[sv[0]]], A.dhat, E, g, H, &d);
   } else {
     int f = i - A.n_act;
     const double* fv = A.fvals + 8 * f;
     V3 u = friction_u(fv, A.fxt + 12 * f, x);
     double y = sqrt(dot(u, u)), f1y, al, be;
     friction_core(y, A.ys, f1y, al, be);
-    double c = A.mu * fv[0];
+    double c = A.mu_sc[A.sv_scene[sv[0]]] * fv[0];
     V3 n = ld3(fv + 1);
     double U[3] = {u.x, u.y, u.z}, N[3] = {n.x, n.y, n.z};
     for (int a = 0; a < 4; ++a)
@@ -524,6 +533,91 @@ __global__ void row_ptr_kernel(int nrows, int nnzc, const int* __restrict__ crow
   cptr[r] = lo;
 }
 
+// ------------------------------------------------------------------ per-scene energy sums (batches)
+// Candidate and friction lists are sorted by the scene-major surface numbering, so
+// every scene owns one run of PT pairs, one of EE pairs and (PT items first) one run
+// of each friction kind; run bounds go to rng[8 sc + slot], rng[8 sc + slot + 1].
+__global__ void runs_kernel(int mode, int n, int base, const int* __restrict__ a, const int* __restrict__ edges,
+                            const int* __restrict__ sv_scene, int ns, int* __restrict__ rng) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  auto key = [&](int j, int& sc, int& slot) {
+    if (mode == 0) {
+      sc = sv_scene[a[2 * j]];
+      slot = 0;
+    } else if (mode == 1) {
+      sc = sv_scene[edges[2 * a[2 * j]]];
+      slot = 2;
+    } else {
+      int kind = a[5 * j];
+      sc = sv_scene[a[5 * j + 1]];
+      slot = 4 + 2 * kind;
+    }
+    return slot * ns + sc;
+  };
+  int sc, slot, o1, o2;
+  int k = key(i, sc, slot);
+  if (i == 0 || key(i - 1, o1, o2) != k) rng[8 * sc + slot] = base + i;
+  if (i == n - 1 || key(i + 1, o1, o2) != k) rng[8 * sc + slot + 1] = base + i + 1;
+}
+
+__device__ inline double range_sum(const double* __restrict__ a, int lo, int hi, double* sh) {
+  double acc = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += kBlock) acc += a[i];
+  return block_sum<kBlock>(acc, sh);
+}
+
+// one block per scene: T[0] inertia, 1 elastic, 2 orthogonality, 3 kinematic,
+// 4 barrier, 5 friction, 6 total, 7 minimum distance (+inf without pairs)
+__global__ void scene_sums_kernel(const int* __restrict__ srng, const int* __restrict__ drng,
+                                  const double* __restrict__ e_in, const double* __restrict__ e_tet,
+                                  const double* __restrict__ e_body, int nb, const double* __restrict__ e_pair,
+                                  const double* __restrict__ e_fric, const unsigned long long* __restrict__ dmin,
+                                  double* __restrict__ out) {
+  __shared__ double sh[kBlock / 64];
+  int k = blockIdx.x;
+  const int* R = srng + 8 * k;
+  const int* D = drng + 8 * k;
+  double in_s = range_sum(e_in, R[0], R[1], sh);
+  double in_b = range_sum(e_body, R[4], R[5], sh);
+  double el = range_sum(e_tet, R[2], R[3], sh);
+  double orth = range_sum(e_body + nb, R[4], R[5], sh);
+  double kin = range_sum(e_body + 2 * nb, R[4], R[5], sh);
+  double bar = range_sum(e_pair, D[0], D[1], sh) + range_sum(e_pair, D[2], D[3], sh);
+  double fr = range_sum(e_fric, D[4], D[5], sh) + range_sum(e_fric, D[6], D[7], sh);
+  if (threadIdx.x == 0) {
+    double* T = out + 8 * k;
+    T[0] = in_s + in_b;
+    T[1] = el;
+    T[2] = orth;
+    T[3] = kin;
+    T[4] = bar;
+    T[5] = fr;
+    T[6] = T[0] + T[1] + T[2] + T[3] + T[4] + T[5];
+    unsigned long long u = dmin[k];
+    T[7] = u == ~0ull ? INFINITY : __longlong_as_double((long long)u);
+  }
+}
+
+void k_scene_sums(zema_scene* s, double* out_host) {
+  const int ns = s->ns;
+  ZCHK(hipMemsetAsync(s->sc_rng.p, 0, sizeof(int) * 8 * ns, s->st));
+  if (s->npt)
+    runs_kernel<<<nblocks(s->npt), kBlock, 0, s->st>>>(0, (int)s->npt, 0, s->pt.p, s->edges.p, s->sv_scene.p, ns,
+                                                       s->sc_rng.p);
+  if (s->nee)
+    runs_kernel<<<nblocks(s->nee), kBlock, 0, s->st>>>(1, (int)s->nee, (int)s->npt, s->ee.p, s->edges.p,
+                                                       s->sv_scene.p, ns, s->sc_rng.p);
+  if (s->nfric)
+    runs_kernel<<<nblocks(s->nfric), kBlock, 0, s->st>>>(2, s->nfric, 0, s->f_ids.p, s->edges.p, s->sv_scene.p, ns,
+                                                         s->sc_rng.p);
+  int nb = (int)s->bodies.size();
+  scene_sums_kernel<<<ns, kBlock, 0, s->st>>>(s->scn_rng.p, s->sc_rng.p, s->e_in.p, s->e_tet.p, s->e_body.p, nb,
+                                              s->e_pair.p, s->e_fric.p, s->sc_dmin.p, s->sc_sum.p);
+  ZCHK(hipMemcpyAsync(out_host, s->sc_sum.p, sizeof(double) * 8 * ns, hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+}
+
 // ------------------------------------------------------------------ launchers
 static int bits_for(unsigned long long v) {
   int b = 0;
@@ -535,17 +629,18 @@ void k_contact_energy(zema_scene* s) {
   int nc = (int)(s->npt + s->nee);
   s->e_pair.reserve(nc + 1);
   s->d_pair.reserve(nc + 1);
-  unsigned long long inf_bits = 0x7ff0000000000000ull;
-  ZCHK(hipMemcpyAsync(s->umin.p + 1, &inf_bits, sizeof(inf_bits), hipMemcpyHostToDevice, s->st));
+  // all-ones bits: no pair in the scene (read back as +infinity)
+  ZCHK(hipMemsetAsync(s->sc_dmin.p, 0xff, sizeof(unsigned long long) * s->ns, s->st));
   if (nc)
     contact_energy_kernel<<<nblocks(nc), kBlock, 0, s->st>>>((int)s->npt, (int)s->nee, s->pt.p, s->ee.p, s->tris.p,
-                                                             s->edges.p, s->elen2.p, s->xs.p, s->kappa, s->P.dhat,
-                                                             s->e_pair.p, s->d_pair.p, s->umin.p + 1);
+                                                             s->edges.p, s->elen2.p, s->xs.p, s->kappa_sc.p,
+                                                             s->sv_scene.p, s->P.dhat, s->e_pair.p, s->d_pair.p,
+                                                             s->sc_dmin.p);
   s->e_fric.reserve(s->nfric + 1);
   if (s->nfric)
     friction_energy_kernel<<<nblocks(s->nfric), kBlock, 0, s->st>>>(s->nfric, s->f_ids.p, s->f_vals.p, s->f_xt.p,
-                                                                     s->xs.p, s->P.mu, s->P.eps_v * s->P.dt,
-                                                                     s->e_fric.p);
+                                                                     s->xs.p, s->mu_sc.p, s->sv_scene.p,
+                                                                     s->P.eps_v * s->P.dt, s->e_fric.p);
 }
 
 void k_friction_build(zema_scene* s) {
@@ -563,8 +658,9 @@ void k_friction_build(zema_scene* s) {
   s->f_xt.reserve(12 * nf + 12);
   if (nf)
     friction_fill_kernel<<<nblocks(nc), kBlock, 0, s->st>>>((int)s->npt, (int)s->nee, s->pt.p, s->ee.p, s->tris.p,
-                                                            s->edges.p, s->elen2.p, s->xs.p, s->kappa, s->P.dhat,
-                                                            s->cnt.p, s->offs.p, s->f_ids.p, s->f_vals.p, s->f_xt.p);
+                                                            s->edges.p, s->elen2.p, s->xs.p, s->kappa_sc.p,
+                                                            s->sv_scene.p, s->P.dhat, s->cnt.p, s->offs.p, s->f_ids.p,
+                                                            s->f_vals.p, s->f_xt.p);
 }
 
 void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
@@ -605,9 +701,10 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   A.sv_x0 = s->sv_x0.p;
   A.fvals = s->f_vals.p;
   A.fxt = s->f_xt.p;
-  A.kappa = s->kappa;
+  A.kappa_sc = s->kappa_sc.p;
+  A.mu_sc = s->mu_sc.p;
+  A.sv_scene = s->sv_scene.p;
   A.dhat = s->P.dhat;
-  A.mu = s->P.mu;
   A.ys = s->P.eps_v * s->P.dt;
   A.nn_total = s->nnodes;
   A.hess = hess ? 1 : 0;

@@ -97,12 +97,16 @@ __global__ void predict_kernel(int nsoft3, int ndof, double h, double gx, double
   yhat[i] = y[i] + h * v[i] + h * h * g;
 }
 
+// per scene: the largest vertex displacement |(J p)_i| over soft and affine vertices
 __global__ void max_disp_kernel(int nsv, int nsurf, const int* __restrict__ ref, const double* __restrict__ x0,
                                 const double* __restrict__ p, const int* __restrict__ bi,
+                                const int* __restrict__ v_scene, const int* __restrict__ sv_scene,
                                 unsigned long long* __restrict__ out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   double m = 0.0;
+  int sc = -1;
   if (i < nsv) {
+    sc = v_scene[i];
     double a = p[3 * i], b = p[3 * i + 1], c = p[3 * i + 2];
     m = sqrt(a * a + b * b + c * c);
   } else if (i < nsv + nsurf) {
@@ -110,6 +114,7 @@ __global__ void max_disp_kernel(int nsv, int nsurf, const int* __restrict__ ref,
     int r = ref[j];
     if (r < 0) {
       int dof0 = bi[4 * (-r - 1) + 1];
+      sc = sv_scene[j];
       if (dof0 >= 0) {
         const double* q = p + dof0;
         double s2 = 0.0;
@@ -121,9 +126,36 @@ __global__ void max_disp_kernel(int nsv, int nsurf, const int* __restrict__ ref,
       }
     }
   }
-  // wave maximum, then one atomic per wave (non-negative doubles order as integers)
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, dbits(m));
+  scene_atomic_ext<true>(out, sc, m);
+}
+
+// out = y + alpha[scene] p, the scene of a DOF taken from its soft vertex or free body
+__global__ void axpy_scene_kernel(int ndof, int nsv, const double* __restrict__ alpha, const int* __restrict__ v_scene,
+                                  const int* __restrict__ f_scene, const double* __restrict__ p,
+                                  const double* __restrict__ y, double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndof) return;
+  int sc = i < 3 * nsv ? v_scene[i / 3] : f_scene[(i - 3 * nsv) / 12];
+  out[i] = y[i] + alpha[sc] * p[i];
+}
+
+// p *= alpha[scene] in place
+__global__ void scale_scene_kernel(int ndof, int nsv, const double* __restrict__ alpha,
+                                   const int* __restrict__ v_scene, const int* __restrict__ f_scene, double* p) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndof) return;
+  int sc = i < 3 * nsv ? v_scene[i / 3] : f_scene[(i - 3 * nsv) / 12];
+  p[i] *= alpha[sc];
+}
+
+// out = mask[scene] ? a : b per DOF
+__global__ void select_scene_kernel(int ndof, int nsv, const int* __restrict__ mask, const int* __restrict__ v_scene,
+                                    const int* __restrict__ f_scene, const double* __restrict__ a,
+                                    const double* __restrict__ b, double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndof) return;
+  int sc = i < 3 * nsv ? v_scene[i / 3] : f_scene[(i - 3 * nsv) / 12];
+  out[i] = mask[sc] ? a[i] : b[i];
 }
 
 constexpr int kSumGrid = 256;
@@ -151,18 +183,15 @@ __global__ void sums_l2(const double* __restrict__ part, double* __restrict__ ou
   if (threadIdx.x == 0) out[k] = r;
 }
 
+// per scene: number of tets with non-positive volume at y
 __global__ void inverted_kernel(int nt, const int4* __restrict__ tets, const double* __restrict__ y,
-                                unsigned int* __restrict__ cnt) {
+                                const int* __restrict__ v_scene, unsigned int* __restrict__ cnt) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
-  int bad = 0;
-  if (e < nt) {
-    int4 t = tets[e];
-    V3 x0 = ld3(y + 3 * t.x), x1 = ld3(y + 3 * t.y), x2 = ld3(y + 3 * t.z), x3 = ld3(y + 3 * t.w);
-    double J = dot(x1 - x0, cross(x2 - x0, x3 - x0));
-    bad = !(J > 0.0);
-  }
-  unsigned long long b = __ballot(bad);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(cnt, (unsigned int)__popcll(b));
+  if (e >= nt) return;
+  int4 t = tets[e];
+  V3 x0 = ld3(y + 3 * t.x), x1 = ld3(y + 3 * t.y), x2 = ld3(y + 3 * t.z), x3 = ld3(y + 3 * t.w);
+  double J = dot(x1 - x0, cross(x2 - x0, x3 - x0));
+  if (!(J > 0.0)) atomicAdd(cnt + v_scene[t.x], 1u);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -200,17 +229,36 @@ void k_predict(zema_scene* s) {
                                                            s->yhat.p);
 }
 
-double k_max_disp(zema_scene* s, const double* p) {
-  ZCHK(hipMemsetAsync(s->umin.p, 0, sizeof(unsigned long long), s->st));
+void k_max_disp(zema_scene* s, const double* p, double* out) {
+  unsigned long long* u = s->sc_u64.p;
+  ZCHK(hipMemsetAsync(u, 0, sizeof(unsigned long long) * s->ns, s->st));
   int n = s->nsv + s->nsurf;
-  if (n) max_disp_kernel<<<nblocks(n), kBlock, 0, s->st>>>(s->nsv, s->nsurf, s->sv_ref.p, s->sv_x0.p, p, s->body_i.p,
-                                                           s->umin.p);
-  unsigned long long u;
-  ZCHK(hipMemcpyAsync(&u, s->umin.p, sizeof(u), hipMemcpyDeviceToHost, s->st));
+  if (n)
+    max_disp_kernel<<<nblocks(n), kBlock, 0, s->st>>>(s->nsv, s->nsurf, s->sv_ref.p, s->sv_x0.p, p, s->body_i.p,
+                                                      s->v_scene.p, s->sv_scene.p, u);
+  ZCHK(hipMemcpyAsync(out, u, sizeof(double) * s->ns, hipMemcpyDeviceToHost, s->st));
   ZCHK(hipStreamSynchronize(s->st));
-  double d;
-  std::memcpy(&d, &u, sizeof(d));
-  return d;
+}
+
+void k_axpy_scene(zema_scene* s, const double* alpha_host, const double* p, const double* y, double* out) {
+  ZCHK(hipMemcpyAsync(s->sc_alpha.p, alpha_host, sizeof(double) * s->ns, hipMemcpyHostToDevice, s->st));
+  if (s->ndof)
+    axpy_scene_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(s->ndof, s->nsv, s->sc_alpha.p, s->v_scene.p,
+                                                              s->f_scene.p, p, y, out);
+}
+
+void k_scale_scene(zema_scene* s, const double* alpha_host, double* p) {
+  ZCHK(hipMemcpyAsync(s->sc_alpha.p, alpha_host, sizeof(double) * s->ns, hipMemcpyHostToDevice, s->st));
+  if (s->ndof)
+    scale_scene_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(s->ndof, s->nsv, s->sc_alpha.p, s->v_scene.p,
+                                                               s->f_scene.p, p);
+}
+
+void k_select_scene(zema_scene* s, const int* mask_host, const double* a, const double* b, double* out) {
+  ZCHK(hipMemcpyAsync(s->sc_mask.p, mask_host, sizeof(int) * s->ns, hipMemcpyHostToDevice, s->st));
+  if (s->ndof)
+    select_scene_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(s->ndof, s->nsv, s->sc_mask.p, s->v_scene.p,
+                                                                s->f_scene.p, a, b, out);
 }
 
 void k_sums(zema_scene* s, int nseg, const double* const* ptr, const int64_t* len, double* out_host,
@@ -228,15 +276,22 @@ void k_sums(zema_scene* s, int nseg, const double* const* ptr, const int64_t* le
   ZCHK(hipStreamSynchronize(s->st));
 }
 
-bool k_any_inverted(zema_scene* s, const double* y) {
-  if (!s->nt) return false;
-  unsigned int* c = reinterpret_cast<unsigned int*>(s->counters.p + 8);
-  ZCHK(hipMemsetAsync(c, 0, sizeof(unsigned int), s->st));
-  inverted_kernel<<<nblocks(s->nt), kBlock, 0, s->st>>>(s->nt, s->tets.p, y, c);
-  unsigned int h;
-  ZCHK(hipMemcpyAsync(&h, c, sizeof(h), hipMemcpyDeviceToHost, s->st));
+// per scene: 1 if any tet of the scene is inverted at y; returns whether any is
+bool k_inverted(zema_scene* s, const double* y, int* out) {
+  unsigned int* c = s->sc_cnt.p;
+  ZCHK(hipMemsetAsync(c, 0, sizeof(unsigned int) * s->ns, s->st));
+  if (s->nt) inverted_kernel<<<nblocks(s->nt), kBlock, 0, s->st>>>(s->nt, s->tets.p, y, s->v_scene.p, c);
+  std::vector<unsigned int> h(s->ns);
+  ZCHK(hipMemcpyAsync(h.data(), c, sizeof(unsigned int) * s->ns, hipMemcpyDeviceToHost, s->st));
   ZCHK(hipStreamSynchronize(s->st));
-  return h != 0;
+  bool any = false;
+  for (int k = 0; k < s->ns; ++k) {
+    if (out) out[k] = h[k] != 0;
+    any = any || h[k] != 0;
+  }
+  return any;
 }
+
+bool k_any_inverted(zema_scene* s, const double* y) { return k_inverted(s, y, nullptr); }
 
 }  // namespace zema

@@ -43,7 +43,7 @@ __device__ inline bf4 pack(f4 a) {
   return r;
 }
 
-struct MlpLds {
+struct __align__(16) MlpLds {
   unsigned short W1[64 * 16], W2[64 * 64], W3[64 * 64], W4[16 * 64];  // [out][in], W4 rows 3..15 zero
   unsigned short W2T[64 * 64], W3T[64 * 64], W4T[64 * 16];             // [in][out]
   float b1[64], b2[64], b3[64], b4[16];
@@ -144,7 +144,8 @@ __global__ void __launch_bounds__(64) mlp_grad_kernel(const float* __restrict__ 
                                                       long nrows, long n, float* __restrict__ gpart,
                                                       double* __restrict__ lpart) {
   __shared__ MlpLds L;
-  __shared__ unsigned short Td[64 * 16], Th[64 * 16];  // [row][vertex] transposition tiles
+  __shared__ __align__(16) unsigned short Td[64 * 16];  // [row][vertex] transposition tiles
+  __shared__ __align__(16) unsigned short Th[64 * 16];
   load_weights(th, L, true);
   __syncthreads();
   const int lane = threadIdx.x, m = lane & 15, q = lane >> 4;

@@ -506,4 +506,264 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   return 0;
 }
 
+
+// ------------------------------------------------------------------ batched PCG
+// A batch of scenes has a block-diagonal Newton system; each scene runs its own CG
+// (own alpha, beta, residual test and breakdown flag) in lockstep with the others.
+// Per-scene dot products are summed by one block per scene over the scene's nodes in
+// a fixed order.  Per-scene scalars [ns][16]: 0 rz, 2 alpha, 3 beta, 4 rr, 5 bb,
+// 6 done, 7 iterations, 8 breakdown, 9 rtol^2 bb.
+
+__device__ inline int node_scene(int node, int nsv, const int* v_scene, const int* f_scene) {
+  return node < nsv ? v_scene[node] : f_scene[(node - nsv) >> 2];
+}
+
+// per-node values of r.z, b.b (init) or r.z, r.r (update): unit-major writes
+__global__ void pcgb_init_kernel(int nsv, int nfree, const double* __restrict__ b, const double* __restrict__ ms,
+                                 const double* __restrict__ mb, double* __restrict__ x, double* __restrict__ r,
+                                 double* __restrict__ z, double* __restrict__ p, double* __restrict__ d1,
+                                 double* __restrict__ d2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsv + nfree) return;
+  int o = i < nsv ? 3 * i : 3 * nsv + 12 * (i - nsv), n = i < nsv ? 3 : 12;
+  for (int k = 0; k < n; ++k) {
+    x[o + k] = 0.0;
+    r[o + k] = b[o + k];
+    p[o + k] = 0.0;
+  }
+  apply_minv(i, nsv, ms, mb, b, z);
+  double rz = 0.0, bb = 0.0;
+  for (int k = 0; k < n; ++k) {
+    rz += b[o + k] * z[o + k];
+    bb += b[o + k] * b[o + k];
+  }
+  d1[i] = rz;
+  d2[i] = bb;
+}
+
+// sum of a per-unit array over scene k's units (soft vertices, then free bodies)
+__device__ inline double scene_unit_sum(const double* __restrict__ a, const int* __restrict__ rng, int k, int nsv,
+                                        double* sh) {
+  const int* R = rng + 8 * k;
+  int nv = R[1] - R[0], nf = R[7] - R[6];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nv + nf; i += kBlock) acc += i < nv ? a[R[0] + i] : a[nsv + R[6] + (i - nv)];
+  return block_sum<kBlock>(acc, sh);
+}
+
+__global__ void pcgb_init_fin(const double* __restrict__ d1, const double* __restrict__ d2,
+                              const int* __restrict__ rng, const int* __restrict__ active, int nsv,
+                              double* __restrict__ sc, double rtol) {
+  __shared__ double sh[kBlock / 64];
+  int k = blockIdx.x;
+  double rz = scene_unit_sum(d1, rng, k, nsv, sh);
+  double bb = scene_unit_sum(d2, rng, k, nsv, sh);
+  if (threadIdx.x == 0) {
+    double* c = sc + 16 * k;
+    c[0] = rz;
+    c[2] = 0.0;
+    c[3] = 0.0;
+    c[4] = bb;
+    c[5] = bb;
+    c[6] = (bb == 0.0 || !active[k]) ? 1.0 : 0.0;
+    c[7] = 0.0;
+    c[8] = 0.0;
+    c[9] = rtol * rtol * bb;
+  }
+}
+
+// q = H p with p = z + beta_scene p_old formed in the gathers; p stored; per-node
+// p.q.  Rows of finished scenes are skipped.
+template <class V>
+__global__ void pcgb_spmv_kernel(Mat<V> M, const int* __restrict__ v_scene, const int* __restrict__ f_scene,
+                                 const double* __restrict__ sc, const double* __restrict__ z,
+                                 const double* __restrict__ pold, double* __restrict__ pnew, double* __restrict__ q,
+                                 double* __restrict__ pq) {
+  __shared__ double red[3 * (kBlock / 64)];
+  int nsoft_blocks = (M.nsv + (kBlock / RG) - 1) / (kBlock / RG);
+  if ((int)blockIdx.x < nsoft_blocks) {
+    int row = blockIdx.x * (kBlock / RG) + threadIdx.x / RG;
+    int lane = threadIdx.x % RG;
+    if (row >= M.nsv) return;
+    const double* c = sc + 16 * v_scene[row];
+    if (c[6] != 0.0) return;  // the whole 16-lane group leaves together
+    double beta = c[3];
+    Acc3<V> acc = row_partial(M, row, lane, RG, z, pold, beta);
+    for (int o = RG / 2; o > 0; o >>= 1) {
+      acc.x += __shfl_xor(acc.x, o, RG);
+      acc.y += __shfl_xor(acc.y, o, RG);
+      acc.z += __shfl_xor(acc.z, o, RG);
+    }
+    if (lane == 0) {
+      V3 qv = v3(double(acc.x), double(acc.y), double(acc.z));
+      st3(q + 3 * row, qv);
+      V3 xv = ld3(z + 3 * row) + beta * ld3(pold + 3 * row);
+      st3(pnew + 3 * row, xv);
+      pq[row] = dot(xv, qv);
+    }
+  } else {
+    int row = M.nsv + (blockIdx.x - nsoft_blocks);
+    const double* c = sc + 16 * f_scene[(row - M.nsv) >> 2];
+    if (c[6] != 0.0) return;  // uniform over the block
+    double beta = c[3];
+    Acc3<V> acc = row_partial(M, row, threadIdx.x, kBlock, z, pold, beta);
+    for (int o = 32; o > 0; o >>= 1) {
+      acc.x += __shfl_xor(acc.x, o, 64);
+      acc.y += __shfl_xor(acc.y, o, 64);
+      acc.z += __shfl_xor(acc.z, o, 64);
+    }
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+      red[3 * w] = double(acc.x);
+      red[3 * w + 1] = double(acc.y);
+      red[3 * w + 2] = double(acc.z);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      V3 sq = v3(0, 0, 0);
+      for (int k = 0; k < kBlock / 64; ++k) sq = sq + v3(red[3 * k], red[3 * k + 1], red[3 * k + 2]);
+      st3(q + 3 * row, sq);
+      V3 xv = ld3(z + 3 * row) + beta * ld3(pold + 3 * row);
+      st3(pnew + 3 * row, xv);
+      pq[row] = dot(xv, sq);
+    }
+  }
+}
+
+// per scene: pq over its nodes (soft vertices, then 4 nodes per free body) -> alpha
+__global__ void pcgb_alpha_kernel(const double* __restrict__ pq, const int* __restrict__ rng, int nsv,
+                                  double* __restrict__ sc) {
+  __shared__ double sh[kBlock / 64];
+  int k = blockIdx.x;
+  double* c = sc + 16 * k;
+  if (c[6] != 0.0) return;
+  const int* R = rng + 8 * k;
+  int nv = R[1] - R[0], nn = 4 * (R[7] - R[6]);
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nv + nn; i += kBlock) acc += i < nv ? pq[R[0] + i] : pq[nsv + 4 * R[6] + (i - nv)];
+  double t = block_sum<kBlock>(acc, sh);
+  if (threadIdx.x == 0) {
+    if (!(t > 0.0)) {
+      c[8] = 1.0;
+      c[6] = 1.0;
+    } else {
+      c[2] = c[0] / t;
+    }
+  }
+}
+
+__global__ void pcgb_update_kernel(int nsv, int nfree, const int* __restrict__ v_scene,
+                                   const int* __restrict__ f_scene, const double* __restrict__ sc,
+                                   const double* __restrict__ p, const double* __restrict__ q,
+                                   const double* __restrict__ ms, const double* __restrict__ mb,
+                                   double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+                                   double* __restrict__ d1, double* __restrict__ d2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsv + nfree) return;
+  const double* c = sc + 16 * (i < nsv ? v_scene[i] : f_scene[i - nsv]);
+  if (c[6] != 0.0) return;
+  double alpha = c[2];
+  int o = i < nsv ? 3 * i : 3 * nsv + 12 * (i - nsv), n = i < nsv ? 3 : 12;
+  for (int k = 0; k < n; ++k) {
+    x[o + k] += alpha * p[o + k];
+    r[o + k] -= alpha * q[o + k];
+  }
+  apply_minv(i, nsv, ms, mb, r, z);
+  double rz = 0.0, rr = 0.0;
+  for (int k = 0; k < n; ++k) {
+    rz += r[o + k] * z[o + k];
+    rr += r[o + k] * r[o + k];
+  }
+  d1[i] = rz;
+  d2[i] = rr;
+}
+
+__global__ void pcgb_beta_kernel(const double* __restrict__ d1, const double* __restrict__ d2,
+                                 const int* __restrict__ rng, int nsv, int it, double* __restrict__ sc) {
+  __shared__ double sh[kBlock / 64];
+  int k = blockIdx.x;
+  double* c = sc + 16 * k;
+  if (c[6] != 0.0) return;
+  double rz = scene_unit_sum(d1, rng, k, nsv, sh);
+  double rr = scene_unit_sum(d2, rng, k, nsv, sh);
+  if (threadIdx.x == 0) {
+    c[7] = it + 1;
+    c[4] = rr;
+    if (rr <= c[9]) {
+      c[6] = 1.0;
+    } else {
+      c[3] = rz / c[0];
+      c[0] = rz;
+    }
+  }
+}
+
+// Batched solve: scenes with active[k] == 0 get x = 0 and count as converged.
+// iters / relres / status: host arrays [ns].
+void k_pcg_batch(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, const int* active_host,
+                 int* iters, double* relres, int* status) {
+  const int ns = s->ns, n = s->ndof, nunits = s->nsv + s->nfree;
+  if (max_iter <= 0) max_iter = std::max(n, 1);
+  k_build_precond(s);  // block-Jacobi inverses of the current Hessian (allocates them)
+  s->pr.reserve(n);
+  s->pz.reserve(n);
+  s->pp0.reserve(n);
+  s->pp1.reserve(n);
+  s->pq.reserve(n);
+  s->partial.reserve((size_t)2 * nunits + s->nnodes + 8);
+  double* d1 = s->partial.p;
+  double* d2 = s->partial.p + nunits + 1;
+  double* pqn = s->partial.p + 2 * (size_t)nunits + 2;
+  s->scal.reserve((size_t)16 * ns);
+  double* sc = s->scal.p;
+  ZCHK(hipMemcpyAsync(s->sc_mask.p, active_host, sizeof(int) * ns, hipMemcpyHostToDevice, s->st));
+  if (nunits)
+    pcgb_init_kernel<<<nblocks(nunits), kBlock, 0, s->st>>>(s->nsv, s->nfree, rhs, s->minv_soft.p, s->minv_body.p,
+                                                            sol, s->pr.p, s->pz.p, s->pp0.p, d1, d2);
+  pcgb_init_fin<<<ns, kBlock, 0, s->st>>>(d1, d2, s->scn_rng.p, s->sc_mask.p, s->nsv, sc, rtol);
+  auto M64 = make_mat<double>(s, s->bsr_val.p, s->c_val.p);
+  auto M32 = make_mat<float>(s, s->bsr_val32.p, s->c_val32.p);
+  int g = spmv_grid(s);
+  double* pold = s->pp0.p;
+  double* pnew = s->pp1.p;
+  std::vector<double> hs((size_t)16 * ns);
+  const int chunk = 16;
+  int it = 0;
+  for (;;) {
+    for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
+      kt_begin(s, KT_SPMV);
+      if (g) {
+        if (s->mixed)
+          pcgb_spmv_kernel<float><<<g, kBlock, 0, s->st>>>(M32, s->v_scene.p, s->f_scene.p, sc, s->pz.p, pold, pnew,
+                                                           s->pq.p, pqn);
+        else
+          pcgb_spmv_kernel<double><<<g, kBlock, 0, s->st>>>(M64, s->v_scene.p, s->f_scene.p, sc, s->pz.p, pold, pnew,
+                                                            s->pq.p, pqn);
+      }
+      kt_end(s, KT_SPMV, (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 32.0 * s->ndof);
+      pcgb_alpha_kernel<<<ns, kBlock, 0, s->st>>>(pqn, s->scn_rng.p, s->nsv, sc);
+      if (nunits)
+        pcgb_update_kernel<<<nblocks(nunits), kBlock, 0, s->st>>>(s->nsv, s->nfree, s->v_scene.p, s->f_scene.p, sc,
+                                                                  pnew, s->pq.p, s->minv_soft.p, s->minv_body.p, sol,
+                                                                  s->pr.p, s->pz.p, d1, d2);
+      pcgb_beta_kernel<<<ns, kBlock, 0, s->st>>>(d1, d2, s->scn_rng.p, s->nsv, it, sc);
+      std::swap(pold, pnew);
+    }
+    ZCHK(hipMemcpyAsync(hs.data(), sc, sizeof(double) * 16 * ns, hipMemcpyDeviceToHost, s->st));
+    ZCHK(hipStreamSynchronize(s->st));
+    bool all = true;
+    for (int k = 0; k < ns; ++k) all = all && hs[16 * k + 6] != 0.0;
+    if (all || it >= max_iter) break;
+  }
+  int bad;
+  ZCHK(hipMemcpyAsync(&bad, s->counters.p + 4, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+  for (int k = 0; k < ns; ++k) {
+    const double* c = hs.data() + 16 * k;
+    iters[k] = (int)c[7];
+    relres[k] = c[5] > 0.0 ? std::sqrt(c[4] / c[5]) : 0.0;
+    status[k] = (bad || c[8] != 0.0 || c[6] == 0.0) ? ZEMA_E_PCG : 0;
+  }
+}
+
 }  // namespace zema

@@ -44,6 +44,16 @@ struct KTimer {
   std::vector<double> pending;  // bytes of launches not folded yet
 };
 
+// Ranges of one scene of a batch (a single scene is a batch of one).  Soft vertices,
+// tets, affine bodies, free affine bodies (nodes nsv + 4 f ...) and surface vertices
+// of a scene are contiguous; so are its candidate pairs, which are sorted by the
+// scene-major surface numbering.
+struct SceneRange {
+  int v0 = 0, v1 = 0, t0 = 0, t1 = 0, b0 = 0, b1 = 0, f0 = 0, f1 = 0, s0 = 0, s1 = 0;
+  double mu = 0.0, cell = 1.0, mbar = 1.0;
+  double kappa = 0.0, kappa_lag = 0.0, dprev = 0.0;
+};
+
 // Buffers for one radix sort of (key, value) pairs.
 struct SortBufs {
   DBuf<unsigned long long> k0, k1;
@@ -59,6 +69,18 @@ struct zema_scene {
   std::string err;
   int n_soft_bodies = 0, n_bodies = 0;
   int nsv = 0, nt = 0, nsurf = 0, ntri = 0, nedge = 0, nfree = 0, ndof = 0, nnodes = 0;
+  // ---- scene table (batches)
+  int ns = 1;
+  std::vector<zema::SceneRange> scn;
+  zema::DBuf<int> body_scene, sv_scene, v_scene, f_scene;  // global body / surface vertex / soft vertex / free body
+  zema::DBuf<int> scn_rng;                                 // [ns][8] v0 v1 t0 t1 b0 b1 f0 f1
+  zema::DBuf<double> icell_sc, mu_sc, kappa_sc;                // per scene
+  zema::DBuf<unsigned long long> sc_u64, sc_dmin, sc_tmin;      // per-scene extrema (bits)
+  zema::DBuf<double> sc_alpha, sc_sum;                          // per-scene step sizes, sums [ns][8]
+  zema::DBuf<int> sc_mask, sc_rng;                              // per-scene flags; pair ranges [ns][8]
+  zema::DBuf<unsigned int> sc_cnt;
+  std::vector<double> kappa_h, scale_h;  // host staging of per-scene uploads
+  std::vector<int> mask_h;
   std::vector<zema::Body> bodies;  // affine bodies, creation order
   std::vector<double> mass_h;
   double cell = 0.0;               // hash cell size
@@ -100,7 +122,6 @@ struct zema_scene {
   zema::DBuf<double> ywarm;              // learned initial guess [ndof]
   // ---- state
   zema::DBuf<double> y, ydot, yt, ydt, yhat, ytmp, grad, pdir;
-  double kappa = 0.0, kappa_lag = 0.0;
   int step = 0;
   // ---- candidates (current set)
   zema::DBuf<int> pt, ee;       // [n][2]
@@ -165,7 +186,11 @@ void k_scale(zema_scene* s, int n, double a, const double* x, double* out);
 void k_iota(zema_scene* s, int* p, int64_t n);  // p[i] = i
 void k_velocity(zema_scene* s, double inv_h);   // ydot = (y - yt) * inv_h
 void k_predict(zema_scene* s);                  // yhat from y^t, ydot^t
-double k_max_disp(zema_scene* s, const double* p);  // max vertex displacement of direction p
+void k_max_disp(zema_scene* s, const double* p, double* out);  // per scene: max vertex displacement of p
+void k_axpy_scene(zema_scene* s, const double* alpha_host, const double* p, const double* y, double* out);
+void k_select_scene(zema_scene* s, const int* mask_host, const double* a, const double* b, double* out);
+void k_scale_scene(zema_scene* s, const double* alpha_host, double* p);
+bool k_inverted(zema_scene* s, const double* y, int* out);  // per scene: any tet inverted
 // multi-segment deterministic sums: out[k] = sum of seg k (host results)
 // (extra: optional device word copied to out_host[nseg] in the same synchronisation)
 void k_sums(zema_scene* s, int nseg, const double* const* ptr, const int64_t* len, double* out_host,
@@ -187,6 +212,7 @@ void k_body_energy(zema_scene* s, const double* y);
 // evaluate the current candidate set at xs: energies / distances; with derivatives,
 // builds the contact matrix (CSR) and adds gradient contributions into grad.
 void k_contact_energy(zema_scene* s);                 // e_pair, d_pair, e_fric at xs
+void k_scene_sums(zema_scene* s, double* out_host);  // per scene [ns][8] energy terms, total, min distance
 void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask);
 void k_friction_build(zema_scene* s);                 // lagged table from current candidates at xs
 
@@ -211,6 +237,8 @@ void k_radix_sort(zema_scene* s, SortBufs& b, int64_t n, int key_bits);  // sort
 void k_hess_matvec(zema_scene* s, const double* v, double* out);
 void k_build_precond(zema_scene* s);
 int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres);
+void k_pcg_batch(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, const int* active_host,
+                 int* iters, double* relres, int* status);
 
 // -------- CCD (k_ccd.hip)
 int k_ccd(zema_scene* s, const double* y, const double* p, double* alpha);

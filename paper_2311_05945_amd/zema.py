@@ -82,6 +82,8 @@ SIGNATURES = [
     ("zema_mlp_forward", [VP, VP, I64, VP]),
     ("zema_mlp_grad", [VP, VP, VP, I64, VP, PD]),
     ("zema_mlp_train_step", [VP, VP, VP, I64, VP, I64, C.c_float, PD]),
+    ("zema_batch_create", [VP, I32, VP, PI32, VP, PI32, VP, C.POINTER(VP)]),
+    ("zema_batch_layout", [VP, C.POINTER(I32), PI64]),
     ("zema_scene_set_mlp", [VP, VP]),
     ("zema_scene_features", [VP, VP]),
     ("zema_scene_warm_target", [VP, VP]),
@@ -144,32 +146,46 @@ def params_struct(p) -> Params:
 class Scene:
     """A scene of libzema bound to one torch (HIP) stream."""
 
-    def __init__(self, scene, device="cuda:0", stream=None):
+    def __init__(self, scene, device="cuda:0", stream=None, _batch=None):
+        """One scene (a `scenegen.Scene`), or with `_batch` a list of scenes stepped
+        together (see `Scene.batch`)."""
         import torch
         self.torch = torch
         self.device = torch.device(device)
         L = lib()
         self._keep = []
-        softs = (SoftDesc * max(1, len(scene.softs)))()
-        for k, b in enumerate(scene.softs):
+        scenes = _batch if _batch is not None else [scene]
+        all_softs = [b for sc in scenes for b in sc.softs]
+        all_affs = [b for sc in scenes for b in sc.affines]
+        softs = (SoftDesc * max(1, len(all_softs)))()
+        for k, b in enumerate(all_softs):
             rp = _f64(b.rest_pos); tt = np.ascontiguousarray(b.tets, dtype=np.int32)
             p0 = _f64(b.pos0) if b.pos0 is not None else None
             v0 = _f64(b.vel0) if b.vel0 is not None else None
             self._keep += [rp, tt, p0, v0]
             softs[k] = SoftDesc(len(rp), len(tt), _pd(rp), tt.ctypes.data_as(PI32), _pd(p0), _pd(v0), b.E, b.nu, b.rho)
-        affs = (AffineDesc * max(1, len(scene.affines)))()
-        for k, b in enumerate(scene.affines):
+        affs = (AffineDesc * max(1, len(all_affs)))()
+        for k, b in enumerate(all_affs):
             rp = _f64(b.rest_pos); tt = np.ascontiguousarray(b.tris, dtype=np.int32)
             self._keep += [rp, tt]
             affs[k] = AffineDesc(len(rp), len(tt), _pd(rp), tt.ctypes.data_as(PI32), b.rho, b.stiffness,
                                  (D * 12)(*np.asarray(b.qdot0, dtype=float)), b.mode, 0, b.kappa_A,
                                  (D * 3)(*np.asarray(b.target_vel, dtype=float)), b.target_stop)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        P = params_struct(scene.params)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            rc = L.zema_scene_create(C.byref(P), softs, len(scene.softs), affs, len(scene.affines),
-                                     C.c_void_p(self.stream.cuda_stream), C.byref(h))
+            if _batch is None:
+                P = params_struct(scene.params)
+                rc = L.zema_scene_create(C.byref(P), softs, len(all_softs), affs, len(all_affs),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h))
+            else:
+                ns = len(scenes)
+                Ps = (Params * ns)(*[params_struct(sc.params) for sc in scenes])
+                so = np.cumsum([0] + [len(sc.softs) for sc in scenes]).astype(np.int32)
+                ao = np.cumsum([0] + [len(sc.affines) for sc in scenes]).astype(np.int32)
+                self._keep += [so, ao]
+                rc = L.zema_batch_create(Ps, ns, softs, so.ctypes.data_as(PI32), affs, ao.ctypes.data_as(PI32),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if rc != 0:
             raise ZemaError(rc, L.zema_status_string(rc).decode())
         self.h = h
@@ -177,7 +193,23 @@ class Scene:
         L.zema_sizes(self.h, s.ctypes.data_as(PI64))
         (self.n_dof, self.n_soft_verts, self.n_tets, self.n_surf, self.n_tris, self.n_edges,
          self.n_free_bodies, self.n_bodies) = [int(x) for x in s]
-        self.params = scene.params
+        ns = I32()
+        L.zema_batch_layout(self.h, C.byref(ns), None)
+        self.n_scenes = ns.value
+        self.layout = np.zeros((self.n_scenes, 8), dtype=np.int64)
+        L.zema_batch_layout(self.h, C.byref(ns), self.layout.ctypes.data_as(PI64))
+        self.params = scenes[0].params
+
+    @classmethod
+    def batch(cls, scenes, device="cuda:0", stream=None):
+        """Scenes stepped together: one launch per phase over all of them."""
+        return cls(None, device, stream, _batch=list(scenes))
+
+    def scene_dofs(self, k):
+        """DOF indices of scene k of a batch in the concatenated y."""
+        v0, v1, f0, f1 = (int(x) for x in self.layout[k, :4])
+        n3 = 3 * self.n_soft_verts
+        return np.concatenate([np.arange(3 * v0, 3 * v1), np.arange(n3 + 12 * f0, n3 + 12 * f1)])
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -266,9 +298,12 @@ class Scene:
         return a.value
 
     def step(self, n=1):
-        st = (StepStats * max(n, 1))()
+        """Statistics of n steps: a list of n dicts (single scene) or of n * n_scenes
+        dicts, step-major (batch)."""
+        m = n * self.n_scenes
+        st = (StepStats * max(m, 1))()
         rc = lib().zema_step(self.h, n, st)
-        out = [{f[0]: getattr(s, f[0]) for f in StepStats._fields_} for s in st[:n]]
+        out = [{f[0]: getattr(s, f[0]) for f in StepStats._fields_} for s in st[:m]]
         if rc != 0:
             raise ZemaError(rc, lib().zema_last_error(self.h).decode())
         return out

@@ -450,6 +450,14 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
     }
     s->v_scene.upload(vs);
     s->f_scene.upload(fs);
+    std::vector<int> sb((size_t)4 * ns);
+    for (int k = 0; k < ns; ++k) {
+      sb[4 * k] = soft_off[k];
+      sb[4 * k + 1] = soft_off[k + 1];
+      sb[4 * k + 2] = n_soft + aff_off[k];
+      sb[4 * k + 3] = n_soft + aff_off[k + 1];
+    }
+    s->scene_bodies.upload(sb);
     s->scn_rng.upload(rng);
     std::vector<double> ic(ns), mu(ns);
     for (int k = 0; k < ns; ++k) {

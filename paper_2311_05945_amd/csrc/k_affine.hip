@@ -4,6 +4,7 @@
 // the kinematic penalty kappa_A/2 |q - q~|^2 of Sec. IV-C-1.  One lane per body.
 #include "geom.hpp"
 #include "scene.hpp"
+#include "wave_jacobi.hpp"
 
 namespace zema {
 
@@ -119,19 +120,78 @@ __global__ void body_assemble_kernel(int nb, const double* __restrict__ bf, cons
     }
 }
 
+// Hessian of the body terms, one wavefront per body: the 9x9 orthogonality Hessian
+// is formed entry-parallel in LDS (padded to 10x10 with a zero row and column, which
+// the projection leaves at zero), projected by parallel Jacobi, and written with the
+// inertia and kinematic diagonals as the body's 4x4 node blocks.
+template <class T>
+__global__ void __launch_bounds__(64) body_hess_kernel(const double* __restrict__ bf, const int* __restrict__ bi,
+                                                       const double* __restrict__ y, const int* __restrict__ bsr_ptr,
+                                                       T* __restrict__ val, int nnzb, double h2, unsigned mask) {
+  constexpr int N = 10, LD = 11;
+  __shared__ double M[N * LD], Vm[N * LD], cs[2 * N];
+  __shared__ int partner[N];
+  __shared__ double A[9], R[9], AtA[9];
+  const int b = blockIdx.x, lane = threadIdx.x;
+  const int mode = bi[4 * b], dof0 = bi[4 * b + 1], node0 = bi[4 * b + 2];
+  if (dof0 < 0) return;  // fixed body: no DOFs (uniform over the block)
+  const double* f = bf + BF * b;
+  const double m = f[BF_M], c = h2 * f[BF_ST] * f[BF_V], kA = f[BF_KA];
+  const double* S = f + BF_S;
+  const double* q = y + dof0;
+  if (lane < 9) A[lane] = q[3 + lane];  // rows a_i = q[3 + 3i .. 5 + 3i]
+  __syncthreads();
+  if (lane < 9) {
+    int i = lane / 3, j = lane % 3;
+    R[lane] = A[3 * i] * A[3 * j] + A[3 * i + 1] * A[3 * j + 1] + A[3 * i + 2] * A[3 * j + 2] - (i == j ? 1.0 : 0.0);
+    AtA[lane] = A[i] * A[j] + A[3 + i] * A[3 + j] + A[6 + i] * A[6 + j];
+  }
+  __syncthreads();
+  for (int e = lane; e < N * N; e += 64) {
+    int r = e / N, cc = e % N;
+    double v = 0.0;
+    if (r < 9 && cc < 9 && (mask & 4u)) {
+      int i = r / 3, j = r % 3, k = cc / 3, l = cc % 3;
+      // d2/dA_ij dA_kl of |A A^T - I|^2 = 4 (delta_ik (A^T A)_lj + A_il A_kj + R_ik delta_jl)
+      v = 4.0 * c * ((i == k ? AtA[3 * l + j] : 0.0) + A[3 * i + l] * A[3 * k + j] + (j == l ? R[3 * i + k] : 0.0));
+    }
+    M[r * LD + cc] = v;
+  }
+  __syncthreads();
+  if (mask & 4u) wave_psd_project<N, LD>(M, Vm, cs, partner, lane);
+  // 12x12 entry (r, cc): p-block inertia m I, a-blocks the projection plus S, kinematic diagonal
+  for (int e = lane; e < 144; e += 64) {
+    int r = e / 12, cc = e % 12;
+    double v = (r >= 3 && cc >= 3) ? M[(r - 3) * LD + (cc - 3)] : 0.0;
+    if (mask & 1u) {
+      if (r < 3 && r == cc) v += m;
+      if (r >= 3 && cc >= 3 && (r - 3) / 3 == (cc - 3) / 3) v += S[3 * ((r - 3) % 3) + (cc - 3) % 3];
+    }
+    if ((mask & 8u) && mode == ZEMA_DRIVEN && r == cc) v += kA;
+    int nr = r / 3, nc = cc / 3;
+    val[(size_t)(3 * (r % 3) + cc % 3) * nnzb + bsr_ptr[node0 + nr] + nc] = T(v);
+  }
+}
+
 void k_body_terms(zema_scene* s, const double* y, double* grad, bool hess, unsigned mask) {
   int nb = (int)s->bodies.size();
   if (!nb) return;
-  if (s->mixed)
+  const double h2 = s->P.dt * s->P.dt;
+  if (s->mixed) {
     body_assemble_kernel<float><<<nblocks(nb, 64), 64, 0, s->st>>>(nb, s->body_f.p, s->body_i.p, s->qtilde.p, y,
                                                                    s->yhat.p, grad, s->e_body.p, s->bsr_ptr.p,
-                                                                   s->bsr_val32.p, s->nnzb, hess ? 1 : 0,
-                                                                   s->P.dt * s->P.dt, mask);
-  else
+                                                                   s->bsr_val32.p, s->nnzb, 0, h2, mask);
+    if (hess)
+      body_hess_kernel<float><<<nb, 64, 0, s->st>>>(s->body_f.p, s->body_i.p, y, s->bsr_ptr.p, s->bsr_val32.p, s->nnzb,
+                                                    h2, mask);
+  } else {
     body_assemble_kernel<double><<<nblocks(nb, 64), 64, 0, s->st>>>(nb, s->body_f.p, s->body_i.p, s->qtilde.p, y,
                                                                     s->yhat.p, grad, s->e_body.p, s->bsr_ptr.p,
-                                                                    s->bsr_val.p, s->nnzb, hess ? 1 : 0,
-                                                                    s->P.dt * s->P.dt, mask);
+                                                                    s->bsr_val.p, s->nnzb, 0, h2, mask);
+    if (hess)
+      body_hess_kernel<double><<<nb, 64, 0, s->st>>>(s->body_f.p, s->body_i.p, y, s->bsr_ptr.p, s->bsr_val.p,
+                                                     s->nnzb, h2, mask);
+  }
 }
 
 void k_body_energy(zema_scene* s, const double* y) {

@@ -312,53 +312,174 @@ __global__ void pcg_init_fin(int nb, const double* __restrict__ partial, double*
   }
 }
 
+// Two accumulators per row: H a and H b over the same gathers, so the product can be
+// formed before beta is known (q = H a + beta H b).
+template <class V>
+__device__ inline void blk_acc2(const V* __restrict__ v, int stride, int j, const double* a, const double* b, int c,
+                                Acc3<V>& A, Acc3<V>& B) {
+  V a0 = V(a[3 * c]), a1 = V(a[3 * c + 1]), a2 = V(a[3 * c + 2]);
+  V b0 = V(b[3 * c]), b1 = V(b[3 * c + 1]), b2 = V(b[3 * c + 2]);
+  V m0 = v[j], m1 = v[stride + j], m2 = v[2 * stride + j], m3 = v[3 * stride + j], m4 = v[4 * stride + j],
+    m5 = v[5 * stride + j], m6 = v[6 * stride + j], m7 = v[7 * stride + j], m8 = v[8 * stride + j];
+  A.x += m0 * a0 + m1 * a1 + m2 * a2;
+  A.y += m3 * a0 + m4 * a1 + m5 * a2;
+  A.z += m6 * a0 + m7 * a1 + m8 * a2;
+  B.x += m0 * b0 + m1 * b1 + m2 * b2;
+  B.y += m3 * b0 + m4 * b1 + m5 * b2;
+  B.z += m6 * b0 + m7 * b1 + m8 * b2;
+}
+
+template <class V>
+__device__ inline void row_partial2(const Mat<V>& M, int row, int lane, int nl, const double* a, const double* b,
+                                    Acc3<V>& A, Acc3<V>& B) {
+  for (int j = M.bp[row] + lane; j < M.bp[row + 1]; j += nl) blk_acc2(M.bv, M.nnzb, j, a, b, M.bc[j], A, B);
+  if (M.cp)
+    for (int j = M.cp[row] + lane; j < M.cp[row + 1]; j += nl) blk_acc2(M.cv, M.nnzc, j, a, b, M.cc[j], A, B);
+}
+
+// sums of two per-thread values over the block (fixed tree), broadcast to all threads
+__device__ inline void block_sum2_bcast(double& a, double& b, double* sh, double* bc) {
+  double x = block_sum<kBlock>(a, sh);
+  double y = block_sum<kBlock>(b, sh);
+  if (threadIdx.x == 0) {
+    bc[0] = x;
+    bc[1] = y;
+  }
+  __syncthreads();
+  a = bc[0];
+  b = bc[1];
+}
+
 // Iteration k, first half: (k > 0) reduce the previous update's partials into
-// rz_k, rr_k, stop if converged, beta = rz_k / rz_{k-1}; then q = H p_k with
-// p_k = z + beta p_{k-1} formed in the gathers, p_k stored, partials of p_k . q.
+// rz_k, rr_k, stop if converged, beta = rz_k / rz_{k-1}; q = H p_k with
+// p_k = z + beta p_{k-1} (gathered as H z and H p_{k-1}, combined once beta is known),
+// p_k stored, block partials of p_k . q.  The scalars, the partials and the matrix
+// gathers are independent loads, issued before any reduction.
 template <class V>
 __global__ void pcg_spmv_kernel(Mat<V> M, int k, int nbu, const double* __restrict__ upart,
                                 const double* __restrict__ z, const double* __restrict__ pold,
                                 double* __restrict__ pnew, double* __restrict__ q, double* __restrict__ spart,
                                 double* __restrict__ sc) {
-  if (sc[6] != 0.0) return;
   __shared__ double sh[kBlock / 64];
-  __shared__ double red[3 * (kBlock / 64)];
-  __shared__ double beta_s;
+  __shared__ double bc[2];
+  __shared__ double red[6 * (kBlock / 64)];
+  __shared__ double done_s;  // block 0 may set the flag during this launch: read once per block
+  if (threadIdx.x == 0) done_s = sc[6];
+  const double tol2 = sc[9], rz_prev = k > 0 ? sc[(k - 1) & 1] : 1.0;
+  double u1 = 0.0, u2 = 0.0;
+  if (k > 0)
+    for (int i = threadIdx.x; i < nbu; i += kBlock) {
+      u1 += upart[2 * i];
+      u2 += upart[2 * i + 1];
+    }
+  const int nsoft_blocks = (M.nsv + (kBlock / RG) - 1) / (kBlock / RG);
+  const bool soft = (int)blockIdx.x < nsoft_blocks;
+  int row;
+  Acc3<V> A{V(0), V(0), V(0)}, B{V(0), V(0), V(0)};
+  if (soft) {
+    row = blockIdx.x * (kBlock / RG) + threadIdx.x / RG;
+    int lane = threadIdx.x % RG;
+    if (row < M.nsv) row_partial2(M, row, lane, RG, z, pold, A, B);
+    for (int o = RG / 2; o > 0; o >>= 1) {
+      A.x += __shfl_xor(A.x, o, RG);
+      A.y += __shfl_xor(A.y, o, RG);
+      A.z += __shfl_xor(A.z, o, RG);
+      B.x += __shfl_xor(B.x, o, RG);
+      B.y += __shfl_xor(B.y, o, RG);
+      B.z += __shfl_xor(B.z, o, RG);
+    }
+  } else {
+    row = M.nsv + (blockIdx.x - nsoft_blocks);
+    row_partial2(M, row, threadIdx.x, kBlock, z, pold, A, B);
+    for (int o = 32; o > 0; o >>= 1) {
+      A.x += __shfl_xor(A.x, o, 64);
+      A.y += __shfl_xor(A.y, o, 64);
+      A.z += __shfl_xor(A.z, o, 64);
+      B.x += __shfl_xor(B.x, o, 64);
+      B.y += __shfl_xor(B.y, o, 64);
+      B.z += __shfl_xor(B.z, o, 64);
+    }
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+      red[6 * w] = double(A.x);
+      red[6 * w + 1] = double(A.y);
+      red[6 * w + 2] = double(A.z);
+      red[6 * w + 3] = double(B.x);
+      red[6 * w + 4] = double(B.y);
+      red[6 * w + 5] = double(B.z);
+    }
+  }
+  __syncthreads();  // done_s and red[] visible to the whole block
+  if (done_s != 0.0) return;
+  double beta = 0.0;
   if (k > 0) {
-    double rz, rr;
-    reduce_partials2(upart, nbu, sh, rz, rr);
-    bool conv = rr <= sc[9];
+    block_sum2_bcast(u1, u2, sh, bc);  // rz_k, rr_k
+    bool conv = u2 <= tol2;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       sc[7] = k;
-      sc[4] = rr;
-      sc[k & 1] = rz;
+      sc[4] = u2;
+      sc[k & 1] = u1;
       if (conv) sc[6] = 1.0;
     }
     if (conv) return;
-    if (threadIdx.x == 0) beta_s = rz / sc[(k - 1) & 1];
-    __syncthreads();
-  } else {
-    if (threadIdx.x == 0) beta_s = 0.0;
-    __syncthreads();
+    beta = u1 / rz_prev;
   }
-  double dotv = spmv_rows(M, z, pold, beta_s, q, pnew, red);
+  double dotv = 0.0;
+  if (soft) {
+    if (threadIdx.x % RG == 0 && row < M.nsv) {
+      V3 qv = v3(double(A.x) + beta * double(B.x), double(A.y) + beta * double(B.y),
+                 double(A.z) + beta * double(B.z));
+      st3(q + 3 * row, qv);
+      V3 pv = ld3(z + 3 * row) + beta * ld3(pold + 3 * row);
+      st3(pnew + 3 * row, pv);
+      dotv = dot(pv, qv);
+    }
+  } else if (threadIdx.x == 0) {
+    V3 sa = v3(0, 0, 0), sb = v3(0, 0, 0);
+    for (int w = 0; w < kBlock / 64; ++w) {
+      sa = sa + v3(red[6 * w], red[6 * w + 1], red[6 * w + 2]);
+      sb = sb + v3(red[6 * w + 3], red[6 * w + 4], red[6 * w + 5]);
+    }
+    V3 qv = sa + beta * sb;
+    st3(q + 3 * row, qv);
+    V3 pv = ld3(z + 3 * row) + beta * ld3(pold + 3 * row);
+    st3(pnew + 3 * row, pv);
+    dotv = dot(pv, qv);
+  }
   double r = block_sum<kBlock>(dotv, sh);
   if (threadIdx.x == 0) spart[blockIdx.x] = r;
 }
 
 // Iteration k, second half: pq from the spmv partials, alpha = rz_k / pq (breakdown
-// if pq <= 0), x += alpha p, r -= alpha q, z = M^-1 r, partials of r.z and r.r.
+// if pq <= 0), x += alpha p, r -= alpha q, z = M^-1 r, partials of r.z and r.r.  A
+// soft vertex's vectors and preconditioner block are loaded with the partials,
+// before the reduction.
 __global__ void pcg_update_kernel(int nsv, int nfree, int k, int nbs, const double* __restrict__ spart,
                                   const double* __restrict__ p, const double* __restrict__ q,
                                   const double* __restrict__ ms, const double* __restrict__ mb, double* __restrict__ x,
                                   double* __restrict__ r, double* __restrict__ z, double* __restrict__ sc,
                                   double* __restrict__ upart) {
-  if (sc[6] != 0.0) return;
   __shared__ double sh[kBlock / 64];
   __shared__ double pq_s;
+  __shared__ double done_s;  // block 0 may set the flag during this launch: read once per block
+  if (threadIdx.x == 0) done_s = sc[6];
+  const double rzk = sc[k & 1];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nbs; i += kBlock) a += spart[i];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool sv = i < nsv;
+  V3 pv{}, qv{}, xv{}, rv{};
+  double m[9];
+  if (sv) {
+    pv = ld3(p + 3 * i);
+    qv = ld3(q + 3 * i);
+    xv = ld3(x + 3 * i);
+    rv = ld3(r + 3 * i);
+    for (int t = 0; t < 9; ++t) m[t] = ms[(size_t)t * nsv + i];
+  }
+  __syncthreads();
+  if (done_s != 0.0) return;
   {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < nbs; i += kBlock) a += spart[i];
     double t = block_sum<kBlock>(a, sh);
     if (threadIdx.x == 0) pq_s = t;
     __syncthreads();
@@ -371,17 +492,26 @@ __global__ void pcg_update_kernel(int nsv, int nfree, int k, int nbs, const doub
     }
     return;
   }
-  const double alpha = sc[k & 1] / pq;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double alpha = rzk / pq;
   double rz = 0.0, rr = 0.0;
-  if (i < nsv + nfree) {
-    int o = i < nsv ? 3 * i : 3 * nsv + 12 * (i - nsv), n = i < nsv ? 3 : 12;
-    for (int kk = 0; kk < n; ++kk) {
+  if (sv) {
+    xv = xv + alpha * pv;
+    rv = rv - alpha * qv;
+    st3(x + 3 * i, xv);
+    st3(r + 3 * i, rv);
+    V3 zv = v3(m[0] * rv.x + m[1] * rv.y + m[2] * rv.z, m[3] * rv.x + m[4] * rv.y + m[5] * rv.z,
+               m[6] * rv.x + m[7] * rv.y + m[8] * rv.z);
+    st3(z + 3 * i, zv);
+    rz = dot(rv, zv);
+    rr = dot(rv, rv);
+  } else if (i < nsv + nfree) {
+    int o = 3 * nsv + 12 * (i - nsv);
+    for (int kk = 0; kk < 12; ++kk) {
       x[o + kk] += alpha * p[o + kk];
       r[o + kk] -= alpha * q[o + kk];
     }
     apply_minv(i, nsv, ms, mb, r, z);
-    for (int kk = 0; kk < n; ++kk) {
+    for (int kk = 0; kk < 12; ++kk) {
       rz += r[o + kk] * z[o + kk];
       rr += r[o + kk] * r[o + kk];
     }

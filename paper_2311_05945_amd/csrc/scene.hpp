@@ -129,9 +129,13 @@ struct zema_scene {
   int64_t npt = 0, nee = 0;
   // broad phase work
   zema::DBuf<double> bb_lo, bb_hi;       // boxes of all primitives
+  zema::DBuf<unsigned long long> body_blo, body_bhi;  // boxes of whole bodies (ordered encoding)
+  zema::DBuf<int> scene_bodies;          // per scene: soft body range, affine body range (global ids)
   zema::DBuf<int> cnt, offs;
   zema::DBuf<unsigned long long> ent_cell;
   zema::DBuf<int> ent_prim, ent_body, bucket_lo, bucket_hi, big_list;
+  zema::DBuf<double> ent_box;                 // sorted entries' boxes [n][6]
+  zema::DBuf<int> q_cnt, q_off, q_big, q_item;  // query work items (query, cell)
   zema::DBuf<unsigned long long> pair_keys;
   zema::DBuf<int> counters;              // small device counters
   zema::SortBufs sort;

@@ -28,22 +28,26 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def collect(seeds, steps, device="cuda:0"):
+def collect(seeds, steps, newton_max=2000, device="cuda:0"):
     """Feature / target tensors (device, float32) of every soft vertex and step."""
     import torch
 
     import scenegen as sg
     from paper_2311_05945_amd import zema
-    B = zema.Scene.batch([sg.batch_scene(s, steps=steps) for s in seeds], device=device)
+    scenes = [sg.batch_scene(s, steps=steps) for s in seeds]
+    for sc in scenes:
+        sc.params.newton_max = newton_max
+    B = zema.Scene.batch(scenes, device=device)
     log(f"data batch: {len(seeds)} scenes, {B.n_soft_verts} soft vertices, {B.n_tets} tets")
     feats, targs = [], []
     t0 = time.perf_counter()
     for k in range(steps):
         feats.append(B.features())
-        B.step(1)
+        st = B.step(1)
         targs.append(B.warm_target())
-        if (k + 1) % 10 == 0:
-            log(f"  step {k + 1}/{steps}: {time.perf_counter() - t0:.1f} s")
+        it = [x["newton_iters"] for x in st]
+        log(f"  step {k + 1}/{steps}: {time.perf_counter() - t0:.1f} s, newton max {max(it)} "
+            f"(scene {it.index(max(it))}), mean {sum(it) / len(it):.1f}")
     return torch.cat(feats).contiguous(), torch.cat(targs).contiguous()
 
 

@@ -248,6 +248,13 @@ int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect
  * stored 3x3 block plus four DOF vectors, for the elastic assembly 320 B per tet;
  * 0 for the other groups) since the timer was enabled.  Both calls synchronise the
  * stream; bytes may be NULL. */
+/* Execution knobs (results are identical for every setting):
+ * ZEMA_TUNE_PCG_GRAPH: 1 (default) replays PCG iterations in chunks of 16 from a
+ * captured HIP graph, 0 launches every kernel individually (as does any solve while
+ * the matrix-vector timer below is enabled).  Errors: ZEMA_E_ARG. */
+enum { ZEMA_TUNE_PCG_GRAPH = 0 };
+int zema_tune(zema_scene* s, int32_t knob, int32_t value);
+
 int zema_kernel_timer(zema_scene* s, int32_t group, int32_t enable);
 int zema_kernel_time(zema_scene* s, int32_t group, double* ms, int64_t* launches, double* bytes);
 

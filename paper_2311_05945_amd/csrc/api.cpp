@@ -889,11 +889,20 @@ void kt_fold(zema_scene* s) {
     t.pending.clear();
   }
 }
+void kt_add(zema_scene* s, int g, double ms, double bytes) {
+  KTimer& t = s->kt[g];
+  if (!t.on) return;
+  t.ms += ms;
+  t.launches++;
+  t.bytes += bytes;
+}
 }  // namespace zema
 
 zema_scene::~zema_scene() {
   for (zema::KTimer& t : kt)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+  if (pcg_graph.exec) (void)hipGraphExecDestroy(pcg_graph.exec);
+  if (cap_st) (void)hipStreamDestroy(cap_st);
 }
 
 namespace {
@@ -1302,6 +1311,15 @@ int zema_mlp_train_step(zema_mlp* m, const float* feat, const float* target, int
     *loss = mlp_grad(m, feat, target, idx, (long)n_rows, (long)batch, true, lr);
     return 0;
   });
+}
+
+int zema_tune(zema_scene* s, int32_t knob, int32_t value) {
+  if (!s) return ZEMA_E_ARG;
+  if (knob == ZEMA_TUNE_PCG_GRAPH && (value == 0 || value == 1)) {
+    s->use_graph = value != 0;
+    return 0;
+  }
+  return ZEMA_E_ARG;
 }
 
 int zema_scene_set_mlp(zema_scene* s, zema_mlp* m) {

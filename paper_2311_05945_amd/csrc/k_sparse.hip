@@ -8,6 +8,8 @@
 // search-direction update p = z + beta p_old folded into the gathers), a one-block
 // scalar step, the vector update with the preconditioner, and a one-block scalar
 // step; scalars stay on the device and the host polls a flag every few iterations.
+#include <cstring>
+
 #include "scene.hpp"
 
 namespace zema {
@@ -355,11 +357,16 @@ __device__ inline void block_sum2_bcast(double& a, double& b, double* sh, double
 // p_k = z + beta p_{k-1} (gathered as H z and H p_{k-1}, combined once beta is known),
 // p_k stored, block partials of p_k . q.  The scalars, the partials and the matrix
 // gathers are independent loads, issued before any reduction.
+// The matrix descriptor is read from device memory so that a captured launch stays
+// valid when the contact matrix is rebuilt; k only selects parities (and k > 0), so a
+// captured chunk of an even number of iterations can be replayed at any odd start;
+// sc[7] counts the iterations on the device.
 template <class V>
-__global__ void pcg_spmv_kernel(Mat<V> M, int k, int nbu, const double* __restrict__ upart,
+__global__ void pcg_spmv_kernel(const Mat<V>* __restrict__ Mp, int k, int nbu, const double* __restrict__ upart,
                                 const double* __restrict__ z, const double* __restrict__ pold,
                                 double* __restrict__ pnew, double* __restrict__ q, double* __restrict__ spart,
                                 double* __restrict__ sc) {
+  const Mat<V> M = *Mp;
   __shared__ double sh[kBlock / 64];
   __shared__ double bc[2];
   __shared__ double red[6 * (kBlock / 64)];
@@ -416,7 +423,7 @@ __global__ void pcg_spmv_kernel(Mat<V> M, int k, int nbu, const double* __restri
     block_sum2_bcast(u1, u2, sh, bc);  // rz_k, rr_k
     bool conv = u2 <= tol2;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc[7] = k;
+      sc[7] += 1.0;  // iterations completed
       sc[4] = u2;
       sc[k & 1] = u1;
       if (conv) sc[6] = 1.0;
@@ -580,6 +587,67 @@ void k_build_precond(zema_scene* s) {
   }
 }
 
+static constexpr int kChunk = 16;  // PCG iterations per captured chunk (even)
+
+struct PcgArgs {
+  const void* mat;
+  int g, nbv;
+  double *upart, *spart, *sc, *sol;
+  double bytes;
+};
+
+static void pcg_iteration(zema_scene* s, const PcgArgs& a, int k, double* pold, double* pnew, hipStream_t st) {
+  if (s->mixed)
+    pcg_spmv_kernel<float><<<a.g, kBlock, 0, st>>>((const Mat<float>*)a.mat, k, a.nbv, a.upart, s->pz.p, pold, pnew,
+                                                   s->pq.p, a.spart, a.sc);
+  else
+    pcg_spmv_kernel<double><<<a.g, kBlock, 0, st>>>((const Mat<double>*)a.mat, k, a.nbv, a.upart, s->pz.p, pold,
+                                                    pnew, s->pq.p, a.spart, a.sc);
+}
+
+static void pcg_update(zema_scene* s, const PcgArgs& a, int k, double* p, hipStream_t st) {
+  pcg_update_kernel<<<a.nbv, kBlock, 0, st>>>(s->nsv, s->nfree, k, a.g, a.spart, p, s->pq.p, s->minv_soft.p,
+                                              s->minv_body.p, a.sol, s->pr.p, s->pz.p, a.sc, a.upart);
+}
+
+// the chunk of iterations k = 1 .. kChunk (pold = pp1 at an odd start), captured once
+// per set of buffers; returns false when capture is unavailable.  Launch timing needs
+// events around every matvec, so timed solves launch individually.
+static bool pcg_graph_ready(zema_scene* s, const PcgArgs& a) {
+  std::vector<const void*> key = {a.mat, a.upart, a.spart, a.sc, a.sol, s->pz.p, s->pp0.p, s->pp1.p, s->pq.p,
+                                  s->pr.p, s->minv_soft.p, s->minv_body.p, (const void*)(intptr_t)a.g,
+                                  (const void*)(intptr_t)a.nbv, (const void*)(intptr_t)s->mixed,
+                                  (const void*)(intptr_t)s->nsv, (const void*)(intptr_t)s->nfree};
+  PcgGraph& G = s->pcg_graph;
+  if (G.exec && G.key == key) return true;
+  if (G.exec) {
+    ZCHK(hipGraphExecDestroy(G.exec));
+    G.exec = nullptr;
+  }
+  if (!s->cap_st) ZCHK(hipStreamCreate(&s->cap_st));
+  if (hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
+  double* pold = s->pp1.p;
+  double* pnew = s->pp0.p;
+  bool ok = true;
+  for (int c = 0; c < kChunk; ++c) {
+    int k = 1 + c;
+    pcg_iteration(s, a, k, pold, pnew, s->cap_st);
+    pcg_update(s, a, k, pnew, s->cap_st);
+    std::swap(pold, pnew);
+  }
+  hipGraph_t graph = nullptr;
+  ok = (hipStreamEndCapture(s->cap_st, &graph) == hipSuccess) && ok && graph;
+  if (ok) ok = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipGetLastError();
+  if (!ok) {
+    G.exec = nullptr;
+    return false;
+  }
+  G.key = key;
+  return true;
+}
+
 int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres) {
   int n = s->ndof;
   if (max_iter <= 0) max_iter = n;
@@ -593,35 +661,56 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   int nbv = nblocks(nunits);
   int g = spmv_grid(s);
   s->partial.reserve(2 * (size_t)nbv + (size_t)g + 4);
-  double* upart = s->partial.p;
-  double* spart = s->partial.p + 2 * (size_t)nbv + 2;
   s->scal.reserve(16);
-  double* sc = s->scal.p;
-  auto M64 = make_mat<double>(s, s->bsr_val.p, s->c_val.p);
-  auto M32 = make_mat<float>(s, s->bsr_val32.p, s->c_val32.p);
+  // matrix descriptors in device memory (the captured kernels read them there)
+  s->mat_h.resize(sizeof(Mat<double>) + sizeof(Mat<float>));
+  Mat<double> M64 = make_mat<double>(s, s->bsr_val.p, s->c_val.p);
+  Mat<float> M32 = make_mat<float>(s, s->bsr_val32.p, s->c_val32.p);
+  std::memcpy(s->mat_h.data(), &M64, sizeof(M64));
+  std::memcpy(s->mat_h.data() + sizeof(M64), &M32, sizeof(M32));
+  s->mat_dev.reserve(s->mat_h.size());
+  ZCHK(hipMemcpyAsync(s->mat_dev.p, s->mat_h.data(), s->mat_h.size(), hipMemcpyHostToDevice, s->st));
+  PcgArgs a;
+  a.mat = s->mixed ? (const void*)(s->mat_dev.p + sizeof(Mat<double>)) : (const void*)s->mat_dev.p;
+  a.g = g;
+  a.nbv = nbv;
+  a.upart = s->partial.p;
+  a.spart = s->partial.p + 2 * (size_t)nbv + 2;
+  a.sc = s->scal.p;
+  a.sol = sol;
+  a.bytes = (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 32.0 * s->ndof;
   pcg_init_kernel<<<nbv, kBlock, 0, s->st>>>(s->nsv, s->nfree, rhs, s->minv_soft.p, s->minv_body.p, sol, s->pr.p,
-                                             s->pz.p, s->pp0.p, upart);
-  pcg_init_fin<<<1, kBlock, 0, s->st>>>(nbv, upart, sc, rtol);
+                                             s->pz.p, s->pp0.p, a.upart);
+  pcg_init_fin<<<1, kBlock, 0, s->st>>>(nbv, a.upart, a.sc, rtol);
+  const bool timed = s->kt[KT_SPMV].on;
   double* pold = s->pp0.p;
   double* pnew = s->pp1.p;
-  const int chunk = 16;
   double hs[10];
   int it = 0;
   for (;;) {
-    for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
+    if (it == 0) {  // iteration 0 eagerly; every later round starts at an odd iteration
       kt_begin(s, KT_SPMV);
-      if (s->mixed)
-        pcg_spmv_kernel<float><<<g, kBlock, 0, s->st>>>(M32, it, nbv, upart, s->pz.p, pold, pnew, s->pq.p, spart, sc);
-      else
-        pcg_spmv_kernel<double><<<g, kBlock, 0, s->st>>>(M64, it, nbv, upart, s->pz.p, pold, pnew, s->pq.p, spart,
-                                                         sc);
-      kt_end(s, KT_SPMV, (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 32.0 * s->ndof);
-      pcg_update_kernel<<<nbv, kBlock, 0, s->st>>>(s->nsv, s->nfree, it, g, spart, pnew, s->pq.p, s->minv_soft.p,
-                                                   s->minv_body.p, sol, s->pr.p, s->pz.p, sc, upart);
+      pcg_iteration(s, a, 0, pold, pnew, s->st);
+      kt_end(s, KT_SPMV, a.bytes);
+      pcg_update(s, a, 0, pnew, s->st);
       std::swap(pold, pnew);
+      it = 1;
     }
-    if (it >= max_iter) pcg_final_kernel<<<1, kBlock, 0, s->st>>>(it, nbv, upart, sc);
-    ZCHK(hipMemcpyAsync(hs, sc, sizeof(hs), hipMemcpyDeviceToHost, s->st));
+    bool graph = (it & 1) && max_iter - it >= kChunk && s->use_graph && !timed && pcg_graph_ready(s, a);
+    if (graph) {
+      ZCHK(hipGraphLaunch(s->pcg_graph.exec, s->st));
+      it += kChunk;  // even: pold / pnew are where they were
+    } else {
+      for (int c = 0; c < kChunk && it < max_iter; ++c, ++it) {
+        kt_begin(s, KT_SPMV);
+        pcg_iteration(s, a, it, pold, pnew, s->st);
+        kt_end(s, KT_SPMV, a.bytes);
+        pcg_update(s, a, it, pnew, s->st);
+        std::swap(pold, pnew);
+      }
+    }
+    if (it >= max_iter) pcg_final_kernel<<<1, kBlock, 0, s->st>>>(it, nbv, a.upart, a.sc);
+    ZCHK(hipMemcpyAsync(hs, a.sc, sizeof(hs), hipMemcpyDeviceToHost, s->st));
     ZCHK(hipStreamSynchronize(s->st));
     if (hs[6] != 0.0 || it >= max_iter) break;
   }
@@ -635,7 +724,6 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   if (hs[6] == 0.0) return ZEMA_E_PCG;
   return 0;
 }
-
 
 // ------------------------------------------------------------------ batched PCG
 // A batch of scenes has a block-diagonal Newton system; each scene runs its own CG

@@ -54,6 +54,13 @@ struct SceneRange {
   double kappa = 0.0, kappa_lag = 0.0, dprev = 0.0;
 };
 
+// A captured chunk of PCG iterations (16 x [matvec, update]) and what it was captured
+// with; replayed as long as every pointer and size matches.
+struct PcgGraph {
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;
+};
+
 // Buffers for one radix sort of (key, value) pairs.
 struct SortBufs {
   DBuf<unsigned long long> k0, k1;
@@ -172,6 +179,12 @@ struct zema_scene {
   double* host_pinned = nullptr;  // small pinned readback area
   bool hess_valid = false;
   zema::KTimer kt[zema::KT_N];
+  // ---- graph-captured PCG chunks
+  bool use_graph = true;
+  hipStream_t cap_st = nullptr;          // capture stream (default priority)
+  zema::PcgGraph pcg_graph;
+  zema::DBuf<unsigned char> mat_dev;     // matrix descriptors read by the captured kernels
+  std::vector<unsigned char> mat_h;
   ~zema_scene();
 };
 
@@ -181,6 +194,7 @@ namespace zema {
 void kt_begin(zema_scene* s, int g);
 void kt_end(zema_scene* s, int g, double bytes = 0.0);
 void kt_fold(zema_scene* s);  // after a stream synchronisation: accumulate elapsed times
+void kt_add(zema_scene* s, int g, double ms, double bytes);  // one timed launch measured elsewhere
 
 // -------- map / vectors (k_misc.hip)
 void k_map_surface(zema_scene* s, const double* y, double* xs);

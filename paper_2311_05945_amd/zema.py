@@ -84,6 +84,7 @@ SIGNATURES = [
     ("zema_mlp_train_step", [VP, VP, VP, I64, VP, I64, C.c_float, PD]),
     ("zema_batch_create", [VP, I32, VP, PI32, VP, PI32, VP, C.POINTER(VP)]),
     ("zema_batch_layout", [VP, C.POINTER(I32), PI64]),
+    ("zema_tune", [VP, I32, I32]),
     ("zema_scene_set_mlp", [VP, VP]),
     ("zema_scene_features", [VP, VP]),
     ("zema_scene_warm_target", [VP, VP]),
@@ -91,6 +92,7 @@ SIGNATURES = [
 MLP_PARAMS = 9603
 MLP_FEATURES = 16
 WARM_EXPLICIT, WARM_LEARNED = 0, 1
+TUNE_PCG_GRAPH = 0
 KT_SPMV, KT_TET, KT_CONTACT, KT_QUERY, KT_CCD = range(5)
 
 
@@ -329,6 +331,9 @@ class Scene:
         self._chk(lib().zema_intersection_count(self.h, _ptr(y), C.byref(ni), C.byref(nv), C.byref(nu), _ptr(unc),
                                                 cap))
         return ni.value, nv.value, nu.value, unc[:min(nu.value, cap)]
+
+    def tune(self, knob, value):
+        self._chk(lib().zema_tune(self.h, int(knob), int(value)))
 
     def kernel_timer(self, group, enable=True):
         self._chk(lib().zema_kernel_timer(self.h, int(group), 1 if enable else 0))

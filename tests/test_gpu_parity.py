@@ -337,3 +337,23 @@ def test_intersection_count_matches_exact(zema):
         assert nu <= 4096 and ni + resolved == n_exact
         assert nv == exact.count_inverted(y1[:n3].reshape(-1, 3), sc.softs[0].tets)
     assert n_exact > 0
+
+
+def test_pcg_graph_replays_match_eager(zema, gripper_full):
+    """The graph-captured PCG chunks give bitwise the eager launches' solution, over
+    several replays with eager work (assembly, matvecs) between them."""
+    sc, R, y, yd = gripper_full
+    G = zema.Scene(sc)
+    G.set_state(y, yd)
+    G.ip_assemble(y)
+    rhs = np.random.default_rng(5).normal(size=G.n_dof)    # a right-hand side that needs many iterations
+    G.tune(zema.TUNE_PCG_GRAPH, 0)
+    x0, it0, rr0 = G.pcg_solve(rhs)
+    G.tune(zema.TUNE_PCG_GRAPH, 1)
+    for rep in range(3):
+        x1, it1, rr1 = G.pcg_solve(rhs)
+        log(f"replay {rep}: {it1} iterations (eager {it0}), rel res {rr1:.3e}")
+        assert it1 == it0 and rr1 == rr0 and torch.equal(x1, x0)
+        G.hessian_matvec(x1)                           # eager work between replays
+        G.ip_assemble(y)
+    assert it0 > 32                                    # several chunks were replayed

@@ -129,6 +129,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=10, help="steps per library call (progress lines)")
     ap.add_argument("--timing-steps", type=int, default=5, help="steps of the roofline pass after the timed run")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / learned / mixed comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default PCG launch shapes")
     ap.add_argument("--form-scenes", type=int, default=8)
     ap.add_argument("--form-steps", type=int, default=16)
     ap.add_argument("--form-seed", type=int, default=10000)
@@ -145,11 +146,19 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     sc = sg.gripper(args.seed, r=args.res, steps=args.steps)
+    tuned = None
     if args.warmup > 0:
         W = zema.Scene(sc)
         W.step(args.warmup)
+        if not args.no_autotune:
+            lanes, ub, us = W.autotune()
+            tuned = {"spmv_lanes": lanes, "update_block": ub, "us_per_pcg_iter": us}
+            log(f"autotuned PCG shapes: {lanes} lanes per soft row, update block {ub}, {us:.2f} us/iteration")
         del W
     G = zema.Scene(sc)
+    if tuned is not None:
+        G.tune(zema.TUNE_SPMV_LANES, tuned["spmv_lanes"])
+        G.tune(zema.TUNE_UPDATE_BLOCK, tuned["update_block"])
     log(f"scene: {G.n_soft_verts} soft vertices, {G.n_tets} tets, {G.n_dof} DOFs, {G.n_tris} surface triangles")
     group = GROUPS[args.timer]
     stats = []
@@ -206,6 +215,7 @@ def main():
                      "bytes_per_launch": bytes_k / max(launches, 1),
                      "timing_steps": args.timing_steps,
                      "share_of_step_time": ms_k * 1e-3 / t_roof},
+        "autotuned": tuned,
         "phase_ms_per_step": {k: sum(s[f"ms_{k}"] for s in stats) / args.steps
                               for k in ("assemble", "pcg", "broad", "ccd", "linesearch")},
         "failed_steps": sum(1 for s in stats if s["status"] != 0),

@@ -248,12 +248,23 @@ int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect
  * stored 3x3 block plus four DOF vectors, for the elastic assembly 320 B per tet;
  * 0 for the other groups) since the timer was enabled.  Both calls synchronise the
  * stream; bytes may be NULL. */
-/* Execution knobs (results are identical for every setting):
+/* Execution knobs of a single scene.
  * ZEMA_TUNE_PCG_GRAPH: 1 (default) replays PCG iterations in chunks of 16 from a
- * captured HIP graph, 0 launches every kernel individually (as does any solve while
- * the matrix-vector timer below is enabled).  Errors: ZEMA_E_ARG. */
-enum { ZEMA_TUNE_PCG_GRAPH = 0 };
+ *   captured HIP graph, 0 launches every kernel individually (as does any solve while
+ *   the matrix-vector timer below is enabled); results are identical.
+ * ZEMA_TUNE_SPMV_LANES: lanes per soft-vertex row of the PCG matrix-vector product
+ *   (8, 16 default, 32); ZEMA_TUNE_UPDATE_BLOCK: threads per block of the PCG vector
+ *   update (64, 128, 256 default).  These change the floating-point summation order
+ *   (results agree to rounding); a fixed setting is deterministic.
+ * Errors: ZEMA_E_ARG for an unknown knob or value. */
+enum { ZEMA_TUNE_PCG_GRAPH = 0, ZEMA_TUNE_SPMV_LANES = 1, ZEMA_TUNE_UPDATE_BLOCK = 2 };
 int zema_tune(zema_scene* s, int32_t knob, int32_t value);
+/* Autotuner: times 64 PCG iterations on the last assembled Hessian (after
+ * zema_ip_assemble or a step) for every lanes x update-block shape, keeps the
+ * fastest and returns it with its time per iteration (microseconds, host outputs).
+ * Overwrites the scene's internal PCG vectors only.  Errors: ZEMA_E_ARG (no Hessian,
+ * batch), ZEMA_E_DEVICE. */
+int zema_autotune(zema_scene* s, int32_t* lanes, int32_t* update_block, double* us_per_iter);
 
 int zema_kernel_timer(zema_scene* s, int32_t group, int32_t enable);
 int zema_kernel_time(zema_scene* s, int32_t group, double* ms, int64_t* launches, double* bytes);

@@ -1319,7 +1319,26 @@ int zema_tune(zema_scene* s, int32_t knob, int32_t value) {
     s->use_graph = value != 0;
     return 0;
   }
+  if (knob == ZEMA_TUNE_SPMV_LANES && (value == 8 || value == 16 || value == 32)) {
+    s->tune_lanes = value;
+    return 0;
+  }
+  if (knob == ZEMA_TUNE_UPDATE_BLOCK && (value == 64 || value == 128 || value == 256)) {
+    s->tune_ublock = value;
+    return 0;
+  }
   return ZEMA_E_ARG;
+}
+
+int zema_autotune(zema_scene* s, int32_t* lanes, int32_t* update_block, double* us_per_iter) {
+  if (!s || !lanes || !update_block || !us_per_iter || s->ns != 1 || !s->hess_valid) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    int l, u;
+    k_autotune(s, &l, &u, us_per_iter);
+    *lanes = l;
+    *update_block = u;
+    return 0;
+  });
 }
 
 int zema_scene_set_mlp(zema_scene* s, zema_mlp* m) {

@@ -361,7 +361,7 @@ __device__ inline void block_sum2_bcast(double& a, double& b, double* sh, double
 // valid when the contact matrix is rebuilt; k only selects parities (and k > 0), so a
 // captured chunk of an even number of iterations can be replayed at any odd start;
 // sc[7] counts the iterations on the device.
-template <class V>
+template <class V, int G>
 __global__ void pcg_spmv_kernel(const Mat<V>* __restrict__ Mp, int k, int nbu, const double* __restrict__ upart,
                                 const double* __restrict__ z, const double* __restrict__ pold,
                                 double* __restrict__ pnew, double* __restrict__ q, double* __restrict__ spart,
@@ -379,21 +379,21 @@ __global__ void pcg_spmv_kernel(const Mat<V>* __restrict__ Mp, int k, int nbu, c
       u1 += upart[2 * i];
       u2 += upart[2 * i + 1];
     }
-  const int nsoft_blocks = (M.nsv + (kBlock / RG) - 1) / (kBlock / RG);
+  const int nsoft_blocks = (M.nsv + (kBlock / G) - 1) / (kBlock / G);
   const bool soft = (int)blockIdx.x < nsoft_blocks;
   int row;
   Acc3<V> A{V(0), V(0), V(0)}, B{V(0), V(0), V(0)};
   if (soft) {
-    row = blockIdx.x * (kBlock / RG) + threadIdx.x / RG;
-    int lane = threadIdx.x % RG;
-    if (row < M.nsv) row_partial2(M, row, lane, RG, z, pold, A, B);
-    for (int o = RG / 2; o > 0; o >>= 1) {
-      A.x += __shfl_xor(A.x, o, RG);
-      A.y += __shfl_xor(A.y, o, RG);
-      A.z += __shfl_xor(A.z, o, RG);
-      B.x += __shfl_xor(B.x, o, RG);
-      B.y += __shfl_xor(B.y, o, RG);
-      B.z += __shfl_xor(B.z, o, RG);
+    row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+    int lane = threadIdx.x % G;
+    if (row < M.nsv) row_partial2(M, row, lane, G, z, pold, A, B);
+    for (int o = G / 2; o > 0; o >>= 1) {
+      A.x += __shfl_xor(A.x, o, G);
+      A.y += __shfl_xor(A.y, o, G);
+      A.z += __shfl_xor(A.z, o, G);
+      B.x += __shfl_xor(B.x, o, G);
+      B.y += __shfl_xor(B.y, o, G);
+      B.z += __shfl_xor(B.z, o, G);
     }
   } else {
     row = M.nsv + (blockIdx.x - nsoft_blocks);
@@ -433,7 +433,7 @@ __global__ void pcg_spmv_kernel(const Mat<V>* __restrict__ Mp, int k, int nbu, c
   }
   double dotv = 0.0;
   if (soft) {
-    if (threadIdx.x % RG == 0 && row < M.nsv) {
+    if (threadIdx.x % G == 0 && row < M.nsv) {
       V3 qv = v3(double(A.x) + beta * double(B.x), double(A.y) + beta * double(B.y),
                  double(A.z) + beta * double(B.z));
       st3(q + 3 * row, qv);
@@ -461,18 +461,19 @@ __global__ void pcg_spmv_kernel(const Mat<V>* __restrict__ Mp, int k, int nbu, c
 // if pq <= 0), x += alpha p, r -= alpha q, z = M^-1 r, partials of r.z and r.r.  A
 // soft vertex's vectors and preconditioner block are loaded with the partials,
 // before the reduction.
-__global__ void pcg_update_kernel(int nsv, int nfree, int k, int nbs, const double* __restrict__ spart,
+template <int UB>
+__global__ void __launch_bounds__(UB) pcg_update_kernel(int nsv, int nfree, int k, int nbs, const double* __restrict__ spart,
                                   const double* __restrict__ p, const double* __restrict__ q,
                                   const double* __restrict__ ms, const double* __restrict__ mb, double* __restrict__ x,
                                   double* __restrict__ r, double* __restrict__ z, double* __restrict__ sc,
                                   double* __restrict__ upart) {
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[UB / 64];
   __shared__ double pq_s;
   __shared__ double done_s;  // block 0 may set the flag during this launch: read once per block
   if (threadIdx.x == 0) done_s = sc[6];
   const double rzk = sc[k & 1];
   double a = 0.0;
-  for (int i = threadIdx.x; i < nbs; i += kBlock) a += spart[i];
+  for (int i = threadIdx.x; i < nbs; i += UB) a += spart[i];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool sv = i < nsv;
   V3 pv{}, qv{}, xv{}, rv{};
@@ -487,7 +488,7 @@ __global__ void pcg_update_kernel(int nsv, int nfree, int k, int nbs, const doub
   __syncthreads();
   if (done_s != 0.0) return;
   {
-    double t = block_sum<kBlock>(a, sh);
+    double t = block_sum<UB>(a, sh);
     if (threadIdx.x == 0) pq_s = t;
     __syncthreads();
   }
@@ -523,8 +524,8 @@ __global__ void pcg_update_kernel(int nsv, int nfree, int k, int nbs, const doub
       rr += r[o + kk] * r[o + kk];
     }
   }
-  double s1 = block_sum<kBlock>(rz, sh);
-  double s2 = block_sum<kBlock>(rr, sh);
+  double s1 = block_sum<UB>(rz, sh);
+  double s2 = block_sum<UB>(rr, sh);
   if (threadIdx.x == 0) {
     upart[2 * blockIdx.x] = s1;
     upart[2 * blockIdx.x + 1] = s2;
@@ -561,6 +562,7 @@ static Mat<V> make_mat(zema_scene* s, const V* bv, const V* cv) {
 }
 
 static int spmv_grid(zema_scene* s) { return (s->nsv + (kBlock / RG) - 1) / (kBlock / RG) + 4 * s->nfree; }
+static int spmv_grid_g(zema_scene* s, int g) { return (s->nsv + (kBlock / g) - 1) / (kBlock / g) + 4 * s->nfree; }
 
 void k_hess_matvec(zema_scene* s, const double* v, double* out) {
   int g = spmv_grid(s);
@@ -589,25 +591,49 @@ void k_build_precond(zema_scene* s) {
 
 static constexpr int kChunk = 16;  // PCG iterations per captured chunk (even)
 
+// launch shapes of the fused PCG kernels (tuned per scene): lanes per soft row of the
+// matrix-vector product, threads per block of the vector update
 struct PcgArgs {
   const void* mat;
-  int g, nbv;
+  int g, nbu, lanes, ub;
   double *upart, *spart, *sc, *sol;
   double bytes;
 };
 
+template <class V>
+static void pcg_iteration_v(zema_scene* s, const PcgArgs& a, int k, double* pold, double* pnew, hipStream_t st) {
+  const Mat<V>* M = (const Mat<V>*)a.mat;
+#define ZEMA_SPMV(G)                                                                                            \
+  pcg_spmv_kernel<V, G><<<a.g, kBlock, 0, st>>>(M, k, a.nbu, a.upart, s->pz.p, pold, pnew, s->pq.p, a.spart, \
+                                                a.sc)
+  if (a.lanes == 8)
+    ZEMA_SPMV(8);
+  else if (a.lanes == 32)
+    ZEMA_SPMV(32);
+  else
+    ZEMA_SPMV(16);
+#undef ZEMA_SPMV
+}
+
 static void pcg_iteration(zema_scene* s, const PcgArgs& a, int k, double* pold, double* pnew, hipStream_t st) {
   if (s->mixed)
-    pcg_spmv_kernel<float><<<a.g, kBlock, 0, st>>>((const Mat<float>*)a.mat, k, a.nbv, a.upart, s->pz.p, pold, pnew,
-                                                   s->pq.p, a.spart, a.sc);
+    pcg_iteration_v<float>(s, a, k, pold, pnew, st);
   else
-    pcg_spmv_kernel<double><<<a.g, kBlock, 0, st>>>((const Mat<double>*)a.mat, k, a.nbv, a.upart, s->pz.p, pold,
-                                                    pnew, s->pq.p, a.spart, a.sc);
+    pcg_iteration_v<double>(s, a, k, pold, pnew, st);
 }
 
 static void pcg_update(zema_scene* s, const PcgArgs& a, int k, double* p, hipStream_t st) {
-  pcg_update_kernel<<<a.nbv, kBlock, 0, st>>>(s->nsv, s->nfree, k, a.g, a.spart, p, s->pq.p, s->minv_soft.p,
-                                              s->minv_body.p, a.sol, s->pr.p, s->pz.p, a.sc, a.upart);
+  int nb = nblocks(s->nsv + s->nfree, a.ub);
+#define ZEMA_UPD(B)                                                                                              \
+  pcg_update_kernel<B><<<nb, B, 0, st>>>(s->nsv, s->nfree, k, a.g, a.spart, p, s->pq.p, s->minv_soft.p,       \
+                                         s->minv_body.p, a.sol, s->pr.p, s->pz.p, a.sc, a.upart)
+  if (a.ub == 64)
+    ZEMA_UPD(64);
+  else if (a.ub == 128)
+    ZEMA_UPD(128);
+  else
+    ZEMA_UPD(256);
+#undef ZEMA_UPD
 }
 
 // the chunk of iterations k = 1 .. kChunk (pold = pp1 at an odd start), captured once
@@ -616,7 +642,8 @@ static void pcg_update(zema_scene* s, const PcgArgs& a, int k, double* p, hipStr
 static bool pcg_graph_ready(zema_scene* s, const PcgArgs& a) {
   std::vector<const void*> key = {a.mat, a.upart, a.spart, a.sc, a.sol, s->pz.p, s->pp0.p, s->pp1.p, s->pq.p,
                                   s->pr.p, s->minv_soft.p, s->minv_body.p, (const void*)(intptr_t)a.g,
-                                  (const void*)(intptr_t)a.nbv, (const void*)(intptr_t)s->mixed,
+                                  (const void*)(intptr_t)a.nbu, (const void*)(intptr_t)a.lanes,
+                                  (const void*)(intptr_t)a.ub, (const void*)(intptr_t)s->mixed,
                                   (const void*)(intptr_t)s->nsv, (const void*)(intptr_t)s->nfree};
   PcgGraph& G = s->pcg_graph;
   if (G.exec && G.key == key) return true;
@@ -659,8 +686,11 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   s->pq.reserve(n);
   int nunits = s->nsv + s->nfree;
   int nbv = nblocks(nunits);
-  int g = spmv_grid(s);
-  s->partial.reserve(2 * (size_t)nbv + (size_t)g + 4);
+  const int lanes = s->tune_lanes, ub = s->tune_ublock;
+  int g = spmv_grid_g(s, lanes);
+  int nbu = nblocks(nunits, ub);
+  size_t np = (size_t)std::max(nbv, nbu);
+  s->partial.reserve(2 * np + (size_t)g + 4);
   s->scal.reserve(16);
   // matrix descriptors in device memory (the captured kernels read them there)
   s->mat_h.resize(sizeof(Mat<double>) + sizeof(Mat<float>));
@@ -673,9 +703,11 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   PcgArgs a;
   a.mat = s->mixed ? (const void*)(s->mat_dev.p + sizeof(Mat<double>)) : (const void*)s->mat_dev.p;
   a.g = g;
-  a.nbv = nbv;
+  a.nbu = nbu;
+  a.lanes = lanes;
+  a.ub = ub;
   a.upart = s->partial.p;
-  a.spart = s->partial.p + 2 * (size_t)nbv + 2;
+  a.spart = s->partial.p + 2 * np + 2;
   a.sc = s->scal.p;
   a.sol = sol;
   a.bytes = (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 32.0 * s->ndof;
@@ -709,7 +741,7 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
         std::swap(pold, pnew);
       }
     }
-    if (it >= max_iter) pcg_final_kernel<<<1, kBlock, 0, s->st>>>(it, nbv, a.upart, a.sc);
+    if (it >= max_iter) pcg_final_kernel<<<1, kBlock, 0, s->st>>>(it, nbu, a.upart, a.sc);
     ZCHK(hipMemcpyAsync(hs, a.sc, sizeof(hs), hipMemcpyDeviceToHost, s->st));
     ZCHK(hipStreamSynchronize(s->st));
     if (hs[6] != 0.0 || it >= max_iter) break;
@@ -723,6 +755,59 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   if (hs[8] != 0.0) return ZEMA_E_PCG;
   if (hs[6] == 0.0) return ZEMA_E_PCG;
   return 0;
+}
+
+// ------------------------------------------------------------------ launch-shape autotuner
+__global__ void probe_rhs_kernel(int n, double* __restrict__ b) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)((i * 2654435761u) & 1023u) / 512.0 - 1.0;  // deterministic, not smooth
+}
+
+// Times a fixed number of PCG iterations on the last assembled Hessian for every
+// (lanes per soft row, update block) shape and keeps the fastest.  The shapes change
+// summation order only; the choice is fixed until the next call.
+void k_autotune(zema_scene* s, int* lanes_out, int* ub_out, double* us_per_iter) {
+  const int n = s->ndof, iters = 64;
+  if (n == 0) {
+    *lanes_out = s->tune_lanes;
+    *ub_out = s->tune_ublock;
+    return;
+  }
+  s->ytmp.reserve(n);
+  probe_rhs_kernel<<<nblocks(n), kBlock, 0, s->st>>>(n, s->ytmp.p);
+  const int L[3] = {8, 16, 32}, U[3] = {64, 128, 256};
+  double best = 1e300;
+  int bl = s->tune_lanes, bu = s->tune_ublock;
+  hipEvent_t e0, e1;
+  ZCHK(hipEventCreate(&e0));
+  ZCHK(hipEventCreate(&e1));
+  for (int li = 0; li < 3; ++li)
+    for (int ui = 0; ui < 3; ++ui) {
+      s->tune_lanes = L[li];
+      s->tune_ublock = U[ui];
+      int it;
+      double rr;
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {  // the first run captures the graph
+        ZCHK(hipEventRecord(e0, s->st));
+        (void)k_pcg(s, s->ytmp.p, s->pdir.p, 0.0, iters, &it, &rr);
+        ZCHK(hipEventRecord(e1, s->st));
+        ZCHK(hipEventSynchronize(e1));
+        ZCHK(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (ms < best) {
+        best = ms;
+        bl = L[li];
+        bu = U[ui];
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->tune_lanes = bl;
+  s->tune_ublock = bu;
+  *lanes_out = bl;
+  *ub_out = bu;
+  *us_per_iter = 1e3 * best / iters;
 }
 
 // ------------------------------------------------------------------ batched PCG

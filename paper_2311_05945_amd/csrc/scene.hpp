@@ -181,6 +181,7 @@ struct zema_scene {
   zema::KTimer kt[zema::KT_N];
   // ---- graph-captured PCG chunks
   bool use_graph = true;
+  int tune_lanes = 16, tune_ublock = 256;  // launch shapes of the fused PCG kernels
   hipStream_t cap_st = nullptr;          // capture stream (default priority)
   zema::PcgGraph pcg_graph;
   zema::DBuf<unsigned char> mat_dev;     // matrix descriptors read by the captured kernels
@@ -255,6 +256,7 @@ void k_radix_sort(zema_scene* s, SortBufs& b, int64_t n, int key_bits);  // sort
 void k_hess_matvec(zema_scene* s, const double* v, double* out);
 void k_build_precond(zema_scene* s);
 int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres);
+void k_autotune(zema_scene* s, int* lanes_out, int* ub_out, double* us_per_iter);
 void k_pcg_batch(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, const int* active_host,
                  int* iters, double* relres, int* status);
 

@@ -85,6 +85,7 @@ SIGNATURES = [
     ("zema_batch_create", [VP, I32, VP, PI32, VP, PI32, VP, C.POINTER(VP)]),
     ("zema_batch_layout", [VP, C.POINTER(I32), PI64]),
     ("zema_tune", [VP, I32, I32]),
+    ("zema_autotune", [VP, PI32, PI32, PD]),
     ("zema_scene_set_mlp", [VP, VP]),
     ("zema_scene_features", [VP, VP]),
     ("zema_scene_warm_target", [VP, VP]),
@@ -92,7 +93,7 @@ SIGNATURES = [
 MLP_PARAMS = 9603
 MLP_FEATURES = 16
 WARM_EXPLICIT, WARM_LEARNED = 0, 1
-TUNE_PCG_GRAPH = 0
+TUNE_PCG_GRAPH, TUNE_SPMV_LANES, TUNE_UPDATE_BLOCK = 0, 1, 2
 KT_SPMV, KT_TET, KT_CONTACT, KT_QUERY, KT_CCD = range(5)
 
 
@@ -334,6 +335,12 @@ class Scene:
 
     def tune(self, knob, value):
         self._chk(lib().zema_tune(self.h, int(knob), int(value)))
+
+    def autotune(self):
+        """(lanes per soft row, update block, microseconds per PCG iteration) chosen."""
+        l, u, t = I32(), I32(), D()
+        self._chk(lib().zema_autotune(self.h, C.byref(l), C.byref(u), C.byref(t)))
+        return l.value, u.value, t.value
 
     def kernel_timer(self, group, enable=True):
         self._chk(lib().zema_kernel_timer(self.h, int(group), 1 if enable else 0))

@@ -357,3 +357,27 @@ def test_pcg_graph_replays_match_eager(zema, gripper_full):
         G.hessian_matvec(x1)                           # eager work between replays
         G.ip_assemble(y)
     assert it0 > 32                                    # several chunks were replayed
+
+
+def test_autotune_changes_rounding_only(zema, gripper_full):
+    """Every launch shape the autotuner may pick solves the same system to the same
+    accuracy: the shapes change only the summation order, so the CG iterates differ by
+    rounding (amplified over ~240 iterations); iteration counts within 5 and solutions
+    within the solve's own relative tolerance 1e-4."""
+    sc, R, y, yd = gripper_full
+    G = zema.Scene(sc)
+    G.set_state(y, yd)
+    G.ip_assemble(y)
+    rhs = np.random.default_rng(6).normal(size=G.n_dof)
+    x0, it0, _ = G.pcg_solve(rhs)
+    for lanes in (8, 16, 32):
+        for ub in (64, 128, 256):
+            G.tune(zema.TUNE_SPMV_LANES, lanes)
+            G.tune(zema.TUNE_UPDATE_BLOCK, ub)
+            x1, it1, _ = G.pcg_solve(rhs)
+            rel = (x1 - x0).abs().max().item() / x0.abs().max().item()
+            log(f"lanes {lanes} block {ub}: {it1} iterations (default {it0}), rel diff {rel:.2e}")
+            assert abs(it1 - it0) <= 5 and rel <= 1e-4, (lanes, ub, it1, it0, rel)
+    lanes, ub, us = G.autotune()
+    log(f"autotune: {lanes} lanes, update block {ub}, {us:.2f} us per PCG iteration")
+    assert lanes in (8, 16, 32) and ub in (64, 128, 256) and us > 0

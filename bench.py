@@ -55,6 +55,22 @@ def cpu_baseline(scene, seconds, max_steps=20):
                       f"these early steps include the contact-free approach of the fingers)"}
 
 
+def hbm_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter profile, or None when
+    the profile is missing or the kernel's source changed since it was taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "pcg_spmv_gripper_r32_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2311_05945_amd", "csrc", "k_sparse.hip")
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for line in open(prof):
+        f = line.split()
+        if len(f) == 6 and f[0] == "traffic" and f[1] == kernel and f[5] == sha:
+            return float(f[3])
+    return None
+
+
 def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5):
     """Steps every scene `steps` times; returns (wall seconds, stats list, intersections)."""
     import torch
@@ -129,7 +145,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=10, help="steps per library call (progress lines)")
     ap.add_argument("--timing-steps", type=int, default=5, help="steps of the roofline pass after the timed run")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / learned / mixed comparison")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default PCG launch shapes")
+    ap.add_argument("--autotune", action="store_true", help="pick the PCG launch shapes by timing (default: fixed)")
+    ap.add_argument("--no-graph", action="store_true", help="launch PCG kernels individually")
+    ap.add_argument("--copy-probe", action="store_true", help="run a 256 MiB device copy (counter scaling)")
     ap.add_argument("--form-scenes", type=int, default=8)
     ap.add_argument("--form-steps", type=int, default=16)
     ap.add_argument("--form-seed", type=int, default=10000)
@@ -150,12 +168,14 @@ def main():
     if args.warmup > 0:
         W = zema.Scene(sc)
         W.step(args.warmup)
-        if not args.no_autotune:
+        if args.autotune:
             lanes, ub, us = W.autotune()
             tuned = {"spmv_lanes": lanes, "update_block": ub, "us_per_pcg_iter": us}
             log(f"autotuned PCG shapes: {lanes} lanes per soft row, update block {ub}, {us:.2f} us/iteration")
         del W
     G = zema.Scene(sc)
+    if args.no_graph:
+        G.tune(zema.TUNE_PCG_GRAPH, 0)
     if tuned is not None:
         G.tune(zema.TUNE_SPMV_LANES, tuned["spmv_lanes"])
         G.tune(zema.TUNE_UPDATE_BLOCK, tuned["update_block"])
@@ -185,6 +205,9 @@ def main():
     t_roof = time.perf_counter() - tr0
     ms_k, launches, bytes_k = G.kernel_time(group)
     log(f"roofline pass: {args.timing_steps} steps, {launches} launches of {args.timer}, {ms_k:.1f} ms")
+    traffic = None
+    if args.timer == "spmv" and tuned is None and not G.params.precision:
+        traffic = hbm_traffic("pcg_spmv_kernel<double,16>")
     newton = sum(s["newton_iters"] for s in stats)
     pcg = sum(s["pcg_iters"] for s in stats)
     achieved = bytes_k / (ms_k * 1e-3) / 1e9 if ms_k > 0 else 0.0
@@ -210,7 +233,8 @@ def main():
                    "seed": args.seed, "res": args.res, "soft_vertices": G.n_soft_verts, "tets": G.n_tets,
                    "dofs": G.n_dof, "surface_triangles": G.n_tris},
         "roofline": {"kernel": args.timer, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
                      "avg_launch_us": 1e3 * ms_k / max(launches, 1), "launches": launches,
                      "bytes_per_launch": bytes_k / max(launches, 1),
                      "timing_steps": args.timing_steps,
@@ -220,6 +244,16 @@ def main():
                               for k in ("assemble", "pcg", "broad", "ccd", "linesearch")},
         "failed_steps": sum(1 for s in stats if s["status"] != 0),
     }
+    if args.copy_probe:
+        # a streaming kernel of known size (reads 256 MiB, writes 256 MiB), for scaling
+        # the HBM counters of a profile
+        n = 1 << 25                                  # 32 Mi doubles
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 8 * n
     if not args.no_forms:
         out["forms"] = forms(args, zema)
     if not args.no_cpu:

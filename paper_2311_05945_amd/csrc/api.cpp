@@ -475,6 +475,7 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
     s->sc_mask.resize(ns);
     s->sc_rng.resize((size_t)8 * ns);
     s->sc_cnt.resize(ns);
+    s->sc_act.resize(ns);
   }
   s->sv_x0.upload(sv_x0);
   s->tris.upload(tris_h);
@@ -730,6 +731,11 @@ int time_step(zema_scene* s, zema_step_stats* st) {
   std::vector<double> alpha(ns), disp(ns), rr(ns);
   int n_active = ns;
   for (int it = 0; it < s->P.newton_max && n_active > 0; ++it) {
+    if (ns > 1) {  // assembly skips scenes that have converged
+      s->mask_h.assign(active.begin(), active.end());
+      ZCHK(hipMemcpyAsync(s->sc_act.p, s->mask_h.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s->st));
+      s->masked = it > 0;
+    }
     q = now_ms();
     bool ok = assemble(s, s->y.p, s->grad.p, true, 0x3fu, T.data());
     ta += now_ms() - q;
@@ -823,6 +829,7 @@ int time_step(zema_scene* s, zema_step_stats* st) {
     }
     if (kchg) upload_kappa(s);
   }
+  s->masked = false;
   std::vector<double> dfin = min_distance(s, s->y.p);
   for (int k = 0; k < ns; ++k) {
     if (active[k]) st[k].newton_iters = s->P.newton_max;
@@ -902,6 +909,7 @@ zema_scene::~zema_scene() {
   for (zema::KTimer& t : kt)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
   if (pcg_graph.exec) (void)hipGraphExecDestroy(pcg_graph.exec);
+  if (pcgb_graph.exec) (void)hipGraphExecDestroy(pcgb_graph.exec);
   if (cap_st) (void)hipStreamDestroy(cap_st);
 }
 
@@ -1153,6 +1161,7 @@ int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
     });
     for (int j = 0; j < s->ns; ++j) stats[(size_t)k * s->ns + j].status = rc;
     s->stepped = rc == 0;
+    s->masked = false;
     if (rc) {
       // restore y^t and ydot^t of the failed step
       (void)hipMemcpyAsync(s->y.p, s->yt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st);

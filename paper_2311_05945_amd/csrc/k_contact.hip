@@ -221,7 +221,7 @@ struct ItemArgs {
   const int *pt, *ee, *tris, *edges, *act, *sv_ref, *bi, *fids;
   const double *elen2, *xs, *sv_x0, *fvals, *fxt;
   const double *kappa_sc, *mu_sc;
-  const int* sv_scene;
+  const int *sv_scene, *active;
   double dhat, ys;
   int nn_total, hess;
 };
@@ -239,9 +239,16 @@ __device__ inline void item_slots(const ItemArgs& A, int i, int& kind, int sv[4]
   }
 }
 
-__global__ void active_flag_kernel(int n, const double* __restrict__ d_pair, double dhat, int* __restrict__ flag) {
+// barrier pairs closer than dhat (of scenes still iterating, when a mask is given)
+__global__ void active_flag_kernel(int n, int npt, const int* __restrict__ pt, const int* __restrict__ ee,
+                                   const int* __restrict__ edges, const int* __restrict__ sv_scene,
+                                   const int* __restrict__ active, const double* __restrict__ d_pair, double dhat,
+                                   int* __restrict__ flag) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) flag[k] = d_pair[k] < dhat ? 1 : 0;
+  if (k >= n) return;
+  int f = d_pair[k] < dhat ? 1 : 0;
+  if (f && active) f = active[sv_scene[k < npt ? pt[2 * k] : edges[2 * ee[2 * (k - npt)]]]];
+  flag[k] = f;
 }
 
 __global__ void compact_kernel(int n, const int* __restrict__ flag, const int* __restrict__ offs, int* __restrict__ out) {
@@ -271,6 +278,12 @@ __global__ void __launch_bounds__(64) pair_deriv_kernel(ItemArgs A, double* __re
   int kind, sv[4], ea, eb;
   bool fric;
   item_slots(A, i, kind, sv, ea, eb, fric);
+  if (fric && A.active && !A.active[A.sv_scene[sv[0]]]) {  // converged scene of a batch
+    for (int k = 0; k < 12; ++k) gout[(size_t)12 * i + k] = 0.0;
+    if (A.hess)
+      for (int k = 0; k < 144; ++k) hout[(size_t)144 * i + k] = 0.0;
+    return;
+  }
   V3 x[4];
   for (int a = 0; a < 4; ++a) x[a] = ld3(A.xs + 3 * sv[a]);
   double g[12];
@@ -670,7 +683,9 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   if ((mask & 16u) && nc) {
     s->cnt.reserve(nc + 1);
     s->offs.reserve(nc + 1);
-    active_flag_kernel<<<nblocks(nc), kBlock, 0, s->st>>>(nc, s->d_pair.p, s->P.dhat, s->cnt.p);
+    active_flag_kernel<<<nblocks(nc), kBlock, 0, s->st>>>(nc, (int)s->npt, s->pt.p, s->ee.p, s->edges.p,
+                                                          s->sv_scene.p, s->act_dev(), s->d_pair.p, s->P.dhat,
+                                                          s->cnt.p);
     s->n_act = (int)k_exclusive_scan(s, s->cnt.p, s->offs.p, nc);
     s->act_idx.reserve(s->n_act + 1);
     compact_kernel<<<nblocks(nc), kBlock, 0, s->st>>>(nc, s->cnt.p, s->offs.p, s->act_idx.p);
@@ -704,6 +719,7 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   A.kappa_sc = s->kappa_sc.p;
   A.mu_sc = s->mu_sc.p;
   A.sv_scene = s->sv_scene.p;
+  A.active = s->act_dev();
   A.dhat = s->P.dhat;
   A.ys = s->P.eps_v * s->P.dt;
   A.nn_total = s->nnodes;

@@ -37,9 +37,11 @@ __global__ void __launch_bounds__(128) tet_assemble_kernel(int nt, const int4* _
                                                             const double* __restrict__ llam,
                                                             const double* __restrict__ y, double* __restrict__ e_out,
                                                             double* __restrict__ g_out, T* __restrict__ h_out,
-                                                            int want_h) {
+                                                            int want_h, const int* __restrict__ v_scene,
+                                                            const int* __restrict__ active) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nt) return;
+  if (active && !active[v_scene[tets[e].x]]) return;  // converged scene of a batch: blocks kept
   double F[3][3], G[4][3];
   int4 t;
   load_tet(e, nt, tets, Dmi, y, F, G, t);
@@ -144,11 +146,13 @@ void k_tet_assemble(zema_scene* s, const double* y, bool hess) {
   if (s->mixed)
     tet_assemble_kernel<float><<<nblocks(s->nt, 128), 128, 0, s->st>>>(s->nt, s->tets.p, s->Dmi.p, s->h2vol.p,
                                                                        s->lmu.p, s->llam.p, y, s->e_tet.p,
-                                                                       s->g_tet.p, s->h_tet32.p, hess ? 1 : 0);
+                                                                       s->g_tet.p, s->h_tet32.p, hess ? 1 : 0,
+                                                                       s->v_scene.p, s->act_dev());
   else
     tet_assemble_kernel<double><<<nblocks(s->nt, 128), 128, 0, s->st>>>(s->nt, s->tets.p, s->Dmi.p, s->h2vol.p,
                                                                         s->lmu.p, s->llam.p, y, s->e_tet.p,
-                                                                        s->g_tet.p, s->h_tet.p, hess ? 1 : 0);
+                                                                        s->g_tet.p, s->h_tet.p, hess ? 1 : 0,
+                                                                        s->v_scene.p, s->act_dev());
   kt_end(s, KT_TET, (s->mixed ? 170.0 : 320.0) * s->nt);
 }
 

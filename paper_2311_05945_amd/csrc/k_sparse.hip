@@ -878,10 +878,12 @@ __global__ void pcgb_init_fin(const double* __restrict__ d1, const double* __res
 // q = H p with p = z + beta_scene p_old formed in the gathers; p stored; per-node
 // p.q.  Rows of finished scenes are skipped.
 template <class V>
-__global__ void pcgb_spmv_kernel(Mat<V> M, const int* __restrict__ v_scene, const int* __restrict__ f_scene,
+__global__ void pcgb_spmv_kernel(const Mat<V>* __restrict__ Mp, const int* __restrict__ v_scene,
+                                 const int* __restrict__ f_scene,
                                  const double* __restrict__ sc, const double* __restrict__ z,
                                  const double* __restrict__ pold, double* __restrict__ pnew, double* __restrict__ q,
                                  double* __restrict__ pq) {
+  const Mat<V> M = *Mp;
   __shared__ double red[3 * (kBlock / 64)];
   int nsoft_blocks = (M.nsv + (kBlock / RG) - 1) / (kBlock / RG);
   if ((int)blockIdx.x < nsoft_blocks) {
@@ -990,7 +992,7 @@ __global__ void pcgb_beta_kernel(const double* __restrict__ d1, const double* __
   double rz = scene_unit_sum(d1, rng, k, nsv, sh);
   double rr = scene_unit_sum(d2, rng, k, nsv, sh);
   if (threadIdx.x == 0) {
-    c[7] = it + 1;
+    c[7] += 1.0;  // iterations completed by this scene
     c[4] = rr;
     if (rr <= c[9]) {
       c[6] = 1.0;
@@ -1024,33 +1026,90 @@ void k_pcg_batch(zema_scene* s, const double* rhs, double* sol, double rtol, int
     pcgb_init_kernel<<<nblocks(nunits), kBlock, 0, s->st>>>(s->nsv, s->nfree, rhs, s->minv_soft.p, s->minv_body.p,
                                                             sol, s->pr.p, s->pz.p, s->pp0.p, d1, d2);
   pcgb_init_fin<<<ns, kBlock, 0, s->st>>>(d1, d2, s->scn_rng.p, s->sc_mask.p, s->nsv, sc, rtol);
-  auto M64 = make_mat<double>(s, s->bsr_val.p, s->c_val.p);
-  auto M32 = make_mat<float>(s, s->bsr_val32.p, s->c_val32.p);
-  int g = spmv_grid(s);
+  s->mat_h.resize(sizeof(Mat<double>) + sizeof(Mat<float>));
+  Mat<double> M64 = make_mat<double>(s, s->bsr_val.p, s->c_val.p);
+  Mat<float> M32 = make_mat<float>(s, s->bsr_val32.p, s->c_val32.p);
+  std::memcpy(s->mat_h.data(), &M64, sizeof(M64));
+  std::memcpy(s->mat_h.data() + sizeof(M64), &M32, sizeof(M32));
+  s->mat_dev.reserve(s->mat_h.size());
+  ZCHK(hipMemcpyAsync(s->mat_dev.p, s->mat_h.data(), s->mat_h.size(), hipMemcpyHostToDevice, s->st));
+  const Mat<double>* D64 = (const Mat<double>*)s->mat_dev.p;
+  const Mat<float>* D32 = (const Mat<float>*)(s->mat_dev.p + sizeof(Mat<double>));
+  const int g = spmv_grid(s);
+  const double bytes = (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 32.0 * s->ndof;
+  auto iteration = [&](double* pold, double* pnew, hipStream_t st) {
+    if (g) {
+      if (s->mixed)
+        pcgb_spmv_kernel<float><<<g, kBlock, 0, st>>>(D32, s->v_scene.p, s->f_scene.p, sc, s->pz.p, pold, pnew, s->pq.p,
+                                                      pqn);
+      else
+        pcgb_spmv_kernel<double><<<g, kBlock, 0, st>>>(D64, s->v_scene.p, s->f_scene.p, sc, s->pz.p, pold, pnew,
+                                                       s->pq.p, pqn);
+    }
+  };
+  auto rest = [&](double* pnew, hipStream_t st) {
+    pcgb_alpha_kernel<<<ns, kBlock, 0, st>>>(pqn, s->scn_rng.p, s->nsv, sc);
+    if (nunits)
+      pcgb_update_kernel<<<nblocks(nunits), kBlock, 0, st>>>(s->nsv, s->nfree, s->v_scene.p, s->f_scene.p, sc, pnew,
+                                                             s->pq.p, s->minv_soft.p, s->minv_body.p, sol, s->pr.p,
+                                                             s->pz.p, d1, d2);
+    pcgb_beta_kernel<<<ns, kBlock, 0, st>>>(d1, d2, s->scn_rng.p, s->nsv, 0, sc);
+  };
+  // a chunk of 16 iterations (even: p_old is pp0 at every chunk start), captured once
+  // per set of buffers and replayed
+  const bool timed = s->kt[KT_SPMV].on;
+  bool graph_ok = false;
+  if (s->use_graph && !timed) {
+    std::vector<const void*> key = {D64, sc, sol, pqn, d1, d2, s->pz.p, s->pp0.p, s->pp1.p, s->pq.p, s->pr.p,
+                                    s->minv_soft.p, s->minv_body.p, (const void*)(intptr_t)g,
+                                    (const void*)(intptr_t)s->mixed, (const void*)(intptr_t)ns};
+    PcgGraph& G = s->pcgb_graph;
+    graph_ok = G.exec && G.key == key;
+    if (!graph_ok) {
+      if (G.exec) {
+        ZCHK(hipGraphExecDestroy(G.exec));
+        G.exec = nullptr;
+      }
+      if (!s->cap_st) ZCHK(hipStreamCreate(&s->cap_st));
+      if (hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeRelaxed) == hipSuccess) {
+        double* po = s->pp0.p;
+        double* pn = s->pp1.p;
+        for (int c = 0; c < 16; ++c) {
+          iteration(po, pn, s->cap_st);
+          rest(pn, s->cap_st);
+          std::swap(po, pn);
+        }
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamEndCapture(s->cap_st, &graph) == hipSuccess && graph;
+        if (ok) ok = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        if (ok) {
+          G.key = key;
+          graph_ok = true;
+        } else {
+          G.exec = nullptr;
+        }
+      }
+    }
+  }
   double* pold = s->pp0.p;
   double* pnew = s->pp1.p;
   std::vector<double> hs((size_t)16 * ns);
   const int chunk = 16;
   int it = 0;
   for (;;) {
-    for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
-      kt_begin(s, KT_SPMV);
-      if (g) {
-        if (s->mixed)
-          pcgb_spmv_kernel<float><<<g, kBlock, 0, s->st>>>(M32, s->v_scene.p, s->f_scene.p, sc, s->pz.p, pold, pnew,
-                                                           s->pq.p, pqn);
-        else
-          pcgb_spmv_kernel<double><<<g, kBlock, 0, s->st>>>(M64, s->v_scene.p, s->f_scene.p, sc, s->pz.p, pold, pnew,
-                                                            s->pq.p, pqn);
+    if (graph_ok && max_iter - it >= chunk) {
+      ZCHK(hipGraphLaunch(s->pcgb_graph.exec, s->st));
+      it += chunk;
+    } else {
+      for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
+        kt_begin(s, KT_SPMV);
+        iteration(pold, pnew, s->st);
+        kt_end(s, KT_SPMV, bytes);
+        rest(pnew, s->st);
+        std::swap(pold, pnew);
       }
-      kt_end(s, KT_SPMV, (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 32.0 * s->ndof);
-      pcgb_alpha_kernel<<<ns, kBlock, 0, s->st>>>(pqn, s->scn_rng.p, s->nsv, sc);
-      if (nunits)
-        pcgb_update_kernel<<<nblocks(nunits), kBlock, 0, s->st>>>(s->nsv, s->nfree, s->v_scene.p, s->f_scene.p, sc,
-                                                                  pnew, s->pq.p, s->minv_soft.p, s->minv_body.p, sol,
-                                                                  s->pr.p, s->pz.p, d1, d2);
-      pcgb_beta_kernel<<<ns, kBlock, 0, s->st>>>(d1, d2, s->scn_rng.p, s->nsv, it, sc);
-      std::swap(pold, pnew);
     }
     ZCHK(hipMemcpyAsync(hs.data(), sc, sizeof(double) * 16 * ns, hipMemcpyDeviceToHost, s->st));
     ZCHK(hipStreamSynchronize(s->st));

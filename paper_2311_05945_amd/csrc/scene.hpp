@@ -86,6 +86,9 @@ struct zema_scene {
   zema::DBuf<double> sc_alpha, sc_sum;                          // per-scene step sizes, sums [ns][8]
   zema::DBuf<int> sc_mask, sc_rng;                              // per-scene flags; pair ranges [ns][8]
   zema::DBuf<unsigned int> sc_cnt;
+  zema::DBuf<int> sc_act;                // scenes still iterating (batches), read by assembly
+  bool masked = false;                   // assembly skips converged scenes
+  const int* act_dev() const { return masked ? sc_act.p : nullptr; }
   std::vector<double> kappa_h, scale_h;  // host staging of per-scene uploads
   std::vector<int> mask_h;
   std::vector<zema::Body> bodies;  // affine bodies, creation order
@@ -183,7 +186,7 @@ struct zema_scene {
   bool use_graph = true;
   int tune_lanes = 16, tune_ublock = 256;  // launch shapes of the fused PCG kernels
   hipStream_t cap_st = nullptr;          // capture stream (default priority)
-  zema::PcgGraph pcg_graph;
+  zema::PcgGraph pcg_graph, pcgb_graph;   // single-scene and batched chunks
   zema::DBuf<unsigned char> mat_dev;     // matrix descriptors read by the captured kernels
   std::vector<unsigned char> mat_h;
   ~zema_scene();

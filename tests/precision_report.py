@@ -26,6 +26,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--res", type=int, default=64)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--newton-max", type=int, default=1000)
     args = ap.parse_args()
     import torch
 
@@ -33,6 +34,7 @@ def main():
     from paper_2311_05945_amd import zema
     sa = sg.gripper(args.seed, r=args.res, steps=args.steps)
     sb = sg.gripper(args.seed, r=args.res, steps=args.steps, precision=1)
+    sa.params.newton_max = sb.params.newton_max = args.newton_max
     A = zema.Scene(sa)
     B = zema.Scene(sb)
     n3 = 3 * A.n_soft_verts

@@ -312,9 +312,8 @@ __device__ inline void dv_to_slots(const DVars& d, double* g, double (*H)[12]) {
         }
 }
 
-// Squared distance of the given type with slot-space gradient and Hessian.
-__device__ inline double d2_derivs(int kind, int type, const V3* x, double* g, double (*H)[12]) {
-  DVars d;
+// Squared distance of the given type with slot-space gradient and Hessian (d: workspace).
+__device__ inline double d2_derivs(int kind, int type, const V3* x, double* g, double (*H)[12], DVars& d) {
   double D;
   if (kind == 0) {
     if (type <= 2)
@@ -382,13 +381,21 @@ __host__ __device__ inline void mollifier(double c, double eps, double& m, doubl
 
 // Barrier energy kappa m b(d) of one pair with slot-space gradient and Hessian
 // (unprojected).  Returns false when inactive (d >= dhat).
+// Workspace of the pair derivatives; callers place it where it is cheap to address
+// (a wavefront's LDS), since a lane's private arrays of this size spill to scratch.
+struct PairWork {
+  DVars d, dw, dc;
+  double gc[12];
+  double Hc[12][12];
+};
+
 __device__ inline bool pair_barrier(int kind, const V3* x, double eps_x, double kappa, double dhat, double& E,
-                                    double* g, double (*H)[12], double* dist) {
+                                    double* g, double (*H)[12], double* dist, PairWork& w) {
   int type;
   double d = pair_dist(kind, x, &type);
   if (dist) *dist = d;
   if (!(d < dhat)) return false;
-  double D = d2_derivs(kind, type, x, g, H);  // g, H hold grad / Hessian of D
+  double D = d2_derivs(kind, type, x, g, H, w.d);  // g, H hold grad / Hessian of D
   d = sqrt(D);
   double b, b1, b2;
   barrier3(d, dhat, b, b1, b2);
@@ -406,7 +413,8 @@ __device__ inline bool pair_barrier(int kind, const V3* x, double eps_x, double 
       double m1, m2;
       mollifier(c, eps_x, m, m1, m2);
       // gradient / Hessian of c = |u x v|^2 with u = a1 - a0, v = b1 - b0
-      DVars dw, dc;
+      DVars& dw = w.dw;
+      DVars& dc = w.dc;
       dvar_triple(x[2] - x[0], u, v, dw, &dc);
       dc.C[0][2] = 1;
       dc.C[0][0] = -1;
@@ -414,8 +422,8 @@ __device__ inline bool pair_barrier(int kind, const V3* x, double eps_x, double 
       dc.C[1][0] = -1;
       dc.C[2][3] = 1;
       dc.C[2][2] = -1;
-      double gc[12];
-      double Hc[12][12];
+      double* gc = w.gc;
+      double (*Hc)[12] = w.Hc;
       dv_to_slots(dc, gc, Hc);
       for (int i = 0; i < 12; ++i)
         for (int j = 0; j < 12; ++j)

@@ -268,53 +268,58 @@ __global__ void item_count_kernel(ItemArgs A, int* __restrict__ cnt) {
   cnt[i] = nd + (A.hess ? nd * nd : 0);
 }
 
-// K1: one lane per item: gradient (12) and full 12x12 Hessian in x-space.  Barrier
-// pairs store the unprojected Hessian (projected by K2); friction Hessians are PSD by
-// construction.
+// K1: one wavefront per item: gradient (12) and full 12x12 Hessian in x-space, formed
+// by lane 0 with the matrices and the derivative workspace in LDS (a lane's private
+// arrays of this size would live in scratch memory), written out by all lanes.
+// Barrier pairs store the unprojected Hessian (projected by K2); friction Hessians
+// are PSD by construction.
 __global__ void __launch_bounds__(64) pair_deriv_kernel(ItemArgs A, double* __restrict__ hout,
                                                         double* __restrict__ gout) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double H[12][12];
+  __shared__ double g[12];
+  __shared__ PairWork W;
+  const int i = blockIdx.x, lane = threadIdx.x;
   if (i >= A.n_act + A.nfric) return;
-  int kind, sv[4], ea, eb;
-  bool fric;
-  item_slots(A, i, kind, sv, ea, eb, fric);
-  if (fric && A.active && !A.active[A.sv_scene[sv[0]]]) {  // converged scene of a batch
-    for (int k = 0; k < 12; ++k) gout[(size_t)12 * i + k] = 0.0;
-    if (A.hess)
-      for (int k = 0; k < 144; ++k) hout[(size_t)144 * i + k] = 0.0;
-    return;
-  }
-  V3 x[4];
-  for (int a = 0; a < 4; ++a) x[a] = ld3(A.xs + 3 * sv[a]);
-  double g[12];
-  double H[12][12];
-  if (!fric) {
-    double eps = kind == 1 ? 1e-3 * A.elen2[ea] * A.elen2[eb] : 0.0;
-    double E, d;
-    pair_barrier(kind, x, eps, A.kappa_sc[A.sv_scene[sv[0]]], A.dhat, E, g, H, &d);
-  } else {
-    int f = i - A.n_act;
-    const double* fv = A.fvals + 8 * f;
-    V3 u = friction_u(fv, A.fxt + 12 * f, x);
-    double y = sqrt(dot(u, u)), f1y, al, be;
-    friction_core(y, A.ys, f1y, al, be);
-    double c = A.mu_sc[A.sv_scene[sv[0]]] * fv[0];
-    V3 n = ld3(fv + 1);
-    double U[3] = {u.x, u.y, u.z}, N[3] = {n.x, n.y, n.z};
-    for (int a = 0; a < 4; ++a)
-      for (int r = 0; r < 3; ++r) g[3 * a + r] = c * f1y * fv[4 + a] * U[r];
-    double core[3][3];
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) core[r][q] = al * ((r == q ? 1.0 : 0.0) - N[r] * N[q]) - be * U[r] * U[q];
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b)
+  if (lane == 0) {
+    int kind, sv[4], ea, eb;
+    bool fric;
+    item_slots(A, i, kind, sv, ea, eb, fric);
+    if (fric && A.active && !A.active[A.sv_scene[sv[0]]]) {  // converged scene of a batch
+      for (int k = 0; k < 12; ++k) g[k] = 0.0;
+      for (int r = 0; r < 12; ++r)
+        for (int q = 0; q < 12; ++q) H[r][q] = 0.0;
+    } else {
+      V3 x[4];
+      for (int a = 0; a < 4; ++a) x[a] = ld3(A.xs + 3 * sv[a]);
+      if (!fric) {
+        double eps = kind == 1 ? 1e-3 * A.elen2[ea] * A.elen2[eb] : 0.0;
+        double E, d;
+        pair_barrier(kind, x, eps, A.kappa_sc[A.sv_scene[sv[0]]], A.dhat, E, g, H, &d, W);
+      } else {
+        int f = i - A.n_act;
+        const double* fv = A.fvals + 8 * f;
+        V3 u = friction_u(fv, A.fxt + 12 * f, x);
+        double y = sqrt(dot(u, u)), f1y, al, be;
+        friction_core(y, A.ys, f1y, al, be);
+        double c = A.mu_sc[A.sv_scene[sv[0]]] * fv[0];
+        V3 n = ld3(fv + 1);
+        double U[3] = {u.x, u.y, u.z}, N[3] = {n.x, n.y, n.z};
+        for (int a = 0; a < 4; ++a)
+          for (int r = 0; r < 3; ++r) g[3 * a + r] = c * f1y * fv[4 + a] * U[r];
+        double core[3][3];
         for (int r = 0; r < 3; ++r)
-          for (int q = 0; q < 3; ++q) H[3 * a + r][3 * b + q] = c * fv[4 + a] * fv[4 + b] * core[r][q];
+          for (int q = 0; q < 3; ++q) core[r][q] = al * ((r == q ? 1.0 : 0.0) - N[r] * N[q]) - be * U[r] * U[q];
+        for (int a = 0; a < 4; ++a)
+          for (int b = 0; b < 4; ++b)
+            for (int r = 0; r < 3; ++r)
+              for (int q = 0; q < 3; ++q) H[3 * a + r][3 * b + q] = c * fv[4 + a] * fv[4 + b] * core[r][q];
+      }
+    }
   }
-  for (int k = 0; k < 12; ++k) gout[(size_t)12 * i + k] = g[k];
+  __syncthreads();
+  if (lane < 12) gout[(size_t)12 * i + lane] = g[lane];
   if (A.hess)
-    for (int r = 0; r < 12; ++r)
-      for (int q = 0; q < 12; ++q) hout[(size_t)144 * i + 12 * r + q] = H[r][q];
+    for (int e = lane; e < 144; e += 64) hout[(size_t)144 * i + e] = H[e / 12][e % 12];
 }
 
 // Round-robin (circle) ordering of the 66 index pairs of a 12x12 matrix: in round r
@@ -738,7 +743,7 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   s->trip_val.reserve((size_t)9 * ntrip + 9);
   s->item_h.reserve((size_t)144 * nitems + 144);
   s->item_g.reserve((size_t)12 * nitems + 12);
-  pair_deriv_kernel<<<nblocks(nitems, 64), 64, 0, s->st>>>(A, s->item_h.p, s->item_g.p);
+  pair_deriv_kernel<<<nitems, 64, 0, s->st>>>(A, s->item_h.p, s->item_g.p);
   kt_begin(s, KT_CONTACT);
   project_emit_kernel<<<nitems, 64, 0, s->st>>>(A, s->item_h.p, s->item_g.p, s->trip_off.p, sb.k0.p, s->trip_val.p);
   kt_end(s, KT_CONTACT);

@@ -256,8 +256,13 @@ int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect
  *   (8, 16 default, 32); ZEMA_TUNE_UPDATE_BLOCK: threads per block of the PCG vector
  *   update (64, 128, 256 default).  These change the floating-point summation order
  *   (results agree to rounding); a fixed setting is deterministic.
+ * ZEMA_TUNE_PCG_FORM: 1 (default) runs each PCG iteration as one launch, with the
+ *   two inner products of an iteration taken in one reduction (the Chronopoulos-Gear
+ *   arrangement of the same iterates); 0 runs the textbook order in two launches per
+ *   iteration.  In exact arithmetic both produce the same iterates; in floating point
+ *   they agree to rounding (the update-block knob applies to form 0 only).
  * Errors: ZEMA_E_ARG for an unknown knob or value. */
-enum { ZEMA_TUNE_PCG_GRAPH = 0, ZEMA_TUNE_SPMV_LANES = 1, ZEMA_TUNE_UPDATE_BLOCK = 2 };
+enum { ZEMA_TUNE_PCG_GRAPH = 0, ZEMA_TUNE_SPMV_LANES = 1, ZEMA_TUNE_UPDATE_BLOCK = 2, ZEMA_TUNE_PCG_FORM = 3 };
 int zema_tune(zema_scene* s, int32_t knob, int32_t value);
 /* Autotuner: times 64 PCG iterations on the last assembled Hessian (after
  * zema_ip_assemble or a step) for every lanes x update-block shape, keeps the

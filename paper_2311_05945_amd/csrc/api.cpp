@@ -909,7 +909,6 @@ zema_scene::~zema_scene() {
   for (zema::KTimer& t : kt)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
   if (pcg_graph.exec) (void)hipGraphExecDestroy(pcg_graph.exec);
-  if (pcgb_graph.exec) (void)hipGraphExecDestroy(pcgb_graph.exec);
   if (cap_st) (void)hipStreamDestroy(cap_st);
 }
 
@@ -1334,6 +1333,10 @@ int zema_tune(zema_scene* s, int32_t knob, int32_t value) {
   }
   if (knob == ZEMA_TUNE_UPDATE_BLOCK && (value == 64 || value == 128 || value == 256)) {
     s->tune_ublock = value;
+    return 0;
+  }
+  if (knob == ZEMA_TUNE_PCG_FORM && (value == 0 || value == 1)) {
+    s->pcg_form = value;
     return 0;
   }
   return ZEMA_E_ARG;

@@ -8,6 +8,7 @@
 // at scanned offsets; the triplets are radix-sorted by key and summed per key in
 // sorted order into a CSR contact matrix over the 3-DOF nodes.
 #include "geom.hpp"
+#include "wave_jacobi.hpp"
 #include "scene.hpp"
 
 namespace zema {
@@ -322,10 +323,6 @@ __global__ void __launch_bounds__(64) pair_deriv_kernel(ItemArgs A, double* __re
     for (int e = lane; e < 144; e += 64) hout[(size_t)144 * i + e] = H[e / 12][e % 12];
 }
 
-// Round-robin (circle) ordering of the 66 index pairs of a 12x12 matrix: in round r
-// the six pairs (L_k, L_{11-k}) are disjoint, L_0 = 0, L_i = ((i - 1 + r) mod 11) + 1.
-__device__ inline int rr_index(int r, int i) { return i == 0 ? 0 : ((i - 1 + r) % 11) + 1; }
-
 // K2: one wavefront (block of 64) per item.  Barrier Hessians are projected to PSD by
 // parallel cyclic Jacobi in LDS (six disjoint rotations per round, the update
 // A <- J^T A J and V <- V J applied to all 144 entries by the 64 lanes); then the
@@ -337,8 +334,7 @@ __global__ void __launch_bounds__(64) project_emit_kernel(ItemArgs A, const doub
                                                           const int* __restrict__ offs,
                                                           unsigned long long* __restrict__ key,
                                                           double* __restrict__ val) {
-  __shared__ double M[12 * LDA], Vm[12 * LDA], G[12], X0[12];
-  __shared__ double cs[12][2];  // per index: c and the signed partner coefficient
+  __shared__ double M[12 * LDA], Vm[12 * LDA], G[12], X0[12], cs[24];
   __shared__ int partner[12];
   const int i = blockIdx.x, lane = threadIdx.x;
   if (i >= A.n_act + A.nfric) return;
@@ -350,81 +346,9 @@ __global__ void __launch_bounds__(64) project_emit_kernel(ItemArgs A, const doub
     X0[lane] = A.sv_x0[3 * sv[lane / 3] + lane % 3];
   }
   if (A.hess) {
-    for (int e = lane; e < 144; e += 64) {
-      int r = e / 12, c = e % 12;
-      M[r * LDA + c] = hin[(size_t)144 * i + e];
-      Vm[r * LDA + c] = r == c ? 1.0 : 0.0;
-    }
+    for (int e = lane; e < 144; e += 64) M[(e / 12) * LDA + e % 12] = hin[(size_t)144 * i + e];
     __syncthreads();
-    if (!fric) {
-      double fro = 0.0;
-      for (int e = lane; e < 144; e += 64) fro += M[(e / 12) * LDA + e % 12] * M[(e / 12) * LDA + e % 12];
-      fro = wave_sum(fro);
-      for (int sweep = 0; sweep < 20; ++sweep) {
-        double off = 0.0;
-        for (int e = lane; e < 144; e += 64) {
-          int r = e / 12, c = e % 12;
-          if (r < c) off += M[r * LDA + c] * M[r * LDA + c];
-        }
-        off = wave_sum(off);
-        if (!(off > 1e-34 * fro)) break;
-        for (int rd = 0; rd < 11; ++rd) {
-          if (lane < 6) {
-            int p = rr_index(rd, lane), q = rr_index(rd, 11 - lane);
-            double apq = M[p * LDA + q], c = 1.0, sn = 0.0;
-            if (apq != 0.0) {
-              double th = (M[q * LDA + q] - M[p * LDA + p]) / (2.0 * apq);
-              double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-              c = 1.0 / sqrt(t * t + 1.0);
-              sn = t * c;
-            }
-            // column p of J: (p: c, q: -s); column q of J: (p: s, q: c)
-            partner[p] = q;
-            partner[q] = p;
-            cs[p][0] = c;
-            cs[p][1] = -sn;
-            cs[q][0] = c;
-            cs[q][1] = sn;
-          }
-          __syncthreads();
-          double na[3], nv[3];
-          int cnt = 0;
-          for (int e = lane; e < 144; e += 64, ++cnt) {
-            int r = e / 12, c = e % 12;
-            int rp = partner[r], cp = partner[c];
-            double jrr = cs[r][0], jpr = cs[r][1];  // J[r][r], J[rp][r]
-            double jcc = cs[c][0], jpc = cs[c][1];  // J[c][c], J[cp][c]
-            // (A J)[k][c] for k in {r, rp}
-            double arc = M[r * LDA + c] * jcc + M[r * LDA + cp] * jpc;
-            double apc = M[rp * LDA + c] * jcc + M[rp * LDA + cp] * jpc;
-            na[cnt] = jrr * arc + jpr * apc;
-            nv[cnt] = Vm[r * LDA + c] * jcc + Vm[r * LDA + cp] * jpc;
-          }
-          __syncthreads();
-          cnt = 0;
-          for (int e = lane; e < 144; e += 64, ++cnt) {
-            M[(e / 12) * LDA + e % 12] = na[cnt];
-            Vm[(e / 12) * LDA + e % 12] = nv[cnt];
-          }
-          __syncthreads();
-        }
-      }
-      // P = V max(Lambda, 0) V^T
-      double pv[3];
-      int cnt = 0;
-      for (int e = lane; e < 144; e += 64, ++cnt) {
-        int r = e / 12, c = e % 12;
-        double acc = 0.0;
-        for (int k = 0; k < 12; ++k) {
-          double l = M[k * LDA + k];
-          if (l > 0.0) acc += l * Vm[r * LDA + k] * Vm[c * LDA + k];
-        }
-        pv[cnt] = acc;
-      }
-      __syncthreads();
-      cnt = 0;
-      for (int e = lane; e < 144; e += 64, ++cnt) M[(e / 12) * LDA + e % 12] = pv[cnt];
-    }
+    if (!fric) wave_psd_project<12, LDA>(M, Vm, cs, partner, lane);  // block-uniform branch
   }
   __syncthreads();
   // node list of the item: entities (soft vertex: one node; free affine body: p, a1..a3)
@@ -440,6 +364,7 @@ __global__ void __launch_bounds__(64) project_emit_kernel(ItemArgs A, const doub
       int e = 0, j = t;
       while (j >= E.nn[e]) j -= E.nn[e++];
       double acc[3] = {0, 0, 0};
+#pragma unroll 1
       for (int a = 0; a < 4; ++a) {
         if (E.of_slot[a] != e) continue;
         if (E.nn[e] == 1 || j == 0) {
@@ -459,8 +384,10 @@ __global__ void __launch_bounds__(64) project_emit_kernel(ItemArgs A, const doub
       while (l >= E.nn[f]) l -= E.nn[f++];
       bool Ij = (E.nn[e] == 1 || j == 0), Il = (E.nn[f] == 1 || l == 0);
       double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
       for (int a = 0; a < 4; ++a) {
         if (E.of_slot[a] != e) continue;
+#pragma unroll 1
         for (int b = 0; b < 4; ++b) {
           if (E.of_slot[b] != f) continue;
           const double* P = M + (3 * a) * LDA + 3 * b;  // P_ab[r][c] = P[r * LDA + c]

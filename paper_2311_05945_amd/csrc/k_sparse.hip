@@ -675,6 +675,9 @@ static bool pcg_graph_ready(zema_scene* s, const PcgArgs& a) {
   return true;
 }
 
+static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, const double* rhs, double* sol,
+                     double rtol, int max_iter, const int* active_host, int* iters, double* relres, int* status);
+
 int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres) {
   int n = s->ndof;
   if (max_iter <= 0) max_iter = n;
@@ -711,6 +714,14 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   a.sc = s->scal.p;
   a.sol = sol;
   a.bytes = (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 32.0 * s->ndof;
+  if (s->pcg_form == 1) {
+    // matrix once; r, w, s, p, x read and written once per DOF; 3x3 inverse blocks;
+    // node records read and written once
+    a.bytes = (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 152.0 * s->ndof;
+    int one = 1, st = 0;
+    k_pcg_cg(s, a.mat, lanes, a.bytes, rhs, sol, rtol, max_iter, &one, iters, relres, &st);
+    return st;
+  }
   pcg_init_kernel<<<nbv, kBlock, 0, s->st>>>(s->nsv, s->nfree, rhs, s->minv_soft.p, s->minv_body.p, sol, s->pr.p,
                                              s->pz.p, s->pp0.p, a.upart);
   pcg_init_fin<<<1, kBlock, 0, s->st>>>(nbv, a.upart, a.sc, rtol);
@@ -755,6 +766,524 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   if (hs[8] != 0.0) return ZEMA_E_PCG;
   if (hs[6] == 0.0) return ZEMA_E_PCG;
   return 0;
+}
+
+// ------------------------------------------------------------------ single-reduction PCG
+// The same preconditioned CG iterates, rearranged after Chronopoulos and Gear (1989) so
+// that both inner products of an iteration come from one reduction:
+//   gamma_k = r_k . z_k,  delta_k = z_k . w_k  (z_k = M^-1 r_k, w_k = H z_k)
+//   beta_k = gamma_k / gamma_{k-1},  alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+//   p_k = z_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}  (s_k = H p_k)
+//   x_{k+1} = x_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k
+// (delta_k - beta_k gamma_k / alpha_{k-1} equals p_k . H p_k, the standard denominator.)
+// One launch per iteration.  Every block reduces the previous launch's partials of its
+// scene into gamma_k, delta_k, |r_k|^2 (same order in every block of the scene).  The
+// product w_{k+1} = H z_{k+1}, z_{k+1} = M^-1 r_k - alpha_k (M^-1 w_k + beta_k M^-1 s_{k-1}),
+// is gathered as three accumulators over a per-node record Z = (M^-1 r_k, M^-1 w_k,
+// M^-1 s_{k-1}) written by the previous launch (double-buffered by parity), so the
+// gathers are issued before the reduction.  r, w, s, p and x are read and written only
+// by the owning row (in place).  An affine body's four node rows share one block,
+// which applies the body's 12x12 inverse block to form the body's Z records.
+//
+// Batches: the Newton system of a batch is block diagonal, and every scene runs its own
+// CG (own scalars, residual test, breakdown flag, iteration count) in the same
+// launches.  Soft-row blocks never straddle scenes, so a scene's blocks, partials and
+// summation order are those it has alone.  Per-scene scalars [ns][16]: 0/1 gamma,
+// 2/3 alpha (by parity), 4 rr, 5 bb, 6 done, 7 iterations, 8 breakdown, 9 tol^2.
+constexpr int kZs = 16;  // doubles per node record: M^-1 r, M^-1 w, M^-1 s (9 used, one cache line)
+
+struct CgVec {
+  const double *ms, *mb;  // preconditioner: 3x3 soft blocks (9 planes), 12x12 body blocks
+  double *x, *p, *r, *w, *s;
+  const double* zin;      // node records of iteration k
+  double* zout;           // node records of iteration k + 1
+  const double* cin;      // partials (gamma_k, delta_k, rr_k) per block, scene-contiguous
+  double* cout;           // partials of iteration k + 1
+  double* sc;             // per-scene scalars
+  const int4* tab;        // soft blocks: first row, rows, scene, partial slot
+  const int2* prng;       // per scene: partial slots [x, y)
+  const int* f_scene;     // free body -> scene
+  const int* fslot;       // free body -> partial slot
+  int nsoft_blocks;
+  double rtol;
+};
+
+template <class V>
+__device__ inline void mul_acc(const V* m, double u0, double u1, double u2, Acc3<V>& acc) {
+  V x0 = V(u0), x1 = V(u1), x2 = V(u2);
+  acc.x += m[0] * x0 + m[1] * x1 + m[2] * x2;
+  acc.y += m[3] * x0 + m[4] * x1 + m[5] * x2;
+  acc.z += m[6] * x0 + m[7] * x1 + m[8] * x2;
+}
+
+template <class V>
+__device__ inline void cg_entry(const V* __restrict__ v, int stride, int j, int col, const double* __restrict__ Z,
+                                Acc3<V>& A, Acc3<V>& B, Acc3<V>& C) {
+  V m[9];
+  for (int t = 0; t < 9; ++t) m[t] = v[(size_t)t * stride + j];
+  const double* z = Z + (size_t)kZs * col;
+  double zz[9];
+  for (int t = 0; t < 9; ++t) zz[t] = z[t];
+  mul_acc(m, zz[0], zz[1], zz[2], A);
+  mul_acc(m, zz[3], zz[4], zz[5], B);
+  mul_acc(m, zz[6], zz[7], zz[8], C);
+}
+
+// row extents [b0, b1) of the static part and [c0, c1) of the contact part
+template <class V>
+__device__ inline void cg_row(const Mat<V>& M, const double* Z, int4 e, int lane, int nl, Acc3<V>& A, Acc3<V>& B,
+                              Acc3<V>& C) {
+  for (int j = e.x + lane; j < e.y; j += nl) cg_entry(M.bv, M.nnzb, j, M.bc[j], Z, A, B, C);
+  for (int j = e.z + lane; j < e.w; j += nl) cg_entry(M.cv, M.nnzc, j, M.cc[j], Z, A, B, C);
+}
+
+template <class V>
+__device__ inline void acc_xor(Acc3<V>& A, int o, int w) {
+  A.x += __shfl_xor(A.x, o, w);
+  A.y += __shfl_xor(A.y, o, w);
+  A.z += __shfl_xor(A.z, o, w);
+}
+
+__device__ inline V3 m3v(const double* m, V3 v) {
+  return v3(m[0] * v.x + m[1] * v.y + m[2] * v.z, m[3] * v.x + m[4] * v.y + m[5] * v.z,
+            m[6] * v.x + m[7] * v.y + m[8] * v.z);
+}
+
+// Scalars: zero, done for scenes that do not solve (their x stays 0).
+__global__ void cg_scal_init(int ns, const int* __restrict__ active, double* __restrict__ sc) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ns) return;
+  for (int t = 0; t < 16; ++t) sc[16 * k + t] = 0.0;
+  sc[16 * k + 6] = active[k] ? 0.0 : 1.0;
+}
+
+// Set-up: x = 0, r_0 = b, w = s = p = 0 and the records (M^-1 b, 0, 0).  Soft nodes one
+// per thread; then one block per free body (12 threads: M^-1 applied to its 12 DOFs).
+__global__ void cg_setup_kernel(int nsv, int nfree, const double* __restrict__ rhs, CgVec a) {
+  const int nsb = (nsv + kBlock - 1) / kBlock;
+  if ((int)blockIdx.x < nsb) {
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nsv) return;
+    double m[9];
+    for (int t = 0; t < 9; ++t) m[t] = a.ms[(size_t)t * nsv + i];
+    V3 b = ld3(rhs + 3 * i), z0 = v3(0, 0, 0);
+    st3(a.r + 3 * i, b);
+    st3(a.x + 3 * i, z0);
+    st3(a.w + 3 * i, z0);
+    st3(a.s + 3 * i, z0);
+    st3(a.p + 3 * i, z0);
+    double* z = a.zout + (size_t)kZs * i;
+    V3 zr = m3v(m, b);
+    z[0] = zr.x;
+    z[1] = zr.y;
+    z[2] = zr.z;
+    for (int t = 3; t < 9; ++t) z[t] = 0.0;
+  } else {
+    int bi = blockIdx.x - nsb, t = threadIdx.x;
+    if (bi >= nfree || t >= 12) return;
+    size_t o = 3 * (size_t)nsv + 12 * (size_t)bi;
+    a.r[o + t] = rhs[o + t];
+    a.x[o + t] = 0.0;
+    a.w[o + t] = 0.0;
+    a.s[o + t] = 0.0;
+    a.p[o + t] = 0.0;
+    double acc = 0.0;
+    const double* M = a.mb + 144 * (size_t)bi + 12 * t;
+    for (int d = 0; d < 12; ++d) acc += M[d] * rhs[o + d];
+    double* z = a.zout + (size_t)kZs * (nsv + 4 * bi + t / 3);
+    z[t % 3] = acc;
+    z[3 + t % 3] = 0.0;
+    z[6 + t % 3] = 0.0;
+  }
+}
+
+// One iteration (START: the first product w_0 = H M^-1 b with alpha = beta = 0 and no
+// reduction; it leaves p = M^-1 b, which the first iteration scales by beta = 0).
+// Blocks of a finished scene return before gathering.
+template <class V, int G, bool START>
+__global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict__ Mp, int k, CgVec a) {
+  const Mat<V> M = *Mp;
+  __shared__ double sh[kBlock / 64];
+  __shared__ double bc[3];
+  __shared__ double bv[3][12];  // a body's r_{k+1}, w_{k+1}, s_k
+  const bool soft = (int)blockIdx.x < a.nsoft_blocks;
+  int scene, slot, row, lane;
+  bool valid;
+  if (soft) {
+    const int4 t = a.tab[blockIdx.x];
+    scene = t.z;
+    slot = t.w;
+    lane = threadIdx.x % G;
+    valid = (int)threadIdx.x / G < t.y;
+    row = t.x + threadIdx.x / G;
+  } else {  // wavefront m of the block: node row m of the body
+    const int bi = blockIdx.x - a.nsoft_blocks;
+    scene = a.f_scene[bi];
+    slot = a.fslot[bi];
+    lane = threadIdx.x & 63;
+    valid = true;
+    row = M.nsv + 4 * bi + (threadIdx.x >> 6);
+  }
+  double* c = a.sc + 16 * scene;
+  // row extents and the scene's flag are independent loads; the flag is read once per
+  // block (the scene's first block may set it during this launch)
+  __shared__ int skip_s;
+  int4 ext = make_int4(0, 0, 0, 0);
+  if (valid) {
+    ext.x = M.bp[row];
+    ext.y = M.bp[row + 1];
+    if (M.cp) {
+      ext.z = M.cp[row];
+      ext.w = M.cp[row + 1];
+    }
+  }
+  if (threadIdx.x == 0) skip_s = START ? 0 : c[6] != 0.0;
+  __syncthreads();
+  if (skip_s) return;
+  double gprev = 1.0, aprev = 1.0, tol2 = 0.0;
+  double c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  if (!START) {
+    if (k > 0) {
+      gprev = c[(k - 1) & 1];
+      aprev = c[2 + ((k - 1) & 1)];
+      tol2 = c[9];
+    }
+    const int2 pr = a.prng[scene];
+    for (int i = pr.x + threadIdx.x; i < pr.y; i += kBlock) {
+      c1 += a.cin[3 * i];
+      c2 += a.cin[3 * i + 1];
+      c3 += a.cin[3 * i + 2];
+    }
+  }
+  Acc3<V> A{V(0), V(0), V(0)}, B{V(0), V(0), V(0)}, C{V(0), V(0), V(0)};
+  if (soft) {
+    cg_row(M, a.zin, ext, lane, G, A, B, C);
+    for (int o = G / 2; o > 0; o >>= 1) {
+      acc_xor(A, o, G);
+      acc_xor(B, o, G);
+      acc_xor(C, o, G);
+    }
+  } else {
+    cg_row(M, a.zin, ext, lane, 64, A, B, C);
+    for (int o = 32; o > 0; o >>= 1) {
+      acc_xor(A, o, 64);
+      acc_xor(B, o, 64);
+      acc_xor(C, o, 64);
+    }
+  }
+  const bool own = lane == 0 && valid;
+  // the finishing lane's own-node values (independent of the scalars)
+  V3 rv{}, wv{}, sv{}, pv{}, xv{}, zr{}, zw{}, zs{};
+  double mi[9];
+  if (own) {
+    rv = ld3(a.r + 3 * row);
+    wv = ld3(a.w + 3 * row);
+    sv = ld3(a.s + 3 * row);
+    pv = ld3(a.p + 3 * row);
+    xv = ld3(a.x + 3 * row);
+    const double* z = a.zin + (size_t)kZs * row;
+    zr = v3(z[0], z[1], z[2]);
+    zw = v3(z[3], z[4], z[5]);
+    zs = v3(z[6], z[7], z[8]);
+    if (soft)
+      for (int t = 0; t < 9; ++t) mi[t] = a.ms[(size_t)t * M.nsv + row];
+  }
+  double alpha = 0.0, beta = 0.0;
+  if (!START) {
+    c1 = block_sum<kBlock>(c1, sh);
+    c2 = block_sum<kBlock>(c2, sh);
+    c3 = block_sum<kBlock>(c3, sh);
+    if (threadIdx.x == 0) {
+      bc[0] = c1;
+      bc[1] = c2;
+      bc[2] = c3;
+    }
+    __syncthreads();
+    const double gam = bc[0], del = bc[1], rr = bc[2];
+    if (k == 0) tol2 = a.rtol * a.rtol * rr;
+    const bool first = slot == a.prng[scene].x && threadIdx.x == 0;  // the scene's first block
+    if (first) {
+      c[4] = rr;
+      if (k == 0) {
+        c[5] = rr;
+        c[9] = tol2;
+      }
+    }
+    if (rr <= tol2) {
+      if (first) c[6] = 1.0;
+      return;
+    }
+    beta = k > 0 ? gam / gprev : 0.0;
+    const double den = k > 0 ? del - beta * gam / aprev : del;
+    if (!(den > 0.0)) {
+      if (first) {
+        c[8] = 1.0;
+        c[6] = 1.0;
+      }
+      return;
+    }
+    alpha = gam / den;
+    if (first) {
+      c[k & 1] = gam;
+      c[2 + (k & 1)] = alpha;
+      c[7] += 1.0;  // iterations completed after this launch
+    }
+  }
+  double g1 = 0.0, d1 = 0.0, r1 = 0.0;
+  if (own) {
+    const V3 wn = v3(double(A.x), double(A.y), double(A.z)) -
+                  alpha * (v3(double(B.x), double(B.y), double(B.z)) + beta * v3(double(C.x), double(C.y), double(C.z)));
+    const V3 sk = wv + beta * sv;
+    const V3 pk = zr + beta * pv;
+    const V3 rn = rv - alpha * sk;
+    const V3 zn = zr - alpha * (zw + beta * zs);
+    st3(a.s + 3 * row, sk);
+    st3(a.p + 3 * row, pk);
+    st3(a.x + 3 * row, xv + alpha * pk);
+    st3(a.r + 3 * row, rn);
+    st3(a.w + 3 * row, wn);
+    g1 = dot(rn, zn);
+    d1 = dot(zn, wn);
+    r1 = dot(rn, rn);
+    if (soft) {
+      double* z = a.zout + (size_t)kZs * row;
+      V3 q = m3v(mi, rn);
+      z[0] = q.x;
+      z[1] = q.y;
+      z[2] = q.z;
+      q = m3v(mi, wn);
+      z[3] = q.x;
+      z[4] = q.y;
+      z[5] = q.z;
+      q = m3v(mi, sk);
+      z[6] = q.x;
+      z[7] = q.y;
+      z[8] = q.z;
+    } else {
+      int m = threadIdx.x >> 6;
+      bv[0][3 * m] = rn.x;
+      bv[0][3 * m + 1] = rn.y;
+      bv[0][3 * m + 2] = rn.z;
+      bv[1][3 * m] = wn.x;
+      bv[1][3 * m + 1] = wn.y;
+      bv[1][3 * m + 2] = wn.z;
+      bv[2][3 * m] = sk.x;
+      bv[2][3 * m + 1] = sk.y;
+      bv[2][3 * m + 2] = sk.z;
+    }
+  }
+  if (!soft) {  // the body's records: its 12x12 inverse block applied to r, w and s
+    __syncthreads();
+    int t = threadIdx.x;
+    if (t < 36) {
+      int q = t / 12, i = t % 12, bi = blockIdx.x - a.nsoft_blocks;
+      const double* Mb = a.mb + 144 * (size_t)bi + 12 * i;
+      double acc = 0.0;
+      for (int d = 0; d < 12; ++d) acc += Mb[d] * bv[q][d];
+      a.zout[(size_t)kZs * (M.nsv + 4 * bi + i / 3) + 3 * q + i % 3] = acc;
+    }
+  }
+  g1 = block_sum<kBlock>(g1, sh);
+  d1 = block_sum<kBlock>(d1, sh);
+  r1 = block_sum<kBlock>(r1, sh);
+  if (threadIdx.x == 0) {
+    a.cout[3 * slot] = g1;
+    a.cout[3 * slot + 1] = d1;
+    a.cout[3 * slot + 2] = r1;
+  }
+}
+
+// after the last iteration: |r|^2 and convergence of every unfinished scene
+__global__ void pcg_cg_final_kernel(const int2* __restrict__ prng, const double* __restrict__ cin,
+                                    double* __restrict__ sc) {
+  double* c = sc + 16 * blockIdx.x;
+  if (c[6] != 0.0) return;
+  __shared__ double sh[kBlock / 64];
+  const int2 pr = prng[blockIdx.x];
+  double rr = 0.0;
+  for (int i = pr.x + threadIdx.x; i < pr.y; i += kBlock) rr += cin[3 * i + 2];
+  rr = block_sum<kBlock>(rr, sh);
+  if (threadIdx.x == 0) {
+    c[4] = rr;
+    if (rr <= c[9]) c[6] = 1.0;
+  }
+}
+
+// Block layout of the single-reduction kernels for the given lanes per soft row:
+// scene-aligned soft blocks, then one block per free body; partial slots grouped by
+// scene (its soft blocks, then its bodies).
+static void cg_layout(zema_scene* s, int lanes) {
+  std::vector<int> key = {lanes, s->ns, s->nsv, s->nfree};
+  if (s->cg_key == key) return;
+  const int rpb = kBlock / lanes;
+  std::vector<int4> tab;
+  std::vector<int2> prng(s->ns);
+  std::vector<int> fslot(std::max(s->nfree, 1));
+  std::vector<int> slot_of_block;
+  int slot = 0;
+  std::vector<int> soft_slot0(s->ns), nsb(s->ns);
+  for (int k = 0; k < s->ns; ++k) {
+    const SceneRange& R = s->scn[k];
+    prng[k].x = slot;
+    soft_slot0[k] = slot;
+    nsb[k] = (R.v1 - R.v0 + rpb - 1) / rpb;
+    slot += nsb[k] + (R.f1 - R.f0);
+    prng[k].y = slot;
+  }
+  for (int k = 0; k < s->ns; ++k) {
+    const SceneRange& R = s->scn[k];
+    for (int b = 0; b < nsb[k]; ++b) {
+      int r0 = R.v0 + b * rpb;
+      tab.push_back(make_int4(r0, std::min(rpb, R.v1 - r0), k, soft_slot0[k] + b));
+    }
+    for (int f = R.f0; f < R.f1; ++f) fslot[f] = soft_slot0[k] + nsb[k] + (f - R.f0);
+  }
+  s->cg_nsoft_blocks = (int)tab.size();
+  s->cg_nslots = slot;
+  if (tab.empty()) tab.push_back(make_int4(0, 0, 0, 0));
+  s->cg_tab.upload(tab);
+  s->cg_prng.upload(prng);
+  s->cg_fslot.upload(fslot);
+  s->cg_key = key;
+}
+
+// records by parity: launch k reads Z and partials of slot k & 1 and writes slot
+// (k + 1) & 1; k = -1 is the first product (the set-up writes slot 1)
+static CgVec cg_vec(zema_scene* s, int k, double* sol, double rtol) {
+  int e = k & 1, o = (k + 1) & 1;
+  size_t zn = (size_t)kZs * s->nnodes;
+  size_t pn = (size_t)3 * s->cg_nslots;
+  CgVec a;
+  a.ms = s->minv_soft.p;
+  a.mb = s->minv_body.p;
+  a.x = sol;
+  a.p = s->pp0.p;
+  a.r = s->pr.p;
+  a.w = s->pq.p;
+  a.s = s->pz.p;
+  a.zin = s->cg_z.p + zn * e;
+  a.zout = s->cg_z.p + zn * o;
+  a.cin = s->cg_part.p + pn * e;
+  a.cout = s->cg_part.p + pn * o;
+  a.sc = s->scal.p;
+  a.tab = s->cg_tab.p;
+  a.prng = s->cg_prng.p;
+  a.f_scene = s->f_scene.p;
+  a.fslot = s->cg_fslot.p;
+  a.nsoft_blocks = s->cg_nsoft_blocks;
+  a.rtol = rtol;
+  return a;
+}
+
+template <class V, bool START>
+static void cg_launch_v(const void* mat, int lanes, int g, int k, const CgVec& a, hipStream_t st) {
+  const Mat<V>* M = (const Mat<V>*)mat;
+  if (lanes == 8)
+    pcg_cg_kernel<V, 8, START><<<g, kBlock, 0, st>>>(M, k, a);
+  else if (lanes == 32)
+    pcg_cg_kernel<V, 32, START><<<g, kBlock, 0, st>>>(M, k, a);
+  else
+    pcg_cg_kernel<V, 16, START><<<g, kBlock, 0, st>>>(M, k, a);
+}
+
+template <bool START>
+static void cg_launch(zema_scene* s, const void* mat, int lanes, int k, const CgVec& a, hipStream_t st) {
+  int g = s->cg_nsoft_blocks + s->nfree;
+  if (g == 0) return;
+  if (s->mixed)
+    cg_launch_v<float, START>(mat, lanes, g, k, a, st);
+  else
+    cg_launch_v<double, START>(mat, lanes, g, k, a, st);
+}
+
+static bool cg_graph_ready(zema_scene* s, const void* mat, int lanes, double* sol) {
+  std::vector<const void*> key = {mat, s->cg_part.p, s->scal.p, sol, s->pp0.p, s->pr.p, s->pq.p, s->pz.p, s->cg_z.p,
+                                  s->minv_soft.p, s->minv_body.p, s->cg_tab.p, s->cg_prng.p, s->cg_fslot.p,
+                                  s->f_scene.p, (const void*)(intptr_t)s->cg_nslots,
+                                  (const void*)(intptr_t)s->cg_nsoft_blocks, (const void*)(intptr_t)lanes,
+                                  (const void*)(intptr_t)s->mixed, (const void*)(intptr_t)s->nsv,
+                                  (const void*)(intptr_t)s->nfree, (const void*)(intptr_t)s->nnodes,
+                                  (const void*)(intptr_t)s->ns};
+  PcgGraph& G = s->pcg_graph;
+  if (G.exec && G.key == key) return true;
+  if (G.exec) {
+    ZCHK(hipGraphExecDestroy(G.exec));
+    G.exec = nullptr;
+  }
+  if (!s->cap_st) ZCHK(hipStreamCreate(&s->cap_st));
+  if (hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
+  for (int c = 0; c < kChunk; ++c) {
+    int k = 1 + c;
+    cg_launch<false>(s, mat, lanes, k, cg_vec(s, k, sol, 0.0), s->cap_st);
+  }
+  hipGraph_t graph = nullptr;
+  bool ok = (hipStreamEndCapture(s->cap_st, &graph) == hipSuccess) && graph;
+  if (ok) ok = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipGetLastError();
+  if (!ok) {
+    G.exec = nullptr;
+    return false;
+  }
+  G.key = key;
+  return true;
+}
+
+// Single-reduction solve of every scene whose active flag is set (others get x = 0);
+// per-scene iterations, relative residuals and status on the host.
+static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, const double* rhs, double* sol,
+                     double rtol, int max_iter, const int* active_host, int* iters, double* relres, int* status) {
+  const int ns = s->ns, n = s->ndof;
+  s->pr.reserve(n);
+  s->pz.reserve(n);
+  s->pp0.reserve(n);
+  s->pq.reserve(n);
+  cg_layout(s, lanes);
+  s->cg_z.reserve((size_t)2 * kZs * s->nnodes + kZs);
+  s->cg_part.reserve((size_t)6 * s->cg_nslots + 6);
+  s->scal.reserve((size_t)16 * ns);
+  ZCHK(hipMemcpyAsync(s->sc_mask.p, active_host, sizeof(int) * ns, hipMemcpyHostToDevice, s->st));
+  cg_scal_init<<<nblocks(ns), kBlock, 0, s->st>>>(ns, s->sc_mask.p, s->scal.p);
+  {
+    int nsb = (s->nsv + kBlock - 1) / kBlock;
+    if (nsb + s->nfree > 0)
+      cg_setup_kernel<<<nsb + s->nfree, kBlock, 0, s->st>>>(s->nsv, s->nfree, rhs, cg_vec(s, 0, sol, rtol));
+    cg_launch<true>(s, mat, lanes, -1, cg_vec(s, -1, sol, rtol), s->st);
+  }
+  const bool timed = s->kt[KT_SPMV].on;
+  std::vector<double> hs((size_t)16 * ns);
+  int it = 0;
+  for (;;) {
+    bool graph = it > 0 && (it & 1) && max_iter - it >= kChunk && s->use_graph && !timed &&
+                 cg_graph_ready(s, mat, lanes, sol);
+    if (graph) {
+      ZCHK(hipGraphLaunch(s->pcg_graph.exec, s->st));
+      it += kChunk;
+    } else {
+      for (int c = 0; c < (it == 0 ? 1 : kChunk) && it < max_iter; ++c, ++it) {
+        kt_begin(s, KT_SPMV);
+        cg_launch<false>(s, mat, lanes, it, cg_vec(s, it, sol, rtol), s->st);
+        kt_end(s, KT_SPMV, bytes);
+      }
+    }
+    if (it >= max_iter)
+      pcg_cg_final_kernel<<<ns, kBlock, 0, s->st>>>(s->cg_prng.p,
+                                                     s->cg_part.p + (size_t)3 * s->cg_nslots * (it & 1), s->scal.p);
+    ZCHK(hipMemcpyAsync(hs.data(), s->scal.p, sizeof(double) * 16 * ns, hipMemcpyDeviceToHost, s->st));
+    ZCHK(hipStreamSynchronize(s->st));
+    bool all = true;
+    for (int k = 0; k < ns; ++k) all = all && hs[16 * k + 6] != 0.0;
+    if (all || it >= max_iter) break;
+  }
+  int bad;
+  ZCHK(hipMemcpyAsync(&bad, s->counters.p + 4, sizeof(int), hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+  for (int k = 0; k < ns; ++k) {
+    const double* c = hs.data() + 16 * k;
+    iters[k] = (int)c[7];
+    relres[k] = c[5] > 0.0 ? std::sqrt(c[4] / c[5]) : 0.0;
+    status[k] = (bad || c[8] != 0.0 || c[6] == 0.0) ? ZEMA_E_PCG : 0;
+  }
 }
 
 // ------------------------------------------------------------------ launch-shape autotuner
@@ -811,221 +1340,13 @@ void k_autotune(zema_scene* s, int* lanes_out, int* ub_out, double* us_per_iter)
 }
 
 // ------------------------------------------------------------------ batched PCG
-// A batch of scenes has a block-diagonal Newton system; each scene runs its own CG
-// (own alpha, beta, residual test and breakdown flag) in lockstep with the others.
-// Per-scene dot products are summed by one block per scene over the scene's nodes in
-// a fixed order.  Per-scene scalars [ns][16]: 0 rz, 2 alpha, 3 beta, 4 rr, 5 bb,
-// 6 done, 7 iterations, 8 breakdown, 9 rtol^2 bb.
-
-__device__ inline int node_scene(int node, int nsv, const int* v_scene, const int* f_scene) {
-  return node < nsv ? v_scene[node] : f_scene[(node - nsv) >> 2];
-}
-
-// per-node values of r.z, b.b (init) or r.z, r.r (update): unit-major writes
-__global__ void pcgb_init_kernel(int nsv, int nfree, const double* __restrict__ b, const double* __restrict__ ms,
-                                 const double* __restrict__ mb, double* __restrict__ x, double* __restrict__ r,
-                                 double* __restrict__ z, double* __restrict__ p, double* __restrict__ d1,
-                                 double* __restrict__ d2) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nsv + nfree) return;
-  int o = i < nsv ? 3 * i : 3 * nsv + 12 * (i - nsv), n = i < nsv ? 3 : 12;
-  for (int k = 0; k < n; ++k) {
-    x[o + k] = 0.0;
-    r[o + k] = b[o + k];
-    p[o + k] = 0.0;
-  }
-  apply_minv(i, nsv, ms, mb, b, z);
-  double rz = 0.0, bb = 0.0;
-  for (int k = 0; k < n; ++k) {
-    rz += b[o + k] * z[o + k];
-    bb += b[o + k] * b[o + k];
-  }
-  d1[i] = rz;
-  d2[i] = bb;
-}
-
-// sum of a per-unit array over scene k's units (soft vertices, then free bodies)
-__device__ inline double scene_unit_sum(const double* __restrict__ a, const int* __restrict__ rng, int k, int nsv,
-                                        double* sh) {
-  const int* R = rng + 8 * k;
-  int nv = R[1] - R[0], nf = R[7] - R[6];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nv + nf; i += kBlock) acc += i < nv ? a[R[0] + i] : a[nsv + R[6] + (i - nv)];
-  return block_sum<kBlock>(acc, sh);
-}
-
-__global__ void pcgb_init_fin(const double* __restrict__ d1, const double* __restrict__ d2,
-                              const int* __restrict__ rng, const int* __restrict__ active, int nsv,
-                              double* __restrict__ sc, double rtol) {
-  __shared__ double sh[kBlock / 64];
-  int k = blockIdx.x;
-  double rz = scene_unit_sum(d1, rng, k, nsv, sh);
-  double bb = scene_unit_sum(d2, rng, k, nsv, sh);
-  if (threadIdx.x == 0) {
-    double* c = sc + 16 * k;
-    c[0] = rz;
-    c[2] = 0.0;
-    c[3] = 0.0;
-    c[4] = bb;
-    c[5] = bb;
-    c[6] = (bb == 0.0 || !active[k]) ? 1.0 : 0.0;
-    c[7] = 0.0;
-    c[8] = 0.0;
-    c[9] = rtol * rtol * bb;
-  }
-}
-
-// q = H p with p = z + beta_scene p_old formed in the gathers; p stored; per-node
-// p.q.  Rows of finished scenes are skipped.
-template <class V>
-__global__ void pcgb_spmv_kernel(const Mat<V>* __restrict__ Mp, const int* __restrict__ v_scene,
-                                 const int* __restrict__ f_scene,
-                                 const double* __restrict__ sc, const double* __restrict__ z,
-                                 const double* __restrict__ pold, double* __restrict__ pnew, double* __restrict__ q,
-                                 double* __restrict__ pq) {
-  const Mat<V> M = *Mp;
-  __shared__ double red[3 * (kBlock / 64)];
-  int nsoft_blocks = (M.nsv + (kBlock / RG) - 1) / (kBlock / RG);
-  if ((int)blockIdx.x < nsoft_blocks) {
-    int row = blockIdx.x * (kBlock / RG) + threadIdx.x / RG;
-    int lane = threadIdx.x % RG;
-    if (row >= M.nsv) return;
-    const double* c = sc + 16 * v_scene[row];
-    if (c[6] != 0.0) return;  // the whole 16-lane group leaves together
-    double beta = c[3];
-    Acc3<V> acc = row_partial(M, row, lane, RG, z, pold, beta);
-    for (int o = RG / 2; o > 0; o >>= 1) {
-      acc.x += __shfl_xor(acc.x, o, RG);
-      acc.y += __shfl_xor(acc.y, o, RG);
-      acc.z += __shfl_xor(acc.z, o, RG);
-    }
-    if (lane == 0) {
-      V3 qv = v3(double(acc.x), double(acc.y), double(acc.z));
-      st3(q + 3 * row, qv);
-      V3 xv = ld3(z + 3 * row) + beta * ld3(pold + 3 * row);
-      st3(pnew + 3 * row, xv);
-      pq[row] = dot(xv, qv);
-    }
-  } else {
-    int row = M.nsv + (blockIdx.x - nsoft_blocks);
-    const double* c = sc + 16 * f_scene[(row - M.nsv) >> 2];
-    if (c[6] != 0.0) return;  // uniform over the block
-    double beta = c[3];
-    Acc3<V> acc = row_partial(M, row, threadIdx.x, kBlock, z, pold, beta);
-    for (int o = 32; o > 0; o >>= 1) {
-      acc.x += __shfl_xor(acc.x, o, 64);
-      acc.y += __shfl_xor(acc.y, o, 64);
-      acc.z += __shfl_xor(acc.z, o, 64);
-    }
-    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) {
-      red[3 * w] = double(acc.x);
-      red[3 * w + 1] = double(acc.y);
-      red[3 * w + 2] = double(acc.z);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      V3 sq = v3(0, 0, 0);
-      for (int k = 0; k < kBlock / 64; ++k) sq = sq + v3(red[3 * k], red[3 * k + 1], red[3 * k + 2]);
-      st3(q + 3 * row, sq);
-      V3 xv = ld3(z + 3 * row) + beta * ld3(pold + 3 * row);
-      st3(pnew + 3 * row, xv);
-      pq[row] = dot(xv, sq);
-    }
-  }
-}
-
-// per scene: pq over its nodes (soft vertices, then 4 nodes per free body) -> alpha
-__global__ void pcgb_alpha_kernel(const double* __restrict__ pq, const int* __restrict__ rng, int nsv,
-                                  double* __restrict__ sc) {
-  __shared__ double sh[kBlock / 64];
-  int k = blockIdx.x;
-  double* c = sc + 16 * k;
-  if (c[6] != 0.0) return;
-  const int* R = rng + 8 * k;
-  int nv = R[1] - R[0], nn = 4 * (R[7] - R[6]);
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nv + nn; i += kBlock) acc += i < nv ? pq[R[0] + i] : pq[nsv + 4 * R[6] + (i - nv)];
-  double t = block_sum<kBlock>(acc, sh);
-  if (threadIdx.x == 0) {
-    if (!(t > 0.0)) {
-      c[8] = 1.0;
-      c[6] = 1.0;
-    } else {
-      c[2] = c[0] / t;
-    }
-  }
-}
-
-__global__ void pcgb_update_kernel(int nsv, int nfree, const int* __restrict__ v_scene,
-                                   const int* __restrict__ f_scene, const double* __restrict__ sc,
-                                   const double* __restrict__ p, const double* __restrict__ q,
-                                   const double* __restrict__ ms, const double* __restrict__ mb,
-                                   double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
-                                   double* __restrict__ d1, double* __restrict__ d2) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nsv + nfree) return;
-  const double* c = sc + 16 * (i < nsv ? v_scene[i] : f_scene[i - nsv]);
-  if (c[6] != 0.0) return;
-  double alpha = c[2];
-  int o = i < nsv ? 3 * i : 3 * nsv + 12 * (i - nsv), n = i < nsv ? 3 : 12;
-  for (int k = 0; k < n; ++k) {
-    x[o + k] += alpha * p[o + k];
-    r[o + k] -= alpha * q[o + k];
-  }
-  apply_minv(i, nsv, ms, mb, r, z);
-  double rz = 0.0, rr = 0.0;
-  for (int k = 0; k < n; ++k) {
-    rz += r[o + k] * z[o + k];
-    rr += r[o + k] * r[o + k];
-  }
-  d1[i] = rz;
-  d2[i] = rr;
-}
-
-__global__ void pcgb_beta_kernel(const double* __restrict__ d1, const double* __restrict__ d2,
-                                 const int* __restrict__ rng, int nsv, int it, double* __restrict__ sc) {
-  __shared__ double sh[kBlock / 64];
-  int k = blockIdx.x;
-  double* c = sc + 16 * k;
-  if (c[6] != 0.0) return;
-  double rz = scene_unit_sum(d1, rng, k, nsv, sh);
-  double rr = scene_unit_sum(d2, rng, k, nsv, sh);
-  if (threadIdx.x == 0) {
-    c[7] += 1.0;  // iterations completed by this scene
-    c[4] = rr;
-    if (rr <= c[9]) {
-      c[6] = 1.0;
-    } else {
-      c[3] = rz / c[0];
-      c[0] = rz;
-    }
-  }
-}
-
-// Batched solve: scenes with active[k] == 0 get x = 0 and count as converged.
-// iters / relres / status: host arrays [ns].
+// A batch of scenes has a block-diagonal Newton system; every scene runs its own CG in
+// the same single-reduction launches (scenes with active[k] == 0 get x = 0 and count
+// as converged).  iters / relres / status: host arrays [ns].
 void k_pcg_batch(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, const int* active_host,
                  int* iters, double* relres, int* status) {
-  const int ns = s->ns, n = s->ndof, nunits = s->nsv + s->nfree;
-  if (max_iter <= 0) max_iter = std::max(n, 1);
+  if (max_iter <= 0) max_iter = std::max(s->ndof, 1);
   k_build_precond(s);  // block-Jacobi inverses of the current Hessian (allocates them)
-  s->pr.reserve(n);
-  s->pz.reserve(n);
-  s->pp0.reserve(n);
-  s->pp1.reserve(n);
-  s->pq.reserve(n);
-  s->partial.reserve((size_t)2 * nunits + s->nnodes + 8);
-  double* d1 = s->partial.p;
-  double* d2 = s->partial.p + nunits + 1;
-  double* pqn = s->partial.p + 2 * (size_t)nunits + 2;
-  s->scal.reserve((size_t)16 * ns);
-  double* sc = s->scal.p;
-  ZCHK(hipMemcpyAsync(s->sc_mask.p, active_host, sizeof(int) * ns, hipMemcpyHostToDevice, s->st));
-  if (nunits)
-    pcgb_init_kernel<<<nblocks(nunits), kBlock, 0, s->st>>>(s->nsv, s->nfree, rhs, s->minv_soft.p, s->minv_body.p,
-                                                            sol, s->pr.p, s->pz.p, s->pp0.p, d1, d2);
-  pcgb_init_fin<<<ns, kBlock, 0, s->st>>>(d1, d2, s->scn_rng.p, s->sc_mask.p, s->nsv, sc, rtol);
   s->mat_h.resize(sizeof(Mat<double>) + sizeof(Mat<float>));
   Mat<double> M64 = make_mat<double>(s, s->bsr_val.p, s->c_val.p);
   Mat<float> M32 = make_mat<float>(s, s->bsr_val32.p, s->c_val32.p);
@@ -1033,99 +1354,9 @@ void k_pcg_batch(zema_scene* s, const double* rhs, double* sol, double rtol, int
   std::memcpy(s->mat_h.data() + sizeof(M64), &M32, sizeof(M32));
   s->mat_dev.reserve(s->mat_h.size());
   ZCHK(hipMemcpyAsync(s->mat_dev.p, s->mat_h.data(), s->mat_h.size(), hipMemcpyHostToDevice, s->st));
-  const Mat<double>* D64 = (const Mat<double>*)s->mat_dev.p;
-  const Mat<float>* D32 = (const Mat<float>*)(s->mat_dev.p + sizeof(Mat<double>));
-  const int g = spmv_grid(s);
-  const double bytes = (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 32.0 * s->ndof;
-  auto iteration = [&](double* pold, double* pnew, hipStream_t st) {
-    if (g) {
-      if (s->mixed)
-        pcgb_spmv_kernel<float><<<g, kBlock, 0, st>>>(D32, s->v_scene.p, s->f_scene.p, sc, s->pz.p, pold, pnew, s->pq.p,
-                                                      pqn);
-      else
-        pcgb_spmv_kernel<double><<<g, kBlock, 0, st>>>(D64, s->v_scene.p, s->f_scene.p, sc, s->pz.p, pold, pnew,
-                                                       s->pq.p, pqn);
-    }
-  };
-  auto rest = [&](double* pnew, hipStream_t st) {
-    pcgb_alpha_kernel<<<ns, kBlock, 0, st>>>(pqn, s->scn_rng.p, s->nsv, sc);
-    if (nunits)
-      pcgb_update_kernel<<<nblocks(nunits), kBlock, 0, st>>>(s->nsv, s->nfree, s->v_scene.p, s->f_scene.p, sc, pnew,
-                                                             s->pq.p, s->minv_soft.p, s->minv_body.p, sol, s->pr.p,
-                                                             s->pz.p, d1, d2);
-    pcgb_beta_kernel<<<ns, kBlock, 0, st>>>(d1, d2, s->scn_rng.p, s->nsv, 0, sc);
-  };
-  // a chunk of 16 iterations (even: p_old is pp0 at every chunk start), captured once
-  // per set of buffers and replayed
-  const bool timed = s->kt[KT_SPMV].on;
-  bool graph_ok = false;
-  if (s->use_graph && !timed) {
-    std::vector<const void*> key = {D64, sc, sol, pqn, d1, d2, s->pz.p, s->pp0.p, s->pp1.p, s->pq.p, s->pr.p,
-                                    s->minv_soft.p, s->minv_body.p, (const void*)(intptr_t)g,
-                                    (const void*)(intptr_t)s->mixed, (const void*)(intptr_t)ns};
-    PcgGraph& G = s->pcgb_graph;
-    graph_ok = G.exec && G.key == key;
-    if (!graph_ok) {
-      if (G.exec) {
-        ZCHK(hipGraphExecDestroy(G.exec));
-        G.exec = nullptr;
-      }
-      if (!s->cap_st) ZCHK(hipStreamCreate(&s->cap_st));
-      if (hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeRelaxed) == hipSuccess) {
-        double* po = s->pp0.p;
-        double* pn = s->pp1.p;
-        for (int c = 0; c < 16; ++c) {
-          iteration(po, pn, s->cap_st);
-          rest(pn, s->cap_st);
-          std::swap(po, pn);
-        }
-        hipGraph_t graph = nullptr;
-        bool ok = hipStreamEndCapture(s->cap_st, &graph) == hipSuccess && graph;
-        if (ok) ok = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) == hipSuccess;
-        if (graph) (void)hipGraphDestroy(graph);
-        (void)hipGetLastError();
-        if (ok) {
-          G.key = key;
-          graph_ok = true;
-        } else {
-          G.exec = nullptr;
-        }
-      }
-    }
-  }
-  double* pold = s->pp0.p;
-  double* pnew = s->pp1.p;
-  std::vector<double> hs((size_t)16 * ns);
-  const int chunk = 16;
-  int it = 0;
-  for (;;) {
-    if (graph_ok && max_iter - it >= chunk) {
-      ZCHK(hipGraphLaunch(s->pcgb_graph.exec, s->st));
-      it += chunk;
-    } else {
-      for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
-        kt_begin(s, KT_SPMV);
-        iteration(pold, pnew, s->st);
-        kt_end(s, KT_SPMV, bytes);
-        rest(pnew, s->st);
-        std::swap(pold, pnew);
-      }
-    }
-    ZCHK(hipMemcpyAsync(hs.data(), sc, sizeof(double) * 16 * ns, hipMemcpyDeviceToHost, s->st));
-    ZCHK(hipStreamSynchronize(s->st));
-    bool all = true;
-    for (int k = 0; k < ns; ++k) all = all && hs[16 * k + 6] != 0.0;
-    if (all || it >= max_iter) break;
-  }
-  int bad;
-  ZCHK(hipMemcpyAsync(&bad, s->counters.p + 4, sizeof(int), hipMemcpyDeviceToHost, s->st));
-  ZCHK(hipStreamSynchronize(s->st));
-  for (int k = 0; k < ns; ++k) {
-    const double* c = hs.data() + 16 * k;
-    iters[k] = (int)c[7];
-    relres[k] = c[5] > 0.0 ? std::sqrt(c[4] / c[5]) : 0.0;
-    status[k] = (bad || c[8] != 0.0 || c[6] == 0.0) ? ZEMA_E_PCG : 0;
-  }
+  const void* mat = s->mixed ? (const void*)(s->mat_dev.p + sizeof(Mat<double>)) : (const void*)s->mat_dev.p;
+  const double bytes = (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 152.0 * s->ndof;
+  k_pcg_cg(s, mat, s->tune_lanes, bytes, rhs, sol, rtol, max_iter, active_host, iters, relres, status);
 }
 
 }  // namespace zema

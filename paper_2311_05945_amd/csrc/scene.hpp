@@ -173,6 +173,12 @@ struct zema_scene {
   zema::DBuf<double> minv_soft;  // [9][nsv]
   zema::DBuf<double> minv_body;  // [nfree][144]
   zema::DBuf<double> pr, pz, pp0, pp1, pq, px;
+  zema::DBuf<double> cg_z, cg_part;  // single-reduction PCG: node records, partials
+  zema::DBuf<int4> cg_tab;   // its block layout: soft blocks (first row, rows, scene, slot)
+  zema::DBuf<int2> cg_prng;  // per scene: partial slots
+  zema::DBuf<int> cg_fslot;  // free body -> partial slot
+  std::vector<int> cg_key;
+  int cg_nsoft_blocks = 0, cg_nslots = 0;
   zema::DBuf<double> partial;    // block partial sums
   zema::DBuf<double> scal;       // PCG scalars
   zema::DBuf<unsigned int> ticket;
@@ -185,8 +191,9 @@ struct zema_scene {
   // ---- graph-captured PCG chunks
   bool use_graph = true;
   int tune_lanes = 16, tune_ublock = 256;  // launch shapes of the fused PCG kernels
+  int pcg_form = 1;                         // 1: single-reduction iteration, 0: two launches
   hipStream_t cap_st = nullptr;          // capture stream (default priority)
-  zema::PcgGraph pcg_graph, pcgb_graph;   // single-scene and batched chunks
+  zema::PcgGraph pcg_graph;               // captured chunk of PCG iterations
   zema::DBuf<unsigned char> mat_dev;     // matrix descriptors read by the captured kernels
   std::vector<unsigned char> mat_h;
   ~zema_scene();

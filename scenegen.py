@@ -13,6 +13,8 @@ scanned/dataset objects, here replaced by analytic shapes of the stated sizes):
   * gripper(seed, r)  soft ellipsoid voxelised on an r^3 grid squeezed by two driven
                       affine finger boxes (the grasp setting of Sec. "Simulation
                       Procedure"/"Parallel Grasp Generation").
+  * box_on_cube()     a free affine box falling onto a soft cube resting on a fixed
+                      slab (the coupled soft-rigid setting with a free rigid body).
   * batch_scene(i)    uneven grasp scenes: box or ellipsoid at r in 8..32, random
                       material, gripper orientation uniform on SO(3).
 """
@@ -250,6 +252,25 @@ def cube_drop(n_cells: int = 4, steps: int = 20) -> Scene:
     soft = SoftBody(verts, tets, E=1e5, nu=0.4, rho=1000.0)
     slab = AffineBody(slab_v, slab_t, rho=1000.0, stiffness=1e8, mode=MODE_FIXED)
     return Scene("cube_drop", p, [soft], [slab], steps)
+
+
+def box_on_cube(n_cells: int = 4, steps: int = 12) -> Scene:
+    """Free affine 0.06 m box (0.2 rad about y, off-centre) 4 mm above a soft 0.1 m cube
+    that rests 2 mm above a fixed slab: soft-rigid coupling with a free body on both
+    sides of the contact."""
+    L = 0.1
+    H = L / n_cells
+    verts, tets = voxel_mesh(np.ones((n_cells,) * 3, dtype=bool), (-L / 2 + 0.0123, 0.002, -L / 2 - 0.0071), H)
+    slab_v, slab_t = box_surface((0.0, -0.025, 0.0), (0.25, 0.025, 0.25), 1)
+    bv, bt = box_surface((0.0, 0.0, 0.0), (0.03, 0.03, 0.03), 3)
+    c, sn = np.cos(0.2), np.sin(0.2)
+    rot = np.array([[c, 0.0, sn], [0.0, 1.0, 0.0], [-sn, 0.0, c]])
+    bv = bv @ rot.T + np.array([0.0171, 0.002 + L + 0.004 + 0.03, -0.0093])
+    p = Params(dt=0.01, dhat=1e-3, kappa=0.0, mu=0.5, eps_v=1e-3, newton_tol=1e-6)
+    soft = SoftBody(verts, tets, E=1e5, nu=0.4, rho=1000.0)
+    box = AffineBody(bv, bt, rho=500.0, stiffness=1e8, mode=MODE_FREE)
+    slab = AffineBody(slab_v, slab_t, rho=1000.0, stiffness=1e8, mode=MODE_FIXED)
+    return Scene("box_on_cube", p, [soft], [box, slab], steps)
 
 
 FINGER_SIZE = (0.01, 0.08, 0.06)     # closing x approach x width (m)

@@ -339,11 +339,13 @@ def test_intersection_count_matches_exact(zema):
     assert n_exact > 0
 
 
-def test_pcg_graph_replays_match_eager(zema, gripper_full):
+@pytest.mark.parametrize("form", [0, 1])
+def test_pcg_graph_replays_match_eager(zema, gripper_full, form):
     """The graph-captured PCG chunks give bitwise the eager launches' solution, over
-    several replays with eager work (assembly, matvecs) between them."""
+    several replays with eager work (assembly, matvecs) between them (both PCG forms)."""
     sc, R, y, yd = gripper_full
     G = zema.Scene(sc)
+    G.tune(zema.TUNE_PCG_FORM, form)
     G.set_state(y, yd)
     G.ip_assemble(y)
     rhs = np.random.default_rng(5).normal(size=G.n_dof)    # a right-hand side that needs many iterations
@@ -381,3 +383,81 @@ def test_autotune_changes_rounding_only(zema, gripper_full):
     lanes, ub, us = G.autotune()
     log(f"autotune: {lanes} lanes, update block {ub}, {us:.2f} us per PCG iteration")
     assert lanes in (8, 16, 32) and ub in (64, 128, 256) and us > 0
+
+
+# ------------------------------------------------------------------ free affine body
+
+@pytest.fixture(scope="module")
+def box_records():
+    sc = sg.box_on_cube()
+    R = ref.RefScene(sc)
+    R.record(True)
+    R.step(5)
+    return sc, R.records()
+
+
+def _solve_state(zema, sc, state):
+    """A scene object holding the Hessian of a recorded Newton iterate."""
+    G = zema.Scene(sc)
+    G.set_state(state["y_t"], state["ydot_t"], state["kappa_lag"], state["step"])
+    G.set_kappa(state["kappa"])
+    G.ip_assemble(state["y_k"])
+    return G
+
+
+@pytest.mark.parametrize("case", ["gripper", "box"])
+def test_pcg_forms_agree(zema, gripper_full, box_records, case):
+    """The single-reduction form (one launch per iteration) and the two-launch form
+    solve the same system: each meets |b - H x| <= rtol |b| (true residual from the
+    product), iteration counts within 5 of each other, solutions within the solve's
+    tolerance.  The box case has a free affine body (12x12 preconditioner blocks, body
+    rows gathering soft contacts)."""
+    if case == "gripper":
+        sc, R, y, yd = gripper_full
+        G = zema.Scene(sc)
+        G.set_state(y, yd)
+        G.ip_assemble(y)
+    else:
+        sc, recs = box_records
+        G = _solve_state(zema, sc, recs[-1])             # a Newton iterate in contact (step 5)
+    rhs = torch.from_numpy(np.random.default_rng(7).normal(size=G.n_dof)).cuda()
+    out = {}
+    for form in (0, 1):
+        G.tune(zema.TUNE_PCG_FORM, form)
+        for rtol in (1e-4, 1e-7):
+            x, it, rr = G.pcg_solve(rhs, rtol=rtol)
+            true = (G.hessian_matvec(x) - rhs).norm().item() / rhs.norm().item()
+            log(f"{case} form {form} rtol {rtol}: {it} iterations, rel res {rr:.3e}, true {true:.3e}")
+            assert rr <= rtol and true <= 1.05 * rtol
+            out[form, rtol] = (x, it)
+    for rtol in (1e-4, 1e-7):
+        (x0, i0), (x1, i1) = out[0, rtol], out[1, rtol]
+        rel = (x1 - x0).norm().item() / x0.norm().item()
+        log(f"{case} rtol {rtol}: forms differ by {rel:.2e}, iterations {i0} / {i1}")
+        assert abs(i1 - i0) <= 5 and rel <= 10 * rtol
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_free_body_on_soft_cube_follows_oracle(zema, form):
+    """A free affine box falling onto a soft cube: the GPU trajectory follows the
+    oracle step by step (same Newton iteration counts, every DOF within 1e-9) and
+    stays intersection-free, with either PCG form."""
+    sc = sg.box_on_cube()
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    G.tune(zema.TUNE_PCG_FORM, form)
+    tris, edges, vb = R.surface()
+    contact = 0
+    for k in range(sc.n_steps):
+        st = G.step(1)[0]
+        so = R.step(1)[0]
+        y = G.get_state()[0].cpu().numpy()
+        yr = R.get_state()[0]
+        err = np.abs(y - yr).max()
+        contact = max(contact, st["n_pt_active"] + st["n_ee_active"])
+        log(f"form {form} step {k}: newton gpu {st['newton_iters']} oracle {so['newton_iters']}, "
+            f"pcg {st['pcg_iters']}, active {st['n_pt_active']}+{st['n_ee_active']}, max |y - y_oracle| {err:.2e}")
+        assert st["status"] == 0 and st["newton_iters"] == so["newton_iters"]
+        assert err <= 1e-9
+        assert exact.count_intersections(R.surface_positions(y), tris, edges, vb) == 0
+    assert contact > 50

@@ -830,6 +830,8 @@ int time_step(zema_scene* s, zema_step_stats* st) {
     if (kchg) upload_kappa(s);
   }
   s->masked = false;
+  // the last searches of a batch left finished scenes out: candidates of every scene
+  if (ns > 1) static_candidates(s, s->y.p);
   std::vector<double> dfin = min_distance(s, s->y.p);
   for (int k = 0; k < ns; ++k) {
     if (active[k]) st[k].newton_iters = s->P.newton_max;

@@ -104,6 +104,7 @@ struct SceneTab {
   const double* icell;
   const int* scene_bodies;
   const unsigned long long *blo, *bhi;
+  const int* active;  // per-scene flags of a batch whose finished scenes are left out, or null
 };
 
 // order-preserving map of doubles to unsigned integers, and back
@@ -151,6 +152,7 @@ __global__ void body_box_kernel(int nv, const double* __restrict__ lo, const dou
 // other's body: skipping primitives that fail it leaves the candidate set unchanged.
 __device__ inline bool near_other_body(const SceneTab& S, int body, int sc, const double* lo, const double* hi,
                                        int i) {
+  if (S.active && !S.active[sc]) return false;  // a finished scene of the batch: no pairs needed
   const int* R = S.scene_bodies + 4 * sc;
   for (int part = 0; part < 2; ++part)
     for (int b = R[2 * part]; b < R[2 * part + 1]; ++b) {
@@ -411,7 +413,8 @@ static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>
     out.resize(0);
     return 0;
   }
-  const SceneTab S{s->sv_body.p, s->body_scene.p, s->icell_sc.p, s->scene_bodies.p, s->body_blo.p, s->body_bhi.p};
+  const SceneTab S{s->sv_body.p,     s->body_scene.p, s->icell_sc.p, s->scene_bodies.p,
+                   s->body_blo.p,     s->body_bhi.p,   s->act_dev()};
   s->cnt.reserve(E.n + 1);
   s->offs.reserve(E.n + 1);
   s->big_list.reserve(E.n + 1);

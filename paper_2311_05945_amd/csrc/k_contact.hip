@@ -506,42 +506,60 @@ __global__ void runs_kernel(int mode, int n, int base, const int* __restrict__ a
   if (i == n - 1 || key(i + 1, o1, o2) != k) rng[8 * sc + slot + 1] = base + i + 1;
 }
 
-__device__ inline double range_sum(const double* __restrict__ a, int lo, int hi, double* sh) {
+constexpr int kSumParts = 32;  // blocks per scene of the energy sums
+
+// part p of kSumParts equal contiguous parts of [lo, hi)
+__device__ inline double range_part_sum(const double* __restrict__ a, int lo, int hi, int p, double* sh) {
+  const int64_t len = hi - lo;
+  const int a0 = lo + (int)(len * p / kSumParts), a1 = lo + (int)(len * (p + 1) / kSumParts);
   double acc = 0.0;
-  for (int i = lo + threadIdx.x; i < hi; i += kBlock) acc += a[i];
+  for (int i = a0 + threadIdx.x; i < a1; i += kBlock) acc += a[i];
   return block_sum<kBlock>(acc, sh);
 }
 
-// one block per scene: T[0] inertia, 1 elastic, 2 orthogonality, 3 kinematic,
-// 4 barrier, 5 friction, 6 total, 7 minimum distance (+inf without pairs)
+// block (p, k): part p of every energy array range of scene k -> part[k][p][6]
+// (inertia, elastic, orthogonality, kinematic, barrier, friction)
 __global__ void scene_sums_kernel(const int* __restrict__ srng, const int* __restrict__ drng,
                                   const double* __restrict__ e_in, const double* __restrict__ e_tet,
                                   const double* __restrict__ e_body, int nb, const double* __restrict__ e_pair,
-                                  const double* __restrict__ e_fric, const unsigned long long* __restrict__ dmin,
-                                  double* __restrict__ out) {
+                                  const double* __restrict__ e_fric, double* __restrict__ part) {
   __shared__ double sh[kBlock / 64];
-  int k = blockIdx.x;
+  const int p = blockIdx.x, k = blockIdx.y;
   const int* R = srng + 8 * k;
   const int* D = drng + 8 * k;
-  double in_s = range_sum(e_in, R[0], R[1], sh);
-  double in_b = range_sum(e_body, R[4], R[5], sh);
-  double el = range_sum(e_tet, R[2], R[3], sh);
-  double orth = range_sum(e_body + nb, R[4], R[5], sh);
-  double kin = range_sum(e_body + 2 * nb, R[4], R[5], sh);
-  double bar = range_sum(e_pair, D[0], D[1], sh) + range_sum(e_pair, D[2], D[3], sh);
-  double fr = range_sum(e_fric, D[4], D[5], sh) + range_sum(e_fric, D[6], D[7], sh);
+  double in_s = range_part_sum(e_in, R[0], R[1], p, sh);
+  double in_b = range_part_sum(e_body, R[4], R[5], p, sh);
+  double el = range_part_sum(e_tet, R[2], R[3], p, sh);
+  double orth = range_part_sum(e_body + nb, R[4], R[5], p, sh);
+  double kin = range_part_sum(e_body + 2 * nb, R[4], R[5], p, sh);
+  double bar = range_part_sum(e_pair, D[0], D[1], p, sh) + range_part_sum(e_pair, D[2], D[3], p, sh);
+  double fr = range_part_sum(e_fric, D[4], D[5], p, sh) + range_part_sum(e_fric, D[6], D[7], p, sh);
   if (threadIdx.x == 0) {
-    double* T = out + 8 * k;
-    T[0] = in_s + in_b;
-    T[1] = el;
-    T[2] = orth;
-    T[3] = kin;
-    T[4] = bar;
-    T[5] = fr;
-    T[6] = T[0] + T[1] + T[2] + T[3] + T[4] + T[5];
-    unsigned long long u = dmin[k];
-    T[7] = u == ~0ull ? INFINITY : __longlong_as_double((long long)u);
+    double* o = part + 6 * ((size_t)k * kSumParts + p);
+    o[0] = in_s + in_b;
+    o[1] = el;
+    o[2] = orth;
+    o[3] = kin;
+    o[4] = bar;
+    o[5] = fr;
   }
+}
+
+// one wavefront per scene: T[0] inertia, 1 elastic, 2 orthogonality, 3 kinematic,
+// 4 barrier, 5 friction, 6 total, 7 minimum distance (+inf without pairs); the parts
+// are added in order
+__global__ void scene_sums_fin(int ns, const double* __restrict__ part, const unsigned long long* __restrict__ dmin,
+                               double* __restrict__ out) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ns) return;
+  double t[6] = {0, 0, 0, 0, 0, 0};
+  for (int p = 0; p < kSumParts; ++p)
+    for (int q = 0; q < 6; ++q) t[q] += part[6 * ((size_t)k * kSumParts + p) + q];
+  double* T = out + 8 * k;
+  for (int q = 0; q < 6; ++q) T[q] = t[q];
+  T[6] = T[0] + T[1] + T[2] + T[3] + T[4] + T[5];
+  unsigned long long u = dmin[k];
+  T[7] = u == ~0ull ? INFINITY : __longlong_as_double((long long)u);
 }
 
 void k_scene_sums(zema_scene* s, double* out_host) {
@@ -557,8 +575,11 @@ void k_scene_sums(zema_scene* s, double* out_host) {
     runs_kernel<<<nblocks(s->nfric), kBlock, 0, s->st>>>(2, s->nfric, 0, s->f_ids.p, s->edges.p, s->sv_scene.p, ns,
                                                          s->sc_rng.p);
   int nb = (int)s->bodies.size();
-  scene_sums_kernel<<<ns, kBlock, 0, s->st>>>(s->scn_rng.p, s->sc_rng.p, s->e_in.p, s->e_tet.p, s->e_body.p, nb,
-                                              s->e_pair.p, s->e_fric.p, s->sc_dmin.p, s->sc_sum.p);
+  s->sc_part.reserve((size_t)6 * kSumParts * ns);
+  scene_sums_kernel<<<dim3(kSumParts, ns), kBlock, 0, s->st>>>(s->scn_rng.p, s->sc_rng.p, s->e_in.p, s->e_tet.p,
+                                                                s->e_body.p, nb, s->e_pair.p, s->e_fric.p,
+                                                                s->sc_part.p);
+  scene_sums_fin<<<nblocks(ns), kBlock, 0, s->st>>>(ns, s->sc_part.p, s->sc_dmin.p, s->sc_sum.p);
   ZCHK(hipMemcpyAsync(out_host, s->sc_sum.p, sizeof(double) * 8 * ns, hipMemcpyDeviceToHost, s->st));
   ZCHK(hipStreamSynchronize(s->st));
 }

@@ -84,10 +84,11 @@ struct zema_scene {
   zema::DBuf<double> icell_sc, mu_sc, kappa_sc;                // per scene
   zema::DBuf<unsigned long long> sc_u64, sc_dmin, sc_tmin;      // per-scene extrema (bits)
   zema::DBuf<double> sc_alpha, sc_sum;                          // per-scene step sizes, sums [ns][8]
+  zema::DBuf<double> sc_part;                                  // partial per-scene energy sums
   zema::DBuf<int> sc_mask, sc_rng;                              // per-scene flags; pair ranges [ns][8]
   zema::DBuf<unsigned int> sc_cnt;
   zema::DBuf<int> sc_act;                // scenes still iterating (batches), read by assembly
-  bool masked = false;                   // assembly skips converged scenes
+  bool masked = false;                   // assembly and candidate search skip converged scenes
   const int* act_dev() const { return masked ? sc_act.p : nullptr; }
   std::vector<double> kappa_h, scale_h;  // host staging of per-scene uploads
   std::vector<int> mask_h;

@@ -31,7 +31,9 @@ __device__ void wave_psd_project(double* M, double* Vm, double* cs, int* partner
       if (r < c) off += M[r * LD + c] * M[r * LD + c];
     }
     off = wave_sum(off);
-    if (!(off > 1e-34 * fro)) break;
+    // stop at rounding level (off-diagonal norm 1e-15 of the Frobenius norm): sweeps
+    // converge quadratically to there, and rounding keeps them from going lower
+    if (!(off > 1e-30 * fro)) break;
     for (int rd = 0; rd < N - 1; ++rd) {
       if (lane < N / 2) {
         int p = rr_pair<N>(rd, lane), q = rr_pair<N>(rd, N - 1 - lane);

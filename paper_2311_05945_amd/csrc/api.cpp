@@ -912,6 +912,9 @@ zema_scene::~zema_scene() {
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
   if (pcg_graph.exec) (void)hipGraphExecDestroy(pcg_graph.exec);
   if (cap_st) (void)hipStreamDestroy(cap_st);
+  for (hipEvent_t e : poll_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (poll_h) (void)hipHostFree(poll_h);
 }
 
 namespace {

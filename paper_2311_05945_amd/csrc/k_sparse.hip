@@ -849,6 +849,36 @@ __device__ inline V3 m3v(const double* m, V3 v) {
             m[6] * v.x + m[7] * v.y + m[8] * v.z);
 }
 
+// Sums of three per-thread values over the block, each in block_sum's order (wave tree,
+// then waves in order); the results are returned to every thread.
+__device__ inline void block_sum3(double& a, double& b, double& c, double* sh /* 3 * waves + 3 */) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[3 * w] = a;
+    sh[3 * w + 1] = b;
+    sh[3 * w + 2] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0.0, y = 0.0, z = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+      x += sh[3 * i];
+      y += sh[3 * i + 1];
+      z += sh[3 * i + 2];
+    }
+    sh[3 * (kBlock / 64)] = x;
+    sh[3 * (kBlock / 64) + 1] = y;
+    sh[3 * (kBlock / 64) + 2] = z;
+  }
+  __syncthreads();
+  a = sh[3 * (kBlock / 64)];
+  b = sh[3 * (kBlock / 64) + 1];
+  c = sh[3 * (kBlock / 64) + 2];
+}
+
 // Scalars: zero, done for scenes that do not solve (their x stays 0).
 __global__ void cg_scal_init(int ns, const int* __restrict__ active, double* __restrict__ sc) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -903,8 +933,7 @@ __global__ void cg_setup_kernel(int nsv, int nfree, const double* __restrict__ r
 template <class V, int G, bool START>
 __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict__ Mp, int k, CgVec a) {
   const Mat<V> M = *Mp;
-  __shared__ double sh[kBlock / 64];
-  __shared__ double bc[3];
+  __shared__ double sh[3 * (kBlock / 64) + 3];
   __shared__ double bv[3][12];  // a body's r_{k+1}, w_{k+1}, s_k
   const bool soft = (int)blockIdx.x < a.nsoft_blocks;
   int scene, slot, row, lane;
@@ -990,16 +1019,8 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
   }
   double alpha = 0.0, beta = 0.0;
   if (!START) {
-    c1 = block_sum<kBlock>(c1, sh);
-    c2 = block_sum<kBlock>(c2, sh);
-    c3 = block_sum<kBlock>(c3, sh);
-    if (threadIdx.x == 0) {
-      bc[0] = c1;
-      bc[1] = c2;
-      bc[2] = c3;
-    }
-    __syncthreads();
-    const double gam = bc[0], del = bc[1], rr = bc[2];
+    block_sum3(c1, c2, c3, sh);
+    const double gam = c1, del = c2, rr = c3;
     if (k == 0) tol2 = a.rtol * a.rtol * rr;
     const bool first = slot == a.prng[scene].x && threadIdx.x == 0;  // the scene's first block
     if (first) {
@@ -1083,9 +1104,7 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
       a.zout[(size_t)kZs * (M.nsv + 4 * bi + i / 3) + 3 * q + i % 3] = acc;
     }
   }
-  g1 = block_sum<kBlock>(g1, sh);
-  d1 = block_sum<kBlock>(d1, sh);
-  r1 = block_sum<kBlock>(r1, sh);
+  block_sum3(g1, d1, r1, sh);
   if (threadIdx.x == 0) {
     a.cout[3 * slot] = g1;
     a.cout[3 * slot + 1] = d1;
@@ -1250,9 +1269,23 @@ static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, co
       cg_setup_kernel<<<nsb + s->nfree, kBlock, 0, s->st>>>(s->nsv, s->nfree, rhs, cg_vec(s, 0, sol, rtol));
     cg_launch<true>(s, mat, lanes, -1, cg_vec(s, -1, sol, rtol), s->st);
   }
+  // The scalars of every chunk are copied to pinned host memory behind it; the host
+  // checks the previous chunk's copy while the next chunk runs, so the device does not
+  // wait for the host.  Launches after convergence return at once (the scene flags).
   const bool timed = s->kt[KT_SPMV].on;
-  std::vector<double> hs((size_t)16 * ns);
-  int it = 0;
+  if (s->poll_cap < 16 * ns) {
+    if (s->poll_h) ZCHK(hipHostFree(s->poll_h));
+    ZCHK(hipHostMalloc((void**)&s->poll_h, sizeof(double) * 32 * ns, hipHostMallocDefault));
+    s->poll_cap = 16 * ns;
+  }
+  for (hipEvent_t& e : s->poll_ev)
+    if (!e) ZCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  auto all_done = [&](const double* h) {
+    for (int k = 0; k < ns; ++k)
+      if (h[16 * k + 6] == 0.0) return false;
+    return true;
+  };
+  int it = 0, slot = 0, pending = -1;
   for (;;) {
     bool graph = it > 0 && (it & 1) && max_iter - it >= kChunk && s->use_graph && !timed &&
                  cg_graph_ready(s, mat, lanes, sol);
@@ -1269,17 +1302,41 @@ static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, co
     if (it >= max_iter)
       pcg_cg_final_kernel<<<ns, kBlock, 0, s->st>>>(s->cg_prng.p,
                                                      s->cg_part.p + (size_t)3 * s->cg_nslots * (it & 1), s->scal.p);
-    ZCHK(hipMemcpyAsync(hs.data(), s->scal.p, sizeof(double) * 16 * ns, hipMemcpyDeviceToHost, s->st));
-    ZCHK(hipStreamSynchronize(s->st));
-    bool all = true;
-    for (int k = 0; k < ns; ++k) all = all && hs[16 * k + 6] != 0.0;
-    if (all || it >= max_iter) break;
+    double* h = s->poll_h + (size_t)16 * ns * slot;
+    ZCHK(hipMemcpyAsync(h, s->scal.p, sizeof(double) * 16 * ns, hipMemcpyDeviceToHost, s->st));
+    ZCHK(hipEventRecord(s->poll_ev[slot], s->st));
+    if (it >= max_iter || timed) break;  // timed solves poll every chunk
+    if (pending >= 0) {
+      ZCHK(hipEventSynchronize(s->poll_ev[pending]));
+      if (all_done(s->poll_h + (size_t)16 * ns * pending)) break;
+    }
+    pending = slot;
+    slot ^= 1;
+  }
+  ZCHK(hipStreamSynchronize(s->st));
+  const double* hs = s->poll_h + (size_t)16 * ns * slot;  // the last copy
+  if (timed && !all_done(hs) && it < max_iter) {
+    // eager timed solve: continue chunk by chunk until done
+    for (;;) {
+      for (int c = 0; c < kChunk && it < max_iter; ++c, ++it) {
+        kt_begin(s, KT_SPMV);
+        cg_launch<false>(s, mat, lanes, it, cg_vec(s, it, sol, rtol), s->st);
+        kt_end(s, KT_SPMV, bytes);
+      }
+      if (it >= max_iter)
+        pcg_cg_final_kernel<<<ns, kBlock, 0, s->st>>>(s->cg_prng.p,
+                                                       s->cg_part.p + (size_t)3 * s->cg_nslots * (it & 1), s->scal.p);
+      ZCHK(hipMemcpyAsync(s->poll_h, s->scal.p, sizeof(double) * 16 * ns, hipMemcpyDeviceToHost, s->st));
+      ZCHK(hipStreamSynchronize(s->st));
+      hs = s->poll_h;
+      if (all_done(hs) || it >= max_iter) break;
+    }
   }
   int bad;
   ZCHK(hipMemcpyAsync(&bad, s->counters.p + 4, sizeof(int), hipMemcpyDeviceToHost, s->st));
   ZCHK(hipStreamSynchronize(s->st));
   for (int k = 0; k < ns; ++k) {
-    const double* c = hs.data() + 16 * k;
+    const double* c = hs + 16 * k;
     iters[k] = (int)c[7];
     relres[k] = c[5] > 0.0 ? std::sqrt(c[4] / c[5]) : 0.0;
     status[k] = (bad || c[8] != 0.0 || c[6] == 0.0) ? ZEMA_E_PCG : 0;

@@ -180,6 +180,9 @@ struct zema_scene {
   zema::DBuf<int> cg_fslot;  // free body -> partial slot
   std::vector<int> cg_key;
   int cg_nsoft_blocks = 0, cg_nslots = 0;
+  double* poll_h = nullptr;  // pinned host copies of the PCG scalars (two slots)
+  int poll_cap = 0;
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   zema::DBuf<double> partial;    // block partial sums
   zema::DBuf<double> scal;       // PCG scalars
   zema::DBuf<unsigned int> ticket;

@@ -240,22 +240,26 @@ int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect
                             int64_t* n_uncertain, int32_t* uncertain_pairs, int64_t cap);
 
 /* Launch timing for benchmarks: with enable != 0 the library records HIP events on
- * the scene's stream around every launch of one kernel group (0 PCG sparse
- * matrix-vector product, 1 per-tet elastic assembly, 2 contact pair assembly,
- * 3 broad-phase query, 4 CCD) and accumulates their durations; zema_kernel_time
- * returns the total milliseconds, the launch count and the algorithmic bytes of
- * those launches (what the method must move: for the matrix-vector product 76 B per
- * stored 3x3 block plus four DOF vectors, for the elastic assembly 320 B per tet;
- * 0 for the other groups) since the timer was enabled.  Both calls synchronise the
- * stream; bytes may be NULL. */
+ * the scene's stream around launches of one kernel group (0 PCG iteration, 1 per-tet
+ * elastic assembly, 2 contact pair assembly, 3 broad-phase query, 4 CCD) and
+ * accumulates their durations; zema_kernel_time returns the total milliseconds, the
+ * launch count and the algorithmic bytes of those launches (what the method must move:
+ * for a single-reduction PCG iteration 76 B per stored 3x3 block plus 152 B per DOF
+ * (r, w, s, p, x read and written, the 3x3 inverse blocks, the node records read and
+ * written), for the two-launch form's product 76 B per block plus four DOF vectors,
+ * for the elastic assembly 320 B per tet; 0 for the other groups) since the timer was
+ * enabled.  Single-reduction PCG iterations are timed per replayed chunk of 16 (events
+ * around the graph launch; chunks in which the solve converged are not counted), the
+ * other groups per launch.  Both calls synchronise the stream; bytes may be NULL. */
 /* Execution knobs of a single scene.
  * ZEMA_TUNE_PCG_GRAPH: 1 (default) replays PCG iterations in chunks of 16 from a
- *   captured HIP graph, 0 launches every kernel individually (as does any solve while
- *   the matrix-vector timer below is enabled); results are identical.
+ *   captured HIP graph, 0 launches every kernel individually (as does the two-launch
+ *   form while the PCG timer above is enabled); results are identical.
  * ZEMA_TUNE_SPMV_LANES: lanes per soft-vertex row of the PCG matrix-vector product
- *   (8, 16 default, 32); ZEMA_TUNE_UPDATE_BLOCK: threads per block of the PCG vector
- *   update (64, 128, 256 default).  These change the floating-point summation order
- *   (results agree to rounding); a fixed setting is deterministic.
+ *   (4 default, 8, 16, 32; the two-launch form below uses 8 where 4 is set);
+ *   ZEMA_TUNE_UPDATE_BLOCK: threads per block of the two-launch form's vector update
+ *   (64, 128, 256 default).  These change the floating-point summation order (results
+ *   agree to rounding); a fixed setting is deterministic.
  * ZEMA_TUNE_PCG_FORM: 1 (default) runs each PCG iteration as one launch, with the
  *   two inner products of an iteration taken in one reduction (the Chronopoulos-Gear
  *   arrangement of the same iterates); 0 runs the textbook order in two launches per
@@ -264,9 +268,13 @@ int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect
  * Errors: ZEMA_E_ARG for an unknown knob or value. */
 enum { ZEMA_TUNE_PCG_GRAPH = 0, ZEMA_TUNE_SPMV_LANES = 1, ZEMA_TUNE_UPDATE_BLOCK = 2, ZEMA_TUNE_PCG_FORM = 3 };
 int zema_tune(zema_scene* s, int32_t knob, int32_t value);
+/* Current value of a knob (host output).  Errors: ZEMA_E_ARG for an unknown knob. */
+int zema_tune_get(zema_scene* s, int32_t knob, int32_t* value);
 /* Autotuner: times 64 PCG iterations on the last assembled Hessian (after
- * zema_ip_assemble or a step) for every lanes x update-block shape, keeps the
- * fastest and returns it with its time per iteration (microseconds, host outputs).
+ * zema_ip_assemble or a step) for every launch shape of the current PCG form (lanes;
+ * the two-launch form also the update block), keeps the fastest and returns it with
+ * its time per iteration (microseconds, host outputs; update_block is unchanged for
+ * the single-reduction form).
  * Overwrites the scene's internal PCG vectors only.  Errors: ZEMA_E_ARG (no Hessian,
  * batch), ZEMA_E_DEVICE. */
 int zema_autotune(zema_scene* s, int32_t* lanes, int32_t* update_block, double* us_per_iter);

@@ -898,11 +898,11 @@ void kt_fold(zema_scene* s) {
     t.pending.clear();
   }
 }
-void kt_add(zema_scene* s, int g, double ms, double bytes) {
+void kt_add(zema_scene* s, int g, double ms, double bytes, long long launches) {
   KTimer& t = s->kt[g];
   if (!t.on) return;
   t.ms += ms;
-  t.launches++;
+  t.launches += launches;
   t.bytes += bytes;
 }
 }  // namespace zema
@@ -913,6 +913,8 @@ zema_scene::~zema_scene() {
   if (pcg_graph.exec) (void)hipGraphExecDestroy(pcg_graph.exec);
   if (cap_st) (void)hipStreamDestroy(cap_st);
   for (hipEvent_t e : poll_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : chunk_ev)
     if (e) (void)hipEventDestroy(e);
   if (poll_h) (void)hipHostFree(poll_h);
 }
@@ -1332,7 +1334,7 @@ int zema_tune(zema_scene* s, int32_t knob, int32_t value) {
     s->use_graph = value != 0;
     return 0;
   }
-  if (knob == ZEMA_TUNE_SPMV_LANES && (value == 8 || value == 16 || value == 32)) {
+  if (knob == ZEMA_TUNE_SPMV_LANES && (value == 4 || value == 8 || value == 16 || value == 32)) {
     s->tune_lanes = value;
     return 0;
   }
@@ -1345,6 +1347,26 @@ int zema_tune(zema_scene* s, int32_t knob, int32_t value) {
     return 0;
   }
   return ZEMA_E_ARG;
+}
+
+int zema_tune_get(zema_scene* s, int32_t knob, int32_t* value) {
+  if (!s || !value) return ZEMA_E_ARG;
+  switch (knob) {
+    case ZEMA_TUNE_PCG_GRAPH:
+      *value = s->use_graph ? 1 : 0;
+      return 0;
+    case ZEMA_TUNE_SPMV_LANES:
+      *value = s->tune_lanes;
+      return 0;
+    case ZEMA_TUNE_UPDATE_BLOCK:
+      *value = s->tune_ublock;
+      return 0;
+    case ZEMA_TUNE_PCG_FORM:
+      *value = s->pcg_form;
+      return 0;
+    default:
+      return ZEMA_E_ARG;
+  }
 }
 
 int zema_autotune(zema_scene* s, int32_t* lanes, int32_t* update_block, double* us_per_iter) {

@@ -689,7 +689,8 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   s->pq.reserve(n);
   int nunits = s->nsv + s->nfree;
   int nbv = nblocks(nunits);
-  const int lanes = s->tune_lanes, ub = s->tune_ublock;
+  // 4 lanes per soft row exist for the single-reduction kernel only
+  const int lanes = (s->tune_lanes == 4 && s->pcg_form != 1) ? 8 : s->tune_lanes, ub = s->tune_ublock;
   int g = spmv_grid_g(s, lanes);
   int nbu = nblocks(nunits, ub);
   size_t np = (size_t)std::max(nbv, nbu);
@@ -1197,7 +1198,9 @@ static CgVec cg_vec(zema_scene* s, int k, double* sol, double rtol) {
 template <class V, bool START>
 static void cg_launch_v(const void* mat, int lanes, int g, int k, const CgVec& a, hipStream_t st) {
   const Mat<V>* M = (const Mat<V>*)mat;
-  if (lanes == 8)
+  if (lanes == 4)
+    pcg_cg_kernel<V, 4, START><<<g, kBlock, 0, st>>>(M, k, a);
+  else if (lanes == 8)
     pcg_cg_kernel<V, 8, START><<<g, kBlock, 0, st>>>(M, k, a);
   else if (lanes == 32)
     pcg_cg_kernel<V, 32, START><<<g, kBlock, 0, st>>>(M, k, a);
@@ -1272,6 +1275,8 @@ static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, co
   // The scalars of every chunk are copied to pinned host memory behind it; the host
   // checks the previous chunk's copy while the next chunk runs, so the device does not
   // wait for the host.  Launches after convergence return at once (the scene flags).
+  // With the launch timer on, every chunk is checked before the next is launched, and
+  // a replayed chunk whose 16 launches all iterated is timed by events around it.
   const bool timed = s->kt[KT_SPMV].on;
   if (s->poll_cap < 16 * ns) {
     if (s->poll_h) ZCHK(hipHostFree(s->poll_h));
@@ -1280,24 +1285,26 @@ static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, co
   }
   for (hipEvent_t& e : s->poll_ev)
     if (!e) ZCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (hipEvent_t& e : s->chunk_ev)
+    if (!e) ZCHK(hipEventCreate(&e));
   auto all_done = [&](const double* h) {
     for (int k = 0; k < ns; ++k)
       if (h[16 * k + 6] == 0.0) return false;
     return true;
   };
   int it = 0, slot = 0, pending = -1;
+  double iters_before = 0.0;
   for (;;) {
-    bool graph = it > 0 && (it & 1) && max_iter - it >= kChunk && s->use_graph && !timed &&
-                 cg_graph_ready(s, mat, lanes, sol);
+    bool graph = it > 0 && (it & 1) && max_iter - it >= kChunk && s->use_graph && cg_graph_ready(s, mat, lanes, sol);
     if (graph) {
+      if (timed) ZCHK(hipEventRecord(s->chunk_ev[0], s->st));
       ZCHK(hipGraphLaunch(s->pcg_graph.exec, s->st));
+      if (timed) ZCHK(hipEventRecord(s->chunk_ev[1], s->st));
       it += kChunk;
-    } else {
-      for (int c = 0; c < (it == 0 ? 1 : kChunk) && it < max_iter; ++c, ++it) {
-        kt_begin(s, KT_SPMV);
+    } else {  // the first launch alone (replays start at odd iterations), then chunks
+      const int nl = it == 0 ? 1 : kChunk;
+      for (int c = 0; c < nl && it < max_iter; ++c, ++it)
         cg_launch<false>(s, mat, lanes, it, cg_vec(s, it, sol, rtol), s->st);
-        kt_end(s, KT_SPMV, bytes);
-      }
     }
     if (it >= max_iter)
       pcg_cg_final_kernel<<<ns, kBlock, 0, s->st>>>(s->cg_prng.p,
@@ -1305,7 +1312,18 @@ static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, co
     double* h = s->poll_h + (size_t)16 * ns * slot;
     ZCHK(hipMemcpyAsync(h, s->scal.p, sizeof(double) * 16 * ns, hipMemcpyDeviceToHost, s->st));
     ZCHK(hipEventRecord(s->poll_ev[slot], s->st));
-    if (it >= max_iter || timed) break;  // timed solves poll every chunk
+    if (timed) {
+      ZCHK(hipEventSynchronize(s->poll_ev[slot]));
+      if (graph && ns == 1 && h[7] - iters_before == kChunk) {
+        float ms = 0.0f;
+        ZCHK(hipEventElapsedTime(&ms, s->chunk_ev[0], s->chunk_ev[1]));
+        kt_add(s, KT_SPMV, ms, kChunk * bytes, kChunk);
+      }
+      iters_before = h[7];
+      if (all_done(h) || it >= max_iter) break;
+      continue;
+    }
+    if (it >= max_iter) break;
     if (pending >= 0) {
       ZCHK(hipEventSynchronize(s->poll_ev[pending]));
       if (all_done(s->poll_h + (size_t)16 * ns * pending)) break;
@@ -1315,23 +1333,6 @@ static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, co
   }
   ZCHK(hipStreamSynchronize(s->st));
   const double* hs = s->poll_h + (size_t)16 * ns * slot;  // the last copy
-  if (timed && !all_done(hs) && it < max_iter) {
-    // eager timed solve: continue chunk by chunk until done
-    for (;;) {
-      for (int c = 0; c < kChunk && it < max_iter; ++c, ++it) {
-        kt_begin(s, KT_SPMV);
-        cg_launch<false>(s, mat, lanes, it, cg_vec(s, it, sol, rtol), s->st);
-        kt_end(s, KT_SPMV, bytes);
-      }
-      if (it >= max_iter)
-        pcg_cg_final_kernel<<<ns, kBlock, 0, s->st>>>(s->cg_prng.p,
-                                                       s->cg_part.p + (size_t)3 * s->cg_nslots * (it & 1), s->scal.p);
-      ZCHK(hipMemcpyAsync(s->poll_h, s->scal.p, sizeof(double) * 16 * ns, hipMemcpyDeviceToHost, s->st));
-      ZCHK(hipStreamSynchronize(s->st));
-      hs = s->poll_h;
-      if (all_done(hs) || it >= max_iter) break;
-    }
-  }
   int bad;
   ZCHK(hipMemcpyAsync(&bad, s->counters.p + 4, sizeof(int), hipMemcpyDeviceToHost, s->st));
   ZCHK(hipStreamSynchronize(s->st));
@@ -1350,7 +1351,8 @@ __global__ void probe_rhs_kernel(int n, double* __restrict__ b) {
 }
 
 // Times a fixed number of PCG iterations on the last assembled Hessian for every
-// (lanes per soft row, update block) shape and keeps the fastest.  The shapes change
+// launch shape of the current form (lanes per soft row; with the two-launch form also
+// the update block) and keeps the fastest.  The shapes change
 // summation order only; the choice is fixed until the next call.
 void k_autotune(zema_scene* s, int* lanes_out, int* ub_out, double* us_per_iter) {
   const int n = s->ndof, iters = 64;
@@ -1361,16 +1363,19 @@ void k_autotune(zema_scene* s, int* lanes_out, int* ub_out, double* us_per_iter)
   }
   s->ytmp.reserve(n);
   probe_rhs_kernel<<<nblocks(n), kBlock, 0, s->st>>>(n, s->ytmp.p);
-  const int L[3] = {8, 16, 32}, U[3] = {64, 128, 256};
+  // the single-reduction form has no separate update kernel: its shapes are the lanes
+  const bool cg = s->pcg_form == 1;
+  const int L[4] = {4, 8, 16, 32}, U[3] = {64, 128, 256};
+  const int l0 = cg ? 0 : 1, nu = cg ? 1 : 3;
   double best = 1e300;
   int bl = s->tune_lanes, bu = s->tune_ublock;
   hipEvent_t e0, e1;
   ZCHK(hipEventCreate(&e0));
   ZCHK(hipEventCreate(&e1));
-  for (int li = 0; li < 3; ++li)
-    for (int ui = 0; ui < 3; ++ui) {
+  for (int li = l0; li < 4; ++li)
+    for (int ui = 0; ui < nu; ++ui) {
       s->tune_lanes = L[li];
-      s->tune_ublock = U[ui];
+      s->tune_ublock = cg ? bu : U[ui];
       int it;
       double rr;
       float ms = 0.0f;
@@ -1384,7 +1389,7 @@ void k_autotune(zema_scene* s, int* lanes_out, int* ub_out, double* us_per_iter)
       if (ms < best) {
         best = ms;
         bl = L[li];
-        bu = U[ui];
+        bu = s->tune_ublock;
       }
     }
   (void)hipEventDestroy(e0);

@@ -183,6 +183,7 @@ struct zema_scene {
   double* poll_h = nullptr;  // pinned host copies of the PCG scalars (two slots)
   int poll_cap = 0;
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};  // timing of a replayed chunk
   zema::DBuf<double> partial;    // block partial sums
   zema::DBuf<double> scal;       // PCG scalars
   zema::DBuf<unsigned int> ticket;
@@ -194,7 +195,7 @@ struct zema_scene {
   zema::KTimer kt[zema::KT_N];
   // ---- graph-captured PCG chunks
   bool use_graph = true;
-  int tune_lanes = 16, tune_ublock = 256;  // launch shapes of the fused PCG kernels
+  int tune_lanes = 4, tune_ublock = 256;   // launch shapes of the fused PCG kernels (form 0: 4 -> 8)
   int pcg_form = 1;                         // 1: single-reduction iteration, 0: two launches
   hipStream_t cap_st = nullptr;          // capture stream (default priority)
   zema::PcgGraph pcg_graph;               // captured chunk of PCG iterations
@@ -209,7 +210,7 @@ namespace zema {
 void kt_begin(zema_scene* s, int g);
 void kt_end(zema_scene* s, int g, double bytes = 0.0);
 void kt_fold(zema_scene* s);  // after a stream synchronisation: accumulate elapsed times
-void kt_add(zema_scene* s, int g, double ms, double bytes);  // one timed launch measured elsewhere
+void kt_add(zema_scene* s, int g, double ms, double bytes, long long launches = 1);  // launches timed elsewhere
 
 // -------- map / vectors (k_misc.hip)
 void k_map_surface(zema_scene* s, const double* y, double* xs);

@@ -85,6 +85,7 @@ SIGNATURES = [
     ("zema_batch_create", [VP, I32, VP, PI32, VP, PI32, VP, C.POINTER(VP)]),
     ("zema_batch_layout", [VP, C.POINTER(I32), PI64]),
     ("zema_tune", [VP, I32, I32]),
+    ("zema_tune_get", [VP, I32, PI32]),
     ("zema_autotune", [VP, PI32, PI32, PD]),
     ("zema_scene_set_mlp", [VP, VP]),
     ("zema_scene_features", [VP, VP]),
@@ -335,6 +336,16 @@ class Scene:
 
     def tune(self, knob, value):
         self._chk(lib().zema_tune(self.h, int(knob), int(value)))
+
+    def tune_get(self, knob):
+        v = I32()
+        self._chk(lib().zema_tune_get(self.h, int(knob), C.byref(v)))
+        return v.value
+
+    def spmv_lanes(self):
+        """Lanes per soft row of the PCG kernels (after the two-launch form's fallback)."""
+        lanes = self.tune_get(TUNE_SPMV_LANES)
+        return 8 if lanes == 4 and self.tune_get(TUNE_PCG_FORM) == 0 else lanes
 
     def autotune(self):
         """(lanes per soft row, update block, microseconds per PCG iteration) chosen."""

@@ -372,17 +372,19 @@ def test_autotune_changes_rounding_only(zema, gripper_full):
     G.ip_assemble(y)
     rhs = np.random.default_rng(6).normal(size=G.n_dof)
     x0, it0, _ = G.pcg_solve(rhs)
-    for lanes in (8, 16, 32):
-        for ub in (64, 128, 256):
-            G.tune(zema.TUNE_SPMV_LANES, lanes)
-            G.tune(zema.TUNE_UPDATE_BLOCK, ub)
-            x1, it1, _ = G.pcg_solve(rhs)
-            rel = (x1 - x0).abs().max().item() / x0.abs().max().item()
-            log(f"lanes {lanes} block {ub}: {it1} iterations (default {it0}), rel diff {rel:.2e}")
-            assert abs(it1 - it0) <= 5 and rel <= 1e-4, (lanes, ub, it1, it0, rel)
-    lanes, ub, us = G.autotune()
-    log(f"autotune: {lanes} lanes, update block {ub}, {us:.2f} us per PCG iteration")
-    assert lanes in (8, 16, 32) and ub in (64, 128, 256) and us > 0
+    for form in (1, 0):
+        G.tune(zema.TUNE_PCG_FORM, form)
+        for lanes in (4, 8, 16, 32):
+            for ub in ((64, 128, 256) if form == 0 else (256,)):
+                G.tune(zema.TUNE_SPMV_LANES, lanes)
+                G.tune(zema.TUNE_UPDATE_BLOCK, ub)
+                x1, it1, _ = G.pcg_solve(rhs)
+                rel = (x1 - x0).abs().max().item() / x0.abs().max().item()
+                log(f"form {form} lanes {lanes} block {ub}: {it1} iterations (default {it0}), rel diff {rel:.2e}")
+                assert abs(it1 - it0) <= 5 and rel <= 1e-4, (form, lanes, ub, it1, it0, rel)
+        lanes, ub, us = G.autotune()
+        log(f"form {form} autotune: {lanes} lanes, update block {ub}, {us:.2f} us per PCG iteration")
+        assert lanes in ((4, 8, 16, 32) if form == 1 else (8, 16, 32)) and ub in (64, 128, 256) and us > 0
 
 
 # ------------------------------------------------------------------ free affine body

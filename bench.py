@@ -88,8 +88,11 @@ def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5):
     stats = []
     for o in objs:
         done = 0
+        # a batch takes all its steps in one call: each scene starts its next step as
+        # soon as it has converged, so the call's length is set by its slowest scene
+        c = steps if batched else chunk
         while done < steps:
-            n = min(chunk, steps - done)
+            n = min(c, steps - done)
             stats += o.step(n)
             done += n
     torch.cuda.synchronize()

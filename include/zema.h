@@ -265,8 +265,22 @@ int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect
  *   arrangement of the same iterates); 0 runs the textbook order in two launches per
  *   iteration.  In exact arithmetic both produce the same iterates; in floating point
  *   they agree to rounding (the update-block knob applies to form 0 only).
+ * ZEMA_TUNE_BATCH_ASYNC (batches): 1 (default) lets each scene start its next time step
+ *   as soon as its Newton loop has converged, so a call of n steps takes as many global
+ *   iterations as its slowest scene needs over the n steps rather than the sum over
+ *   steps of the slowest scene's; 0 steps all scenes in lockstep.  Each scene's
+ *   arithmetic is the same either way (its trajectory agrees to rounding: the
+ *   candidate set of its initial guess is the swept set of h ydot^t, and per-scene
+ *   sums may group differently).  The learned initial guess always runs in lockstep.
+ *   On failure every scene returns to the start of the step it was in.
  * Errors: ZEMA_E_ARG for an unknown knob or value. */
-enum { ZEMA_TUNE_PCG_GRAPH = 0, ZEMA_TUNE_SPMV_LANES = 1, ZEMA_TUNE_UPDATE_BLOCK = 2, ZEMA_TUNE_PCG_FORM = 3 };
+enum {
+  ZEMA_TUNE_PCG_GRAPH = 0,
+  ZEMA_TUNE_SPMV_LANES = 1,
+  ZEMA_TUNE_UPDATE_BLOCK = 2,
+  ZEMA_TUNE_PCG_FORM = 3,
+  ZEMA_TUNE_BATCH_ASYNC = 4
+};
 int zema_tune(zema_scene* s, int32_t knob, int32_t value);
 /* Current value of a knob (host output).  Errors: ZEMA_E_ARG for an unknown knob. */
 int zema_tune_get(zema_scene* s, int32_t knob, int32_t* value);

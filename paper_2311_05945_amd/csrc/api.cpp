@@ -484,6 +484,7 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   size_t ns3 = (size_t)3 * std::max(s->nsurf, 1);
   s->xs.resize(ns3);
   s->xs1.resize(ns3);
+  s->xs2.resize(ns3);
   s->dxs.resize(ns3);
   size_t nd = std::max(s->ndof, 1);
   for (DBuf<double>* v : {&s->y, &s->ydot, &s->yt, &s->ydt, &s->yhat, &s->ytmp, &s->grad, &s->pdir, &s->yd_prev})
@@ -596,28 +597,36 @@ std::vector<double> min_distance(zema_scene* s, const double* y) {
 }
 
 // predictor, kinematic targets and the lagged friction table at y^t = s->y
-void begin_step(zema_scene* s) {
-  k_predict(s);
+// kinematic targets of the bodies of the scenes flagged in which (every scene when
+// null) for the step each of those scenes is starting
+void body_targets(zema_scene* s, const int* which) {
   int nb = (int)s->bodies.size();
-  std::vector<double> qt((size_t)12 * std::max(nb, 1), 0.0);
-  double tnext = (s->step + 1) * s->P.dt;
-  for (int b = 0; b < nb; ++b) {
-    const Body& B = s->bodies[b];
-    double tt = std::min(tnext, B.tstop);
-    for (int k = 0; k < 12; ++k) qt[12 * b + k] = B.qrest[k];
-    for (int k = 0; k < 3; ++k) qt[12 * b + k] += tt * B.tvel[k];
+  s->qt_h.resize((size_t)12 * std::max(nb, 1), 0.0);
+  s->body_tv_h.resize((size_t)3 * std::max(nb, 1), 0.0);
+  for (int k = 0; k < s->ns; ++k) {
+    if (which && !which[k]) continue;
+    const double tnext = (s->scene_step[k] + 1) * s->P.dt;
+    for (int b = s->scn[k].b0; b < s->scn[k].b1; ++b) {
+      const Body& B = s->bodies[b];
+      double tt = std::min(tnext, B.tstop);
+      for (int q = 0; q < 12; ++q) s->qt_h[12 * b + q] = B.qrest[q];
+      for (int q = 0; q < 3; ++q) s->qt_h[12 * b + q] += tt * B.tvel[q];
+      // translational target velocity of a driven body over this step (learned guess input)
+      for (int q = 0; q < 3; ++q) s->body_tv_h[3 * b + q] = 0.0;
+      if (B.mode != ZEMA_DRIVEN) continue;
+      double span = std::min(tnext, B.tstop) - std::min(tnext - s->P.dt, B.tstop);
+      for (int q = 0; q < 3; ++q) s->body_tv_h[3 * b + q] = B.tvel[q] * span / s->P.dt;
+    }
   }
-  ZCHK(hipMemcpyAsync(s->qtilde.p, qt.data(), sizeof(double) * qt.size(), hipMemcpyHostToDevice, s->st));
-  // translational target velocity of each driven body over this step (learned guess input)
-  s->body_tv_h.assign((size_t)3 * std::max(nb, 1), 0.0);
-  for (int b = 0; b < nb; ++b) {
-    const Body& B = s->bodies[b];
-    if (B.mode != ZEMA_DRIVEN) continue;
-    double span = std::min(tnext, B.tstop) - std::min(tnext - s->P.dt, B.tstop);
-    for (int k = 0; k < 3; ++k) s->body_tv_h[3 * b + k] = B.tvel[k] * span / s->P.dt;
-  }
+  ZCHK(hipMemcpyAsync(s->qtilde.p, s->qt_h.data(), sizeof(double) * s->qt_h.size(), hipMemcpyHostToDevice, s->st));
   ZCHK(hipMemcpyAsync(s->body_tv.p, s->body_tv_h.data(), sizeof(double) * s->body_tv_h.size(),
                       hipMemcpyHostToDevice, s->st));
+}
+
+void begin_step(zema_scene* s) {
+  k_predict(s);
+  s->scene_step.assign(s->ns, s->step);
+  body_targets(s, nullptr);
   for (SceneRange& R : s->scn) R.kappa_lag = R.kappa;
   upload_kappa(s);
   static_candidates(s, s->y.p);
@@ -846,6 +855,7 @@ int time_step(zema_scene* s, zema_step_stats* st) {
   ZCHK(hipMemcpyAsync(s->yd_prev.p, s->ydt.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s->st));
   k_velocity(s, 1.0 / h);
   s->step += 1;
+  s->scene_step.assign(ns, s->step);
   ZCHK(hipStreamSynchronize(s->st));
   kt_fold(s);
   double tt = now_ms() - t0;
@@ -861,6 +871,255 @@ int time_step(zema_scene* s, zema_step_stats* st) {
   return 0;
 }
 
+
+// n_steps time steps of every scene of a batch, each scene starting its next step as
+// soon as its Newton loop has converged (scenes are independent; only the launches
+// are shared).  Every global iteration: one Newton iteration (assembly, PCG,
+// convergence) of the scenes inside a step; the start of a step (predictor, targets,
+// lagged friction, explicit initial guess) of the scenes between steps; one shared
+// swept candidate search (the Newton direction, or h ydot^t for a starting scene),
+// one CCD pass and one backtracking loop (energy and inversion for an iterate,
+// inversion for an initial guess).  Per scene the arithmetic is that of time_step;
+// the candidate set of an initial guess is the swept set of h ydot^t (a superset of
+// the pairs within d-hat at y^t and at the guess).  stats: [n_steps][ns].
+int time_steps_async(zema_scene* s, int n_steps, zema_step_stats* stats) {
+  const double h = s->P.dt;
+  const int n = s->ndof, ns = s->ns;
+  for (int k = 0; k < n_steps * ns; ++k) {
+    std::memset(&stats[k], 0, sizeof(stats[k]));
+    stats[k].alpha_ccd_min = 1.0;
+  }
+  if (s->scene_step.size() != (size_t)ns) s->scene_step.assign(ns, s->step);
+  enum { BEGIN = 0, NEWTON = 1, FINISHED = 2 };
+  std::vector<int> phase(ns, n_steps > 0 ? BEGIN : FINISHED), done(ns, 0), it(ns, 0);
+  std::vector<int> inN(ns), inB(ns), live(ns), fin(ns), pit(ns), pst(ns), inv(ns), acc(ns);
+  std::vector<double> alpha(ns), disp(ns), rr(ns), dprev(ns, INFINITY), scale(ns), t0s(ns, now_ms());
+  std::vector<double> T((size_t)8 * ns), T1((size_t)8 * ns), E0((size_t)8 * ns), T2((size_t)8 * ns);
+  std::vector<double> alpha2(ns, 0.0);
+  std::vector<int> use2(ns, 0);
+  const bool learned = s->P.warm_start == ZEMA_WARM_LEARNED;
+  double tw = 0;
+  auto cur = [&](int k) -> zema_step_stats& { return stats[(size_t)done[k] * ns + k]; };
+  const bool auto_k = s->P.kappa <= 0.0;
+  const double tol = s->P.newton_tol * h;
+  double ta = 0, tp = 0, tb = 0, tc = 0, tl = 0, q;
+  // phase times of a global iteration go to the step each scene was in
+  auto charge = [&](int k, int step, double dt_a, double dt_p, double dt_b, double dt_c, double dt_l) {
+    zema_step_stats& st = stats[(size_t)step * ns + k];
+    st.ms_assemble += dt_a;
+    st.ms_pcg += dt_p;
+    st.ms_broad += dt_b;
+    st.ms_ccd += dt_c;
+    st.ms_linesearch += dt_l;
+  };
+  std::vector<int> wasN(ns);
+  for (;;) {
+    int nN = 0, nB = 0;
+    for (int k = 0; k < ns; ++k) {
+      inN[k] = phase[k] == NEWTON;
+      inB[k] = phase[k] == BEGIN;
+      nN += inN[k];
+      nB += inB[k];
+    }
+    if (nN + nB == 0) break;
+    ta = tp = tb = tc = tl = tw = 0;
+    std::fill(fin.begin(), fin.end(), 0);
+    wasN = inN;
+    // ---- one Newton iteration of the scenes inside a step
+    if (nN) {
+      ZCHK(hipMemcpyAsync(s->sc_act.p, inN.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s->st));
+      s->masked = true;
+      q = now_ms();
+      bool ok = assemble(s, s->y.p, s->grad.p, true, 0x3fu, T.data());
+      ta += now_ms() - q;
+      if (!ok) throw Error(ZEMA_E_INTERSECT, "infeasible Newton iterate");
+      for (int k = 0; k < ns; ++k)
+        if (inN[k]) {
+          cur(k).energy = T[8 * k + 6];
+          cur(k).newton_iters = it[k];
+        }
+      k_scale(s, n, -1.0, s->grad.p, s->ytmp.p);
+      q = now_ms();
+      k_pcg_batch(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, s->P.pcg_max, inN.data(), pit.data(), rr.data(),
+                  pst.data());
+      tp += now_ms() - q;
+      for (int k = 0; k < ns; ++k)
+        if (inN[k]) {
+          cur(k).pcg_iters += pit[k];
+          if (pst[k]) throw Error(pst[k], "PCG failed");
+        }
+      k_max_disp(s, s->pdir.p, disp.data());
+      for (int k = 0; k < ns; ++k)
+        if (inN[k] && disp[k] <= tol) {
+          fin[k] = 1;
+          inN[k] = 0;
+          --nN;
+        }
+    }
+    // ---- scenes that converged end their step: velocity, statistics
+    bool any_fin = false;
+    for (int k = 0; k < ns; ++k) any_fin = any_fin || fin[k];
+    if (any_fin) {
+      k_select_scene(s, fin.data(), s->ydt.p, s->yd_prev.p, s->yd_prev.p);
+      k_velocity_to(s, 1.0 / h, s->ytmp.p);
+      k_select_scene(s, fin.data(), s->ytmp.p, s->ydot.p, s->ydot.p);
+      for (int k = 0; k < ns; ++k) {
+        if (!fin[k]) continue;
+        zema_step_stats& st = cur(k);
+        st.kappa = s->scn[k].kappa;
+        st.d_min = T[8 * k + 7];
+        st.ms_total = now_ms() - t0s[k];
+        s->scene_step[k] += 1;
+        done[k] += 1;
+        phase[k] = done[k] < n_steps ? BEGIN : FINISHED;
+        if (phase[k] == BEGIN) {
+          inB[k] = 1;
+          ++nB;
+        }
+      }
+    }
+    // ---- the start of a step: y^t, ydot^t, predictor, targets, kappa_lag
+    if (nB) {
+      for (int k = 0; k < ns; ++k)
+        if (inB[k]) t0s[k] = now_ms();
+      k_select_scene(s, inB.data(), s->y.p, s->yt.p, s->yt.p);
+      k_select_scene(s, inB.data(), s->ydot.p, s->ydt.p, s->ydt.p);
+      k_predict_to(s, s->ytmp.p);
+      k_select_scene(s, inB.data(), s->ytmp.p, s->yhat.p, s->yhat.p);
+      body_targets(s, inB.data());
+      for (int k = 0; k < ns; ++k)
+        if (inB[k]) s->scn[k].kappa_lag = s->scn[k].kappa;
+      // explicit initial-guess direction h ydot^t
+      k_scale(s, n, h, s->ydot.p, s->ytmp.p);
+      k_select_scene(s, inB.data(), s->ytmp.p, s->pdir.p, s->pdir.p);
+      if (learned) {  // the network's direction of the starting scenes (its own search)
+        q = now_ms();
+        ZCHK(hipMemcpyAsync(s->sc_act.p, inB.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s->st));
+        s->masked = true;
+        s->feat.reserve((size_t)16 * s->nsv + 16);
+        s->mlp_out.reserve((size_t)3 * s->nsv + 3);
+        s->ywarm.reserve(n);
+        s->pdir2.reserve(n);
+        k_features(s, s->feat.p);
+        mlp_forward(s->mlp, s->st, s->feat.p, s->nsv, s->mlp_out.p);
+        k_warm_dir(s, s->mlp_out.p, s->pdir2.p);
+        for (int k = 0; k < ns; ++k) scale[k] = inB[k] ? 1.0 : 0.0;
+        k_scale_scene(s, scale.data(), s->pdir2.p);
+        tw += now_ms() - q;
+      }
+    }
+    const bool two = learned && nB > 0;  // a second proposal of the starting scenes
+    // directions of scenes that take no move are zero
+    for (int k = 0; k < ns; ++k) {
+      live[k] = inN[k] || inB[k];
+      scale[k] = live[k] ? 1.0 : 0.0;
+    }
+    k_scale_scene(s, scale.data(), s->pdir.p);
+    // ---- shared swept search over the moving scenes, friction of the starting ones
+    ZCHK(hipMemcpyAsync(s->sc_act.p, live.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s->st));
+    s->masked = true;
+    q = now_ms();
+    if (two) {  // boxes over y, y + p and y + p2: both proposals of a starting scene
+      k_axpy(s, n, 1.0, s->pdir.p, s->y.p, s->ytmp.p);
+      k_map_surface(s, s->y.p, s->xs.p);
+      k_map_surface(s, s->ytmp.p, s->xs1.p);
+      k_axpy(s, n, 1.0, s->pdir2.p, s->y.p, s->ytmp.p);
+      k_map_surface(s, s->ytmp.p, s->xs2.p);
+      k_candidates(s, s->xs.p, s->xs1.p, s->P.dhat, s->xs2.p);
+    } else {
+      swept_candidates(s, s->y.p, s->pdir.p);
+    }
+    if (nB) k_friction_rebuild(s, inB.data());
+    tb += now_ms() - q;
+    q = now_ms();
+    int rc = k_ccd(s, s->y.p, s->pdir.p, alpha.data());
+    if (!rc && two) rc = k_ccd(s, s->y.p, s->pdir2.p, alpha2.data());
+    tc += now_ms() - q;
+    if (rc) throw Error(rc, "intersecting pair at CCD start");
+    for (int k = 0; k < ns; ++k) {
+      if (!live[k]) alpha[k] = 0.0;
+      else if (inN[k]) cur(k).alpha_ccd_min = std::min(cur(k).alpha_ccd_min, alpha[k]);
+    }
+    // ---- backtracking: an iterate needs no energy increase (and no inverted tet, where
+    // the energy is infinite), an initial guess no inverted tet
+    q = now_ms();
+    if (two) {  // the network's proposal: halved while a tet inverts, then its energy
+      for (int k = 0; k < ns; ++k)
+        if (!inB[k]) alpha2[k] = 0.0;
+      for (;;) {
+        k_axpy_scene(s, alpha2.data(), s->pdir2.p, s->y.p, s->ywarm.p);
+        if (!k_inverted(s, s->ywarm.p, inv.data())) break;
+        for (int k = 0; k < ns; ++k)
+          if (inB[k] && inv[k]) alpha2[k] = alpha2[k] * 0.5 < 1e-10 ? 0.0 : alpha2[k] * 0.5;
+      }
+      eval_energy(s, s->ywarm.p, T2.data());
+    }
+    if (nN) eval_energy(s, s->y.p, E0.data());
+    for (int k = 0; k < ns; ++k) acc[k] = !live[k];
+    std::fill(use2.begin(), use2.end(), 0);
+    for (;;) {
+      k_axpy_scene(s, alpha.data(), s->pdir.p, s->y.p, s->ytmp.p);
+      eval_energy(s, s->ytmp.p, T1.data());
+      if (nB) k_inverted(s, s->ytmp.p, inv.data());
+      bool all = true;
+      for (int k = 0; k < ns; ++k) {
+        if (acc[k]) continue;
+        if (inN[k]) {
+          if (std::isfinite(T1[8 * k + 6]) && T1[8 * k + 6] <= E0[8 * k + 6]) {
+            acc[k] = 1;
+            double dm = T1[8 * k + 7];
+            if (auto_k && dm < 1e-3 * s->P.dhat && dm < dprev[k]) s->scn[k].kappa *= 2.0;
+            dprev[k] = dm;
+            continue;
+          }
+          all = false;
+          alpha[k] *= 0.5;
+          cur(k).ls_backtracks++;
+          if (alpha[k] < 1e-10) throw Error(ZEMA_E_LINESEARCH, "line search failed");
+        } else {  // initial guess of a starting scene
+          if (!inv[k]) {
+            acc[k] = 1;
+            dprev[k] = T1[8 * k + 7];
+            // the network's proposal is kept when its energy is not higher
+            if (two && std::isfinite(T2[8 * k + 6]) && T2[8 * k + 6] <= T1[8 * k + 6]) {
+              use2[k] = 1;
+              dprev[k] = T2[8 * k + 7];
+            }
+            cur(k).warm_learned = use2[k];
+            continue;
+          }
+          all = false;
+          alpha[k] = alpha[k] * 0.5 < 1e-10 ? 0.0 : alpha[k] * 0.5;
+        }
+      }
+      if (all) break;
+    }
+    tl += now_ms() - q;
+    if (two) k_select_scene(s, use2.data(), s->ywarm.p, s->ytmp.p, s->ytmp.p);
+    std::swap(s->y.p, s->ytmp.p);
+    upload_kappa(s);
+    for (int k = 0; k < ns; ++k) {
+      if (inN[k]) {
+        if (++it[k] >= s->P.newton_max) {
+          cur(k).status = ZEMA_E_NEWTON;
+          throw Error(ZEMA_E_NEWTON, "Newton did not converge");
+        }
+      }
+      if (inB[k]) {
+        phase[k] = NEWTON;
+        it[k] = 0;
+      }
+      if (fin[k]) charge(k, done[k] - 1, ta, tp, 0.0, 0.0, 0.0);  // the step it finished
+      if (live[k]) charge(k, done[k], wasN[k] && !fin[k] ? ta : 0.0, wasN[k] && !fin[k] ? tp : 0.0, tb, tc, tl);
+      if (inB[k]) stats[(size_t)done[k] * ns + k].ms_warm += tw;
+    }
+  }
+  s->masked = false;
+  s->step += n_steps;
+  ZCHK(hipStreamSynchronize(s->st));
+  kt_fold(s);
+  return 0;
+}
 }  // namespace
 
 // ------------------------------------------------------------------ launch timing
@@ -1158,6 +1417,26 @@ int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
     s->err = "learned initial guess selected but no network attached";
     return ZEMA_E_ARG;
   }
+  if (s->ns > 1 && s->batch_async && n_steps > 0) {
+    // scenes of a batch start their next step as they converge; a failure returns every
+    // scene to the start of the step it was in (y^t, ydot^t are kept per scene)
+    int rc = guard(s, [&]() {
+      ZCHK(hipMemcpyAsync(s->yt.p, s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+      ZCHK(hipMemcpyAsync(s->ydt.p, s->ydot.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+      return time_steps_async(s, n_steps, stats);
+    });
+    s->masked = false;
+    s->stepped = rc == 0;
+    if (rc) {
+      for (int k = 0; k < n_steps * s->ns; ++k)
+        if (stats[k].ms_total == 0.0) stats[k].status = rc;  // steps that did not complete
+      (void)hipMemcpyAsync(s->y.p, s->yt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st);
+      (void)hipMemcpyAsync(s->ydot.p, s->ydt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st);
+      (void)hipStreamSynchronize(s->st);
+      s->scene_step.assign(s->ns, s->step);
+    }
+    return rc;
+  }
   for (int k = 0; k < n_steps; ++k) {
     // y^t / ydot^t are saved first so a failed step can restore them
     int rc = guard(s, [&]() {
@@ -1346,6 +1625,10 @@ int zema_tune(zema_scene* s, int32_t knob, int32_t value) {
     s->pcg_form = value;
     return 0;
   }
+  if (knob == ZEMA_TUNE_BATCH_ASYNC && (value == 0 || value == 1)) {
+    s->batch_async = value != 0;
+    return 0;
+  }
   return ZEMA_E_ARG;
 }
 
@@ -1363,6 +1646,9 @@ int zema_tune_get(zema_scene* s, int32_t knob, int32_t* value) {
       return 0;
     case ZEMA_TUNE_PCG_FORM:
       *value = s->pcg_form;
+      return 0;
+    case ZEMA_TUNE_BATCH_ASYNC:
+      *value = s->batch_async ? 1 : 0;
       return 0;
     default:
       return ZEMA_E_ARG;

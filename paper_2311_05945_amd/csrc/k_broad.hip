@@ -32,10 +32,12 @@ __device__ inline unsigned long long pack_cell(int ix, int iy, int iz) {
          (unsigned long long)(iz + kCellBias);
 }
 
-// boxes of vertices [0, nv), triangles [nv, nv+nt), edges [nv+nt, nv+nt+ne)
+// boxes of vertices [0, nv), triangles [nv, nv+nt), edges [nv+nt, nv+nt+ne) over the
+// positions xs0, xs1 and, when given, xs2
 __global__ void boxes_kernel(int nv, int nt, int ne, const int* __restrict__ tris, const int* __restrict__ edges,
-                             const double* __restrict__ xs0, const double* __restrict__ xs1, double r,
-                             double* __restrict__ lo, double* __restrict__ hi) {
+                             const double* __restrict__ xs0, const double* __restrict__ xs1,
+                             const double* __restrict__ xs2, double r, double* __restrict__ lo,
+                             double* __restrict__ hi) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv + nt + ne) return;
   int v[3], n;
@@ -60,6 +62,11 @@ __global__ void boxes_kernel(int nv, int nt, int ne, const int* __restrict__ tri
       double p = xs0[3 * v[a] + k], q = xs1[3 * v[a] + k];
       l = fmin(l, fmin(p, q));
       h = fmax(h, fmax(p, q));
+      if (xs2) {
+        double w = xs2[3 * v[a] + k];
+        l = fmin(l, w);
+        h = fmax(h, w);
+      }
     }
     lo[3 * i + k] = __dsub_rn(l, r);
     hi[3 * i + k] = __dadd_rn(h, r);
@@ -502,20 +509,20 @@ int64_t k_edge_tri_pairs(zema_scene* s, const double* xs, DBuf<int>& out) {
   s->bb_hi.reserve(3 * (size_t)np);
   if (s->pair_keys.cap < 4096) s->pair_keys.reserve(1 << 16);
   if (np)
-    boxes_kernel<<<nblocks(np), kBlock, 0, s->st>>>(nv, nt, ne, s->tris.p, s->edges.p, xs, xs, 0.0, s->bb_lo.p,
+    boxes_kernel<<<nblocks(np), kBlock, 0, s->st>>>(nv, nt, ne, s->tris.p, s->edges.p, xs, xs, nullptr, 0.0, s->bb_lo.p,
                                                     s->bb_hi.p);
   body_boxes(s);
   return search(s, PrimSet{nv + nt, ne}, PrimSet{nv, nt}, PairRule{2, 1, 0}, out);
 }
 
-void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r) {
+void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r, const double* xs2) {
   int nv = s->nsurf, nt = s->ntri, ne = s->nedge;
   int np = nv + nt + ne;
   s->bb_lo.reserve(3 * (size_t)np);
   s->bb_hi.reserve(3 * (size_t)np);
   if (s->pair_keys.cap < 4096) s->pair_keys.reserve(1 << 16);
   if (np)
-    boxes_kernel<<<nblocks(np), kBlock, 0, s->st>>>(nv, nt, ne, s->tris.p, s->edges.p, xs0, xs1 ? xs1 : xs0, r,
+    boxes_kernel<<<nblocks(np), kBlock, 0, s->st>>>(nv, nt, ne, s->tris.p, s->edges.p, xs0, xs1 ? xs1 : xs0, xs2, r,
                                                     s->bb_lo.p, s->bb_hi.p);
   body_boxes(s);
   s->npt = search(s, PrimSet{0, nv}, PrimSet{nv, nt}, PairRule{0, 1, 0}, s->pt);

@@ -98,13 +98,19 @@ __global__ void friction_energy_kernel(int nf, const int* __restrict__ fids, con
 }
 
 // ------------------------------------------------------------------ lagged friction table
+// only : per-scene flags of the scenes whose entries are built, or null for all
 __global__ void friction_flag_kernel(int npt, int nee, const int* __restrict__ pt, const int* __restrict__ ee,
                                      const int* __restrict__ tris, const int* __restrict__ edges,
-                                     const double* __restrict__ xs, double dhat, int* __restrict__ flag) {
+                                     const double* __restrict__ xs, double dhat, const int* __restrict__ only,
+                                     const int* __restrict__ sv_scene, int* __restrict__ flag) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npt + nee) return;
   int kind, sv[4], ea, eb;
   pair_slots(k, npt, pt, ee, tris, edges, kind, sv, ea, eb);
+  if (only && !only[sv_scene[sv[0]]]) {
+    flag[k] = 0;
+    return;
+  }
   V3 x[4];
   for (int a = 0; a < 4; ++a) x[a] = ld3(xs + 3 * sv[a]);
   double d = pair_dist(kind, x, nullptr);
@@ -616,7 +622,8 @@ void k_friction_build(zema_scene* s) {
   s->cnt.reserve(nc + 1);
   s->offs.reserve(nc + 1);
   friction_flag_kernel<<<nblocks(nc), kBlock, 0, s->st>>>((int)s->npt, (int)s->nee, s->pt.p, s->ee.p, s->tris.p,
-                                                          s->edges.p, s->xs.p, s->P.dhat, s->cnt.p);
+                                                          s->edges.p, s->xs.p, s->P.dhat, nullptr, s->sv_scene.p,
+                                                          s->cnt.p);
   int64_t nf = k_exclusive_scan(s, s->cnt.p, s->offs.p, nc);
   s->nfric = (int)nf;
   s->f_ids.reserve(5 * nf + 5);
@@ -627,6 +634,74 @@ void k_friction_build(zema_scene* s) {
                                                             s->edges.p, s->elen2.p, s->xs.p, s->kappa_sc.p,
                                                             s->sv_scene.p, s->P.dhat, s->cnt.p, s->offs.p, s->f_ids.p,
                                                             s->f_vals.p, s->f_xt.p);
+}
+
+// entries of the scenes that keep their table: flag = 1
+__global__ void friction_keep_kernel(int nf, const int* __restrict__ fids, const int* __restrict__ sv_scene,
+                                     const int* __restrict__ rebuild, int* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nf) flag[i] = rebuild[sv_scene[fids[5 * i + 1]]] ? 0 : 1;
+}
+
+__global__ void friction_move_kernel(int nf, const int* __restrict__ flag, const int* __restrict__ offs,
+                                     const int* __restrict__ fids, const double* __restrict__ fvals,
+                                     const double* __restrict__ fxt, int* __restrict__ oids, double* __restrict__ ovals,
+                                     double* __restrict__ oxt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf || !flag[i]) return;
+  int o = offs[i];
+  for (int q = 0; q < 5; ++q) oids[5 * (size_t)o + q] = fids[5 * (size_t)i + q];
+  for (int q = 0; q < 8; ++q) ovals[8 * (size_t)o + q] = fvals[8 * (size_t)i + q];
+  for (int q = 0; q < 12; ++q) oxt[12 * (size_t)o + q] = fxt[12 * (size_t)i + q];
+}
+
+// Rebuilds the lagged friction entries of the scenes flagged in rebuild_host from the
+// current candidates at s->xs (their state at the start of their step) and keeps the
+// entries of every other scene: kept entries first, in their order, then the new ones
+// in pair order, so each scene's point-triangle and edge-edge entries stay contiguous.
+void k_friction_rebuild(zema_scene* s, const int* rebuild_host) {
+  const int ns = s->ns;
+  ZCHK(hipMemcpyAsync(s->sc_mask.p, rebuild_host, sizeof(int) * ns, hipMemcpyHostToDevice, s->st));
+  const int nold = s->nfric;
+  int64_t nk = 0;
+  s->fr_flag.reserve(nold + 1);
+  s->fr_offs.reserve(nold + 1);
+  if (nold) {
+    friction_keep_kernel<<<nblocks(nold), kBlock, 0, s->st>>>(nold, s->f_ids.p, s->sv_scene.p, s->sc_mask.p,
+                                                              s->fr_flag.p);
+    nk = k_exclusive_scan(s, s->fr_flag.p, s->fr_offs.p, nold);
+  }
+  const int nc = (int)(s->npt + s->nee);
+  int64_t nn = 0;
+  s->cnt.reserve(nc + 1);
+  s->offs.reserve(nc + 1);
+  if (nc) {
+    friction_flag_kernel<<<nblocks(nc), kBlock, 0, s->st>>>((int)s->npt, (int)s->nee, s->pt.p, s->ee.p, s->tris.p,
+                                                            s->edges.p, s->xs.p, s->P.dhat, s->sc_mask.p,
+                                                            s->sv_scene.p, s->cnt.p);
+    nn = k_exclusive_scan(s, s->cnt.p, s->offs.p, nc);
+  }
+  const int64_t nf = nk + nn;
+  s->f_ids2.reserve(5 * nf + 5);
+  s->f_vals2.reserve(8 * nf + 8);
+  s->f_xt2.reserve(12 * nf + 12);
+  if (nk)
+    friction_move_kernel<<<nblocks(nold), kBlock, 0, s->st>>>(nold, s->fr_flag.p, s->fr_offs.p, s->f_ids.p,
+                                                              s->f_vals.p, s->f_xt.p, s->f_ids2.p, s->f_vals2.p,
+                                                              s->f_xt2.p);
+  if (nn)
+    friction_fill_kernel<<<nblocks(nc), kBlock, 0, s->st>>>((int)s->npt, (int)s->nee, s->pt.p, s->ee.p, s->tris.p,
+                                                            s->edges.p, s->elen2.p, s->xs.p, s->kappa_sc.p,
+                                                            s->sv_scene.p, s->P.dhat, s->cnt.p, s->offs.p,
+                                                            s->f_ids2.p + 5 * nk, s->f_vals2.p + 8 * nk,
+                                                            s->f_xt2.p + 12 * nk);
+  std::swap(s->f_ids.p, s->f_ids2.p);
+  std::swap(s->f_ids.cap, s->f_ids2.cap);
+  std::swap(s->f_vals.p, s->f_vals2.p);
+  std::swap(s->f_vals.cap, s->f_vals2.cap);
+  std::swap(s->f_xt.p, s->f_xt2.p);
+  std::swap(s->f_xt.cap, s->f_xt2.cap);
+  s->nfric = (int)nf;
 }
 
 void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {

@@ -222,6 +222,16 @@ void k_velocity(zema_scene* s, double inv_h) {
   if (s->ndof) velocity_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(s->ndof, inv_h, s->y.p, s->yt.p, s->ydot.p);
 }
 
+void k_velocity_to(zema_scene* s, double inv_h, double* out) {
+  if (s->ndof) velocity_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(s->ndof, inv_h, s->y.p, s->yt.p, out);
+}
+
+void k_predict_to(zema_scene* s, double* out) {
+  if (s->ndof)
+    predict_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(3 * s->nsv, s->ndof, s->P.dt, s->P.gravity[0],
+                                                           s->P.gravity[1], s->P.gravity[2], s->y.p, s->ydot.p, out);
+}
+
 void k_predict(zema_scene* s) {
   if (s->ndof)
     predict_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(3 * s->nsv, s->ndof, s->P.dt, s->P.gravity[0],

@@ -120,7 +120,7 @@ struct zema_scene {
   zema::DBuf<int> tris, edges;
   zema::DBuf<double> elen2;
   zema::DBuf<unsigned char> body_fixed;  // per global body
-  zema::DBuf<double> xs, xs1, dxs;      // surface positions / displacements
+  zema::DBuf<double> xs, xs1, xs2, dxs;  // surface positions / displacements
   // ---- learned initial guess
   zema_mlp* mlp = nullptr;               // network used when P.warm_start == 1 (not owned)
   bool stepped = false;                  // a step completed since the state was set
@@ -134,6 +134,9 @@ struct zema_scene {
   // ---- state
   zema::DBuf<double> y, ydot, yt, ydt, yhat, ytmp, grad, pdir;
   int step = 0;
+  std::vector<int> scene_step;  // per scene of a batch (scenes may be at different steps)
+  std::vector<double> qt_h;     // host copy of the kinematic targets [nb][12]
+  bool batch_async = true;      // a batch's scenes start their next step as they converge
   // ---- candidates (current set)
   zema::DBuf<int> pt, ee;       // [n][2]
   zema::DBuf<int> et_pairs, unc_pairs;  // intersection check work
@@ -169,11 +172,14 @@ struct zema_scene {
   zema::DBuf<int> f_ids;       // [n][5]
   zema::DBuf<double> f_vals;   // [n][8] lambda, n, w
   zema::DBuf<double> f_xt;     // [n][12]
+  zema::DBuf<int> f_ids2, fr_flag, fr_offs;  // partial rebuild of the table (batches)
+  zema::DBuf<double> f_vals2, f_xt2;
   zema::DBuf<double> e_fric;
   // ---- PCG
   zema::DBuf<double> minv_soft;  // [9][nsv]
   zema::DBuf<double> minv_body;  // [nfree][144]
   zema::DBuf<double> pr, pz, pp0, pp1, pq, px;
+  zema::DBuf<double> pdir2;  // second initial-guess direction of a batch's starting scenes
   zema::DBuf<double> cg_z, cg_part;  // single-reduction PCG: node records, partials
   zema::DBuf<int4> cg_tab;   // its block layout: soft blocks (first row, rows, scene, slot)
   zema::DBuf<int2> cg_prng;  // per scene: partial slots
@@ -219,7 +225,9 @@ void k_axpy(zema_scene* s, int n, double a, const double* x, const double* y, do
 void k_scale(zema_scene* s, int n, double a, const double* x, double* out);
 void k_iota(zema_scene* s, int* p, int64_t n);  // p[i] = i
 void k_velocity(zema_scene* s, double inv_h);   // ydot = (y - yt) * inv_h
+void k_velocity_to(zema_scene* s, double inv_h, double* out);  // (y - yt) * inv_h into out
 void k_predict(zema_scene* s);                  // yhat from y^t, ydot^t
+void k_predict_to(zema_scene* s, double* out);  // the prediction into out
 void k_max_disp(zema_scene* s, const double* p, double* out);  // per scene: max vertex displacement of p
 void k_axpy_scene(zema_scene* s, const double* alpha_host, const double* p, const double* y, double* out);
 void k_select_scene(zema_scene* s, const int* mask_host, const double* a, const double* b, double* out);
@@ -249,9 +257,10 @@ void k_contact_energy(zema_scene* s);                 // e_pair, d_pair, e_fric 
 void k_scene_sums(zema_scene* s, double* out_host);  // per scene [ns][8] energy terms, total, min distance
 void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask);
 void k_friction_build(zema_scene* s);                 // lagged table from current candidates at xs
+void k_friction_rebuild(zema_scene* s, const int* rebuild_host);  // the same for some scenes of a batch
 
 // -------- broad phase (k_broad.hip)
-void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r);
+void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r, const double* xs2 = nullptr);
 void k_features(zema_scene* s, float* feat);
 void k_warm_dir(zema_scene* s, const float* out, double* p);
 void k_warm_target(zema_scene* s, float* target);

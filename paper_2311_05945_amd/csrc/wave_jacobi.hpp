@@ -24,6 +24,7 @@ __device__ void wave_psd_project(double* M, double* Vm, double* cs, int* partner
   double fro = 0.0;
   for (int e = lane; e < NE; e += 64) fro += M[(e / N) * LD + e % N] * M[(e / N) * LD + e % N];
   fro = wave_sum(fro);
+  double off_prev = INFINITY;
   for (int sweep = 0; sweep < 20; ++sweep) {
     double off = 0.0;
     for (int e = lane; e < NE; e += 64) {
@@ -31,9 +32,12 @@ __device__ void wave_psd_project(double* M, double* Vm, double* cs, int* partner
       if (r < c) off += M[r * LD + c] * M[r * LD + c];
     }
     off = wave_sum(off);
-    // stop at rounding level (off-diagonal norm 1e-15 of the Frobenius norm): sweeps
-    // converge quadratically to there, and rounding keeps them from going lower
-    if (!(off > 1e-30 * fro)) break;
+    // Stop once the off-diagonal norm is 1e-13 of the Frobenius norm (the eigenvalues
+    // are then those of a matrix within that distance), or when a sweep no longer
+    // shrinks it fourfold: sweeps converge quadratically until rounding stalls them,
+    // which for badly scaled matrices (barrier Hessians) happens above 1e-15.
+    if (!(off > 1e-26 * fro) || (sweep > 2 && off > 0.25 * off_prev)) break;
+    off_prev = off;
     for (int rd = 0; rd < N - 1; ++rd) {
       if (lane < N / 2) {
         int p = rr_pair<N>(rd, lane), q = rr_pair<N>(rd, N - 1 - lane);

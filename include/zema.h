@@ -183,8 +183,12 @@ int zema_ip_assemble(zema_scene* s, const double* y, uint32_t flags, double* ter
 int zema_hessian_matvec(zema_scene* s, const double* v, double* out);
 
 /* Block-Jacobi preconditioned CG on the last assembled Hessian: H sol = rhs, start
- * at 0, stop at |r|_2 <= rtol |rhs|_2 or max_iter (<= 0: n_dof) iterations.
- * ZEMA_E_PCG on breakdown or no convergence.  rhs, sol device; iters, rel_res host. */
+ * at 0, stop at |r|_2 <= rtol |rhs|_2 or max_iter (<= 0: n_dof) iterations.  With
+ * the default single-reduction form, non-positive curvature (p.Hp <= 0, which FP32
+ * rounding of a PSD-projected Hessian can produce) ends the solve with the current
+ * iterate, or M^-1 rhs if it happens at the first iteration (truncated CG); the
+ * two-launch form reports it as ZEMA_E_PCG.  ZEMA_E_PCG on no convergence or a
+ * singular preconditioner block.  rhs, sol device; iters, rel_res host. */
 int zema_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, int32_t max_iter,
                    int32_t* iters, double* rel_res);
 

@@ -290,30 +290,25 @@ __device__ inline double dvar_triple(V3 w, V3 u, V3 v, DVars& d, DVars* dW) {
   return s * s * iW;
 }
 
-// slot-space gradient (12) and Hessian (12x12) from variable space
-__device__ inline void dv_to_slots(const DVars& d, double* g, double (*H)[12]) {
-  for (int m = 0; m < 4; ++m)
-    for (int i = 0; i < 3; ++i) {
-      double acc = 0.0;
-      for (int u = 0; u < d.nv; ++u) acc += d.C[u][m] * d.g[u][i];
-      g[3 * m + i] = acc;
-    }
-  for (int m = 0; m < 4; ++m)
-    for (int n = 0; n < 4; ++n)
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          double acc = 0.0;
-          for (int u = 0; u < d.nv; ++u) {
-            if (!d.C[u][m]) continue;
-            for (int v = 0; v < d.nv; ++v)
-              if (d.C[v][n]) acc += d.C[u][m] * d.C[v][n] * d.H[u][v][i][j];
-          }
-          H[3 * m + i][3 * n + j] = acc;
-        }
+// slot-space gradient entry (slot m, component i) and Hessian entry ((m, i), (n, j))
+// from variable space
+__device__ inline double dv_grad_entry(const DVars& d, int m, int i) {
+  double acc = 0.0;
+  for (int u = 0; u < d.nv; ++u) acc += d.C[u][m] * d.g[u][i];
+  return acc;
+}
+__device__ inline double dv_hess_entry(const DVars& d, int m, int i, int n, int j) {
+  double acc = 0.0;
+  for (int u = 0; u < d.nv; ++u) {
+    if (!d.C[u][m]) continue;
+    for (int v = 0; v < d.nv; ++v)
+      if (d.C[v][n]) acc += d.C[u][m] * d.C[v][n] * d.H[u][v][i][j];
+  }
+  return acc;
 }
 
-// Squared distance of the given type with slot-space gradient and Hessian (d: workspace).
-__device__ inline double d2_derivs(int kind, int type, const V3* x, double* g, double (*H)[12], DVars& d) {
+// Squared distance of the given type with its variable-space derivatives in d.
+__device__ inline double d2_vars(int kind, int type, const V3* x, DVars& d) {
   double D;
   if (kind == 0) {
     if (type <= 2)
@@ -349,7 +344,6 @@ __device__ inline double d2_derivs(int kind, int type, const V3* x, double* g, d
       d.C[2][2] = -1;
     }
   }
-  dv_to_slots(d, g, H);
   return D;
 }
 
@@ -377,65 +371,6 @@ __host__ __device__ inline void mollifier(double c, double eps, double& m, doubl
     m = 1.0;
     m1 = m2 = 0.0;
   }
-}
-
-// Barrier energy kappa m b(d) of one pair with slot-space gradient and Hessian
-// (unprojected).  Returns false when inactive (d >= dhat).
-// Workspace of the pair derivatives; callers place it where it is cheap to address
-// (a wavefront's LDS), since a lane's private arrays of this size spill to scratch.
-struct PairWork {
-  DVars d, dw, dc;
-  double gc[12];
-  double Hc[12][12];
-};
-
-__device__ inline bool pair_barrier(int kind, const V3* x, double eps_x, double kappa, double dhat, double& E,
-                                    double* g, double (*H)[12], double* dist, PairWork& w) {
-  int type;
-  double d = pair_dist(kind, x, &type);
-  if (dist) *dist = d;
-  if (!(d < dhat)) return false;
-  double D = d2_derivs(kind, type, x, g, H, w.d);  // g, H hold grad / Hessian of D
-  d = sqrt(D);
-  double b, b1, b2;
-  barrier3(d, dhat, b, b1, b2);
-  double cg = b1 / (2.0 * d);
-  double ch = b2 / (4.0 * D) - b1 / (4.0 * D * d);
-  for (int i = 0; i < 12; ++i)
-    for (int j = 0; j < 12; ++j) H[i][j] = ch * g[i] * g[j] + cg * H[i][j];
-  for (int i = 0; i < 12; ++i) g[i] *= cg;  // now grad b
-  double m = 1.0;
-  if (kind == 1) {
-    V3 u = x[1] - x[0], v = x[3] - x[2];
-    V3 n = cross(u, v);
-    double c = dot(n, n);
-    if (c < eps_x) {
-      double m1, m2;
-      mollifier(c, eps_x, m, m1, m2);
-      // gradient / Hessian of c = |u x v|^2 with u = a1 - a0, v = b1 - b0
-      DVars& dw = w.dw;
-      DVars& dc = w.dc;
-      dvar_triple(x[2] - x[0], u, v, dw, &dc);
-      dc.C[0][2] = 1;
-      dc.C[0][0] = -1;
-      dc.C[1][1] = 1;
-      dc.C[1][0] = -1;
-      dc.C[2][3] = 1;
-      dc.C[2][2] = -1;
-      double* gc = w.gc;
-      double (*Hc)[12] = w.Hc;
-      dv_to_slots(dc, gc, Hc);
-      for (int i = 0; i < 12; ++i)
-        for (int j = 0; j < 12; ++j)
-          H[i][j] = m * H[i][j] + m1 * (g[i] * gc[j] + gc[i] * g[j]) + b * (m2 * gc[i] * gc[j] + m1 * Hc[i][j]);
-      for (int i = 0; i < 12; ++i) g[i] = m * g[i] + b * m1 * gc[i];
-    }
-  }
-  E = kappa * m * b;
-  for (int i = 0; i < 12; ++i) g[i] *= kappa;
-  for (int i = 0; i < 12; ++i)
-    for (int j = 0; j < 12; ++j) H[i][j] *= kappa;
-  return true;
 }
 
 // barrier energy only (line search)

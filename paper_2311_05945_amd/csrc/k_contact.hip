@@ -275,58 +275,122 @@ __global__ void item_count_kernel(ItemArgs A, int* __restrict__ cnt) {
   cnt[i] = nd + (A.hess ? nd * nd : 0);
 }
 
-// K1: one wavefront per item: gradient (12) and full 12x12 Hessian in x-space, formed
-// by lane 0 with the matrices and the derivative workspace in LDS (a lane's private
-// arrays of this size would live in scratch memory), written out by all lanes.
-// Barrier pairs store the unprojected Hessian (projected by K2); friction Hessians
-// are PSD by construction.
+// K1: one wavefront per item: gradient (12) and full 12x12 Hessian in x-space.  Lane 0
+// classifies the pair and forms the variable-space derivatives of the squared
+// distance (and of the edge-edge mollifier's argument) in LDS, with the barrier's
+// scalar factors; then every lane forms its entries of the slot-space gradient and
+// Hessian (barrier: kappa (m (b'' terms + b' terms) + mollifier terms); friction:
+// c w_a w_b core).  Barrier pairs store the unprojected Hessian (projected by K2);
+// friction Hessians are PSD by construction.
 __global__ void __launch_bounds__(64) pair_deriv_kernel(ItemArgs A, double* __restrict__ hout,
                                                         double* __restrict__ gout) {
-  __shared__ double H[12][12];
-  __shared__ double g[12];
-  __shared__ PairWork W;
+  __shared__ DVars Dd, Dc, Dw;          // distance, mollifier argument, scratch
+  __shared__ double gD[12], gC[12];     // slot gradients of D and of the mollifier argument
+  __shared__ double fw[4], core[9], U3[3];
+  __shared__ double k_cg, k_ch, k_kappa, k_m, k_m1, k_m2, k_b, k_c, k_cf;
+  __shared__ int mode;                  // 0 zero, 1 barrier, 2 mollified barrier, 3 friction
   const int i = blockIdx.x, lane = threadIdx.x;
   if (i >= A.n_act + A.nfric) return;
   if (lane == 0) {
     int kind, sv[4], ea, eb;
     bool fric;
     item_slots(A, i, kind, sv, ea, eb, fric);
-    if (fric && A.active && !A.active[A.sv_scene[sv[0]]]) {  // converged scene of a batch
-      for (int k = 0; k < 12; ++k) g[k] = 0.0;
-      for (int r = 0; r < 12; ++r)
-        for (int q = 0; q < 12; ++q) H[r][q] = 0.0;
-    } else {
+    mode = 0;
+    if (!(fric && A.active && !A.active[A.sv_scene[sv[0]]])) {  // else a converged scene of a batch
       V3 x[4];
       for (int a = 0; a < 4; ++a) x[a] = ld3(A.xs + 3 * sv[a]);
       if (!fric) {
-        double eps = kind == 1 ? 1e-3 * A.elen2[ea] * A.elen2[eb] : 0.0;
-        double E, d;
-        pair_barrier(kind, x, eps, A.kappa_sc[A.sv_scene[sv[0]]], A.dhat, E, g, H, &d, W);
+        int type;
+        double d = pair_dist(kind, x, &type);
+        if (d < A.dhat) {
+          double D = d2_vars(kind, type, x, Dd);
+          d = sqrt(D);
+          double b, b1, b2;
+          barrier3(d, A.dhat, b, b1, b2);
+          k_cg = b1 / (2.0 * d);
+          k_ch = b2 / (4.0 * D) - b1 / (4.0 * D * d);
+          k_kappa = A.kappa_sc[A.sv_scene[sv[0]]];
+          k_b = b;
+          mode = 1;
+          if (kind == 1) {
+            const double eps = 1e-3 * A.elen2[ea] * A.elen2[eb];
+            V3 u = x[1] - x[0], v = x[3] - x[2];
+            V3 nn = cross(u, v);
+            double c = dot(nn, nn);
+            if (c < eps) {
+              double m, m1, m2;
+              mollifier(c, eps, m, m1, m2);
+              k_m = m;
+              k_m1 = m1;
+              k_m2 = m2;
+              // gradient / Hessian of c = |u x v|^2 with u = a1 - a0, v = b1 - b0
+              dvar_triple(x[2] - x[0], u, v, Dw, &Dc);
+              Dc.C[0][2] = 1;
+              Dc.C[0][0] = -1;
+              Dc.C[1][1] = 1;
+              Dc.C[1][0] = -1;
+              Dc.C[2][3] = 1;
+              Dc.C[2][2] = -1;
+              mode = 2;
+            }
+          }
+        }
       } else {
         int f = i - A.n_act;
         const double* fv = A.fvals + 8 * f;
         V3 u = friction_u(fv, A.fxt + 12 * f, x);
         double y = sqrt(dot(u, u)), f1y, al, be;
         friction_core(y, A.ys, f1y, al, be);
-        double c = A.mu_sc[A.sv_scene[sv[0]]] * fv[0];
+        const double c = A.mu_sc[A.sv_scene[sv[0]]] * fv[0];
         V3 n = ld3(fv + 1);
-        double U[3] = {u.x, u.y, u.z}, N[3] = {n.x, n.y, n.z};
-        for (int a = 0; a < 4; ++a)
-          for (int r = 0; r < 3; ++r) g[3 * a + r] = c * f1y * fv[4 + a] * U[r];
-        double core[3][3];
+        double N[3] = {n.x, n.y, n.z};
+        U3[0] = u.x;
+        U3[1] = u.y;
+        U3[2] = u.z;
+        for (int a = 0; a < 4; ++a) fw[a] = fv[4 + a];
         for (int r = 0; r < 3; ++r)
-          for (int q = 0; q < 3; ++q) core[r][q] = al * ((r == q ? 1.0 : 0.0) - N[r] * N[q]) - be * U[r] * U[q];
-        for (int a = 0; a < 4; ++a)
-          for (int b = 0; b < 4; ++b)
-            for (int r = 0; r < 3; ++r)
-              for (int q = 0; q < 3; ++q) H[3 * a + r][3 * b + q] = c * fv[4 + a] * fv[4 + b] * core[r][q];
+          for (int q = 0; q < 3; ++q) core[3 * r + q] = al * ((r == q ? 1.0 : 0.0) - N[r] * N[q]) - be * U3[r] * U3[q];
+        k_c = c;
+        k_cf = c * f1y;
+        mode = 3;
       }
     }
   }
   __syncthreads();
-  if (lane < 12) gout[(size_t)12 * i + lane] = g[lane];
-  if (A.hess)
-    for (int e = lane; e < 144; e += 64) hout[(size_t)144 * i + e] = H[e / 12][e % 12];
+  const int md = mode;
+  if ((md == 1 || md == 2) && lane < 12) {
+    gD[lane] = dv_grad_entry(Dd, lane / 3, lane % 3);
+    if (md == 2) gC[lane] = dv_grad_entry(Dc, lane / 3, lane % 3);
+  }
+  __syncthreads();
+  if (lane < 12) {
+    double g = 0.0;
+    if (md == 1 || md == 2) {
+      g = k_cg * gD[lane];
+      if (md == 2) g = k_m * g + k_b * k_m1 * gC[lane];
+      g *= k_kappa;
+    } else if (md == 3) {
+      g = k_cf * fw[lane / 3] * U3[lane % 3];
+    }
+    gout[(size_t)12 * i + lane] = g;
+  }
+  if (!A.hess) return;
+  for (int e = lane; e < 144; e += 64) {
+    const int r = e / 12, q = e % 12;
+    double H = 0.0;
+    if (md == 1 || md == 2) {
+      H = k_ch * gD[r] * gD[q] + k_cg * dv_hess_entry(Dd, r / 3, r % 3, q / 3, q % 3);
+      if (md == 2) {
+        const double gr = k_cg * gD[r], gq = k_cg * gD[q];
+        H = k_m * H + k_m1 * (gr * gC[q] + gC[r] * gq) +
+            k_b * (k_m2 * gC[r] * gC[q] + k_m1 * dv_hess_entry(Dc, r / 3, r % 3, q / 3, q % 3));
+      }
+      H *= k_kappa;
+    } else if (md == 3) {
+      H = k_c * fw[r / 3] * fw[q / 3] * core[3 * (r % 3) + q % 3];
+    }
+    hout[(size_t)144 * i + e] = H;
+  }
 }
 
 // K2: one wavefront (block of 64) per item.  Barrier Hessians are projected to PSD by

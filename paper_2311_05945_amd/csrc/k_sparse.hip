@@ -1113,6 +1113,18 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
   }
 }
 
+// x = M^-1 b for the units of the scenes flagged in mask (a solve that met
+// non-positive curvature at its first iteration)
+__global__ void cg_precond_rhs_kernel(int nsv, int nfree, const double* __restrict__ ms, const double* __restrict__ mb,
+                                      const double* __restrict__ rhs, double* __restrict__ sol,
+                                      const int* __restrict__ mask, const int* __restrict__ v_scene,
+                                      const int* __restrict__ f_scene) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsv + nfree) return;
+  if (!mask[i < nsv ? v_scene[i] : f_scene[i - nsv]]) return;
+  apply_minv(i, nsv, ms, mb, rhs, sol);
+}
+
 // after the last iteration: |r|^2 and convergence of every unfinished scene
 __global__ void pcg_cg_final_kernel(const int2* __restrict__ prng, const double* __restrict__ cin,
                                     double* __restrict__ sc) {
@@ -1336,11 +1348,26 @@ static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, co
   int bad;
   ZCHK(hipMemcpyAsync(&bad, s->counters.p + 4, sizeof(int), hipMemcpyDeviceToHost, s->st));
   ZCHK(hipStreamSynchronize(s->st));
+  // Non-positive curvature (p.Hp <= 0, possible when FP32 rounding leaves the Hessian
+  // slightly indefinite) ends a scene's solve with its current iterate, a descent
+  // direction; at the first iteration that iterate is 0 and M^-1 b is taken instead.
+  std::vector<int> first(ns, 0);
+  bool any_first = false;
   for (int k = 0; k < ns; ++k) {
     const double* c = hs + 16 * k;
     iters[k] = (int)c[7];
     relres[k] = c[5] > 0.0 ? std::sqrt(c[4] / c[5]) : 0.0;
-    status[k] = (bad || c[8] != 0.0 || c[6] == 0.0) ? ZEMA_E_PCG : 0;
+    status[k] = (bad || c[6] == 0.0) ? ZEMA_E_PCG : 0;
+    if (c[8] != 0.0 && iters[k] == 0 && active_host[k]) {
+      first[k] = 1;
+      any_first = true;
+    }
+  }
+  if (any_first && s->nsv + s->nfree > 0) {
+    ZCHK(hipMemcpyAsync(s->sc_mask.p, first.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s->st));
+    cg_precond_rhs_kernel<<<nblocks(s->nsv + s->nfree), kBlock, 0, s->st>>>(
+        s->nsv, s->nfree, s->minv_soft.p, s->minv_body.p, rhs, sol, s->sc_mask.p, s->v_scene.p, s->f_scene.p);
+    ZCHK(hipStreamSynchronize(s->st));
   }
 }
 

@@ -806,6 +806,7 @@ struct CgVec {
   const int* f_scene;     // free body -> scene
   const int* fslot;       // free body -> partial slot
   int nsoft_blocks;
+  int nsv_single;  // a single scene: its soft rows (the block table is then implied), else -1
   double rtol;
 };
 
@@ -940,12 +941,19 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
   int scene, slot, row, lane;
   bool valid;
   if (soft) {
-    const int4 t = a.tab[blockIdx.x];
-    scene = t.z;
-    slot = t.w;
     lane = threadIdx.x % G;
-    valid = (int)threadIdx.x / G < t.y;
-    row = t.x + threadIdx.x / G;
+    if (a.nsv_single >= 0) {  // one scene: block b holds rows b * (kBlock / G) onward
+      scene = 0;
+      slot = blockIdx.x;
+      row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
+      valid = row < a.nsv_single;
+    } else {
+      const int4 t = a.tab[blockIdx.x];
+      scene = t.z;
+      slot = t.w;
+      valid = (int)threadIdx.x / G < t.y;
+      row = t.x + threadIdx.x / G;
+    }
   } else {  // wavefront m of the block: node row m of the body
     const int bi = blockIdx.x - a.nsoft_blocks;
     scene = a.f_scene[bi];
@@ -1203,6 +1211,7 @@ static CgVec cg_vec(zema_scene* s, int k, double* sol, double rtol) {
   a.f_scene = s->f_scene.p;
   a.fslot = s->cg_fslot.p;
   a.nsoft_blocks = s->cg_nsoft_blocks;
+  a.nsv_single = s->ns == 1 ? s->nsv : -1;
   a.rtol = rtol;
   return a;
 }

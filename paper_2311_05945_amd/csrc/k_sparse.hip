@@ -818,25 +818,51 @@ __device__ inline void mul_acc(const V* m, double u0, double u1, double u2, Acc3
   acc.z += m[6] * x0 + m[7] * x1 + m[8] * x2;
 }
 
+// loads through global-memory pointers (the matrix descriptor is read from device
+// memory, so its pointers would otherwise be generic and load through the flat path)
+template <class T>
+__device__ inline T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
+// Entries [j, end) step nl of one part of a row, software-pipelined: the column index
+// and values of the next entry are requested while the current entry's node record
+// is in flight, so each entry costs about one memory round trip instead of two.
 template <class V>
-__device__ inline void cg_entry(const V* __restrict__ v, int stride, int j, int col, const double* __restrict__ Z,
-                                Acc3<V>& A, Acc3<V>& B, Acc3<V>& C) {
+__device__ inline void cg_seg(const V* v, int stride, const int* cols, int j, int end, int nl, const double* Z,
+                              Acc3<V>& A, Acc3<V>& B, Acc3<V>& C) {
+  if (j >= end) return;
+  int c = gld(cols + j);
   V m[9];
-  for (int t = 0; t < 9; ++t) m[t] = v[(size_t)t * stride + j];
-  const double* z = Z + (size_t)kZs * col;
-  double zz[9];
-  for (int t = 0; t < 9; ++t) zz[t] = z[t];
-  mul_acc(m, zz[0], zz[1], zz[2], A);
-  mul_acc(m, zz[3], zz[4], zz[5], B);
-  mul_acc(m, zz[6], zz[7], zz[8], C);
+  for (int t = 0; t < 9; ++t) m[t] = gld(v + (size_t)t * stride + j);
+  for (;;) {
+    const double* z = Z + (size_t)kZs * c;
+    double zz[9];
+    for (int t = 0; t < 9; ++t) zz[t] = z[t];
+    const int jn = j + nl;
+    const bool more = jn < end;
+    int cn = 0;
+    V mn[9];
+    if (more) {
+      cn = gld(cols + jn);
+      for (int t = 0; t < 9; ++t) mn[t] = gld(v + (size_t)t * stride + jn);
+    }
+    mul_acc(m, zz[0], zz[1], zz[2], A);
+    mul_acc(m, zz[3], zz[4], zz[5], B);
+    mul_acc(m, zz[6], zz[7], zz[8], C);
+    if (!more) break;
+    j = jn;
+    c = cn;
+    for (int t = 0; t < 9; ++t) m[t] = mn[t];
+  }
 }
 
 // row extents [b0, b1) of the static part and [c0, c1) of the contact part
 template <class V>
 __device__ inline void cg_row(const Mat<V>& M, const double* Z, int4 e, int lane, int nl, Acc3<V>& A, Acc3<V>& B,
                               Acc3<V>& C) {
-  for (int j = e.x + lane; j < e.y; j += nl) cg_entry(M.bv, M.nnzb, j, M.bc[j], Z, A, B, C);
-  for (int j = e.z + lane; j < e.w; j += nl) cg_entry(M.cv, M.nnzc, j, M.cc[j], Z, A, B, C);
+  cg_seg(M.bv, M.nnzb, M.bc, e.x + lane, e.y, nl, Z, A, B, C);
+  cg_seg(M.cv, M.nnzc, M.cc, e.z + lane, e.w, nl, Z, A, B, C);
 }
 
 template <class V>
@@ -968,11 +994,11 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
   __shared__ int skip_s;
   int4 ext = make_int4(0, 0, 0, 0);
   if (valid) {
-    ext.x = M.bp[row];
-    ext.y = M.bp[row + 1];
+    ext.x = gld(M.bp + row);
+    ext.y = gld(M.bp + row + 1);
     if (M.cp) {
-      ext.z = M.cp[row];
-      ext.w = M.cp[row + 1];
+      ext.z = gld(M.cp + row);
+      ext.w = gld(M.cp + row + 1);
     }
   }
   if (threadIdx.x == 0) skip_s = START ? 0 : c[6] != 0.0;

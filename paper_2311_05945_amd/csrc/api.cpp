@@ -1433,7 +1433,8 @@ int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
       (void)hipMemcpyAsync(s->y.p, s->yt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st);
       (void)hipMemcpyAsync(s->ydot.p, s->ydt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st);
       (void)hipStreamSynchronize(s->st);
-      s->scene_step.assign(s->ns, s->step);
+      // each scene keeps the steps it completed; the batch's count is the least of them
+      s->step = *std::min_element(s->scene_step.begin(), s->scene_step.end());
     }
     return rc;
   }

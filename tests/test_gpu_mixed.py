@@ -121,3 +121,26 @@ def test_mixed_trajectory_matches_fp64(zema):
         log(f"steps {5 * (k + 1)}: max |y_mixed - y_fp64| {d:.3e}, newton fp64 {na} mixed {nb}")
     assert worst <= 1e-6
     assert abs(nb - na) <= 0.25 * na + 4
+
+
+def test_mixed_batch_converges_intersection_free(zema):
+    """An uneven batch in the mixed form (scenes running ahead of each other): every
+    scene-step converges (a solve that meets non-positive curvature from FP32 rounding
+    ends at its current iterate instead of failing) and stays intersection-free; the
+    Newton counts stay within a few iterations of the FP64 batch."""
+    seeds = (10001, 10003, 10005)
+    B = zema.Scene.batch([mixed(sg.batch_scene(s)) for s in seeds])
+    F = zema.Scene.batch([sg.batch_scene(s) for s in seeds])
+    sb = B.step(12)
+    sf = F.step(12)
+    assert all(x["status"] == 0 for x in sb)
+    nb = sum(x["newton_iters"] for x in sb)
+    nf = sum(x["newton_iters"] for x in sf)
+    y = B.get_state()[0].cpu().numpy()
+    yf = F.get_state()[0].cpu().numpy()
+    log(f"mixed batch: {nb} Newton iterations (FP64 {nf}), max |y - y_fp64| {np.abs(y - yf).max():.2e}")
+    assert abs(nb - nf) <= 0.1 * nf + 5
+    for j, s in enumerate(seeds):
+        R = ref.RefScene(sg.batch_scene(s))
+        tris, edges, vb = R.surface()
+        assert exact.count_intersections(R.surface_positions(y[B.scene_dofs(j)]), tris, edges, vb) == 0

@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sim steps/s + Newton iters/step, learned+batched vs plain at same tol, 1 GPU"
 HBM_PEAK_GBS = 8000.0
-GROUPS = {"spmv": 0, "tet": 1, "contact": 2, "query": 3, "ccd": 4}
+GROUPS_T = {"spmv": 0, "tet": 1, "contact": 2, "query": 3, "ccd": 4}
+GROUPS = 4  # batch objects (and streams) of the batched forms: the device's hardware queues
 
 
 def log(msg):
@@ -79,20 +80,23 @@ def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5):
     for sc in scenes:
         sc.params.precision = 1 if mixed else 0
         sc.params.warm_start = 1 if learned is not None else 0
-    objs = [zema.Scene.batch(scenes)] if batched else [zema.Scene(sc) for sc in scenes]
+    # batched: the scenes in GROUPS batch objects on as many streams, stepped together
+    # (zema_step_group); each batch takes all its steps in one call, every scene
+    # starting its next step as soon as it has converged
+    objs = zema.batch_group(scenes, GROUPS)[0] if batched else [zema.Scene(sc) for sc in scenes]
     for o in objs:
         if learned is not None:
             o.set_mlp(learned)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
-    for o in objs:
+    if batched:
+        for st in zema.step_group(objs, steps):
+            stats += st
+    for o in objs if not batched else []:
         done = 0
-        # a batch takes all its steps in one call: each scene starts its next step as
-        # soon as it has converged, so the call's length is set by its slowest scene
-        c = steps if batched else chunk
         while done < steps:
-            n = min(c, steps - done)
+            n = min(chunk, steps - done)
             stats += o.step(n)
             done += n
     torch.cuda.synchronize()
@@ -117,12 +121,16 @@ def forms(args, zema):
         mlp = zema.Mlp(np.load(args.mlp))
     out = {"sample": f"{len(seeds)} uneven grasp scenes (seeds {seeds[0]}-{seeds[-1]}), {args.form_steps} steps "
                      f"each from rest, dt=0.005 s, Newton tol 1e-6 dt",
-           "network": os.path.basename(args.mlp) if mlp is not None else None}
+           "network": os.path.basename(args.mlp) if mlp is not None else None,
+           "batched_as": f"{GROUPS} batch objects of similar size on {GROUPS} HIP streams, stepped together "
+                         f"(zema_step_group); plain: one scene object after the other"}
     cases = [("plain", False, None, False), ("batched", True, None, False)]
     if mlp is not None:
         cases += [("learned", False, mlp, False), ("batched_learned", True, mlp, False),
                   ("batched_learned_mixed", True, mlp, True)]
     total = len(seeds) * args.form_steps
+    # untimed warm-up of the grouped batch path (streams, host threads, first launches)
+    run_form(zema, mk(), 2, True)
     for name, batched, learned, mixed in cases:
         t, st, inter = run_form(zema, mk(), args.form_steps, batched, learned, mixed)
         newton = sum(x["newton_iters"] for x in st)
@@ -146,7 +154,7 @@ def main():
     ap.add_argument("--res", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--timer", default="spmv", choices=sorted(GROUPS))
+    ap.add_argument("--timer", default="spmv", choices=sorted(GROUPS_T))
     ap.add_argument("--chunk", type=int, default=10, help="steps per library call (progress lines)")
     ap.add_argument("--timing-steps", type=int, default=5, help="steps of the roofline pass after the timed run")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / learned / mixed comparison")
@@ -185,7 +193,7 @@ def main():
         G.tune(zema.TUNE_SPMV_LANES, tuned["spmv_lanes"])
         G.tune(zema.TUNE_UPDATE_BLOCK, tuned["update_block"])
     log(f"scene: {G.n_soft_verts} soft vertices, {G.n_tets} tets, {G.n_dof} DOFs, {G.n_tris} surface triangles")
-    group = GROUPS[args.timer]
+    group = GROUPS_T[args.timer]
     stats = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()

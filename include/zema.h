@@ -240,6 +240,18 @@ int zema_friction_table(zema_scene* s, int64_t* n, int32_t* ids5, double* vals8,
  * orient3d) cannot certify.  The first min(n_uncertain, cap) uncertain (edge,
  * triangle) pairs are written to uncertain_pairs (device, [cap][2]) for an exact
  * check by the caller; uncertain tets are only counted.  Counts are host outputs. */
+/* Steps several scene objects (single scenes or batches) concurrently: one host thread
+ * per object, each object's launches on its own stream (objects created on distinct
+ * streams overlap on the GPU; objects sharing a stream still run correctly, in turn).
+ * Splitting independent scenes into a few batch objects on a few streams (as many as
+ * the device has hardware queues) overlaps one object's host synchronisation and
+ * latency-bound launches with the others' work.  Each object is stepped exactly as by
+ * zema_step; stats[k] is object k's array (n_steps x its scene count), status[k]
+ * (host) its result.  Returns the first nonzero status, else 0.  Errors: ZEMA_E_ARG
+ * (null pointers, an object listed twice). */
+int zema_step_group(zema_scene* const* scenes, int32_t n_scenes, int32_t n_steps, zema_step_stats* const* stats,
+                    int32_t* status);
+
 int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect, int64_t* n_inverted,
                             int64_t* n_uncertain, int32_t* uncertain_pairs, int64_t cap);
 

@@ -11,6 +11,7 @@
 //   double the automatic barrier stiffness when the minimum distance fell below
 //   1e-3 dhat and decreased.
 #include <algorithm>
+#include <thread>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -1456,6 +1457,24 @@ int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
       return rc;
     }
   }
+  return 0;
+}
+
+int zema_step_group(zema_scene* const* scenes, int32_t n_scenes, int32_t n_steps, zema_step_stats* const* stats,
+                    int32_t* status) {
+  if (!scenes || n_scenes <= 0 || n_steps < 0 || !status || (n_steps && !stats)) return ZEMA_E_ARG;
+  for (int k = 0; k < n_scenes; ++k)
+    if (!scenes[k] || (n_steps && !stats[k])) return ZEMA_E_ARG;
+  for (int k = 0; k < n_scenes; ++k)
+    for (int j = 0; j < k; ++j)
+      if (scenes[j] == scenes[k]) return ZEMA_E_ARG;  // one host thread per object
+  std::vector<std::thread> workers;
+  workers.reserve(n_scenes);
+  for (int k = 0; k < n_scenes; ++k)
+    workers.emplace_back([=]() { status[k] = zema_step(scenes[k], n_steps, stats[k]); });
+  for (std::thread& t : workers) t.join();
+  for (int k = 0; k < n_scenes; ++k)
+    if (status[k]) return status[k];
   return 0;
 }
 

@@ -651,7 +651,7 @@ static bool pcg_graph_ready(zema_scene* s, const PcgArgs& a) {
     ZCHK(hipGraphExecDestroy(G.exec));
     G.exec = nullptr;
   }
-  if (!s->cap_st) ZCHK(hipStreamCreate(&s->cap_st));
+  if (!s->cap_st) ZCHK(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
   if (hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
   double* pold = s->pp1.p;
   double* pnew = s->pp0.p;
@@ -1279,7 +1279,7 @@ static bool cg_graph_ready(zema_scene* s, const void* mat, int lanes, double* so
     ZCHK(hipGraphExecDestroy(G.exec));
     G.exec = nullptr;
   }
-  if (!s->cap_st) ZCHK(hipStreamCreate(&s->cap_st));
+  if (!s->cap_st) ZCHK(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
   if (hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
   for (int c = 0; c < kChunk; ++c) {
     int k = 1 + c;

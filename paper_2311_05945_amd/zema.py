@@ -85,6 +85,7 @@ SIGNATURES = [
     ("zema_batch_create", [VP, I32, VP, PI32, VP, PI32, VP, C.POINTER(VP)]),
     ("zema_batch_layout", [VP, C.POINTER(I32), PI64]),
     ("zema_tune", [VP, I32, I32]),
+    ("zema_step_group", [C.POINTER(VP), I32, I32, C.POINTER(VP), PI32]),
     ("zema_tune_get", [VP, I32, PI32]),
     ("zema_autotune", [VP, PI32, PI32, PD]),
     ("zema_scene_set_mlp", [VP, VP]),
@@ -448,3 +449,33 @@ class Mlp:
 
 def scene_create(scene, device="cuda:0", stream=None) -> Scene:
     return Scene(scene, device, stream)
+
+
+def step_group(objs, n=1):
+    """zema_step_group: steps the scene objects `objs` (single scenes or batches, each
+    created on its own stream) concurrently, n steps each; returns one statistics list
+    per object (as Scene.step)."""
+    k = len(objs)
+    arrs = [(StepStats * max(n * o.n_scenes, 1))() for o in objs]
+    hs = (VP * k)(*[o.h for o in objs])
+    ps = (VP * k)(*[C.cast(a, VP) for a in arrs])
+    status = (I32 * k)()
+    rc = lib().zema_step_group(hs, k, n, ps, status)
+    outs = [[{f[0]: getattr(s, f[0]) for f in StepStats._fields_} for s in a[:n * o.n_scenes]]
+            for a, o in zip(arrs, objs)]
+    if rc != 0:
+        bad = next(i for i in range(k) if status[i] != 0)
+        raise ZemaError(rc, lib().zema_last_error(objs[bad].h).decode())
+    return outs
+
+
+def batch_group(scenes, n_groups=4, device="cuda:0"):
+    """The scenes split into n_groups batch objects of similar size (by soft vertex
+    count, largest first, dealt round-robin), each on a stream of its own; step them
+    with step_group."""
+    import torch
+    order = sorted(range(len(scenes)), key=lambda i: -sum(len(b.rest_pos) for b in scenes[i].softs))
+    groups = [order[g::n_groups] for g in range(n_groups) if order[g::n_groups]]
+    objs = [Scene.batch([scenes[i] for i in g], device=device, stream=torch.cuda.Stream(device=device))
+            for g in groups]
+    return objs, groups

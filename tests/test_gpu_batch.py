@@ -104,3 +104,20 @@ def test_async_batch_matches_lockstep(zema):
     log(f"newton per scene-step async {na}, lockstep {nl}; max |y_async - y_lockstep| {err:.2e}")
     assert all(x["status"] == 0 for x in sa)
     assert na == nl and err <= 1e-9
+
+
+def test_step_group_equals_separate_steps(zema):
+    """Two batch objects stepped concurrently on two streams (zema_step_group) reach
+    bitwise the states of the same objects stepped one after the other."""
+    seeds = [(10001, 10003), (10005, 10002)]
+    mk = lambda: [zema.Scene.batch([sg.batch_scene(s) for s in g], stream=torch.cuda.Stream()) for g in seeds]
+    G = mk()
+    S = mk()
+    sg_ = zema.step_group(G, 6)
+    for o in S:
+        o.step(6)
+    torch.cuda.synchronize()
+    for a, b, st in zip(G, S, sg_):
+        assert all(x["status"] == 0 for x in st)
+        assert torch.equal(a.get_state()[0], b.get_state()[0])
+    log("step_group: " + ", ".join(str(sum(x["newton_iters"] for x in st)) for st in sg_) + " Newton iterations")

@@ -161,7 +161,7 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick the PCG launch shapes by timing (default: fixed)")
     ap.add_argument("--no-graph", action="store_true", help="launch PCG kernels individually")
     ap.add_argument("--copy-probe", action="store_true", help="run a 256 MiB device copy (counter scaling)")
-    ap.add_argument("--form-scenes", type=int, default=8)
+    ap.add_argument("--form-scenes", type=int, default=32)
     ap.add_argument("--form-steps", type=int, default=16)
     ap.add_argument("--form-seed", type=int, default=10000)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_05945_amd", "warm_mlp.npy"))

@@ -49,9 +49,17 @@ struct DBuf {
     reserve(m);
     n = m;
   }
-  void upload(const std::vector<T>& v) {
+  // st: copy on that stream and wait for it (uploads while other threads capture graphs
+  // must stay off the legacy stream); null: a synchronous copy
+  void upload(const std::vector<T>& v, hipStream_t st = nullptr) {
     resize(v.size());
-    if (!v.empty()) ZCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (v.empty()) return;
+    if (st) {
+      ZCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+      ZCHK(hipStreamSynchronize(st));
+    } else {
+      ZCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
   }
   void upload(const T* v, size_t m) {
     resize(m);

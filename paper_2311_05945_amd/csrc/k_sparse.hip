@@ -1207,9 +1207,9 @@ static void cg_layout(zema_scene* s, int lanes) {
   s->cg_nsoft_blocks = (int)tab.size();
   s->cg_nslots = slot;
   if (tab.empty()) tab.push_back(make_int4(0, 0, 0, 0));
-  s->cg_tab.upload(tab);
-  s->cg_prng.upload(prng);
-  s->cg_fslot.upload(fslot);
+  s->cg_tab.upload(tab, s->st);
+  s->cg_prng.upload(prng, s->st);
+  s->cg_fslot.upload(fslot, s->st);
   s->cg_key = key;
 }
 

@@ -69,3 +69,19 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(zema, "LIB_PATH", "/nonexistent/libzema.so")
     with pytest.raises(RuntimeError):
         zema.lib()
+
+
+def test_argument_errors_need_no_device():
+    """Entry points reject invalid arguments before any HIP call (so this runs on the
+    CPU): null objects, an empty or duplicated group, unknown knobs."""
+    from paper_2311_05945_amd import zema
+    L = zema.lib()
+    E_ARG = zema.E_ARG
+    st = (ctypes.c_int32 * 2)()
+    assert L.zema_step_group(None, 1, 1, None, st) == E_ARG
+    one = (ctypes.c_void_p * 1)(None)
+    assert L.zema_step_group(one, 0, 1, None, st) == E_ARG
+    assert L.zema_step_group(one, 1, 1, None, st) == E_ARG
+    v = ctypes.c_int32()
+    assert L.zema_tune(None, zema.TUNE_PCG_FORM, 1) == E_ARG
+    assert L.zema_tune_get(None, zema.TUNE_PCG_FORM, ctypes.byref(v)) == E_ARG

@@ -315,7 +315,7 @@ int zema_kernel_time(zema_scene* s, int32_t group, double* ms, int64_t* launches
 /* ---------------------------------------------------------------- learned initial guess
  * Not part of the paper's method: a per-soft-vertex network proposes the Newton
  * initial guess of a time step; the step itself (tolerance, CCD filter, line
- * search) is unchanged, so the result is judged by the same Newton loop.
+ * search) is unchanged, so the result is accepted by the same Newton loop.
  *
  * Network: 16 -> 64 -> 64 -> 64 -> 3, ReLU, weight matrices used in bfloat16 (round to
  * nearest even from the FP32 master copy), biases FP32, FP32 accumulation on the

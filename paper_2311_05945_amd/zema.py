@@ -104,8 +104,8 @@ def lib():
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2311_05945_amd/build.py "
-                               "(or __graft_entry__.build()); there is no CPU fallback")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2311_05945_amd/build.py; "
+                               "there is no CPU fallback")
         L = C.CDLL(LIB_PATH)
         for name, args in SIGNATURES:
             f = getattr(L, name)

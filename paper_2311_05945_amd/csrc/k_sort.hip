@@ -143,8 +143,54 @@ __global__ void rs_scatter(const unsigned long long* __restrict__ kin, const int
   }
 }
 
+// Small inputs: one workgroup sorts (key, value) pairs in LDS by a bitonic network,
+// ordering equal keys by value.  Every caller's values are distinct input positions
+// or its keys are distinct, so the result equals the stable radix sort's, in one
+// launch instead of several per digit.
+constexpr int kSmallSort = 4096;
+
+__global__ void __launch_bounds__(1024) small_sort_kernel(int n, int m, unsigned long long* __restrict__ keys,
+                                                          int* __restrict__ vals) {
+  __shared__ unsigned long long K[kSmallSort];
+  __shared__ int Vs[kSmallSort];
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    K[i] = i < n ? keys[i] : ~0ull;
+    Vs[i] = i < n ? vals[i] : 0x7fffffff;
+  }
+  __syncthreads();
+  for (int k = 2; k <= m; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const unsigned long long a = K[i], c = K[l];
+          const int va = Vs[i], vc = Vs[l];
+          const bool gt = a > c || (a == c && va > vc);
+          if (gt == up) {
+            K[i] = c;
+            K[l] = a;
+            Vs[i] = vc;
+            Vs[l] = va;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    keys[i] = K[i];
+    vals[i] = Vs[i];
+  }
+}
+
 void k_radix_sort(zema_scene* s, SortBufs& b, int64_t n, int key_bits) {
   if (n <= 1) return;
+  if (n <= kSmallSort) {
+    int m = 2;
+    while (m < n) m <<= 1;
+    small_sort_kernel<<<1, 1024, 0, s->st>>>((int)n, m, b.k0.p, b.v0.p);
+    return;
+  }
   int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
   b.k1.reserve(n);
   b.v1.reserve(n);

@@ -250,6 +250,13 @@ __global__ void entry_permute_kernel(int n, int ebase, const int* __restrict__ s
   }
 }
 
+// totals of two exclusive scans: out[0] = offs_a[na-1] + cnt_a[na-1], out[1] likewise
+__global__ void totals_kernel(int na, const int* __restrict__ cnt_a, const int* __restrict__ offs_a, int nb,
+                              const int* __restrict__ cnt_b, const int* __restrict__ offs_b, long long* __restrict__ out) {
+  if (threadIdx.x == 0) out[0] = na > 0 ? (long long)offs_a[na - 1] + cnt_a[na - 1] : 0;
+  if (threadIdx.x == 1) out[1] = nb > 0 ? (long long)offs_b[nb - 1] + cnt_b[nb - 1] : 0;
+}
+
 struct PairRule {
   int qkind, ekind;  // 0 vertex, 1 triangle, 2 edge
   int same_set;      // edge-edge: report (q, e) only when q < e
@@ -425,9 +432,23 @@ static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>
   s->cnt.reserve(E.n + 1);
   s->offs.reserve(E.n + 1);
   s->big_list.reserve(E.n + 1);
+  s->q_cnt.reserve(Q.n + 1);
+  s->q_off.reserve(Q.n + 1);
+  s->q_big.reserve(Q.n + 1);
+  // entry cells and query work items are counted and scanned together, their totals
+  // read back in one transfer
   entry_count_kernel<<<nblocks(E.n), kBlock, 0, s->st>>>(E, R.ekind, s->bb_lo.p, s->bb_hi.p, S, s->tris.p, s->edges.p,
                                                          s->cnt.p, s->big_list.p);
-  int64_t total = k_exclusive_scan(s, s->cnt.p, s->offs.p, E.n);
+  query_count_kernel<<<nblocks(Q.n), kBlock, 0, s->st>>>(Q, R, s->bb_lo.p, s->bb_hi.p, S, s->tris.p, s->edges.p,
+                                                         s->q_cnt.p, s->q_big.p);
+  k_exclusive_scan(s, s->cnt.p, s->offs.p, E.n, false);
+  k_exclusive_scan(s, s->q_cnt.p, s->q_off.p, Q.n, false);
+  long long tot2[2];
+  s->tot_dev.reserve(2);
+  totals_kernel<<<1, 64, 0, s->st>>>(E.n, s->cnt.p, s->offs.p, Q.n, s->q_cnt.p, s->q_off.p, s->tot_dev.p);
+  ZCHK(hipMemcpyAsync(tot2, s->tot_dev.p, sizeof(tot2), hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+  const int64_t total = tot2[0], nitems = tot2[1];
   unsigned tsize = 1024;
   while (tsize < 2 * total) tsize <<= 1;
   unsigned mask = tsize - 1;
@@ -458,12 +479,6 @@ static int64_t search(zema_scene* s, PrimSet Q, PrimSet E, PairRule R, DBuf<int>
   unsigned long long nE = (unsigned long long)E.n;
   int* counter = s->counters.p;
   // query work items
-  s->q_cnt.reserve(Q.n + 1);
-  s->q_off.reserve(Q.n + 1);
-  s->q_big.reserve(Q.n + 1);
-  query_count_kernel<<<nblocks(Q.n), kBlock, 0, s->st>>>(Q, R, s->bb_lo.p, s->bb_hi.p, S, s->tris.p, s->edges.p,
-                                                         s->q_cnt.p, s->q_big.p);
-  int64_t nitems = k_exclusive_scan(s, s->q_cnt.p, s->q_off.p, Q.n);
   s->q_item.reserve(nitems + 1);
   if (nitems) query_expand_kernel<<<nblocks(Q.n), kBlock, 0, s->st>>>(Q.n, s->q_cnt.p, s->q_off.p, s->q_item.p);
   for (int attempt = 0; attempt < 2; ++attempt) {

@@ -150,6 +150,7 @@ struct zema_scene {
   zema::DBuf<int> ent_prim, ent_body, bucket_lo, bucket_hi, big_list;
   zema::DBuf<double> ent_box;                 // sorted entries' boxes [n][6]
   zema::DBuf<int> q_cnt, q_off, q_big, q_item;  // query work items (query, cell)
+  zema::DBuf<long long> tot_dev;                 // totals of the search's two count scans
   zema::DBuf<unsigned long long> pair_keys;
   zema::DBuf<int> counters;              // small device counters
   zema::SortBufs sort;

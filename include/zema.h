@@ -289,13 +289,21 @@ int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect
  *   candidate set of its initial guess is the swept set of h ydot^t, and per-scene
  *   sums may group differently).  The learned initial guess always runs in lockstep.
  *   On failure every scene returns to the start of the step it was in.
+ * ZEMA_TUNE_CG_ROWS: soft-vertex rows per workgroup of the single-launch PCG form
+ *   (1..64, capped at 256 / lanes).  0 (default) spreads the rows over the device's
+ *   compute units: ceil(soft rows / compute units), capped the same way, so a system
+ *   of 10k rows runs on every compute unit instead of 256 / lanes rows on fewer.
+ *   Each row's products do not depend on the setting; the inner products are summed
+ *   per workgroup, so different settings agree to rounding (a fixed setting is
+ *   deterministic).
  * Errors: ZEMA_E_ARG for an unknown knob or value. */
 enum {
   ZEMA_TUNE_PCG_GRAPH = 0,
   ZEMA_TUNE_SPMV_LANES = 1,
   ZEMA_TUNE_UPDATE_BLOCK = 2,
   ZEMA_TUNE_PCG_FORM = 3,
-  ZEMA_TUNE_BATCH_ASYNC = 4
+  ZEMA_TUNE_BATCH_ASYNC = 4,
+  ZEMA_TUNE_CG_ROWS = 5
 };
 int zema_tune(zema_scene* s, int32_t knob, int32_t value);
 /* Current value of a knob (host output).  Errors: ZEMA_E_ARG for an unknown knob. */

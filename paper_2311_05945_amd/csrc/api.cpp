@@ -1649,6 +1649,10 @@ int zema_tune(zema_scene* s, int32_t knob, int32_t value) {
     s->batch_async = value != 0;
     return 0;
   }
+  if (knob == ZEMA_TUNE_CG_ROWS && value >= 0 && value <= 64) {
+    s->tune_cg_rows = value;
+    return 0;
+  }
   return ZEMA_E_ARG;
 }
 
@@ -1669,6 +1673,9 @@ int zema_tune_get(zema_scene* s, int32_t knob, int32_t* value) {
       return 0;
     case ZEMA_TUNE_BATCH_ASYNC:
       *value = s->batch_async ? 1 : 0;
+      return 0;
+    case ZEMA_TUNE_CG_ROWS:
+      *value = s->tune_cg_rows;
       return 0;
     default:
       return ZEMA_E_ARG;

@@ -802,10 +802,10 @@ struct CgVec {
   double* cout;           // partials of iteration k + 1
   double* sc;             // per-scene scalars
   const int4* tab;        // soft blocks: first row, rows, scene, partial slot
-  const int2* prng;       // per scene: partial slots [x, y)
-  const int* f_scene;     // free body -> scene
-  const int* fslot;       // free body -> partial slot
+  const int4* binfo;      // every block: its scene's partial slots [x, y), scene, own slot
   int nsoft_blocks;
+  int nslots;             // partial slots of all scenes
+  int rpb;                // soft rows per block
   int nsv_single;  // a single scene: its soft rows (the block table is then implied), else -1
   double rtol;
 };
@@ -965,32 +965,36 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
   __shared__ double bv[3][12];  // a body's r_{k+1}, w_{k+1}, s_k
   const bool soft = (int)blockIdx.x < a.nsoft_blocks;
   int scene, slot, row, lane;
+  int2 pr;
   bool valid;
+  if (a.nsv_single >= 0) {  // one scene: block b holds partial slot b
+    scene = 0;
+    slot = blockIdx.x;
+    pr = make_int2(0, a.nslots);
+  } else {
+    const int4 b = a.binfo[blockIdx.x];
+    pr = make_int2(b.x, b.y);
+    scene = b.z;
+    slot = b.w;
+  }
   if (soft) {
     lane = threadIdx.x % G;
-    if (a.nsv_single >= 0) {  // one scene: block b holds rows b * (kBlock / G) onward
-      scene = 0;
-      slot = blockIdx.x;
-      row = blockIdx.x * (kBlock / G) + threadIdx.x / G;
-      valid = row < a.nsv_single;
+    if (a.nsv_single >= 0) {  // block b holds rows b * rpb onward
+      row = blockIdx.x * a.rpb + threadIdx.x / G;
+      valid = (int)threadIdx.x / G < a.rpb && row < a.nsv_single;
     } else {
       const int4 t = a.tab[blockIdx.x];
-      scene = t.z;
-      slot = t.w;
       valid = (int)threadIdx.x / G < t.y;
       row = t.x + threadIdx.x / G;
     }
   } else {  // wavefront m of the block: node row m of the body
-    const int bi = blockIdx.x - a.nsoft_blocks;
-    scene = a.f_scene[bi];
-    slot = a.fslot[bi];
     lane = threadIdx.x & 63;
     valid = true;
-    row = M.nsv + 4 * bi + (threadIdx.x >> 6);
+    row = M.nsv + 4 * (blockIdx.x - a.nsoft_blocks) + (threadIdx.x >> 6);
   }
   double* c = a.sc + 16 * scene;
-  // row extents and the scene's flag are independent loads; the flag is read once per
-  // block (the scene's first block may set it during this launch)
+  // row extents, the scene's scalars and its flag are independent loads; the flag is
+  // read once per block (the scene's first block may set it during this launch)
   __shared__ int skip_s;
   int4 ext = make_int4(0, 0, 0, 0);
   if (valid) {
@@ -1001,24 +1005,25 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
       ext.w = gld(M.cp + row + 1);
     }
   }
-  if (threadIdx.x == 0) skip_s = START ? 0 : c[6] != 0.0;
-  __syncthreads();
-  if (skip_s) return;
   double gprev = 1.0, aprev = 1.0, tol2 = 0.0;
   double c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  const int i0 = pr.x + threadIdx.x;
   if (!START) {
     if (k > 0) {
       gprev = c[(k - 1) & 1];
       aprev = c[2 + ((k - 1) & 1)];
       tol2 = c[9];
     }
-    const int2 pr = a.prng[scene];
-    for (int i = pr.x + threadIdx.x; i < pr.y; i += kBlock) {
+  }
+  if (threadIdx.x == 0) skip_s = START ? 0 : c[6] != 0.0;
+  __syncthreads();
+  if (skip_s) return;
+  if (!START)  // a scene with more partial slots than threads per block
+    for (int i = i0; i < pr.y; i += kBlock) {
       c1 += a.cin[3 * i];
       c2 += a.cin[3 * i + 1];
       c3 += a.cin[3 * i + 2];
     }
-  }
   Acc3<V> A{V(0), V(0), V(0)}, B{V(0), V(0), V(0)}, C{V(0), V(0), V(0)};
   if (soft) {
     cg_row(M, a.zin, ext, lane, G, A, B, C);
@@ -1036,7 +1041,6 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
     }
   }
   const bool own = lane == 0 && valid;
-  // the finishing lane's own-node values (independent of the scalars)
   V3 rv{}, wv{}, sv{}, pv{}, xv{}, zr{}, zw{}, zs{};
   double mi[9];
   if (own) {
@@ -1057,7 +1061,7 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
     block_sum3(c1, c2, c3, sh);
     const double gam = c1, del = c2, rr = c3;
     if (k == 0) tol2 = a.rtol * a.rtol * rr;
-    const bool first = slot == a.prng[scene].x && threadIdx.x == 0;  // the scene's first block
+    const bool first = slot == pr.x && threadIdx.x == 0;  // the scene's first block
     if (first) {
       c[4] = rr;
       if (k == 0) {
@@ -1178,13 +1182,24 @@ __global__ void pcg_cg_final_kernel(const int2* __restrict__ prng, const double*
 // Block layout of the single-reduction kernels for the given lanes per soft row:
 // scene-aligned soft blocks, then one block per free body; partial slots grouped by
 // scene (its soft blocks, then its bodies).
+static int cg_rows_per_block(zema_scene* s, int lanes) {
+  const int cap = kBlock / lanes;
+  if (s->tune_cg_rows > 0) return std::min(s->tune_cg_rows, cap);
+  if (s->n_cu <= 0) {
+    int dev = 0;
+    ZCHK(hipGetDevice(&dev));
+    ZCHK(hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  return std::min(cap, std::max(1, (s->nsv + s->n_cu - 1) / std::max(s->n_cu, 1)));
+}
+
 static void cg_layout(zema_scene* s, int lanes) {
-  std::vector<int> key = {lanes, s->ns, s->nsv, s->nfree};
+  const int rpb = cg_rows_per_block(s, lanes);
+  std::vector<int> key = {lanes, s->ns, s->nsv, s->nfree, rpb};
   if (s->cg_key == key) return;
-  const int rpb = kBlock / lanes;
   std::vector<int4> tab;
   std::vector<int2> prng(s->ns);
-  std::vector<int> fslot(std::max(s->nfree, 1));
+  std::vector<int> fslot(std::max(s->nfree, 1)), fscene(std::max(s->nfree, 1));
   std::vector<int> slot_of_block;
   int slot = 0;
   std::vector<int> soft_slot0(s->ns), nsb(s->ns);
@@ -1202,14 +1217,23 @@ static void cg_layout(zema_scene* s, int lanes) {
       int r0 = R.v0 + b * rpb;
       tab.push_back(make_int4(r0, std::min(rpb, R.v1 - r0), k, soft_slot0[k] + b));
     }
-    for (int f = R.f0; f < R.f1; ++f) fslot[f] = soft_slot0[k] + nsb[k] + (f - R.f0);
+    for (int f = R.f0; f < R.f1; ++f) {
+      fslot[f] = soft_slot0[k] + nsb[k] + (f - R.f0);
+      fscene[f] = k;
+    }
   }
+  std::vector<int4> binfo;
+  for (const int4& t : tab) binfo.push_back(make_int4(prng[t.z].x, prng[t.z].y, t.z, t.w));
+  for (int f = 0; f < s->nfree; ++f)
+    binfo.push_back(make_int4(prng[fscene[f]].x, prng[fscene[f]].y, fscene[f], fslot[f]));
   s->cg_nsoft_blocks = (int)tab.size();
   s->cg_nslots = slot;
+  s->cg_rpb = rpb;
   if (tab.empty()) tab.push_back(make_int4(0, 0, 0, 0));
   s->cg_tab.upload(tab, s->st);
   s->cg_prng.upload(prng, s->st);
-  s->cg_fslot.upload(fslot, s->st);
+  if (binfo.empty()) binfo.push_back(make_int4(0, 0, 0, 0));
+  s->cg_binfo.upload(binfo, s->st);
   s->cg_key = key;
 }
 
@@ -1233,10 +1257,10 @@ static CgVec cg_vec(zema_scene* s, int k, double* sol, double rtol) {
   a.cout = s->cg_part.p + pn * o;
   a.sc = s->scal.p;
   a.tab = s->cg_tab.p;
-  a.prng = s->cg_prng.p;
-  a.f_scene = s->f_scene.p;
-  a.fslot = s->cg_fslot.p;
+  a.binfo = s->cg_binfo.p;
   a.nsoft_blocks = s->cg_nsoft_blocks;
+  a.nslots = s->cg_nslots;
+  a.rpb = s->cg_rpb;
   a.nsv_single = s->ns == 1 ? s->nsv : -1;
   a.rtol = rtol;
   return a;
@@ -1267,9 +1291,10 @@ static void cg_launch(zema_scene* s, const void* mat, int lanes, int k, const Cg
 
 static bool cg_graph_ready(zema_scene* s, const void* mat, int lanes, double* sol) {
   std::vector<const void*> key = {mat, s->cg_part.p, s->scal.p, sol, s->pp0.p, s->pr.p, s->pq.p, s->pz.p, s->cg_z.p,
-                                  s->minv_soft.p, s->minv_body.p, s->cg_tab.p, s->cg_prng.p, s->cg_fslot.p,
-                                  s->f_scene.p, (const void*)(intptr_t)s->cg_nslots,
+                                  s->minv_soft.p, s->minv_body.p, s->cg_tab.p, s->cg_prng.p, s->cg_binfo.p,
+                                  (const void*)(intptr_t)s->cg_nslots,
                                   (const void*)(intptr_t)s->cg_nsoft_blocks, (const void*)(intptr_t)lanes,
+                                  (const void*)(intptr_t)s->cg_rpb,
                                   (const void*)(intptr_t)s->mixed, (const void*)(intptr_t)s->nsv,
                                   (const void*)(intptr_t)s->nfree, (const void*)(intptr_t)s->nnodes,
                                   (const void*)(intptr_t)s->ns};

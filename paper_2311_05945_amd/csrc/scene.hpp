@@ -184,9 +184,12 @@ struct zema_scene {
   zema::DBuf<double> cg_z, cg_part;  // single-reduction PCG: node records, partials
   zema::DBuf<int4> cg_tab;   // its block layout: soft blocks (first row, rows, scene, slot)
   zema::DBuf<int2> cg_prng;  // per scene: partial slots
-  zema::DBuf<int> cg_fslot;  // free body -> partial slot
+  zema::DBuf<int4> cg_binfo;  // per block: its scene's partial slots, scene, own slot
   std::vector<int> cg_key;
   int cg_nsoft_blocks = 0, cg_nslots = 0;
+  int cg_rpb = 0;             // soft rows per block of that layout
+  int tune_cg_rows = 0;       // requested rows per block (0: spread over the compute units)
+  int n_cu = 0;               // compute units of the scene's device (0: not yet queried)
   double* poll_h = nullptr;  // pinned host copies of the PCG scalars (two slots)
   int poll_cap = 0;
   hipEvent_t poll_ev[2] = {nullptr, nullptr};

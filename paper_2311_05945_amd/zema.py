@@ -95,7 +95,7 @@ SIGNATURES = [
 MLP_PARAMS = 9603
 MLP_FEATURES = 16
 WARM_EXPLICIT, WARM_LEARNED = 0, 1
-TUNE_PCG_GRAPH, TUNE_SPMV_LANES, TUNE_UPDATE_BLOCK, TUNE_PCG_FORM, TUNE_BATCH_ASYNC = 0, 1, 2, 3, 4
+TUNE_PCG_GRAPH, TUNE_SPMV_LANES, TUNE_UPDATE_BLOCK, TUNE_PCG_FORM, TUNE_BATCH_ASYNC, TUNE_CG_ROWS = 0, 1, 2, 3, 4, 5
 KT_SPMV, KT_TET, KT_CONTACT, KT_QUERY, KT_CCD = range(5)
 
 

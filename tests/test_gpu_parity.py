@@ -439,6 +439,44 @@ def test_pcg_forms_agree(zema, gripper_full, box_records, case):
         assert abs(i1 - i0) <= 5 and rel <= 10 * rtol
 
 
+@pytest.mark.parametrize("case", ["gripper", "box"])
+def test_cg_rows_per_block_change_rounding_only(zema, gripper_full, box_records, case):
+    """Rows per workgroup of the single-launch PCG (automatic, 1, a ragged 7, 33 and the
+    cap 64): every layout meets |b - H x| <= rtol |b| from the product, iteration counts
+    within 5 of the automatic layout's and solutions within 10 rtol; graph replays of
+    a ragged layout are bitwise the eager launches.  The box case has a free body."""
+    if case == "gripper":
+        sc, R, y, yd = gripper_full
+        G = zema.Scene(sc)
+        G.set_state(y, yd)
+        G.ip_assemble(y)
+    else:
+        sc, recs = box_records
+        G = _solve_state(zema, sc, recs[-1])
+    assert G.tune_get(zema.TUNE_CG_ROWS) == 0
+    with pytest.raises(zema.ZemaError):
+        G.tune(zema.TUNE_CG_ROWS, 65)
+    rhs = torch.from_numpy(np.random.default_rng(8).normal(size=G.n_dof)).cuda()
+    rtol = 1e-6
+    x0, i0, _ = G.pcg_solve(rhs, rtol=rtol)
+    for rows in (1, 7, 33, 64):
+        G.tune(zema.TUNE_CG_ROWS, rows)
+        x, it, rr = G.pcg_solve(rhs, rtol=rtol)
+        true = (G.hessian_matvec(x) - rhs).norm().item() / rhs.norm().item()
+        rel = (x - x0).norm().item() / x0.norm().item()
+        log(f"{case} rows {rows}: {it} iterations (automatic {i0}), true rel res {true:.2e}, rel diff {rel:.2e}")
+        assert rr <= rtol and true <= 1.05 * rtol
+        assert abs(it - i0) <= 5 and rel <= 10 * rtol
+    G.tune(zema.TUNE_CG_ROWS, 7)
+    G.tune(zema.TUNE_PCG_GRAPH, 0)
+    xe, ie, re = G.pcg_solve(rhs, rtol=rtol)
+    G.tune(zema.TUNE_PCG_GRAPH, 1)
+    for rep in range(2):
+        xg, ig, rg = G.pcg_solve(rhs, rtol=rtol)
+        assert ig == ie and rg == re and torch.equal(xg, xe)
+        G.hessian_matvec(xg)
+
+
 @pytest.mark.parametrize("form", [0, 1])
 def test_free_body_on_soft_cube_follows_oracle(zema, form):
     """A free affine box falling onto a soft cube: the GPU trajectory follows the

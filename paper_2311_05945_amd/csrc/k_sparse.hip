@@ -955,6 +955,18 @@ __global__ void cg_setup_kernel(int nsv, int nfree, const double* __restrict__ r
   }
 }
 
+// Workgroups of a launch are dispatched round-robin over the device's 8 XCDs (workgroup
+// b to XCD b mod 8), each with its own L2.  In a single-scene solve, soft workgroup b
+// takes logical block xcd_block(b, n), so each XCD holds a contiguous run of rows: the
+// neighbour records its rows gather are shared in its own L2 rather than fetched by
+// every XCD, and each XCD works on the same rows in every iteration.  (Batches keep
+// the plain order: there a contiguous run would be about one scene per XCD, and the
+// XCDs of scenes that have converged would idle.)  A bijection of [0, n).
+__device__ inline int xcd_block(int b, int n) {
+  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
+}
+
 // One iteration (START: the first product w_0 = H M^-1 b with alpha = beta = 0 and no
 // reduction; it leaves p = M^-1 b, which the first iteration scales by beta = 0).
 // Blocks of a finished scene return before gathering.
@@ -964,15 +976,16 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
   __shared__ double sh[3 * (kBlock / 64) + 3];
   __shared__ double bv[3][12];  // a body's r_{k+1}, w_{k+1}, s_k
   const bool soft = (int)blockIdx.x < a.nsoft_blocks;
+  const int blk = soft && a.nsv_single >= 0 ? xcd_block(blockIdx.x, a.nsoft_blocks) : (int)blockIdx.x;
   int scene, slot, row, lane;
   int2 pr;
   bool valid;
   if (a.nsv_single >= 0) {  // one scene: block b holds partial slot b
     scene = 0;
-    slot = blockIdx.x;
+    slot = blk;
     pr = make_int2(0, a.nslots);
   } else {
-    const int4 b = a.binfo[blockIdx.x];
+    const int4 b = a.binfo[blk];
     pr = make_int2(b.x, b.y);
     scene = b.z;
     slot = b.w;
@@ -980,10 +993,10 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
   if (soft) {
     lane = threadIdx.x % G;
     if (a.nsv_single >= 0) {  // block b holds rows b * rpb onward
-      row = blockIdx.x * a.rpb + threadIdx.x / G;
+      row = blk * a.rpb + threadIdx.x / G;
       valid = (int)threadIdx.x / G < a.rpb && row < a.nsv_single;
     } else {
-      const int4 t = a.tab[blockIdx.x];
+      const int4 t = a.tab[blk];
       valid = (int)threadIdx.x / G < t.y;
       row = t.x + threadIdx.x / G;
     }

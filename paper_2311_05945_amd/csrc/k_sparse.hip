@@ -1213,7 +1213,6 @@ static void cg_layout(zema_scene* s, int lanes) {
   std::vector<int4> tab;
   std::vector<int2> prng(s->ns);
   std::vector<int> fslot(std::max(s->nfree, 1)), fscene(std::max(s->nfree, 1));
-  std::vector<int> slot_of_block;
   int slot = 0;
   std::vector<int> soft_slot0(s->ns), nsb(s->ns);
   for (int k = 0; k < s->ns; ++k) {
@@ -1234,6 +1233,39 @@ static void cg_layout(zema_scene* s, int lanes) {
       fslot[f] = soft_slot0[k] + nsb[k] + (f - R.f0);
       fscene[f] = k;
     }
+  }
+  // Batches: soft workgroup b runs on XCD b mod 8 (round-robin dispatch).  Each scene's
+  // blocks are cut into 8 contiguous runs, run x placed on XCD x, so a scene's rows stay
+  // in the same XCD's L2 from one iteration to the next while every XCD holds a share of
+  // every scene (a converged scene frees all XCDs alike).  A permutation of the table:
+  // slots, and so every sum, are unchanged.
+  const int nsoft = (int)tab.size();
+  if (s->ns > 1 && nsoft >= 8) {
+    std::vector<std::vector<int>> q(8);
+    int l0 = 0;
+    for (int k = 0; k < s->ns; ++k) {
+      for (int x = 0; x < 8; ++x)
+        for (int l = l0 + x * nsb[k] / 8; l < l0 + (x + 1) * nsb[k] / 8; ++l) q[x].push_back(l);
+      l0 += nsb[k];
+    }
+    std::vector<int> spill;
+    for (int x = 0; x < 8; ++x) {
+      const size_t cap = nsoft / 8 + (x < nsoft % 8 ? 1 : 0);
+      while (q[x].size() > cap) {
+        spill.push_back(q[x].back());
+        q[x].pop_back();
+      }
+    }
+    for (int x = 0; x < 8; ++x) {
+      const size_t cap = nsoft / 8 + (x < nsoft % 8 ? 1 : 0);
+      while (q[x].size() < cap) {
+        q[x].push_back(spill.back());
+        spill.pop_back();
+      }
+    }
+    std::vector<int4> perm(nsoft);
+    for (int b = 0; b < nsoft; ++b) perm[b] = tab[q[b % 8][b / 8]];
+    tab.swap(perm);
   }
   std::vector<int4> binfo;
   for (const int4& t : tab) binfo.push_back(make_int4(prng[t.z].x, prng[t.z].y, t.z, t.w));

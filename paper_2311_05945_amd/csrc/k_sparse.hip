@@ -801,7 +801,7 @@ struct CgVec {
   const double* cin;      // partials (gamma_k, delta_k, rr_k) per block, scene-contiguous
   double* cout;           // partials of iteration k + 1
   double* sc;             // per-scene scalars
-  const int4* tab;        // soft blocks: first row, rows, scene, partial slot
+  const int4* tab;        // soft workgroups in launch order: first row, rows, scene, partial slot
   const int4* binfo;      // every block: its scene's partial slots [x, y), scene, own slot
   int nsoft_blocks;
   int nslots;             // partial slots of all scenes
@@ -980,7 +980,7 @@ __global__ void __launch_bounds__(kBlock) pcg_cg_kernel(const Mat<V>* __restrict
   int scene, slot, row, lane;
   int2 pr;
   bool valid;
-  if (a.nsv_single >= 0) {  // one scene: block b holds partial slot b
+  if (a.nsv_single >= 0) {  // one scene: logical block b holds partial slot b
     scene = 0;
     slot = blk;
     pr = make_int2(0, a.nslots);
@@ -1192,9 +1192,8 @@ __global__ void pcg_cg_final_kernel(const int2* __restrict__ prng, const double*
   }
 }
 
-// Block layout of the single-reduction kernels for the given lanes per soft row:
-// scene-aligned soft blocks, then one block per free body; partial slots grouped by
-// scene (its soft blocks, then its bodies).
+// Soft rows per workgroup: the requested number, else enough rows for one workgroup
+// per compute unit (a 10k-row system on 256 compute units: 40), at most kBlock / lanes.
 static int cg_rows_per_block(zema_scene* s, int lanes) {
   const int cap = kBlock / lanes;
   if (s->tune_cg_rows > 0) return std::min(s->tune_cg_rows, cap);
@@ -1206,6 +1205,9 @@ static int cg_rows_per_block(zema_scene* s, int lanes) {
   return std::min(cap, std::max(1, (s->nsv + s->n_cu - 1) / std::max(s->n_cu, 1)));
 }
 
+// Block layout of the single-reduction kernels for the given lanes per soft row:
+// scene-aligned soft blocks, then one block per free body; partial slots grouped by
+// scene (its soft blocks, then its bodies).
 static void cg_layout(zema_scene* s, int lanes) {
   const int rpb = cg_rows_per_block(s, lanes);
   std::vector<int> key = {lanes, s->ns, s->nsv, s->nfree, rpb};

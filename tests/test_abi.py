@@ -33,6 +33,17 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_functions()) == bound
 
 
+def test_tune_knobs_match_header():
+    """Every ZEMA_TUNE_* value of the header has the binding's constant of the same
+    value, and no binding constant is missing from the header."""
+    from paper_2311_05945_amd import zema
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    knobs = {k: int(v) for k, v in re.findall(r"\bZEMA_TUNE_([A-Z_]+)\s*=\s*(\d+)", src)}
+    assert "CG_ROWS" in knobs and len(knobs) >= 6
+    bound = {k[len("TUNE_"):]: getattr(zema, k) for k in dir(zema) if k.startswith("TUNE_")}
+    assert bound == knobs
+
+
 def test_struct_layout_matches_header(tmp_path):
     from paper_2311_05945_amd import zema
     prog = tmp_path / "sizes.c"

@@ -11,7 +11,9 @@ Gates:
   * a batch of one equals the single-scene object bitwise;
   * scenes that start their next step as soon as they converge (the default) follow the
     same trajectories as lockstep stepping: same Newton iteration counts per scene and
-    step, positions within 1e-9 m.
+    step, positions within 1e-9 m;
+  * a ragged PCG block layout (7 rows per workgroup) follows the automatic one to the
+    same bar.
 """
 import numpy as np
 import pytest
@@ -121,3 +123,21 @@ def test_step_group_equals_separate_steps(zema):
         assert all(x["status"] == 0 for x in st)
         assert torch.equal(a.get_state()[0], b.get_state()[0])
     log("step_group: " + ", ".join(str(sum(x["newton_iters"] for x in st)) for st in sg_) + " Newton iterations")
+
+
+def test_batch_rows_per_block_change_rounding_only(zema):
+    """A batch stepped with 7 soft rows per PCG workgroup (ragged per-scene runs in the
+    per-XCD block order) follows the automatic layout: same Newton iteration counts per
+    scene, positions within 1e-9 m."""
+    seeds = (10002, 10015, 10025)
+    A = zema.Scene.batch([sg.batch_scene(s) for s in seeds])
+    B = zema.Scene.batch([sg.batch_scene(s) for s in seeds])
+    B.tune(zema.TUNE_CG_ROWS, 7)
+    sa = A.step(10)
+    sb = B.step(10)
+    na = [x["newton_iters"] for x in sa]
+    nb = [x["newton_iters"] for x in sb]
+    err = np.abs(A.get_state()[0].cpu().numpy() - B.get_state()[0].cpu().numpy()).max()
+    log(f"newton per scene-step automatic {na}, 7 rows {nb}; max |y_a - y_b| {err:.2e}")
+    assert all(x["status"] == 0 for x in sa + sb)
+    assert na == nb and err <= 1e-9

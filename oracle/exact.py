@@ -59,26 +59,52 @@ def _in_tri2(p, a, b, c):
     return all(x >= 0 for x in s) or all(x <= 0 for x in s)
 
 
+def _cross(u, v):
+    return (u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0])
+
+
+def _drop_axis(n):
+    """Coordinates kept when projecting onto the plane whose normal is n: the axis
+    of n's largest component is dropped, so the projection is one-to-one."""
+    ax = max(range(3), key=lambda k: abs(n[k]))
+    return [k for k in range(3) if k != ax]
+
+
+def seg_seg_intersect(p, q, a, b) -> bool:
+    """Closed segment pq against closed segment ab in 3-D, exact (Fraction inputs).
+    Either segment may be a single point."""
+    if orient3d(p, q, a, b) != 0:
+        return False                      # not coplanar: skew or apart
+    pq, ab, ap = _sub(q, p), _sub(b, a), _sub(p, a)
+    for n in (_cross(pq, ab), _cross(pq, _sub(a, p)), _cross(pq, _sub(b, p)), _cross(ab, ap),
+              _cross(ab, _sub(q, a))):
+        if any(c != 0 for c in n):
+            keep = _drop_axis(n)
+            p2, q2, a2, b2 = (tuple(v[k] for k in keep) for v in (p, q, a, b))
+            return _seg_seg2(p2, q2, a2, b2)
+    # all four points on one line (or coincident): overlap of the 1-D intervals along
+    # an axis on which the points differ
+    diffs = [pq, ab, ap]
+    ax = max(range(3), key=lambda k: max(abs(d[k]) for d in diffs))
+    lo1, hi1 = min(p[ax], q[ax]), max(p[ax], q[ax])
+    lo2, hi2 = min(a[ax], b[ax]), max(a[ax], b[ax])
+    return lo1 <= hi2 and lo2 <= hi1
+
+
 def seg_tri_intersect(p, q, a, b, c) -> bool:
-    """Closed segment pq against closed triangle abc, exact."""
+    """Closed segment pq against closed triangle abc, exact.  A degenerate triangle
+    (collinear or coincident corners) is the union of its three edges."""
     p, q, a, b, c = map(_F, (p, q, a, b, c))
+    n = _cross(_sub(b, a), _sub(c, a))
+    if all(x == 0 for x in n):
+        return any(seg_seg_intersect(p, q, u, v) for u, v in ((a, b), (b, c), (c, a)))
     s1, s2 = orient3d(a, b, c, p), orient3d(a, b, c, q)
     if s1 * s2 > 0:
         return False
     if s1 == 0 and s2 == 0:
-        # coplanar: drop the axis along which the triangle normal is largest
-        n = (
-            (b[1] - a[1]) * (c[2] - a[2]) - (b[2] - a[2]) * (c[1] - a[1]),
-            (b[2] - a[2]) * (c[0] - a[0]) - (b[0] - a[0]) * (c[2] - a[2]),
-            (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]),
-        )
-        ax = max(range(3), key=lambda k: abs(n[k]))
-        if n[ax] == 0:  # degenerate triangle: treat as its three edges
-            keep = [k for k in range(3) if k != 0]
-        else:
-            keep = [k for k in range(3) if k != ax]
-        P = [tuple(v[k] for k in keep) for v in (p, q, a, b, c)]
-        p2, q2, a2, b2, c2 = P
+        # coplanar: project along the triangle normal's largest component
+        keep = _drop_axis(n)
+        p2, q2, a2, b2, c2 = (tuple(v[k] for k in keep) for v in (p, q, a, b, c))
         if _in_tri2(p2, a2, b2, c2) or _in_tri2(q2, a2, b2, c2):
             return True
         return _seg_seg2(p2, q2, a2, b2) or _seg_seg2(p2, q2, b2, c2) or _seg_seg2(p2, q2, c2, a2)

@@ -57,6 +57,7 @@ enum {
 enum {
   ZEMA_GRAD = 1u,       /* write the gradient of the selected terms */
   ZEMA_HESS = 2u,       /* assemble the PSD-projected Hessian of the selected terms */
+  ZEMA_REBUILD = 4u,    /* rebuild the candidate set statically at y (r = dhat) first */
   ZEMA_TERMS_SHIFT = 8u /* bits 8..13 select terms (0 inertia, 1 elastic,
                            2 orthogonality, 3 kinematic, 4 barrier, 5 friction);
                            0 selects all */
@@ -123,15 +124,19 @@ typedef struct {
 typedef struct {
   int32_t status, newton_iters, pcg_iters, ls_backtracks;
   int32_t n_pt_active, n_ee_active, n_pt_cand, n_ee_cand;
-  int32_t warm_learned, reserved_;  /* 1 if the learned initial guess was kept */
+  int32_t warm_learned;    /* 1 if the learned initial guess was kept */
+  int32_t pcg_breakdowns;  /* PCG solves of the step ended at non-positive curvature */
   double alpha_ccd_min, kappa, d_min, energy;
   double ms_total, ms_assemble, ms_pcg, ms_broad, ms_ccd, ms_linesearch, ms_warm;
 } zema_step_stats;
 
-/* Create a scene: copies every input, precomputes rest-shape inverses, volumes,
- * lumped masses, boundary surfaces, affine mass properties (volume, mass, centre,
- * second moment) and the static sparsity pattern, and sets the initial state
- * (rest or pos0, velocities vel0 / qdot0).  hip_stream: a hipStream_t or NULL.
+/* Create a scene from the problem statement of Sec. III (eqs. 1-3): tetrahedral soft
+ * bodies with a lumped (diagonal) mass and affine bodies with M_b = int rho J^T J.
+ * Copies every input, precomputes rest-shape inverses, volumes, lumped masses,
+ * boundary surfaces, affine mass properties (volume, mass, centre, second moment;
+ * the rest shape x0 is measured from the centre) and the static sparsity pattern,
+ * and sets the initial state (rest or pos0, velocities vel0 / qdot0).  hip_stream:
+ * a hipStream_t or NULL.  The scene owns its device memory until zema_scene_destroy.
  * Errors: ZEMA_E_ARG, ZEMA_E_MESH, ZEMA_E_INTERSECT, ZEMA_E_DEVICE. */
 int zema_scene_create(const zema_params* params, const zema_soft_desc* soft, int32_t n_soft,
                       const zema_affine_desc* affine, int32_t n_affine, void* hip_stream,
@@ -170,25 +175,57 @@ int zema_contact_candidates(zema_scene* s, const double* xs0, const double* xs1,
                             int32_t* pt, int64_t pt_cap, int64_t* n_pt, int32_t* ee, int64_t ee_cap,
                             int64_t* n_ee);
 
-/* Incremental potential at y (device, n_dof) on the static candidate set at y
- * (r = dhat): energy terms (host, 8 doubles: inertia, elastic, orthogonality,
+/* Barrier-augmented incremental potential of Sec. III (eqs. 1-5 with the lagged
+ * friction of eqs. 9-10) at y (device, n_dof).  The active set is every pair of the
+ * scene's current candidate set (the last one stored by zema_contact_candidates,
+ * zema_set_state, a step or an earlier assemble) closer than dhat at y; with
+ * ZEMA_REBUILD the set is first rebuilt statically at y (r = dhat), which stores it.
+ * Outputs: energy terms (host, 8 doubles: inertia, elastic, orthogonality,
  * kinematic, barrier, friction, total, minimum candidate distance), the gradient
- * (device, n_dof; optional) and, with ZEMA_HESS, the PSD-projected Hessian kept in
- * the scene (eqs. 6-8: x-space pair blocks projected, then mapped through the
- * affine Jacobian) for zema_hessian_matvec / zema_pcg_solve.  ZEMA_E_INTERSECT if a
- * tet is inverted or a candidate distance is zero (total = +inf). */
+ * (device, n_dof; with ZEMA_GRAD) and, with ZEMA_HESS, the PSD-projected Hessian kept
+ * in the scene (eqs. 6-8: x-space pair blocks projected, then mapped through the
+ * affine Jacobian) for zema_hessian_matvec, zema_hessian_bsr and zema_pcg_solve.
+ * ZEMA_E_INTERSECT if a tet is inverted or a candidate distance is zero (total =
+ * +inf); ZEMA_E_ARG on a batch. */
 int zema_ip_assemble(zema_scene* s, const double* y, uint32_t flags, double* terms, double* grad);
 
-/* out = H v for the last assembled Hessian (device vectors, n_dof). */
+/* out = H v for the last assembled Hessian (device vectors, n_dof).  ZEMA_E_ARG
+ * before the first assembly with ZEMA_HESS. */
 int zema_hessian_matvec(zema_scene* s, const double* v, double* out);
 
-/* Block-Jacobi preconditioned CG on the last assembled Hessian: H sol = rhs, start
- * at 0, stop at |r|_2 <= rtol |rhs|_2 or max_iter (<= 0: n_dof) iterations.  With
- * the default single-reduction form, non-positive curvature (p.Hp <= 0, which FP32
- * rounding of a PSD-projected Hessian can produce) ends the solve with the current
- * iterate, or M^-1 rhs if it happens at the first iteration (truncated CG); the
- * two-launch form reports it as ZEMA_E_PCG.  ZEMA_E_PCG on no convergence or a
- * singular preconditioner block.  rhs, sol device; iters, rel_res host. */
+/* The last assembled Hessian (the PSD-projected Newton matrix of eqs. 6-8) as block
+ * sparse rows over 3-DOF nodes: node n holds DOFs 3n .. 3n+2 of y (soft vertex i is
+ * node i; a free affine body's p, a1, a2, a3 are four consecutive nodes).  Device
+ * outputs: row_ptr [n_dof/3 + 1], col [nnzb] (ascending within a row) and val
+ * [nnzb][3][3] (row-major blocks, FP64; the mixed form's FP32 blocks are converted).
+ * Both triangles are stored; the matrix is symmetric.  cap is the capacity of col
+ * and val in blocks; *nnzb (host) receives the block count, also with
+ * ZEMA_E_CAPACITY when cap is too small (row_ptr, col and val may then be NULL).
+ * ZEMA_E_ARG without an assembled Hessian or on a batch. */
+int zema_hessian_bsr(zema_scene* s, int32_t* row_ptr, int32_t* col, double* val, int64_t cap, int64_t* nnzb);
+
+/* Surface topology that the pair lists of zema_contact_candidates and the
+ * intersection check index (the primitives of the contact set C of Sec. III eq. 4):
+ * tris [n_tris][3] and edges [n_edges][2] in surface vertex ids, the global body of
+ * each surface vertex vbody [n_surf] (soft bodies first, then affine bodies, in
+ * creation order) and its source vsrc [n_surf] (>= 0: the soft vertex, whose DOFs are
+ * 3 vsrc .. 3 vsrc + 2; < 0: -(1 + affine body index), the vertex x = A x0 + p of that
+ * body).  Device outputs, each optional (NULL skips it).  Errors: ZEMA_E_ARG. */
+int zema_surface_view(zema_scene* s, int32_t* tris, int32_t* edges, int32_t* vbody, int32_t* vsrc);
+
+/* The linear solve of a projected-Newton step (Sec. III; the runtime table of
+ * Sec. V lists it as "Linear"): block-Jacobi preconditioned CG on the last assembled
+ * Hessian, H sol = rhs, start at 0, stop at |r|_2 <= rtol |rhs|_2 or max_iter (<= 0:
+ * n_dof) iterations.  The preconditioner inverts the 3x3 diagonal block of each soft
+ * vertex and the 12x12 diagonal block of each free affine body.  rhs, sol device;
+ * iters, rel_res host.  FP64 form: non-positive curvature (p.Hp <= 0) is
+ * ZEMA_E_PCG.  Mixed form: the FP32 products' recurrence residual is checked at exit
+ * against b - H sol recomputed with FP64 accumulation; while that true residual
+ * exceeds rtol (at most twice), the residual equation is solved and its solution
+ * added, and rel_res reports the true residual.  Non-positive curvature, which FP32
+ * rounding of a PSD-projected Hessian can produce, ends a mixed solve with the
+ * current iterate (M^-1 rhs at the first iteration).  ZEMA_E_PCG also on no
+ * convergence or a singular preconditioner block. */
 int zema_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, int32_t max_iter,
                    int32_t* iters, double* rel_res);
 
@@ -198,11 +235,14 @@ int zema_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, i
  * starts at zero distance. */
 int zema_ccd_max_step(zema_scene* s, const double* y, const double* p, double* alpha);
 
-/* Advance n_steps time steps of the Newton method (warm start, lagged friction,
- * assemble, PCG, convergence test, swept candidates, CCD bound, backtracking line
- * search on the energy with an inversion check, kappa rule, velocity update).  On an
- * error the scene keeps the last accepted state.  stats: host array of
- * n_steps * n_scenes entries, step-major (n_scenes = 1 for a single scene). */
+/* Advance n_steps time steps: each is the minimisation of eq. 11 by projected
+ * Newton (Sec. III) -- predictor of eq. 3 and kinematic targets, lagged friction
+ * (eqs. 9-10) at y^t, warm start, then per iteration assembly (eqs. 1-8), PCG,
+ * convergence test, swept candidates, CCD bound, backtracking line search on the
+ * energy with an inversion check (intersection-free), kappa rule -- and the velocity
+ * update (y - y^t)/h.  On an error the scene keeps the last accepted state.  stats:
+ * host array of n_steps * n_scenes entries, step-major (n_scenes = 1 for a single
+ * scene). */
 int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats);
 
 /* ---------------------------------------------------------------- batches
@@ -233,13 +273,6 @@ int zema_batch_layout(const zema_scene* s, int32_t* n_scenes, int64_t* ranges);
  * (kind 0 PT / 1 EE, 4 surface vertices), vals8 [n][8] = (lambda, n(3), w(4)). */
 int zema_friction_table(zema_scene* s, int64_t* n, int32_t* ids5, double* vals8, int64_t cap);
 
-/* Validation of the intersection-free guarantee: at y (device), the number of
- * inter-body (surface edge, surface triangle) pairs whose closed segment and closed
- * triangle intersect, the number of tets with non-positive volume, and the number of
- * pairs / tets whose orientation signs the FP64 filter (static error bound of
- * orient3d) cannot certify.  The first min(n_uncertain, cap) uncertain (edge,
- * triangle) pairs are written to uncertain_pairs (device, [cap][2]) for an exact
- * check by the caller; uncertain tets are only counted.  Counts are host outputs. */
 /* Steps several scene objects (single scenes or batches) concurrently: one host thread
  * per object, each object's launches on its own stream (objects created on distinct
  * streams overlap on the GPU; objects sharing a stream still run correctly, in turn).
@@ -252,21 +285,16 @@ int zema_friction_table(zema_scene* s, int64_t* n, int32_t* ids5, double* vals8,
 int zema_step_group(zema_scene* const* scenes, int32_t n_scenes, int32_t n_steps, zema_step_stats* const* stats,
                     int32_t* status);
 
+/* Validation of the intersection-free guarantee: at y (device), the number of
+ * inter-body (surface edge, surface triangle) pairs whose closed segment and closed
+ * triangle intersect, the number of tets with non-positive volume, and the number of
+ * pairs / tets whose orientation signs the FP64 filter (static error bound of
+ * orient3d) cannot certify.  The first min(n_uncertain, cap) uncertain (edge,
+ * triangle) pairs are written to uncertain_pairs (device, [cap][2]) for an exact
+ * check by the caller; uncertain tets are only counted.  Counts are host outputs. */
 int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect, int64_t* n_inverted,
                             int64_t* n_uncertain, int32_t* uncertain_pairs, int64_t cap);
 
-/* Launch timing for benchmarks: with enable != 0 the library records HIP events on
- * the scene's stream around launches of one kernel group (0 PCG iteration, 1 per-tet
- * elastic assembly, 2 contact pair assembly, 3 broad-phase query, 4 CCD) and
- * accumulates their durations; zema_kernel_time returns the total milliseconds, the
- * launch count and the algorithmic bytes of those launches (what the method must move:
- * for a single-reduction PCG iteration 76 B per stored 3x3 block plus 152 B per DOF
- * (r, w, s, p, x read and written, the 3x3 inverse blocks, the node records read and
- * written), for the two-launch form's product 76 B per block plus four DOF vectors,
- * for the elastic assembly 320 B per tet; 0 for the other groups) since the timer was
- * enabled.  Single-reduction PCG iterations are timed per replayed chunk of 16 (events
- * around the graph launch; chunks in which the solve converged are not counted), the
- * other groups per launch.  Both calls synchronise the stream; bytes may be NULL. */
 /* Execution knobs of a single scene.
  * ZEMA_TUNE_PCG_GRAPH: 1 (default) replays PCG iterations in chunks of 16 from a
  *   captured HIP graph, 0 launches every kernel individually (as does the two-launch
@@ -317,6 +345,18 @@ int zema_tune_get(zema_scene* s, int32_t knob, int32_t* value);
  * batch), ZEMA_E_DEVICE. */
 int zema_autotune(zema_scene* s, int32_t* lanes, int32_t* update_block, double* us_per_iter);
 
+/* Launch timing for benchmarks: with enable != 0 the library records HIP events on
+ * the scene's stream around launches of one kernel group (0 PCG iteration, 1 per-tet
+ * elastic assembly, 2 contact pair assembly, 3 broad-phase query, 4 CCD) and
+ * accumulates their durations; zema_kernel_time returns the total milliseconds, the
+ * launch count and the algorithmic bytes of those launches (what the method must move:
+ * for a single-reduction PCG iteration 76 B per stored 3x3 block plus 152 B per DOF
+ * (r, w, s, p, x read and written, the 3x3 inverse blocks, the node records read and
+ * written), for the two-launch form's product 76 B per block plus four DOF vectors,
+ * for the elastic assembly 320 B per tet; 0 for the other groups) since the timer was
+ * enabled.  Single-reduction PCG iterations are timed per replayed chunk of 16 (events
+ * around the graph launch; chunks in which the solve converged are not counted), the
+ * other groups per launch.  Both calls synchronise the stream; bytes may be NULL. */
 int zema_kernel_timer(zema_scene* s, int32_t group, int32_t enable);
 int zema_kernel_time(zema_scene* s, int32_t group, double* ms, int64_t* launches, double* bytes);
 

@@ -737,7 +737,7 @@ int time_step(zema_scene* s, zema_step_stats* st) {
   const bool auto_k = s->P.kappa <= 0.0;
   const double tol = s->P.newton_tol * h;
   const int pcg_max = s->P.pcg_max;
-  std::vector<int> active(ns, 1), done(ns, 0), pit(ns), pst(ns);
+  std::vector<int> active(ns, 1), done(ns, 0), pit(ns), pst(ns), pbd(ns);
   std::vector<double> alpha(ns), disp(ns), rr(ns);
   int n_active = ns;
   for (int it = 0; it < s->P.newton_max && n_active > 0; ++it) {
@@ -761,18 +761,13 @@ int time_step(zema_scene* s, zema_step_stats* st) {
     }
     k_scale(s, n, -1.0, s->grad.p, s->ytmp.p);
     q = now_ms();
-    if (ns == 1) {
-      double r1;
-      int rc = k_pcg(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, pcg_max, &pit[0], &r1);
-      pst[0] = rc;
-    } else {
-      k_pcg_batch(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, pcg_max, active.data(), pit.data(), rr.data(),
-                  pst.data());
-    }
+    k_pcg_solve(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, pcg_max, active.data(), pit.data(), rr.data(), pst.data(),
+                pbd.data());
     tp += now_ms() - q;
     for (int k = 0; k < ns; ++k)
       if (active[k]) {
         st[k].pcg_iters += pit[k];
+        st[k].pcg_breakdowns += pbd[k];
         if (pst[k]) throw Error(pst[k], "PCG failed");
       }
     k_max_disp(s, s->pdir.p, disp.data());
@@ -893,7 +888,7 @@ int time_steps_async(zema_scene* s, int n_steps, zema_step_stats* stats) {
   if (s->scene_step.size() != (size_t)ns) s->scene_step.assign(ns, s->step);
   enum { BEGIN = 0, NEWTON = 1, FINISHED = 2 };
   std::vector<int> phase(ns, n_steps > 0 ? BEGIN : FINISHED), done(ns, 0), it(ns, 0);
-  std::vector<int> inN(ns), inB(ns), live(ns), fin(ns), pit(ns), pst(ns), inv(ns), acc(ns);
+  std::vector<int> inN(ns), inB(ns), live(ns), fin(ns), pit(ns), pst(ns), pbd(ns), inv(ns), acc(ns);
   std::vector<double> alpha(ns), disp(ns), rr(ns), dprev(ns, INFINITY), scale(ns), t0s(ns, now_ms());
   std::vector<double> T((size_t)8 * ns), T1((size_t)8 * ns), E0((size_t)8 * ns), T2((size_t)8 * ns);
   std::vector<double> alpha2(ns, 0.0);
@@ -941,12 +936,13 @@ int time_steps_async(zema_scene* s, int n_steps, zema_step_stats* stats) {
         }
       k_scale(s, n, -1.0, s->grad.p, s->ytmp.p);
       q = now_ms();
-      k_pcg_batch(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, s->P.pcg_max, inN.data(), pit.data(), rr.data(),
-                  pst.data());
+      k_pcg_solve(s, s->ytmp.p, s->pdir.p, s->P.pcg_rtol, s->P.pcg_max, inN.data(), pit.data(), rr.data(),
+                  pst.data(), pbd.data());
       tp += now_ms() - q;
       for (int k = 0; k < ns; ++k)
         if (inN[k]) {
           cur(k).pcg_iters += pit[k];
+          cur(k).pcg_breakdowns += pbd[k];
           if (pst[k]) throw Error(pst[k], "PCG failed");
         }
       k_max_disp(s, s->pdir.p, disp.data());
@@ -1366,7 +1362,7 @@ int zema_ip_assemble(zema_scene* s, const double* y, uint32_t flags, double* ter
   return guard(s, [&]() {
     unsigned mask = (flags >> ZEMA_TERMS_SHIFT) & 0x3fu;
     if (!mask) mask = 0x3fu;
-    static_candidates(s, y);
+    if (flags & ZEMA_REBUILD) static_candidates(s, y);
     double T[8];
     assemble(s, y, (flags & ZEMA_GRAD) ? s->grad.p : nullptr, (flags & ZEMA_HESS) != 0, mask, T);
     std::memcpy(terms, T, sizeof(T));
@@ -1388,16 +1384,48 @@ int zema_hessian_matvec(zema_scene* s, const double* v, double* out) {
   });
 }
 
+int zema_hessian_bsr(zema_scene* s, int32_t* row_ptr, int32_t* col, double* val, int64_t cap, int64_t* nnzb) {
+  if (!s || !nnzb || cap < 0 || s->ns != 1) return ZEMA_E_ARG;
+  if (!s->hess_valid) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    int64_t n = k_hessian_bsr(s, row_ptr, col, val, cap);
+    *nnzb = n;
+    if (n > cap || (n > 0 && (!row_ptr || !col || !val))) throw Error(ZEMA_E_CAPACITY, "BSR capacity");
+    if (!n && row_ptr) {
+      ZCHK(hipMemsetAsync(row_ptr, 0, sizeof(int) * ((size_t)s->nnodes + 1), s->st));
+      ZCHK(hipStreamSynchronize(s->st));
+    }
+    return 0;
+  });
+}
+
+int zema_surface_view(zema_scene* s, int32_t* tris, int32_t* edges, int32_t* vbody, int32_t* vsrc) {
+  if (!s) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    if (tris && s->ntri)
+      ZCHK(hipMemcpyAsync(tris, s->tris.p, sizeof(int) * 3 * s->ntri, hipMemcpyDeviceToDevice, s->st));
+    if (edges && s->nedge)
+      ZCHK(hipMemcpyAsync(edges, s->edges.p, sizeof(int) * 2 * s->nedge, hipMemcpyDeviceToDevice, s->st));
+    if (vbody && s->nsurf)
+      ZCHK(hipMemcpyAsync(vbody, s->sv_body.p, sizeof(int) * s->nsurf, hipMemcpyDeviceToDevice, s->st));
+    if (vsrc && s->nsurf)
+      ZCHK(hipMemcpyAsync(vsrc, s->sv_ref.p, sizeof(int) * s->nsurf, hipMemcpyDeviceToDevice, s->st));
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
+}
+
 int zema_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, int32_t max_iter, int32_t* iters,
                    double* rel_res) {
   if (!s || !rhs || !sol || !iters || !rel_res || !s->hess_valid || s->ns != 1) return ZEMA_E_ARG;
   return guard(s, [&]() {
-    int it;
-    double rr;
-    int rc = k_pcg(s, rhs, sol, rtol, max_iter, &it, &rr);
+    int it = 0, one = 1, rc = 0, bd = 0;
+    double rr = 0.0;
+    k_pcg_solve(s, rhs, sol, rtol, max_iter, &one, &it, &rr, &rc, &bd);
     *iters = it;
     *rel_res = rr;
-    if (rc) throw Error(rc, "PCG breakdown or no convergence");
+    if (rc) throw Error(rc, "PCG no convergence or singular preconditioner block");
+    if (bd && !s->mixed) throw Error(ZEMA_E_PCG, "PCG breakdown: non-positive curvature");
     return 0;
   });
 }

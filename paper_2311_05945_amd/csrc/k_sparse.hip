@@ -8,6 +8,7 @@
 // search-direction update p = z + beta p_old folded into the gathers), a one-block
 // scalar step, the vector update with the preconditioner, and a one-block scalar
 // step; scalars stay on the device and the host polls a flag every few iterations.
+#include <climits>
 #include <cstring>
 
 #include "scene.hpp"
@@ -30,36 +31,39 @@ struct Acc3 {
   V x, y, z;
 };
 
-// x = a + beta b at node c (DOF vectors stay FP64; converted to V for the product)
-template <class V>
+// x = a + beta b at node c (DOF vectors stay FP64; converted to the accumulation type
+// A for the product: A = V, or double for the FP64 residual check of FP32 blocks)
+template <class V, class A = V>
 __device__ inline void blk_acc(const V* __restrict__ v, int stride, int j, const double* a, const double* b,
-                               double beta, int c, Acc3<V>& acc) {
+                               double beta, int c, Acc3<A>& acc) {
   double u0 = a[3 * c], u1 = a[3 * c + 1], u2 = a[3 * c + 2];
   if (b) {
     u0 += beta * b[3 * c];
     u1 += beta * b[3 * c + 1];
     u2 += beta * b[3 * c + 2];
   }
-  V x0 = V(u0), x1 = V(u1), x2 = V(u2);
-  acc.x += v[j] * x0 + v[stride + j] * x1 + v[2 * stride + j] * x2;
-  acc.y += v[3 * stride + j] * x0 + v[4 * stride + j] * x1 + v[5 * stride + j] * x2;
-  acc.z += v[6 * stride + j] * x0 + v[7 * stride + j] * x1 + v[8 * stride + j] * x2;
+  A x0 = A(u0), x1 = A(u1), x2 = A(u2);
+  acc.x += A(v[j]) * x0 + A(v[stride + j]) * x1 + A(v[2 * stride + j]) * x2;
+  acc.y += A(v[3 * stride + j]) * x0 + A(v[4 * stride + j]) * x1 + A(v[5 * stride + j]) * x2;
+  acc.z += A(v[6 * stride + j]) * x0 + A(v[7 * stride + j]) * x1 + A(v[8 * stride + j]) * x2;
 }
 
-template <class V>
-__device__ inline Acc3<V> row_partial(const Mat<V>& M, int row, int lane, int nl, const double* a, const double* b,
+template <class V, class A = V>
+__device__ inline Acc3<A> row_partial(const Mat<V>& M, int row, int lane, int nl, const double* a, const double* b,
                                       double beta) {
-  Acc3<V> acc{V(0), V(0), V(0)};
-  for (int j = M.bp[row] + lane; j < M.bp[row + 1]; j += nl) blk_acc(M.bv, M.nnzb, j, a, b, beta, M.bc[j], acc);
+  Acc3<A> acc{A(0), A(0), A(0)};
+  for (int j = M.bp[row] + lane; j < M.bp[row + 1]; j += nl)
+    blk_acc<V, A>(M.bv, M.nnzb, j, a, b, beta, M.bc[j], acc);
   if (M.cp)
-    for (int j = M.cp[row] + lane; j < M.cp[row + 1]; j += nl) blk_acc(M.cv, M.nnzc, j, a, b, beta, M.cc[j], acc);
+    for (int j = M.cp[row] + lane; j < M.cp[row + 1]; j += nl)
+      blk_acc<V, A>(M.cv, M.nnzc, j, a, b, beta, M.cc[j], acc);
   return acc;
 }
 
 // q = H x with x = a + beta b.  Writes xo = x for the rows it owns and the block
 // partial of x . q when those pointers are given.  Soft rows: 16 lanes each; affine
 // rows: one block each.
-template <class V>
+template <class V, class A = V>
 __device__ inline double spmv_rows(const Mat<V>& M, const double* a, const double* b, double beta, double* q,
                                    double* xo, double* sh_red /* 3 * waves */) {
   int nsoft_blocks = (M.nsv + (kBlock / RG) - 1) / (kBlock / RG);
@@ -67,8 +71,8 @@ __device__ inline double spmv_rows(const Mat<V>& M, const double* a, const doubl
   if ((int)blockIdx.x < nsoft_blocks) {
     int row = blockIdx.x * (kBlock / RG) + threadIdx.x / RG;
     int lane = threadIdx.x % RG;
-    Acc3<V> acc{V(0), V(0), V(0)};
-    if (row < M.nsv) acc = row_partial(M, row, lane, RG, a, b, beta);
+    Acc3<A> acc{A(0), A(0), A(0)};
+    if (row < M.nsv) acc = row_partial<V, A>(M, row, lane, RG, a, b, beta);
     for (int o = RG / 2; o > 0; o >>= 1) {
       acc.x += __shfl_xor(acc.x, o, RG);
       acc.y += __shfl_xor(acc.y, o, RG);
@@ -84,7 +88,7 @@ __device__ inline double spmv_rows(const Mat<V>& M, const double* a, const doubl
     }
   } else {
     int row = M.nsv + (blockIdx.x - nsoft_blocks);
-    Acc3<V> acc = row_partial(M, row, threadIdx.x, kBlock, a, b, beta);
+    Acc3<A> acc = row_partial<V, A>(M, row, threadIdx.x, kBlock, a, b, beta);
     for (int o = 32; o > 0; o >>= 1) {
       acc.x += __shfl_xor(acc.x, o, 64);
       acc.y += __shfl_xor(acc.y, o, 64);
@@ -111,10 +115,10 @@ __device__ inline double spmv_rows(const Mat<V>& M, const double* a, const doubl
   return dotv;
 }
 
-template <class V>
+template <class V, class A = V>
 __global__ void spmv_kernel(Mat<V> M, const double* __restrict__ x, double* __restrict__ out) {
   __shared__ double red[3 * (kBlock / 64)];
-  spmv_rows(M, x, nullptr, 0.0, out, nullptr, red);
+  spmv_rows<V, A>(M, x, nullptr, 0.0, out, nullptr, red);
 }
 
 // ------------------------------------------------------------------ preconditioner
@@ -573,6 +577,94 @@ void k_hess_matvec(zema_scene* s, const double* v, double* out) {
     spmv_kernel<double><<<g, kBlock, 0, s->st>>>(make_mat<double>(s, s->bsr_val.p, s->c_val.p), v, out);
 }
 
+// ------------------------------------------------------------------ BSR export
+// Static blocks (tets, affine bodies) and contact blocks share the node numbering and
+// both keep ascending columns per row; a row of the export is their merge, a column
+// present in both summed in FP64.  One thread per row (an export, not the hot loop).
+template <class V>
+__global__ void bsr_export_count_kernel(Mat<V> M, int* __restrict__ cnt) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= M.nnodes) return;
+  int i = M.bp[r], ie = M.bp[r + 1], j = 0, je = 0;
+  if (M.cp) {
+    j = M.cp[r];
+    je = M.cp[r + 1];
+  }
+  int n = 0;
+  while (i < ie || j < je) {
+    int ci = i < ie ? M.bc[i] : INT_MAX, cj = j < je ? M.cc[j] : INT_MAX;
+    if (ci <= cj) ++i;
+    if (cj <= ci) ++j;
+    ++n;
+  }
+  cnt[r] = n;
+}
+
+template <class V>
+__global__ void bsr_export_fill_kernel(Mat<V> M, const int* __restrict__ off, int* __restrict__ col,
+                                       double* __restrict__ val) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= M.nnodes) return;
+  int i = M.bp[r], ie = M.bp[r + 1], j = 0, je = 0;
+  if (M.cp) {
+    j = M.cp[r];
+    je = M.cp[r + 1];
+  }
+  int o = off[r];
+  while (i < ie || j < je) {
+    int ci = i < ie ? M.bc[i] : INT_MAX, cj = j < je ? M.cc[j] : INT_MAX;
+    int c = ci < cj ? ci : cj;
+    double b[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (ci == c) {
+      for (int q = 0; q < 9; ++q) b[q] += double(M.bv[(size_t)q * M.nnzb + i]);
+      ++i;
+    }
+    if (cj == c) {
+      for (int q = 0; q < 9; ++q) b[q] += double(M.cv[(size_t)q * M.nnzc + j]);
+      ++j;
+    }
+    col[o] = c;
+    for (int q = 0; q < 9; ++q) val[(size_t)9 * o + q] = b[q];
+    ++o;
+  }
+}
+
+int64_t k_hessian_bsr(zema_scene* s, int* row_ptr, int* col, double* val, int64_t cap) {
+  const int n = s->nnodes;
+  s->cnt.reserve((size_t)n + 1);
+  s->offs.reserve((size_t)n + 1);
+  if (n == 0) return 0;
+  if (s->mixed)
+    bsr_export_count_kernel<float><<<nblocks(n), kBlock, 0, s->st>>>(make_mat<float>(s, s->bsr_val32.p, s->c_val32.p),
+                                                                     s->cnt.p);
+  else
+    bsr_export_count_kernel<double><<<nblocks(n), kBlock, 0, s->st>>>(make_mat<double>(s, s->bsr_val.p, s->c_val.p),
+                                                                      s->cnt.p);
+  int64_t total = k_exclusive_scan(s, s->cnt.p, s->offs.p, n, true);
+  if (total > cap || !row_ptr || !col || !val) return total;
+  if (s->mixed)
+    bsr_export_fill_kernel<float><<<nblocks(n), kBlock, 0, s->st>>>(make_mat<float>(s, s->bsr_val32.p, s->c_val32.p),
+                                                                    s->offs.p, col, val);
+  else
+    bsr_export_fill_kernel<double><<<nblocks(n), kBlock, 0, s->st>>>(make_mat<double>(s, s->bsr_val.p, s->c_val.p),
+                                                                     s->offs.p, col, val);
+  int tot32 = (int)total;
+  ZCHK(hipMemcpyAsync(row_ptr, s->offs.p, sizeof(int) * n, hipMemcpyDeviceToDevice, s->st));
+  ZCHK(hipMemcpyAsync(row_ptr + n, &tot32, sizeof(int), hipMemcpyHostToDevice, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+  return total;
+}
+
+// out = H v with FP64 accumulation (the mixed form's FP32 blocks converted exactly)
+void k_hess_matvec64(zema_scene* s, const double* v, double* out) {
+  int g = spmv_grid(s);
+  if (!g) return;
+  if (s->mixed)
+    spmv_kernel<float, double><<<g, kBlock, 0, s->st>>>(make_mat<float>(s, s->bsr_val32.p, s->c_val32.p), v, out);
+  else
+    spmv_kernel<double><<<g, kBlock, 0, s->st>>>(make_mat<double>(s, s->bsr_val.p, s->c_val.p), v, out);
+}
+
 void k_build_precond(zema_scene* s) {
   s->minv_soft.reserve((size_t)9 * s->nsv + 9);
   s->minv_body.reserve((size_t)144 * s->nfree + 144);
@@ -676,9 +768,11 @@ static bool pcg_graph_ready(zema_scene* s, const PcgArgs& a) {
 }
 
 static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, const double* rhs, double* sol,
-                     double rtol, int max_iter, const int* active_host, int* iters, double* relres, int* status);
+                     double rtol, int max_iter, const int* active_host, int* iters, double* relres, int* status,
+                     int* breakdown);
 
-int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres) {
+int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres,
+          int* breakdown) {
   int n = s->ndof;
   if (max_iter <= 0) max_iter = n;
   k_build_precond(s);
@@ -720,7 +814,7 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
     // node records read and written once
     a.bytes = (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 152.0 * s->ndof;
     int one = 1, st = 0;
-    k_pcg_cg(s, a.mat, lanes, a.bytes, rhs, sol, rtol, max_iter, &one, iters, relres, &st);
+    k_pcg_cg(s, a.mat, lanes, a.bytes, rhs, sol, rtol, max_iter, &one, iters, relres, &st, breakdown);
     return st;
   }
   pcg_init_kernel<<<nbv, kBlock, 0, s->st>>>(s->nsv, s->nfree, rhs, s->minv_soft.p, s->minv_body.p, sol, s->pr.p,
@@ -763,6 +857,7 @@ int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_it
   ZCHK(hipStreamSynchronize(s->st));
   *iters = (int)hs[7];
   *relres = hs[5] > 0.0 ? sqrt(hs[4] / hs[5]) : 0.0;
+  if (breakdown) *breakdown = hs[8] != 0.0;
   if (bad) return ZEMA_E_PCG;
   if (hs[8] != 0.0) return ZEMA_E_PCG;
   if (hs[6] == 0.0) return ZEMA_E_PCG;
@@ -1373,7 +1468,8 @@ static bool cg_graph_ready(zema_scene* s, const void* mat, int lanes, double* so
 // Single-reduction solve of every scene whose active flag is set (others get x = 0);
 // per-scene iterations, relative residuals and status on the host.
 static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, const double* rhs, double* sol,
-                     double rtol, int max_iter, const int* active_host, int* iters, double* relres, int* status) {
+                     double rtol, int max_iter, const int* active_host, int* iters, double* relres, int* status,
+                     int* breakdown) {
   const int ns = s->ns, n = s->ndof;
   s->pr.reserve(n);
   s->pz.reserve(n);
@@ -1465,6 +1561,7 @@ static void k_pcg_cg(zema_scene* s, const void* mat, int lanes, double bytes, co
     iters[k] = (int)c[7];
     relres[k] = c[5] > 0.0 ? std::sqrt(c[4] / c[5]) : 0.0;
     status[k] = (bad || c[6] == 0.0) ? ZEMA_E_PCG : 0;
+    if (breakdown) breakdown[k] = active_host[k] && c[8] != 0.0;
     if (c[8] != 0.0 && iters[k] == 0 && active_host[k]) {
       first[k] = 1;
       any_first = true;
@@ -1540,7 +1637,7 @@ void k_autotune(zema_scene* s, int* lanes_out, int* ub_out, double* us_per_iter)
 // the same single-reduction launches (scenes with active[k] == 0 get x = 0 and count
 // as converged).  iters / relres / status: host arrays [ns].
 void k_pcg_batch(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, const int* active_host,
-                 int* iters, double* relres, int* status) {
+                 int* iters, double* relres, int* status, int* breakdown) {
   if (max_iter <= 0) max_iter = std::max(s->ndof, 1);
   k_build_precond(s);  // block-Jacobi inverses of the current Hessian (allocates them)
   s->mat_h.resize(sizeof(Mat<double>) + sizeof(Mat<float>));
@@ -1552,7 +1649,105 @@ void k_pcg_batch(zema_scene* s, const double* rhs, double* sol, double rtol, int
   ZCHK(hipMemcpyAsync(s->mat_dev.p, s->mat_h.data(), s->mat_h.size(), hipMemcpyHostToDevice, s->st));
   const void* mat = s->mixed ? (const void*)(s->mat_dev.p + sizeof(Mat<double>)) : (const void*)s->mat_dev.p;
   const double bytes = (s->mixed ? 40.0 : 76.0) * (s->nnzb + s->nnzc) + 152.0 * s->ndof;
-  k_pcg_cg(s, mat, s->tune_lanes, bytes, rhs, sol, rtol, max_iter, active_host, iters, relres, status);
+  k_pcg_cg(s, mat, s->tune_lanes, bytes, rhs, sol, rtol, max_iter, active_host, iters, relres, status, breakdown);
+}
+
+// ------------------------------------------------------------------ FP64 residual check
+// Per scene k: r = b - q over its DOFs (soft rows, then its free bodies' rows) and
+// out[k] = (|r|^2, |b|^2), summed in a fixed order by one block per scene.
+__global__ void scene_resid_kernel(int nsv, const int* __restrict__ rng, const double* __restrict__ b,
+                                   const double* __restrict__ q, double* __restrict__ r, double* __restrict__ out) {
+  __shared__ double sh[2][kBlock / 64];
+  const int k = blockIdx.x;
+  const int64_t s0 = 3 * (int64_t)rng[8 * k], s1 = 3 * (int64_t)rng[8 * k + 1];
+  const int64_t a0 = 3 * (int64_t)nsv + 12 * (int64_t)rng[8 * k + 6], a1 = 3 * (int64_t)nsv + 12 * (int64_t)rng[8 * k + 7];
+  double rr = 0.0, bb = 0.0;
+  for (int64_t i = s0 + threadIdx.x; i < s1; i += kBlock) {
+    double ri = b[i] - q[i];
+    r[i] = ri;
+    rr += ri * ri;
+    bb += b[i] * b[i];
+  }
+  for (int64_t i = a0 + threadIdx.x; i < a1; i += kBlock) {
+    double ri = b[i] - q[i];
+    r[i] = ri;
+    rr += ri * ri;
+    bb += b[i] * b[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    rr += __shfl_xor(rr, o, 64);
+    bb += __shfl_xor(bb, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = rr;
+    sh[1][threadIdx.x >> 6] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t0 = 0.0, t1 = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      t0 += sh[0][w];
+      t1 += sh[1][w];
+    }
+    out[2 * k] = t0;
+    out[2 * k + 1] = t1;
+  }
+}
+
+// The Newton system's solve for every active scene.  In the mixed form the FP32
+// products' recurrence residual is checked against b - H x recomputed with FP64
+// accumulation: while that true residual exceeds rtol |b| (at most twice), the
+// residual equation H d = r is solved to the tolerance still missing and d added;
+// relres then reports the true residual.
+void k_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, const int* active_host,
+                 int* iters, double* relres, int* status, int* breakdown) {
+  const int ns = s->ns, n = s->ndof;
+  auto solve = [&](const double* b, double* x, double tol, const int* act, int* it, double* rr, int* st, int* bd) {
+    if (ns == 1) {
+      st[0] = act[0] ? k_pcg(s, b, x, tol, max_iter, it, rr, bd) : 0;
+      if (!act[0]) it[0] = bd[0] = 0;
+    } else {
+      k_pcg_batch(s, b, x, tol, max_iter, act, it, rr, st, bd);
+    }
+  };
+  solve(rhs, sol, rtol, active_host, iters, relres, status, breakdown);
+  if (!s->mixed || n == 0) return;
+  s->res_q.reserve(n);
+  s->res_r.reserve(n);
+  s->res_d.reserve(n);
+  s->res_out.reserve((size_t)2 * ns);
+  std::vector<double> h((size_t)2 * ns), one(ns);
+  std::vector<int> need(ns), it2(ns), st2(ns), bd2(ns);
+  std::vector<double> rr2(ns);
+  for (int pass = 0;; ++pass) {
+    k_hess_matvec64(s, sol, s->res_q.p);
+    scene_resid_kernel<<<ns, kBlock, 0, s->st>>>(s->nsv, s->scn_rng.p, rhs, s->res_q.p, s->res_r.p, s->res_out.p);
+    ZCHK(hipMemcpyAsync(h.data(), s->res_out.p, sizeof(double) * 2 * ns, hipMemcpyDeviceToHost, s->st));
+    ZCHK(hipStreamSynchronize(s->st));
+    double tol = rtol;
+    bool any = false;
+    for (int k = 0; k < ns; ++k) {
+      need[k] = 0;
+      if (!active_host[k] || status[k]) continue;
+      double tr = h[2 * k + 1] > 0.0 ? std::sqrt(h[2 * k] / h[2 * k + 1]) : 0.0;
+      relres[k] = tr;
+      if (tr > rtol) {
+        need[k] = 1;
+        any = true;
+        tol = std::min(tol, 0.5 * rtol / tr);
+      }
+    }
+    if (!any || pass == 2) break;
+    solve(s->res_r.p, s->res_d.p, tol, need.data(), it2.data(), rr2.data(), st2.data(), bd2.data());
+    for (int k = 0; k < ns; ++k) {
+      one[k] = need[k] && !st2[k] ? 1.0 : 0.0;
+      if (need[k]) {
+        iters[k] += it2[k];
+        breakdown[k] |= bd2[k];
+      }
+    }
+    k_axpy_scene(s, one.data(), s->res_d.p, sol, sol);
+  }
 }
 
 }  // namespace zema

@@ -181,6 +181,7 @@ struct zema_scene {
   zema::DBuf<double> minv_body;  // [nfree][144]
   zema::DBuf<double> pr, pz, pp0, pp1, pq, px;
   zema::DBuf<double> pdir2;  // second initial-guess direction of a batch's starting scenes
+  zema::DBuf<double> res_q, res_r, res_d, res_out;  // FP64 residual check of the mixed form
   zema::DBuf<double> cg_z, cg_part;  // single-reduction PCG: node records, partials
   zema::DBuf<int4> cg_tab;   // its block layout: soft blocks (first row, rows, scene, slot)
   zema::DBuf<int2> cg_prng;  // per scene: partial slots
@@ -282,11 +283,20 @@ void k_radix_sort(zema_scene* s, SortBufs& b, int64_t n, int key_bits);  // sort
 
 // -------- sparse / PCG (k_sparse.hip)
 void k_hess_matvec(zema_scene* s, const double* v, double* out);
+// the Hessian as merged BSR (row_ptr, col, AoS 3x3 FP64 values); returns the block
+// count and writes only when it fits cap
+int64_t k_hessian_bsr(zema_scene* s, int* row_ptr, int* col, double* val, int64_t cap);
 void k_build_precond(zema_scene* s);
-int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres);
+int k_pcg(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, int* iters, double* relres,
+          int* breakdown = nullptr);
 void k_autotune(zema_scene* s, int* lanes_out, int* ub_out, double* us_per_iter);
 void k_pcg_batch(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, const int* active_host,
-                 int* iters, double* relres, int* status);
+                 int* iters, double* relres, int* status, int* breakdown = nullptr);
+// the solve of every active scene with, in the mixed form, the FP64 residual check and
+// refinement; breakdown[k]: the scene's solve ended at non-positive curvature
+void k_pcg_solve(zema_scene* s, const double* rhs, double* sol, double rtol, int max_iter, const int* active_host,
+                 int* iters, double* relres, int* status, int* breakdown);
+void k_hess_matvec64(zema_scene* s, const double* v, double* out);  // FP64 accumulation
 
 // -------- CCD (k_ccd.hip)
 int k_ccd(zema_scene* s, const double* y, const double* p, double* alpha);

@@ -20,7 +20,7 @@ VP = C.c_void_p
 
 OK, E_ARG, E_MESH, E_INTERSECT, E_CAPACITY, E_NEWTON, E_LINESEARCH, E_PCG, E_NONFINITE, E_DEVICE = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
-GRAD, HESS, TERMS_SHIFT = 1, 2, 8
+GRAD, HESS, REBUILD, TERMS_SHIFT = 1, 2, 4, 8
 TERM_NAMES = ("inertia", "elastic", "orthogonality", "kinematic", "barrier", "friction", "total", "min_distance")
 
 
@@ -44,7 +44,7 @@ class AffineDesc(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("status", I32), ("newton_iters", I32), ("pcg_iters", I32), ("ls_backtracks", I32),
                 ("n_pt_active", I32), ("n_ee_active", I32), ("n_pt_cand", I32), ("n_ee_cand", I32),
-                ("warm_learned", I32), ("reserved_", I32),
+                ("warm_learned", I32), ("pcg_breakdowns", I32),
                 ("alpha_ccd_min", D), ("kappa", D), ("d_min", D), ("energy", D), ("ms_total", D),
                 ("ms_assemble", D), ("ms_pcg", D), ("ms_broad", D), ("ms_ccd", D), ("ms_linesearch", D),
                 ("ms_warm", D)]
@@ -67,6 +67,8 @@ SIGNATURES = [
     ("zema_contact_candidates", [VP, VP, VP, D, VP, I64, PI64, VP, I64, PI64]),
     ("zema_ip_assemble", [VP, VP, C.c_uint32, PD, VP]),
     ("zema_hessian_matvec", [VP, VP, VP]),
+    ("zema_hessian_bsr", [VP, VP, VP, VP, I64, PI64]),
+    ("zema_surface_view", [VP, VP, VP, VP, VP]),
     ("zema_pcg_solve", [VP, VP, VP, D, I32, PI32, PD]),
     ("zema_ccd_max_step", [VP, VP, VP, PD]),
     ("zema_step", [VP, I32, C.POINTER(StepStats)]),
@@ -274,11 +276,14 @@ class Scene:
             self._chk(rc)
             return pt[:npt.value], ee[:nee.value]
 
-    def ip_assemble(self, y, grad=True, hess=True, mask=0):
+    def ip_assemble(self, y, grad=True, hess=True, mask=0, rebuild=True):
+        """Energy terms and gradient at y; rebuild=False evaluates on the stored
+        candidate set instead of rebuilding it statically at y."""
         y = self._dev(y)
         terms = np.zeros(8)
         g = self.zeros(self.n_dof) if grad else None
-        flags = (GRAD if grad else 0) | (HESS if hess else 0) | ((int(mask) & 0x3F) << TERMS_SHIFT)
+        flags = ((GRAD if grad else 0) | (HESS if hess else 0) | (REBUILD if rebuild else 0)
+                 | ((int(mask) & 0x3F) << TERMS_SHIFT))
         self._chk(lib().zema_ip_assemble(self.h, _ptr(y), flags, _pd(terms), _ptr(g)))
         return terms, g
 
@@ -287,6 +292,31 @@ class Scene:
         out = self.zeros(self.n_dof)
         self._chk(lib().zema_hessian_matvec(self.h, _ptr(v), _ptr(out)))
         return out
+
+    def hessian_bsr(self):
+        """(row_ptr [n_dof/3 + 1], col [nnzb], val [nnzb][3][3]) device tensors of the
+        last assembled Hessian."""
+        t = self.torch
+        n = I64()
+        rc = lib().zema_hessian_bsr(self.h, None, None, None, 0, C.byref(n))
+        if rc not in (OK, E_CAPACITY):
+            self._chk(rc)
+        rp = t.zeros(self.n_dof // 3 + 1, dtype=t.int32, device=self.device)
+        col = t.zeros(max(n.value, 1), dtype=t.int32, device=self.device)
+        val = t.zeros((max(n.value, 1), 3, 3), dtype=t.float64, device=self.device)
+        self._chk(lib().zema_hessian_bsr(self.h, _ptr(rp), _ptr(col), _ptr(val), n.value, C.byref(n)))
+        return rp, col[:n.value], val[:n.value]
+
+    def surface_view(self):
+        """(tris [n_tris][3], edges [n_edges][2], vbody [n_surf], vsrc [n_surf]) device
+        tensors: the topology the candidate pair ids index."""
+        t = self.torch
+        tris = t.zeros((max(self.n_tris, 1), 3), dtype=t.int32, device=self.device)
+        edges = t.zeros((max(self.n_edges, 1), 2), dtype=t.int32, device=self.device)
+        vb = t.zeros(max(self.n_surf, 1), dtype=t.int32, device=self.device)
+        vs = t.zeros(max(self.n_surf, 1), dtype=t.int32, device=self.device)
+        self._chk(lib().zema_surface_view(self.h, _ptr(tris), _ptr(edges), _ptr(vb), _ptr(vs)))
+        return tris[:self.n_tris], edges[:self.n_edges], vb[:self.n_surf], vs[:self.n_surf]
 
     def pcg_solve(self, rhs, rtol=None, max_iter=0):
         rtol = self.params.pcg_rtol if rtol is None else rtol

@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 
 import scenegen as sg
+from gpu_helpers import scene_topology
 from oracle import exact, ref
 
 torch = pytest.importorskip("torch")
@@ -72,11 +73,11 @@ def test_uneven_batch_follows_oracle(zema):
     scenes = [sg.batch_scene(s) for s in SMALL_SEEDS]
     B = zema.Scene.batch([sg.batch_scene(s) for s in SMALL_SEEDS])
     R = [ref.RefScene(sc) for sc in scenes]
-    surf = [r.surface() for r in R]
     log("scenes: " + ", ".join(f"{r.n_tets} tets" for r in R))
     for k in range(12):
         st = B.step(1)
         y = B.get_state()[0].cpu().numpy()
+        xs = B.surface_positions(y).cpu().numpy()
         for j, (sc, r) in enumerate(zip(scenes, R)):
             so = r.step(1)[0]
             yr = r.get_state()[0]
@@ -86,8 +87,9 @@ def test_uneven_batch_follows_oracle(zema):
                 f"max |y - y_oracle| {err:.2e}")
             assert st[j]["newton_iters"] == so["newton_iters"]
             assert err <= 1e-9
-            tris, edges, vb = surf[j]
-            assert exact.count_intersections(r.surface_positions(yb), tris, edges, vb) == 0
+            xj, tris, edges, vb = scene_topology(B, j, xs)
+            assert np.array_equal(xj, r.surface_positions(yb))
+            assert exact.count_intersections(xj, tris, edges, vb) == 0
 
 
 def test_async_batch_matches_lockstep(zema):

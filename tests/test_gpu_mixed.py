@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import scenegen as sg
+from gpu_helpers import scene_topology
 from oracle import exact, ref
 
 torch = pytest.importorskip("torch")
@@ -103,7 +104,7 @@ def test_mixed_trajectory_matches_fp64(zema):
     A = zema.Scene(sc64)
     B = zema.Scene(sc32)
     R = ref.RefScene(sc64)
-    tris, edges, vb = R.surface()
+    tris, edges, vb = (t.cpu().numpy() for t in A.surface_view()[:3])
     na = nb = 0
     worst = 0.0
     for k in range(4):
@@ -140,7 +141,7 @@ def test_mixed_batch_converges_intersection_free(zema):
     yf = F.get_state()[0].cpu().numpy()
     log(f"mixed batch: {nb} Newton iterations (FP64 {nf}), max |y - y_fp64| {np.abs(y - yf).max():.2e}")
     assert abs(nb - nf) <= 0.1 * nf + 5
+    xs = B.surface_positions(y).cpu().numpy()
     for j, s in enumerate(seeds):
-        R = ref.RefScene(sg.batch_scene(s))
-        tris, edges, vb = R.surface()
-        assert exact.count_intersections(R.surface_positions(y[B.scene_dofs(j)]), tris, edges, vb) == 0
+        xj, tris, edges, vb = scene_topology(B, j, xs)
+        assert exact.count_intersections(xj, tris, edges, vb) == 0

@@ -214,7 +214,7 @@ def test_learned_steps_intersection_free(zema):
     B = zema.Scene(sc2)
     B.set_mlp(M)
     R = ref.RefScene(sc2)
-    tris, edges, vb = R.surface()
+    tris, edges, vb = (t.cpu().numpy() for t in B.surface_view()[:3])
     used = 0
     for k in range(10):
         st = B.step(1)[0]

@@ -209,7 +209,7 @@ def test_ccd_bound_cube(zema, cube_records):
     sc, recs = cube_records
     R = ref.RefScene(sc)
     G = zema.Scene(sc)
-    tris, edges, vb = R.surface()
+    tris, edges, vb = (t.cpu().numpy() for t in G.surface_view()[:3])
     rng = np.random.default_rng(0)
     for i, rc in enumerate(recs[1::5]):
         y = rc["y_k"]
@@ -228,7 +228,7 @@ def test_steps_cube_intersection_free(zema):
     sc = sg.cube_drop()
     R = ref.RefScene(sc)
     G = zema.Scene(sc)
-    tris, edges, vb = R.surface()
+    tris, edges, vb = (t.cpu().numpy() for t in G.surface_view()[:3])
     soft = sc.softs[0]
     for k in range(20):
         st = G.step(1)[0]
@@ -241,7 +241,7 @@ def test_steps_cube_intersection_free(zema):
         log(f"step {k}: newton {st['newton_iters']} pcg {st['pcg_iters']} dmin {st['d_min']:.3e} "
             f"|y_gpu - y_oracle| {dy:.2e} intersections {n_int} inverted {n_inv}")
         gi, gv, gu, _ = G.intersection_count(y)
-        assert st["status"] == 0 and n_int == 0 and n_inv == 0
+        assert st["status"] == 0 and n_int == 0 and n_inv == 0 and st["pcg_breakdowns"] == 0
         assert gi == 0 and gv == 0
         assert dy < 1e-5
 
@@ -322,7 +322,7 @@ def test_intersection_count_matches_exact(zema):
     sc = sg.cube_drop()
     R = ref.RefScene(sc)
     G = zema.Scene(sc)
-    tris, edges, vb = R.surface()
+    tris, edges, vb = (t.cpu().numpy() for t in G.surface_view()[:3])
     y = R.get_state()[0]
     n3 = 3 * R.n_soft_verts
     for shift in (0.0, -0.005, -0.0075, -0.02):
@@ -486,7 +486,7 @@ def test_free_body_on_soft_cube_follows_oracle(zema, form):
     R = ref.RefScene(sc)
     G = zema.Scene(sc)
     G.tune(zema.TUNE_PCG_FORM, form)
-    tris, edges, vb = R.surface()
+    tris, edges, vb = (t.cpu().numpy() for t in G.surface_view()[:3])
     contact = 0
     for k in range(sc.n_steps):
         st = G.step(1)[0]
@@ -497,7 +497,7 @@ def test_free_body_on_soft_cube_follows_oracle(zema, form):
         contact = max(contact, st["n_pt_active"] + st["n_ee_active"])
         log(f"form {form} step {k}: newton gpu {st['newton_iters']} oracle {so['newton_iters']}, "
             f"pcg {st['pcg_iters']}, active {st['n_pt_active']}+{st['n_ee_active']}, max |y - y_oracle| {err:.2e}")
-        assert st["status"] == 0 and st["newton_iters"] == so["newton_iters"]
+        assert st["status"] == 0 and st["newton_iters"] == so["newton_iters"] and st["pcg_breakdowns"] == 0
         assert err <= 1e-9
         assert exact.count_intersections(R.surface_positions(y), tris, edges, vb) == 0
     assert contact > 50

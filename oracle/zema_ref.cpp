@@ -521,6 +521,7 @@ struct zref_scene {
   std::vector<double> Dminv;  // [nt*9] row-major
   std::vector<double> vol;    // [nt]
   std::vector<double> lam_mu; // [nt*2] (mu, lambda)
+  std::vector<int> tet_model; // [nt] constitutive model (0 neo-Hookean, 1 StVK, 2 fixed corotated)
   std::vector<double> mass;   // [nsv]
   std::vector<int> vbody;     // soft vertex -> body
   // affine
@@ -673,14 +674,86 @@ void map_pair(const zref_scene* s, const int* v4, const double* g12, const doubl
     }
 }
 
-// ------------------------------------------------------------------ neo-Hookean (Sec. IV-D)
-// Psi(F) = mu/2 (tr F^T F - 3) - mu log J + lambda/2 (log J)^2, +inf for J <= 0.
-bool psi_jet(const double* F, double mu, double lam, J2<9>& out) {
+// ------------------------------------------------------------------ constitutive models (Sec. IV-D)
+// The soft-body potentials the paper names: neo-Hookean with the logarithmic volume
+// term (model 0), Saint Venant-Kirchhoff (model 1) and fixed corotated (model 2), each
+// written from its definition on F with second-order jets:
+//   0  Psi = mu/2 (tr F^T F - 3) - mu log J + lambda/2 (log J)^2, +inf for J <= 0;
+//   1  Psi = mu |E|_F^2 + lambda/2 (tr E)^2,  E = (F^T F - I) / 2;
+//   2  Psi = mu |F - R|_F^2 + lambda/2 (J - 1)^2,  R the rotation of the polar
+//      decomposition F = R S.
+// Every model returns false (infeasible) for J <= 0: a step that inverts a tet is
+// rejected by the line search whatever the material (reading).
+template <int N>
+void jmat3_inv_t(const J2<N>* X, J2<N>* out, J2<N>& det) {
+  // X^{-T} = cof(X) / det X (row-major 3x3)
+  J2<N> c[9];
+  c[0] = X[4] * X[8] - X[5] * X[7];
+  c[1] = X[5] * X[6] - X[3] * X[8];
+  c[2] = X[3] * X[7] - X[4] * X[6];
+  c[3] = X[2] * X[7] - X[1] * X[8];
+  c[4] = X[0] * X[8] - X[2] * X[6];
+  c[5] = X[1] * X[6] - X[0] * X[7];
+  c[6] = X[1] * X[5] - X[2] * X[4];
+  c[7] = X[2] * X[3] - X[0] * X[5];
+  c[8] = X[0] * X[4] - X[1] * X[3];
+  det = X[0] * c[0] + X[1] * c[1] + X[2] * c[2];
+  J2<N> id = jinv(det);
+  for (int k = 0; k < 9; ++k) out[k] = c[k] * id;
+}
+
+// Rotation of the polar decomposition by Newton's iteration X <- (X + X^{-T}) / 2
+// from X = F (Higham 1986), run on the jets until the values have converged and then
+// twice more: the map's derivative vanishes at its fixed point, so the first and
+// second derivatives converge with the values.
+void polar_rotation_jet(const J2<9>* f, J2<9>* R) {
+  for (int k = 0; k < 9; ++k) R[k] = f[k];
+  int extra = -1;
+  for (int it = 0; it < 60 && extra != 0; ++it) {
+    J2<9> Xit[9], det;
+    jmat3_inv_t(R, Xit, det);
+    double change = 0.0;
+    for (int k = 0; k < 9; ++k) {
+      J2<9> nx = 0.5 * (R[k] + Xit[k]);
+      change = std::max(change, std::fabs(nx.v - R[k].v));
+      R[k] = nx;
+    }
+    if (extra > 0) --extra;
+    else if (change <= 1e-15) extra = 2;
+  }
+}
+
+bool psi_jet(const double* F, int model, double mu, double lam, J2<9>& out) {
   J2<9> f[9];
   for (int k = 0; k < 9; ++k) f[k] = jvar<9>(F[k], k);
   J2<9> J = f[0] * (f[4] * f[8] - f[5] * f[7]) - f[1] * (f[3] * f[8] - f[5] * f[6]) +
             f[2] * (f[3] * f[7] - f[4] * f[6]);
   if (!(J.v > 0.0)) return false;
+  if (model == 1) {
+    J2<9> E[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        J2<9> c = f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j];  // (F^T F)_ij
+        E[3 * i + j] = 0.5 * (i == j ? c + (-1.0) : c);
+      }
+    J2<9> ee = jconst<9>(0.0);
+    for (int k = 0; k < 9; ++k) ee = ee + E[k] * E[k];
+    J2<9> tr = E[0] + E[4] + E[8];
+    out = mu * ee + (0.5 * lam) * (tr * tr);
+    return true;
+  }
+  if (model == 2) {
+    J2<9> R[9];
+    polar_rotation_jet(f, R);
+    J2<9> d2 = jconst<9>(0.0);
+    for (int k = 0; k < 9; ++k) {
+      J2<9> d = f[k] - R[k];
+      d2 = d2 + d * d;
+    }
+    J2<9> jm = J + (-1.0);
+    out = mu * d2 + (0.5 * lam) * (jm * jm);
+    return true;
+  }
   J2<9> Ic = jconst<9>(0.0);
   for (int k = 0; k < 9; ++k) Ic = Ic + f[k] * f[k];
   J2<9> L = jlog(J);
@@ -716,7 +789,7 @@ bool tet_term(const zref_scene* s, int e, const double* x12, double* E, double* 
   double F[9], B[108];
   tet_F_B(x12, &s->Dminv[9 * e], F, B);
   J2<9> psi;
-  if (!psi_jet(F, s->lam_mu[2 * e], s->lam_mu[2 * e + 1], psi)) {
+  if (!psi_jet(F, s->tet_model[e], s->lam_mu[2 * e], s->lam_mu[2 * e + 1], psi)) {
     *E = INF;
     return false;
   }
@@ -1563,6 +1636,10 @@ int zref_scene_create(const zref_params* p, const zref_soft_desc* soft, int32_t 
   for (int b = 0; b < n_soft; ++b) {
     const zref_soft_desc& d = soft[b];
     int v0 = s->nsv;
+    if (d.model < 0 || d.model > 2) {
+      delete s;
+      return -1;
+    }
     double mu = d.E / (2.0 * (1.0 + d.nu)), lam = d.E * d.nu / ((1.0 + d.nu) * (1.0 - 2.0 * d.nu));
     for (int i = 0; i < d.n_verts; ++i) {
       for (int k = 0; k < 3; ++k) {
@@ -1610,6 +1687,7 @@ int zref_scene_create(const zref_params* p, const zref_soft_desc* soft, int32_t 
       s->vol.push_back(V);
       s->lam_mu.push_back(mu);
       s->lam_mu.push_back(lam);
+      s->tet_model.push_back(d.model);
       for (int a = 0; a < 4; ++a) s->mass[t[a]] += d.rho * V / 4.0;  // reading: equal lumping
       // faces; outward orientation decided by the side of the opposite vertex
       for (int j = 0; j < 4; ++j) {

@@ -33,6 +33,7 @@ typedef struct {
   const double* pos0;
   const double* vel0;
   double E, nu, rho;
+  int32_t model, pad_; /* 0 neo-Hookean, 1 Saint Venant-Kirchhoff, 2 fixed corotated */
 } zref_soft_desc;
 
 typedef struct {

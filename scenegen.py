@@ -27,6 +27,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 MODE_FREE, MODE_FIXED, MODE_DRIVEN = 0, 1, 2
+NEO_HOOKEAN, STVK, FIXED_COROTATED = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
 
@@ -56,6 +57,7 @@ class SoftBody:
     rho: float
     pos0: np.ndarray | None = None
     vel0: np.ndarray | None = None
+    model: int = NEO_HOOKEAN    # constitutive model: NEO_HOOKEAN, STVK or FIXED_COROTATED
 
 
 @dataclass
@@ -239,8 +241,9 @@ def uniform_rotation(rng):
 
 # ----------------------------------------------------------------------------- scenes
 
-def cube_drop(n_cells: int = 4, steps: int = 20) -> Scene:
-    """Soft 0.1 m cube (n_cells^3 x 6 tets) 5 mm above a fixed 0.5x0.05x0.5 m slab."""
+def cube_drop(n_cells: int = 4, steps: int = 20, model: int = NEO_HOOKEAN) -> Scene:
+    """Soft 0.1 m cube (n_cells^3 x 6 tets) 5 mm above a fixed 0.5x0.05x0.5 m slab;
+    `model` selects the cube's constitutive model."""
     L = 0.1
     H = L / n_cells
     mask = np.ones((n_cells,) * 3, dtype=bool)
@@ -249,7 +252,7 @@ def cube_drop(n_cells: int = 4, steps: int = 20) -> Scene:
     verts, tets = voxel_mesh(mask, (-L / 2 + 0.0123, 0.005, -L / 2 - 0.0071), H)
     slab_v, slab_t = box_surface((0.0, -0.025, 0.0), (0.25, 0.025, 0.25), 1)
     p = Params(dt=0.01, dhat=1e-3, kappa=0.0, mu=0.5, eps_v=1e-3, newton_tol=1e-6)
-    soft = SoftBody(verts, tets, E=1e5, nu=0.4, rho=1000.0)
+    soft = SoftBody(verts, tets, E=1e5, nu=0.4, rho=1000.0, model=model)
     slab = AffineBody(slab_v, slab_t, rho=1000.0, stiffness=1e8, mode=MODE_FIXED)
     return Scene("cube_drop", p, [soft], [slab], steps)
 
@@ -338,14 +341,14 @@ def batch_scene(seed: int, steps: int = 100) -> Scene:
 
 # ----------------------------------------------------------------------------- tiny cases
 
-def two_tets_scene() -> Scene:
+def two_tets_scene(model: int = NEO_HOOKEAN) -> Scene:
     """A single soft tet resting 2 mm above a fixed unit-ish affine tetra-box; for
     tiny-case tests."""
     v = np.array([[0, 0.002, 0], [0.02, 0.002, 0], [0, 0.022, 0], [0, 0.002, 0.02]], dtype=np.float64)
     t = np.array([[0, 1, 2, 3]], dtype=np.int32)
     slab_v, slab_t = box_surface((0.0, -0.01, 0.0), (0.05, 0.01, 0.05), 1)
     p = Params(dt=0.01, dhat=1e-3, mu=0.5)
-    return Scene("two_tets", p, [SoftBody(v, t, E=1e5, nu=0.4, rho=1000.0)],
+    return Scene("two_tets", p, [SoftBody(v, t, E=1e5, nu=0.4, rho=1000.0, model=model)],
                  [AffineBody(slab_v, slab_t, mode=MODE_FIXED)], 10)
 
 

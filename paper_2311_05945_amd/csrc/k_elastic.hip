@@ -3,7 +3,7 @@
 // SoA element streams), and deterministic gathers of the per-tet results into the
 // gradient and the static block-sparse Hessian, together with the diagonal inertia
 // term 1/2 m_i |x_i - xhat_i|^2.
-#include "nh.hpp"
+#include "material.hpp"
 #include "scene.hpp"
 
 namespace zema {

@@ -88,7 +88,9 @@ def test_uneven_batch_follows_oracle(zema):
             assert st[j]["newton_iters"] == so["newton_iters"]
             assert err <= 1e-9
             xj, tris, edges, vb = scene_topology(B, j, xs)
-            assert np.array_equal(xj, r.surface_positions(yb))
+            # the same surface vertices in the same order (the affine rest frames of the
+            # two implementations may differ in the last bit of the centre of mass)
+            assert np.abs(xj - r.surface_positions(yb)).max() <= 1e-12
             assert exact.count_intersections(xj, tris, edges, vb) == 0
 
 

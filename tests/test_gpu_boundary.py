@@ -53,11 +53,15 @@ def check_bsr(G, hv, n_dof, rng, ctx):
     rpn, cn = rp.cpu().numpy(), col.cpu().numpy()
     for r in range(n):                                  # ascending columns within each row
         assert np.all(np.diff(cn[rpn[r]:rpn[r + 1]]) > 0)
-    # symmetric: block (r, c) is the transpose of block (c, r)
+    # symmetric: block (r, c) is the transpose of block (c, r), up to the rounding of
+    # entries (i, j) and (j, i) of a local block formed in different orders
     keys = {(r, c): k for r in range(n) for k, c in zip(range(rpn[r], rpn[r + 1]), cn[rpn[r]:rpn[r + 1]])}
-    vn = val.cpu().numpy()
+    vn = val.cpu().numpy().astype(np.float64)
+    big = np.abs(vn).max()
+    eps = np.finfo(val.cpu().numpy().dtype).eps
     for (r, c), k in list(keys.items())[::7]:
-        assert (c, r) in keys and np.array_equal(vn[k], vn[keys[(c, r)]].T)
+        assert (c, r) in keys
+        assert np.abs(vn[k] - vn[keys[(c, r)]].T).max() <= 64 * eps * big, (r, c)
     worst = 0.0
     for _ in range(3):
         v = rng.normal(size=n_dof)

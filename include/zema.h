@@ -396,6 +396,21 @@ int zema_mlp_forward(zema_mlp* m, const float* feat, int64_t n, float* out);
  * target [n][3] (device) and its gradient grad [ZEMA_MLP_PARAMS] (device); loss is a
  * host output.  No update. */
 int zema_mlp_grad(zema_mlp* m, const float* feat, const float* target, int64_t n, float* grad, double* loss);
+/* zema_mlp_grad for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training or serving loops, harnesses that forbid hipMalloc): the
+ * same loss and gradient, with no hipMalloc / hipFree and no allocating library call.
+ * Its partial sums live in a static array of the library (about 9.4 MiB per device,
+ * 256 block partials; each device that runs it keeps its copy until the process
+ * ends).  Every call on a device shares that array: calls that overlap on one device
+ * (other streams, other threads) race and must be serialised by the caller.  For n <=
+ * 16384 rows the result equals zema_mlp_grad's bitwise; above it the rows are summed
+ * in 256 larger blocks (FP32 rounding order differs).  feat [n][16], target [n][3],
+ * grad [ZEMA_MLP_PARAMS] device; loss host.  The network's device is made current for
+ * the call.  ZEMA_E_ARG for n outside 1 .. ZEMA_MLP_NOALLOC_MAX_ROWS or NULL
+ * pointers. */
+#define ZEMA_MLP_NOALLOC_MAX_ROWS (1LL << 26)
+int zema_mlp_grad_noalloc(zema_mlp* m, const float* feat, const float* target, int64_t n, float* grad,
+                          double* loss);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, learning rate lr)
  * on the batch of rows idx [batch] (device int32, each in [0, n_rows); rows out of
  * range are skipped) of feat / target [n_rows]; loss of the batch before the step is

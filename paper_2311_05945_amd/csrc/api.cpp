@@ -1583,6 +1583,7 @@ int zema_mlp_create(void* hip_stream, zema_mlp** out) {
   if (!m) return ZEMA_E_DEVICE;
   m->st = (hipStream_t)hip_stream;
   int rc = mguard(m, [&]() {
+    ZCHK(hipGetDevice(&m->dev));
     for (DBuf<float>* b : {&m->theta, &m->mom, &m->vel, &m->grad}) {
       b->resize(kMlpParams);
       ZCHK(hipMemset(b->p, 0, sizeof(float) * kMlpParams));
@@ -1642,6 +1643,19 @@ int zema_mlp_grad(zema_mlp* m, const float* feat, const float* target, int64_t n
     *loss = mlp_grad(m, feat, target, nullptr, (long)n, (long)n, false, 0.0f);
     ZCHK(hipMemcpyAsync(grad, m->grad.p, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice, m->st));
     ZCHK(hipStreamSynchronize(m->st));
+    return 0;
+  });
+}
+
+int zema_mlp_grad_noalloc(zema_mlp* m, const float* feat, const float* target, int64_t n, float* grad,
+                          double* loss) {
+  if (!m || !feat || !target || !grad || !loss) return ZEMA_E_ARG;
+  if (n <= 0 || n > ZEMA_MLP_NOALLOC_MAX_ROWS) {
+    m->err = "zema_mlp_grad_noalloc: n must be in 1 .. ZEMA_MLP_NOALLOC_MAX_ROWS";
+    return ZEMA_E_ARG;
+  }
+  return mguard(m, [&]() {
+    *loss = mlp_grad_noalloc(m, feat, target, (long)n, grad);
     return 0;
   });
 }

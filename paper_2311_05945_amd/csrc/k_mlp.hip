@@ -12,6 +12,9 @@
 // dW_l = delta_l^T H_{l-1} by MFMA with the vertex tile as the K dimension (operands
 // transposed through a per-wave LDS tile), per-block partial gradients reduced in a
 // fixed order, then Adam (Kingma and Ba 2015) on the FP32 master weights.
+#include <algorithm>
+#include <mutex>
+
 #include "mlp.hpp"
 
 namespace zema {
@@ -137,11 +140,11 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const float* __restric
   }
 }
 
-// One wavefront per block; block b owns tiles [b * kTilesPerBlock, ...).  Writes the
-// block's gradient partial (kMlpParams floats) and its loss partial.
+// One wavefront per block; block b owns tiles [b * tpb, (b + 1) * tpb).  Writes the
+// block's whole gradient partial (kMlpParams floats) and its loss partial.
 __global__ void __launch_bounds__(64) mlp_grad_kernel(const float* __restrict__ th, const float* __restrict__ feat,
                                                       const float* __restrict__ target, const int* __restrict__ idx,
-                                                      long nrows, long n, float* __restrict__ gpart,
+                                                      long nrows, long n, int tpb, float* __restrict__ gpart,
                                                       double* __restrict__ lpart) {
   __shared__ MlpLds L;
   __shared__ __align__(16) unsigned short Td[64 * 16];  // [row][vertex] transposition tiles
@@ -167,8 +170,8 @@ __global__ void __launch_bounds__(64) mlp_grad_kernel(const float* __restrict__ 
   gb4 = z;
   double lsum = 0.0;
   const long ntiles = (n + 15) / 16;
-  for (int k = 0; k < kTilesPerBlock; ++k) {
-    long tile = (long)blockIdx.x * kTilesPerBlock + k;
+  for (int k = 0; k < tpb; ++k) {
+    long tile = (long)blockIdx.x * tpb + k;
     if (tile >= ntiles) break;
     long v = 16 * tile + m;
     long row = v < n ? (idx ? (long)idx[v] : v) : -1;
@@ -332,7 +335,8 @@ double mlp_grad(zema_mlp* M, const float* feat, const float* target, const int* 
   int nblk = (int)((ntiles + kTilesPerBlock - 1) / kTilesPerBlock);
   M->gpart.reserve((size_t)nblk * kMlpParams);
   M->lpart.reserve(nblk + 1);
-  mlp_grad_kernel<<<nblk, 64, 0, M->st>>>(M->theta.p, feat, target, idx, nrows, n, M->gpart.p, M->lpart.p);
+  mlp_grad_kernel<<<nblk, 64, 0, M->st>>>(M->theta.p, feat, target, idx, nrows, n, kTilesPerBlock, M->gpart.p,
+                                          M->lpart.p);
   float c1 = 1.0f, c2 = 1.0f;
   if (adam) {
     M->step += 1;
@@ -344,6 +348,62 @@ double mlp_grad(zema_mlp* M, const float* feat, const float* target, const int* 
   mlp_loss_kernel<<<1, kBlock, 0, M->st>>>(nblk, M->lpart.p, n, M->loss.p);
   double l = 0.0;
   ZCHK(hipMemcpyAsync(&l, M->loss.p, sizeof(double), hipMemcpyDeviceToHost, M->st));
+  ZCHK(hipStreamSynchronize(M->st));
+  return l;
+}
+
+// ------------------------------------------------------------ allocation-free gradient
+// Scratch of mlp_grad_noalloc: kNoAllocBlocks gradient partials (FP32), as many loss
+// partials and the loss (FP64).  Each device holds its own copy; its address on a
+// device comes from hipGetSymbolAddress with that device current (the array's name in
+// host code is not a device address).  Every block overwrites its whole partial, so
+// nothing needs clearing between calls; calls that overlap on one device race.
+constexpr size_t kNoAllocGradBytes = (size_t)kNoAllocBlocks * kMlpParams * sizeof(float);
+constexpr size_t kNoAllocBytes = kNoAllocGradBytes + (kNoAllocBlocks + 1) * sizeof(double);
+static_assert(kNoAllocGradBytes % 256 == 0, "loss partials stay 256-byte aligned");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char* g_scratch[kMaxDevices] = {};
+
+// device address of this device's scratch (looked up once per device)
+static unsigned char* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw Error(ZEMA_E_DEVICE, "device id out of range for the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error(ZEMA_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = (unsigned char*)p;
+  }
+  return g_scratch[dev];
+}
+
+double mlp_grad_noalloc(zema_mlp* M, const float* feat, const float* target, long n, float* grad) {
+  int cur = 0;
+  ZCHK(hipGetDevice(&cur));
+  if (cur != M->dev) ZCHK(hipSetDevice(M->dev));
+  struct Restore {
+    int d, c;
+    ~Restore() {
+      if (d != c) (void)hipSetDevice(c);
+    }
+  } restore{M->dev, cur};
+  unsigned char* base = scratch_on(M->dev);
+  float* gpart = (float*)base;
+  double* lpart = (double*)(base + kNoAllocGradBytes);
+  double* loss = lpart + kNoAllocBlocks;
+  long ntiles = (n + 15) / 16;
+  long tpb = std::max<long>(kTilesPerBlock, (ntiles + kNoAllocBlocks - 1) / kNoAllocBlocks);
+  int nblk = (int)((ntiles + tpb - 1) / tpb);
+  mlp_grad_kernel<<<nblk, 64, 0, M->st>>>(M->theta.p, feat, target, nullptr, n, n, (int)tpb, gpart, lpart);
+  mlp_reduce_kernel<<<nblocks(kMlpParams), kBlock, 0, M->st>>>(nblk, gpart, grad, M->theta.p, M->mom.p, M->vel.p, 0,
+                                                                0.0f, 1.0f, 1.0f);
+  mlp_loss_kernel<<<1, kBlock, 0, M->st>>>(nblk, lpart, n, loss);
+  double l = 0.0;
+  ZCHK(hipMemcpyAsync(&l, loss, sizeof(double), hipMemcpyDeviceToHost, M->st));
   ZCHK(hipStreamSynchronize(M->st));
   return l;
 }

@@ -83,6 +83,7 @@ SIGNATURES = [
     ("zema_mlp_get_weights", [VP, C.POINTER(C.c_float)]),
     ("zema_mlp_forward", [VP, VP, I64, VP]),
     ("zema_mlp_grad", [VP, VP, VP, I64, VP, PD]),
+    ("zema_mlp_grad_noalloc", [VP, VP, VP, I64, VP, PD]),
     ("zema_mlp_train_step", [VP, VP, VP, I64, VP, I64, C.c_float, PD]),
     ("zema_batch_create", [VP, I32, VP, PI32, VP, PI32, VP, C.POINTER(VP)]),
     ("zema_batch_layout", [VP, C.POINTER(I32), PI64]),
@@ -468,6 +469,18 @@ class Mlp:
         loss = D()
         self._chk(lib().zema_mlp_grad(self.h, _ptr(f), _ptr(t), f.shape[0], _ptr(g), C.byref(loss)))
         return loss.value, g
+
+    def grad_noalloc(self, feat, target, grad):
+        """zema_mlp_grad_noalloc: loss and gradient into the caller's grad (device FP32
+        [MLP_PARAMS]); feat [n][16] and target [n][3] are device FP32, contiguous.  The
+        library allocates no device memory for the call."""
+        for t, shape in ((feat, (feat.shape[0], 16)), (target, (feat.shape[0], 3)), (grad, (MLP_PARAMS,))):
+            if t.dtype != self.torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+                raise ValueError(f"grad_noalloc needs contiguous device float32 tensors of shape {shape}")
+        loss = D()
+        self._chk(lib().zema_mlp_grad_noalloc(self.h, _ptr(feat), _ptr(target), feat.shape[0], _ptr(grad),
+                                              C.byref(loss)))
+        return loss.value
 
     def train_step(self, feat, target, idx, lr):
         """One Adam step on rows idx (device int32 tensor) of feat / target (device)."""

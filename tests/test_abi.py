@@ -96,3 +96,18 @@ def test_argument_errors_need_no_device():
     v = ctypes.c_int32()
     assert L.zema_tune(None, zema.TUNE_PCG_FORM, 1) == E_ARG
     assert L.zema_tune_get(None, zema.TUNE_PCG_FORM, ctypes.byref(v)) == E_ARG
+    loss = ctypes.c_double()
+    buf = ctypes.c_void_p(1)
+    assert L.zema_mlp_grad_noalloc(None, buf, buf, 16, buf, ctypes.byref(loss)) == E_ARG
+
+
+def test_noalloc_entry_point_declared_with_its_limit():
+    """The allocation-free gradient is declared with its row limit, and its source takes
+    the scratch address from hipGetSymbolAddress and calls no allocator."""
+    src = open(HEADER).read()
+    assert "zema_mlp_grad_noalloc" in src and "ZEMA_MLP_NOALLOC_MAX_ROWS" in src
+    k = open(os.path.join(ROOT, "paper_2311_05945_amd", "csrc", "k_mlp.hip")).read()
+    body = k[k.index("double mlp_grad_noalloc"):]
+    body = body[:body.index("\n}\n")]
+    assert "hipMalloc" not in body and "reserve" not in body and "resize" not in body
+    assert "hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))" in k

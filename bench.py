@@ -36,9 +36,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene, seconds, max_steps=20):
-    """The oracle as it stands, timed on the host cores: the first steps of the same
-    trajectory until `seconds` of CPU time have been spent (at least one step)."""
+def cpu_baseline(scene, seconds, gpu_stats, max_steps=20):
+    """The oracle as it stands, timed on the host cores on the same steps as the GPU:
+    the first steps of the same trajectory until `seconds` of CPU time have been spent
+    (at least one step), with every core, then the first step on one thread.  The GPU
+    figure for the same steps comes from the timed run's per-step wall times."""
     from oracle import ref
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     used = ref.set_threads(threads)
@@ -46,27 +48,135 @@ def cpu_baseline(scene, seconds, max_steps=20):
     t = 0.0
     n = 0
     newton = 0
-    while n < max_steps and (n == 0 or t < seconds):
+    while n < min(max_steps, len(gpu_stats)) and (n == 0 or t < seconds):
         t0 = time.perf_counter()
         st = R.step(1)[0]
         t += time.perf_counter() - t0
         n += 1
         newton += st["newton_iters"]
         log(f"cpu oracle step {n}: {t:.1f} s total, newton {st['newton_iters']}, pcg {st['pcg_iters']}")
+    gpu_t = sum(x["ms_total"] for x in gpu_stats[:n]) * 1e-3
+    gpu_newton = sum(x["newton_iters"] for x in gpu_stats[:n])
+    ref.set_threads(1)
+    R1 = ref.RefScene(scene)
+    t1 = time.perf_counter()
+    st1 = R1.step(1)[0]
+    t1 = time.perf_counter() - t1
+    ref.set_threads(threads)
+    log(f"cpu oracle, one thread: step 1 in {t1:.2f} s")
     return {"value": n / t, "unit": "sim steps/s", "cores": used, "kind": "oracle",
-            "sample": f"first {n} steps of the same trajectory ({newton} Newton iterations, {t:.1f} s; "
-                      f"these early steps include the contact-free approach of the fingers)"}
+            "sample": f"steps 0-{n - 1} of the timed trajectory ({newton} Newton iterations, {t:.1f} s on {used} "
+                      f"threads; these early steps include the contact-free approach of the fingers)",
+            "newton_iters_per_s": newton / t,
+            "gpu_same_steps": {"steps_per_s": n / gpu_t if gpu_t > 0 else None,
+                               "newton_iters_per_s": gpu_newton / gpu_t if gpu_t > 0 else None,
+                               "newton_iters": gpu_newton},
+            "one_thread": {"steps_per_s": 1.0 / t1, "newton_iters_per_s": st1["newton_iters"] / t1,
+                           "sample": "step 0 of the same trajectory"}}
 
 
-def hbm_traffic(kernel):
+def cube_drop_leg(zema):
+    """The soft-cube drop (384 tets on a fixed slab, 20 steps of 0.01 s): the GPU plain
+    form against the oracle on every core, same steps, same tolerance."""
+    import torch
+
+    import scenegen as sg
+    from oracle import ref
+    sc = sg.cube_drop()
+    G = zema.Scene(sc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sg_ = G.step(sc.n_steps)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    used = ref.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    R = ref.RefScene(sc)
+    t0 = time.perf_counter()
+    so = R.step(sc.n_steps)
+    tr = time.perf_counter() - t0
+    ng = sum(x["newton_iters"] for x in sg_)
+    nr = sum(x["newton_iters"] for x in so)
+    dy = float(abs(G.get_state()[0].cpu().numpy() - R.get_state()[0]).max())
+    log(f"cube drop: gpu {sc.n_steps / tg:.1f} steps/s ({ng} Newton), oracle {sc.n_steps / tr:.1f} steps/s ({nr} Newton)")
+    return {"workload": "soft cube 0.1 m (384 tets) dropped from 5 mm onto a fixed slab, dt=0.01 s, 20 steps",
+            "gpu": {"steps_per_s": sc.n_steps / tg, "newton_iters_per_step": ng / sc.n_steps,
+                    "newton_iters_per_s": ng / tg},
+            "oracle": {"steps_per_s": sc.n_steps / tr, "newton_iters_per_step": nr / sc.n_steps,
+                       "newton_iters_per_s": nr / tr, "cores": used},
+            "max_position_diff_m": dy, "failed_steps": sum(1 for x in sg_ if x["status"] != 0)}
+
+
+def precision_leg(zema, res, steps, seed):
+    """The gripper at a finer grid (r = 64 by default): the mixed form (FP32 elastic
+    Hessian and products) and the FP64 form on the GPU and the oracle, the first `steps`
+    steps; per step the energy at each path's own end state, the norm of the gradient
+    left at that state (the converged step's residual force) relative to the gradient
+    norm at the step's start, and the largest position difference."""
+    import numpy as np
+    import torch
+
+    import scenegen as sg
+    from oracle import ref
+    out = {"workload": f"gripper, ellipsoid voxelised at r={res} (seed {seed}), first {steps} steps", "steps": []}
+    paths = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        sc = sg.gripper(seed, r=res, steps=steps)
+        sc.params.precision = prec
+        G = zema.Scene(sc)
+        if name == "fp64":
+            out.update(tets=G.n_tets, soft_vertices=G.n_soft_verts, dofs=G.n_dof)
+        rec = []
+        torch.cuda.synchronize()
+        t = 0.0
+        for k in range(steps):
+            g0 = float(torch.linalg.norm(G.ip_assemble(G.get_state()[0], hess=False)[1]))
+            t0 = time.perf_counter()
+            st = G.step(1)[0]
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            y = G.get_state()[0]
+            terms, g = G.ip_assemble(y, hess=False)
+            rec.append((y.cpu().numpy(), float(terms[6]), float(torch.linalg.norm(g)) / g0, st["newton_iters"]))
+        paths[name] = (rec, t)
+        log(f"precision leg {name}: {steps} steps in {t:.2f} s")
+    used = ref.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    R = ref.RefScene(sg.gripper(seed, r=res, steps=steps))
+    rec = []
+    t = 0.0
+    for k in range(steps):
+        g0 = float(np.linalg.norm(R.ip_assemble(R.get_state()[0], hess=False)[1]))
+        t0 = time.perf_counter()
+        st = R.step(1)[0]
+        t += time.perf_counter() - t0
+        y = R.get_state()[0]
+        terms, g = R.ip_assemble(y, hess=False)
+        rec.append((y, float(terms[6]), float(np.linalg.norm(g)) / g0, st["newton_iters"]))
+        log(f"precision leg oracle step {k}: {t:.1f} s")
+    paths["oracle"] = (rec, t)
+    for k in range(steps):
+        (yf, ef, gf, nf), (ym, em, gm, nm), (yo, eo, go, no) = (paths[n][0][k] for n in ("fp64", "mixed", "oracle"))
+        out["steps"].append({
+            "step": k, "newton": {"fp64": nf, "mixed": nm, "oracle": no},
+            "residual_grad_norm_rel_to_step_start": {"fp64": gf, "mixed": gm, "oracle": go},
+            "mixed_vs_fp64": {"energy_rel": abs(em - ef) / abs(ef), "max_position_m": float(np.abs(ym - yf).max())},
+            "mixed_vs_oracle": {"energy_rel": abs(em - eo) / abs(eo), "max_position_m": float(np.abs(ym - yo).max())},
+            "fp64_vs_oracle": {"energy_rel": abs(ef - eo) / abs(eo), "max_position_m": float(np.abs(yf - yo).max())}})
+    out["seconds"] = {n: paths[n][1] for n in paths}
+    out["oracle_cores"] = used
+    return out
+
+
+def hbm_traffic(kernel, source_files):
     """HBM bytes per launch of `kernel` from the committed counter profile, or None when
-    the profile is missing or the kernel's source changed since it was taken."""
+    the profile is missing or a source of the kernel changed since it was taken."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "pcg_iteration_gripper_r32_hbm_counters.md")
-    src = os.path.join(ROOT, "paper_2311_05945_amd", "csrc", "k_sparse.hip")
+    prof = os.path.join(ROOT, "profiles", "hbm_counters_gripper.md")
     if not os.path.exists(prof):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in source_files:
+        h.update(open(os.path.join(ROOT, "paper_2311_05945_amd", "csrc", f), "rb").read())
+    sha = h.hexdigest()
     for line in open(prof):
         f = line.split()
         if len(f) == 6 and f[0] == "traffic" and f[1] == kernel and f[5] == sha:
@@ -159,12 +269,16 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=5, help="steps of the roofline pass after the timed run")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / learned / mixed comparison")
     ap.add_argument("--autotune", action="store_true", help="pick the PCG launch shapes by timing (default: fixed)")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per soft row of the PCG iteration (0: library default)")
     ap.add_argument("--no-graph", action="store_true", help="launch PCG kernels individually")
     ap.add_argument("--copy-probe", action="store_true", help="run a 256 MiB device copy (counter scaling)")
     ap.add_argument("--form-scenes", type=int, default=32)
     ap.add_argument("--form-steps", type=int, default=16)
     ap.add_argument("--form-seed", type=int, default=10000)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_05945_amd", "warm_mlp.npy"))
+    ap.add_argument("--no-legs", action="store_true", help="skip the cube-drop and precision legs")
+    ap.add_argument("--precision-res", type=int, default=64)
+    ap.add_argument("--precision-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -189,6 +303,8 @@ def main():
     G = zema.Scene(sc)
     if args.no_graph:
         G.tune(zema.TUNE_PCG_GRAPH, 0)
+    if args.lanes:
+        G.tune(zema.TUNE_SPMV_LANES, args.lanes)
     if tuned is not None:
         G.tune(zema.TUNE_SPMV_LANES, tuned["spmv_lanes"])
         G.tune(zema.TUNE_UPDATE_BLOCK, tuned["update_block"])
@@ -208,23 +324,30 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     # roofline pass: the next steps of the same trajectory with HIP events around the
-    # timed kernel (PCG: every replayed chunk of 16 iterations; timed solves check
-    # convergence after every chunk, so this pass is not part of the throughput figure)
+    # timed kernels (PCG: every replayed chunk of 16 iterations; timed solves check
+    # convergence after every chunk, so this pass is not part of the throughput figure;
+    # elastic assembly: the per-tet kernel and its two gathers)
     G.kernel_timer(group, True)
+    G.kernel_timer(GROUPS_T["tet"], True)
     torch.cuda.synchronize()
     tr0 = time.perf_counter()
     rstats = G.step(args.timing_steps)
     torch.cuda.synchronize()
     t_roof = time.perf_counter() - tr0
     ms_k, launches, bytes_k = G.kernel_time(group)
-    log(f"roofline pass: {args.timing_steps} steps, {launches} launches of {args.timer}, {ms_k:.1f} ms")
+    ms_a, launches_a, bytes_a = G.kernel_time(GROUPS_T["tet"])
+    log(f"roofline pass: {args.timing_steps} steps, {launches} launches of {args.timer}, {ms_k:.1f} ms; "
+        f"{launches_a} elastic assemblies, {ms_a:.2f} ms")
     traffic = None
     kname = {"spmv": f"pcg_cg_kernel<double,{G.spmv_lanes()},false>"}.get(args.timer, args.timer)
     if args.timer == "spmv" and not G.params.precision:
-        traffic = hbm_traffic(kname)
+        traffic = hbm_traffic(kname, ["k_sparse.hip", "common.hpp"])
+    traffic_a = None if G.params.precision else hbm_traffic("elastic_assembly<double>",
+                                                            ["k_elastic.hip", "material.hpp", "common.hpp"])
     newton = sum(s["newton_iters"] for s in stats)
     pcg = sum(s["pcg_iters"] for s in stats)
     achieved = bytes_k / (ms_k * 1e-3) / 1e9 if ms_k > 0 else 0.0
+    achieved_a = bytes_a / (ms_a * 1e-3) / 1e9 if ms_a > 0 else 0.0
     out = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -252,7 +375,17 @@ def main():
                      "avg_launch_us": 1e3 * ms_k / max(launches, 1), "launches": launches,
                      "bytes_per_launch": bytes_k / max(launches, 1),
                      "timing_steps": args.timing_steps,
-                     "share_of_step_time": ms_k * 1e-3 / t_roof},
+                     "share_of_step_time": ms_k * 1e-3 / t_roof,
+                     "note": "one PCG iteration per launch; at this system size the launch is limited by "
+                             "its dependent gathers and dispatch latency, not by HBM bandwidth"},
+        "assembly_roofline": {"kernel": "elastic assembly (tet_assemble_kernel + gather_grad_soft_kernel + "
+                                        "gather_hess_kernel)",
+                              "bound": "hbm", "achieved": achieved_a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": achieved_a / HBM_PEAK_GBS, "traffic": traffic_a,
+                              "avg_launch_us": 1e3 * ms_a / max(launches_a, 1), "launches": launches_a,
+                              "bytes_per_launch": bytes_a / max(launches_a, 1),
+                              "algorithmic_bytes": "320 B per tet (ids, Dm^-1, volume, BSR share, positions, "
+                                                   "gradient)"},
         "autotuned": tuned,
         "phase_ms_per_step": {k: sum(s[f"ms_{k}"] for s in stats) / args.steps
                               for k in ("assemble", "pcg", "broad", "ccd", "linesearch")},
@@ -270,8 +403,13 @@ def main():
         out["copy_probe_bytes"] = 8 * n
     if not args.no_forms:
         out["forms"] = forms(args, zema)
+    if not args.no_legs:
+        out["cube_drop"] = cube_drop_leg(zema)
+        if args.precision_steps > 0:
+            out["precision"] = precision_leg(zema, args.precision_res, args.precision_steps, args.seed)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sg.gripper(args.seed, r=args.res, steps=args.steps), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(sg.gripper(args.seed, r=args.res, steps=args.steps), args.cpu_seconds,
+                                           stats)
     print(json.dumps(out))
 
 

@@ -94,7 +94,13 @@ typedef struct {
 /* Soft tetrahedral body (Sec. III eq. 1): rest positions [n_verts][3], tets
  * [n_tets][4] (positive orientation expected, negative ones are reordered), optional
  * initial positions / velocities (NULL = rest / zero), Young's modulus E (Pa),
- * Poisson ratio nu, density rho (kg/m^3). */
+ * Poisson ratio nu, density rho (kg/m^3) and the constitutive model (Sec. IV-D):
+ * ZEMA_NEO_HOOKEAN  Psi = mu/2 (|F|^2 - 3) - mu log J + lambda/2 (log J)^2,
+ * ZEMA_STVK         Psi = mu |E|^2 + lambda/2 (tr E)^2, E = (F^T F - I)/2,
+ * ZEMA_FIXED_COROTATED  Psi = mu |F - R|^2 + lambda/2 (J - 1)^2, F = R S;
+ * mu, lambda the Lame parameters of E and nu; J <= 0 is infeasible for every model.
+ * An unknown model is ZEMA_E_ARG. */
+enum { ZEMA_NEO_HOOKEAN = 0, ZEMA_STVK = 1, ZEMA_FIXED_COROTATED = 2 };
 typedef struct {
   int32_t n_verts, n_tets;
   const double* rest_pos;
@@ -102,6 +108,7 @@ typedef struct {
   const double* pos0;
   const double* vel0;
   double E, nu, rho;
+  int32_t model, pad_;
 } zema_soft_desc;
 
 /* Affine body (Sec. III eq. 2): closed outward triangle surface in world
@@ -346,8 +353,9 @@ int zema_tune_get(zema_scene* s, int32_t knob, int32_t* value);
 int zema_autotune(zema_scene* s, int32_t* lanes, int32_t* update_block, double* us_per_iter);
 
 /* Launch timing for benchmarks: with enable != 0 the library records HIP events on
- * the scene's stream around launches of one kernel group (0 PCG iteration, 1 per-tet
- * elastic assembly, 2 contact pair assembly, 3 broad-phase query, 4 CCD) and
+ * the scene's stream around launches of one kernel group (0 PCG iteration, 1 elastic
+ * assembly: the per-tet kernel and the gradient and Hessian gathers of one assembly,
+ * 2 contact pair assembly, 3 broad-phase query, 4 CCD) and
  * accumulates their durations; zema_kernel_time returns the total milliseconds, the
  * launch count and the algorithmic bytes of those launches (what the method must move:
  * for a single-reduction PCG iteration 76 B per stored 3x3 block plus 152 B per DOF

@@ -20,6 +20,7 @@
 #include <new>
 #include <vector>
 
+#include "material.hpp"
 #include "scene.hpp"
 
 using namespace zema;
@@ -62,6 +63,7 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   }
   std::vector<double> X, x_init, v_init, Dmi_aos, vol, lmu, llam, mass;
   std::vector<int> tets, vbody;
+  std::vector<unsigned char> tmodel;
   // ---- soft bodies
   std::vector<std::array<int, 4>> faces;  // packed (a, b, c) outward + body
   std::vector<unsigned long long> fkey;
@@ -74,6 +76,8 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
     }
     if (d.n_verts < 0 || d.n_tets < 0 || (d.n_verts && !d.rest_pos) || (d.n_tets && !d.tets))
       throw Error(ZEMA_E_ARG, "bad soft body descriptor");
+    if (d.model < ZEMA_NEO_HOOKEAN || d.model > ZEMA_FIXED_COROTATED)
+      throw Error(ZEMA_E_ARG, "unknown constitutive model");
     int v0 = (int)mass.size();
     double mu = d.E / (2.0 * (1.0 + d.nu)), la = d.E * d.nu / ((1.0 + d.nu) * (1.0 - 2.0 * d.nu));
     for (int i = 0; i < d.n_verts; ++i) {
@@ -113,6 +117,7 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
       vol.push_back(V);
       lmu.push_back(mu);
       llam.push_back(la);
+      tmodel.push_back((unsigned char)d.model);
       for (int a = 0; a < 4; ++a) {
         tets.push_back(t[a]);
         mass[t[a]] += 0.25 * d.rho * V;
@@ -384,6 +389,7 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   s->h2vol.upload(h2vol);
   s->lmu.upload(lmu);
   s->llam.upload(llam);
+  s->tmodel.upload(tmodel);
   s->mass.upload(mass);
   s->mass_h = mass;
   s->vt_ptr.upload(vtp);
@@ -394,18 +400,41 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   s->bsr_diag.upload(bdiag);
   s->hc_ptr.upload(hcnt);
   s->hc_list.upload(hlist);
+  {  // destination slots of the element records (diagonal / gradient: position in the
+     // vertex's incident list; off-diagonal: position in the upper block's tet list)
+    std::vector<int> slot((size_t)10 * s->nt), optr(1, 0), oblk, omir;
+    for (int k = 0; k < (int)vtl.size(); ++k) slot[(size_t)(vtl[k] & 3) * s->nt + (vtl[k] >> 2)] = k;
+    for (int j = 0; j < s->bsr_row_soft_end; ++j) {
+      if (!(brow[j] < bcol[j])) continue;
+      for (int k = hcnt[j]; k < hcnt[j + 1]; ++k) {
+        int ent = hlist[k], e = ent >> 4, a = (ent >> 2) & 3, b = ent & 3;
+        int lo = std::min(a, b), hi = std::max(a, b);
+        int p = lo == 0 ? hi - 1 : (lo == 1 ? 1 + hi : 5);  // pair order (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)
+        slot[(size_t)(4 + p) * s->nt + e] = optr.back() + (k - hcnt[j]);
+      }
+      optr.push_back(optr.back() + (hcnt[j + 1] - hcnt[j]));
+      oblk.push_back(j);
+      unsigned long long key = (unsigned long long)bcol[j] * nn + brow[j];
+      omir.push_back((int)(std::lower_bound(ukeys.begin(), ukeys.end(), key) - ukeys.begin()));
+    }
+    if (optr.back() != 6 * s->nt) throw Error(ZEMA_E_MESH, "tet pair blocks do not match the static pattern");
+    s->tslot.upload(slot);
+    s->off_ptr.upload(optr);
+    s->off_blk.upload(oblk);
+    s->off_mir.upload(omir);
+  }
   // the mixed-precision form keeps Hessian blocks and their products in FP32; only
   // the buffers of the chosen form are allocated at full size
   s->mixed = s->P.precision == ZEMA_MIXED;
-  size_t nbv = (size_t)9 * s->nnzb + 9, nht = (size_t)90 * s->nt + 90;
+  size_t nbv = (size_t)9 * s->nnzb + 9, nht = (size_t)kTetHess * s->nt + kTetHess;
   s->bsr_val.resize(s->mixed ? 9 : nbv);
   ZCHK(hipMemset(s->bsr_val.p, 0, sizeof(double) * s->bsr_val.n));
   s->bsr_val32.resize(s->mixed ? nbv : 9);
   ZCHK(hipMemset(s->bsr_val32.p, 0, sizeof(float) * s->bsr_val32.n));
   s->e_tet.resize(s->nt + 1);
-  s->g_tet.resize((size_t)12 * s->nt + 12);
-  s->h_tet.resize(s->mixed ? 90 : nht);
-  s->h_tet32.resize(s->mixed ? nht : 90);
+  s->g_tet.resize((size_t)12 * s->nt + 12);  // [4 nt][3] gradient records
+  s->h_tet.resize(s->mixed ? kTetHess : nht);
+  s->h_tet32.resize(s->mixed ? nht : kTetHess);
   s->e_in.resize(s->nsv + 1);
   int nb = (int)s->bodies.size();
   std::vector<double> bf((size_t)BF * std::max(nb, 1), 0.0);
@@ -568,10 +597,15 @@ bool assemble(zema_scene* s, const double* y, double* grad, bool hess, unsigned 
   eval_energy(s, y, T);
   for (int k = 0; k < s->ns; ++k)
     if (!std::isfinite(T[8 * k + 6])) return false;
+  // the elastic assembly (per-tet kernel, gradient and Hessian gathers) is timed as one
+  // group when the Hessian is assembled
+  const bool timed = hess && grad && s->nt;
+  if (timed) kt_begin(s, KT_TET);
   if (grad || hess) k_tet_assemble(s, y, hess);
   if (grad) k_gather_grad_soft(s, y, grad, mask);
-  k_body_terms(s, y, grad, hess, mask);
   if (hess) k_gather_hess_static(s, mask);
+  if (timed) kt_end(s, KT_TET, (s->mixed ? 170.0 : 320.0) * s->nt);
+  k_body_terms(s, y, grad, hess, mask);
   k_contact_assemble(s, grad, hess, mask);
   s->hess_valid = hess;
   return true;

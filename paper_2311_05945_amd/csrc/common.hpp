@@ -25,6 +25,15 @@ struct Error : std::runtime_error {
 constexpr int kBlock = 256;
 inline int nblocks(int64_t n, int b = kBlock) { return (int)((n + b - 1) / b); }
 
+// Workgroup b of a launch runs on XCD b mod 8 (round-robin dispatch, 8 XCDs with an
+// L2 each).  xcd_block(b, n) is the logical block of workgroup b when each XCD takes a
+// contiguous run of the n logical blocks (XCD x: runs of q or q + 1 blocks, n = 8q + r),
+// so neighbouring blocks share their XCD's L2.  A bijection of [0, n).
+__device__ inline int xcd_block(int b, int n) {
+  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
+}
+
 // Device buffer with capacity; growing discards the old contents.
 template <class T>
 struct DBuf {

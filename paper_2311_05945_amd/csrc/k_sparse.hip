@@ -1050,17 +1050,13 @@ __global__ void cg_setup_kernel(int nsv, int nfree, const double* __restrict__ r
   }
 }
 
-// Workgroups of a launch are dispatched round-robin over the device's 8 XCDs (workgroup
-// b to XCD b mod 8), each with its own L2.  In a single-scene solve, soft workgroup b
-// takes logical block xcd_block(b, n), so each XCD holds a contiguous run of rows: the
+// Workgroups of a launch are dispatched round-robin over the device's 8 XCDs, each
+// with its own L2.  In a single-scene solve, soft workgroup b takes logical block
+// xcd_block(b, n) (common.hpp), so each XCD holds a contiguous run of rows: the
 // neighbour records its rows gather are shared in its own L2 rather than fetched by
 // every XCD, and each XCD works on the same rows in every iteration.  (Batches keep
 // the plain order: there a contiguous run would be about one scene per XCD, and the
-// XCDs of scenes that have converged would idle.)  A bijection of [0, n).
-__device__ inline int xcd_block(int b, int n) {
-  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
-  return x * q + min(x, r) + k;
-}
+// XCDs of scenes that have converged would idle.)
 
 // One iteration (START: the first product w_0 = H M^-1 b with alpha = beta = 0 and no
 // reduction; it leaves p = M^-1 b, which the first iteration scales by beta = 0).

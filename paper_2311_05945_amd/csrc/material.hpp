@@ -1,10 +1,20 @@
-// Neo-Hookean element (Sec. IV-D: the model with logarithmic volume terms,
-// Psi = mu/2 (|F|^2 - 3) - mu log J + lambda/2 (log J)^2, infinite for J <= 0),
-// scaled by h^2 V as in Sec. III eq. 1, with the PSD projection of d2Psi/dF2 built
-// from its analytic eigensystem (Smith, de Goes, Kim 2019, "Analytic eigensystems
-// for isotropic distortion energies"): three scaling modes from the 3x3 Hessian in
-// the singular values, and per pair (i,j) a twist and a flip mode with eigenvalues
-// mu + (lambda log J - mu)/(s_i s_j) and mu - (lambda log J - mu)/(s_i s_j).
+// Soft-body elements (Sec. IV-D names three isotropic potentials), each scaled by
+// h^2 V as in Sec. III eq. 1:
+//   neo-Hookean with logarithmic volume terms
+//     Psi = mu/2 (|F|^2 - 3) - mu log J + lambda/2 (log J)^2,
+//   Saint Venant-Kirchhoff
+//     Psi = mu |E|^2 + lambda/2 (tr E)^2,  E = (F^T F - I) / 2,
+//   fixed corotated
+//     Psi = mu |F - R|^2 + lambda/2 (J - 1)^2,  R the rotation of F = R S;
+// every model is infinite for J <= 0 (an inverting step is infeasible).
+//
+// The Hessian d2Psi/dF2 is projected to PSD through its analytic eigensystem in the
+// singular values of the rotation-variant SVD F = U diag(s) V^T (Smith, de Goes, Kim
+// 2019, "Analytic eigensystems for isotropic distortion energies"): three scaling
+// modes U diag(e) V^T from the 3x3 Hessian of Psi in s, and for each pair (i, j) a
+// twist mode (u_i v_j^T - u_j v_i^T)/sqrt2 with eigenvalue (psi_i + psi_j)/(s_i + s_j)
+// and a flip mode (u_i v_j^T + u_j v_i^T)/sqrt2 with eigenvalue
+// (psi_i - psi_j)/(s_i - s_j), psi_i = dPsi/ds_i, both written without the division.
 #pragma once
 #include "common.hpp"
 
@@ -46,6 +56,9 @@ __host__ __device__ inline void eig3(T A[3][3], T V[3][3]) {
       }
   }
 }
+
+// index of (i, j), i <= j, in the packed upper triangle of a 9x9 matrix
+__host__ __device__ inline int up9(int i, int j) { return i * 9 - (i * (i - 1)) / 2 + (j - i); }
 
 // Rotation-variant SVD F = U diag(s) V^T with U, V rotations (s[2] carries the sign
 // of det F), singular values descending in magnitude.
@@ -104,12 +117,34 @@ __host__ __device__ inline void svd3(const double F[3][3], double U[3][3], doubl
   U[2][2] = u2.z;
 }
 
-// Energy h^2 V Psi(F) of one tet; G is the 4x3 map with F = sum_a x_a G_a^T
-// (G_a = row a-1 of Dm^-1 for a >= 1, G_0 = -sum of rows).  Returns +inf for J <= 0.
-__host__ __device__ inline double nh_energy(const double F[3][3], double mu, double lam, double c) {
-  double J = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
-             F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+enum : int { MAT_NEO_HOOKEAN = 0, MAT_STVK = 1, MAT_FIXED_COROTATED = 2 };
+
+__host__ __device__ inline double det3(const double F[3][3]) {
+  return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+         F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+}
+
+// Energy h^2 V Psi(F) of one tet (c = h^2 V); +inf for J <= 0.
+__host__ __device__ inline double tet_psi(int model, const double F[3][3], double mu, double lam, double c) {
+  double J = det3(F);
   if (!(J > 0.0)) return INFINITY;
+  if (model == MAT_STVK) {
+    double E[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        E[i][j] = 0.5 * (F[0][i] * F[0][j] + F[1][i] * F[1][j] + F[2][i] * F[2][j] - (i == j ? 1.0 : 0.0));
+    double ee = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) ee += E[i][j] * E[i][j];
+    double tr = E[0][0] + E[1][1] + E[2][2];
+    return c * (mu * ee + 0.5 * lam * tr * tr);
+  }
+  if (model == MAT_FIXED_COROTATED) {  // singular values of the same SVD as the gradient's
+    double U[3][3], s[3], V[3][3];
+    svd3(F, U, s, V);
+    double d = (s[0] - 1.0) * (s[0] - 1.0) + (s[1] - 1.0) * (s[1] - 1.0) + (s[2] - 1.0) * (s[2] - 1.0);
+    return c * (mu * d + 0.5 * lam * (J - 1.0) * (J - 1.0));
+  }
   double I = 0.0;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) I += F[i][j] * F[i][j];
@@ -117,102 +152,175 @@ __host__ __device__ inline double nh_energy(const double F[3][3], double mu, dou
   return c * (0.5 * mu * (I - 3.0) - mu * L + 0.5 * lam * L * L);
 }
 
-// index of (i, j), i <= j, in the packed upper triangle of a 9x9 matrix
-__host__ __device__ inline int up9(int i, int j) { return i * 9 - (i * (i - 1)) / 2 + (j - i); }
+// Element Hessian layout (kTetHess values per tet): the diagonal blocks (a, a),
+// a = 0..3, as their upper entries xx, xy, xz, yy, yz, zz (6 each), then the
+// off-diagonal blocks (a, b), a < b, in the pair order (0,1), (0,2), (0,3), (1,2),
+// (1,3), (2,3), row-major 3x3 (rows of vertex a).  78 values: the upper triangle of the
+// 12x12 element matrix.
+constexpr int kTetOff = 24, kTetHess = 78;
+__host__ __device__ constexpr int sym3(int r, int c) { return r == 0 ? c : (r == 1 ? 2 + c : 5); }  // r <= c
+__host__ __device__ constexpr int tet_pair(int a, int b) { return a == 0 ? b - 1 : (a == 1 ? 1 + b : 5); }  // a < b
 
-// The 10 upper 3x3 blocks (order (0,0),(0,1),(0,2),(0,3),(1,1),(1,2),(1,3),(2,2),
-// (2,3),(3,3)) of h^2 V B^T P9 B, P9 the PSD projection of d2Psi/dF2, computed in
-// arithmetic type T (double, or float for the mixed-precision form).  P9 is
-// accumulated mode by mode from the analytic eigensystem, then contracted with the
-// rows of G (F = sum_a x_a G_a^T).
+// The upper triangle of c B^T P9 B (layout above), P9 the PSD projection of
+// d2Psi/dF2, in arithmetic type T (double, or float for the mixed-precision form).
+// With F = sum_a x_a G_a^T, a mode Q of eigenvalue l adds l w_a w_b^T to block (a, b),
+// w_a = Q G_a = U M (V^T G_a) for Q = U M V^T; the blocks of vertices 1..3 are
+// accumulated mode by mode and vertex 0 follows from G_0 = -(G_1 + G_2 + G_3).
+// Output sink of tet_hess_blocks: diag(a, k, v) receives entry k (sym3 order) of block
+// (a, a), off(p, r, c, v) entry (r, c) of the off-diagonal block of pair p (tet_pair).
 template <class T>
-__host__ __device__ inline void nh_hess_blocks(const double F[3][3], const double Gd[4][3], double mu_d, double lam_d,
-                                               double c_d, T* hblk) {
-  double J = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
-             F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
-  const T mu = T(mu_d), lam = T(lam_d), L = T(log(J));
+struct PackedHess {  // the element layout above, kTetHess values at h
+  T* h;
+  __host__ __device__ void diag(int a, int k, T v) const { h[6 * a + k] = v; }
+  __host__ __device__ void off(int p, int r, int c, T v) const { h[kTetOff + 9 * p + 3 * r + c] = v; }
+};
+
+template <class T, class Out>
+__host__ __device__ inline void tet_hess_blocks(int model, const double F[3][3], const double Gd[4][3], double mu_d,
+                                                double lam_d, double c_d, const Out& out) {
+  const double J = det3(F);
   double Ud[3][3], sd[3], Vd[3][3];
   svd3(F, Ud, sd, Vd);
-  T U[3][3], V[3][3], s[3], G[4][3];
+  const T mu = T(mu_d), lam = T(lam_d);
+  T U[3][3], s[3], gt[3][3];  // gt[a-1] = V^T G_a
   for (int i = 0; i < 3; ++i) {
     s[i] = T(sd[i]);
-    for (int j = 0; j < 3; ++j) {
-      U[i][j] = T(Ud[i][j]);
-      V[i][j] = T(Vd[i][j]);
+    for (int j = 0; j < 3; ++j) U[i][j] = T(Ud[i][j]);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      gt[a][k] = T(Vd[0][k] * Gd[a + 1][0] + Vd[1][k] * Gd[a + 1][1] + Vd[2][k] * Gd[a + 1][2]);
+  // 3x3 Hessian of Psi in the singular values, and the twist / flip eigenvalues
+  T A[3][3], twist[3], flip[3];
+  const int pi[3] = {0, 1, 0}, pj[3] = {1, 2, 2}, pk[3] = {2, 0, 1};
+  if (model == MAT_STVK) {
+    T tr = T(0.5) * (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] - T(3));
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        A[i][j] = (i == j ? mu * (T(3) * s[i] * s[i] - T(1)) + lam * tr : T(0)) + lam * s[i] * s[j];
+    for (int t = 0; t < 3; ++t) {
+      T si = s[pi[t]], sj = s[pj[t]];
+      twist[t] = mu * (si * si - si * sj + sj * sj - T(1)) + lam * tr;
+      flip[t] = mu * (si * si + si * sj + sj * sj - T(1)) + lam * tr;
+    }
+  } else if (model == MAT_FIXED_COROTATED) {
+    const T Jm = T(J - 1.0), two_mu = T(2) * mu;
+    T P[3] = {s[1] * s[2], s[0] * s[2], s[0] * s[1]};  // J / s_i
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) A[i][j] = i == j ? two_mu + lam * P[i] * P[i] : lam * P[i] * P[j] + lam * Jm * s[3 - i - j];
+    for (int t = 0; t < 3; ++t) {
+      T si = s[pi[t]], sj = s[pj[t]], sk = s[pk[t]];
+      twist[t] = two_mu - T(2) * two_mu / (si + sj) + lam * Jm * sk;
+      flip[t] = two_mu - lam * Jm * sk;
+    }
+  } else {
+    const T L = T(log(J));
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        A[i][j] = i == j ? mu + (mu + lam - lam * L) / (s[i] * s[i]) : lam / (s[i] * s[j]);
+    for (int t = 0; t < 3; ++t) {
+      T q = (lam * L - mu) / (s[pi[t]] * s[pj[t]]);
+      twist[t] = mu + q;
+      flip[t] = mu - q;
     }
   }
-  for (int a = 0; a < 4; ++a)
-    for (int j = 0; j < 3; ++j) G[a][j] = T(Gd[a][j]);
-  T A[3][3], Ev[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      A[i][j] = i == j ? mu + (mu + lam - lam * L) / (s[i] * s[i]) : lam / (s[i] * s[j]);
+  T Ev[3][3];
   eig3<T>(A, Ev);
-  T P[45];
-  for (int k = 0; k < 45; ++k) P[k] = T(0);
-  T q[9];
-  // scaling modes: U diag(e_m) V^T
-  for (int m = 0; m < 3; ++m) {
-    T lm = A[m][m];
-    if (!(lm > T(0))) continue;
-    for (int r = 0; r < 3; ++r)
-      for (int cc = 0; cc < 3; ++cc)
-        q[3 * r + cc] = Ev[0][m] * U[r][0] * V[cc][0] + Ev[1][m] * U[r][1] * V[cc][1] + Ev[2][m] * U[r][2] * V[cc][2];
-    for (int i = 0; i < 9; ++i)
-      for (int j = i; j < 9; ++j) P[up9(i, j)] += lm * q[i] * q[j];
-  }
-  // twist (antisymmetric) and flip (symmetric) modes of each pair of singular values
-  const T is2 = T(0.70710678118654752440);
-  const int pi[3] = {0, 1, 0}, pj[3] = {1, 2, 2};
+  // the nine eigenvalues clamped at zero (a clamped mode adds exact zeros)
+  T lm[9];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) lm[m] = A[m][m] > T(0) ? A[m][m] : T(0);
+#pragma unroll
   for (int t = 0; t < 3; ++t) {
-    int i = pi[t], j = pj[t];
-    T qq = (lam * L - mu) / (s[i] * s[j]);
-    for (int mode = 0; mode < 2; ++mode) {
-      T lm = mode == 0 ? mu + qq : mu - qq;
-      if (!(lm > T(0))) continue;
-      T sg = mode == 0 ? T(-1) : T(1);
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc) q[3 * r + cc] = is2 * (U[r][i] * V[cc][j] + sg * U[r][j] * V[cc][i]);
-      for (int a = 0; a < 9; ++a)
-        for (int b = a; b < 9; ++b) P[up9(a, b)] += lm * q[a] * q[b];
+    lm[3 + 2 * t] = twist[t] > T(0) ? twist[t] : T(0);
+    lm[4 + 2 * t] = flip[t] > T(0) ? flip[t] : T(0);
+  }
+  // K: blocks (a, b), a, b = 1..3, as the upper triangle of a 9x9 matrix
+  T K[45];
+#pragma unroll
+  for (int k = 0; k < 45; ++k) K[k] = T(0);
+  const T is2 = T(0.70710678118654752440);
+#pragma unroll
+  for (int mode = 0; mode < 9; ++mode) {
+    T w[9];
+    if (mode < 3) {  // scaling mode U diag(e) V^T, e = column `mode` of Ev
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        T e0 = Ev[0][mode] * gt[a][0], e1 = Ev[1][mode] * gt[a][1], e2 = Ev[2][mode] * gt[a][2];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) w[3 * a + r] = U[r][0] * e0 + U[r][1] * e1 + U[r][2] * e2;
+      }
+    } else {  // twist (antisymmetric) or flip (symmetric) mode of the pair (i, j)
+      const int t = (mode - 3) / 2, i = pi[t], j = pj[t];
+      const T sg = (mode - 3) % 2 == 0 ? T(-1) : T(1);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) w[3 * a + r] = is2 * (U[r][i] * gt[a][j] + sg * U[r][j] * gt[a][i]);
+    }
+#pragma unroll
+    for (int x = 0; x < 9; ++x) {
+      const T lw = lm[mode] * w[x];
+#pragma unroll
+      for (int y = x; y < 9; ++y) K[up9(x, y)] += lw * w[y];
     }
   }
   const T c = T(c_d);
-  int blk = 0;
-  for (int a = 0; a < 4; ++a)
-    for (int bb = a; bb < 4; ++bb, ++blk)
-      for (int r = 0; r < 3; ++r)
-        for (int cc = 0; cc < 3; ++cc) {
-          T acc = T(0);
-          for (int j = 0; j < 3; ++j)
-            for (int l = 0; l < 3; ++l) {
-              int x = 3 * r + j, y = 3 * cc + l;
-              T pv = x <= y ? P[up9(x, y)] : P[up9(y, x)];
-              acc += G[a][j] * G[bb][l] * pv;
-            }
-          hblk[9 * blk + 3 * r + cc] = c * acc;
+  // off-diagonal blocks (0, b) = -sum_a K(a, b), b = 1..3; diagonal block (0, 0) =
+  // -sum_b block (0, b), upper entries only
+  T D00[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) D00[k] = T(0);
+#pragma unroll
+  for (int b = 1; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        T v = T(0);
+#pragma unroll
+        for (int a = 1; a < 4; ++a) {
+          const int x = 3 * (a - 1) + r, y = 3 * (b - 1) + cc;
+          v += x <= y ? K[up9(x, y)] : K[up9(y, x)];
         }
+        v = -v;
+        out.off(b - 1, r, cc, c * v);  // pairs (0,1), (0,2), (0,3)
+        if (cc >= r) D00[sym3(r, cc)] += v;
+      }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out.diag(0, k, -c * D00[k]);
+  // diagonal blocks (a, a) and off-diagonal blocks (1,2), (1,3), (2,3) from K
+#pragma unroll
+  for (int a = 1; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = r; cc < 3; ++cc) out.diag(a, sym3(r, cc), c * K[up9(3 * (a - 1) + r, 3 * (a - 1) + cc)]);
+#pragma unroll
+  for (int a = 1; a < 3; ++a)
+#pragma unroll
+    for (int b = a + 1; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+          out.off(tet_pair(a, b), r, cc, c * K[up9(3 * (a - 1) + r, 3 * (b - 1) + cc)]);
 }
 
-// Gradient (12) and optionally the 10 upper 3x3 blocks of the projected Hessian
-// (order (0,0),(0,1),(0,2),(0,3),(1,1),(1,2),(1,3),(2,2),(2,3),(3,3), row-major 3x3).
-__host__ __device__ inline double nh_element(const double F[3][3], const double G[4][3], double mu, double lam, double c,
-                                             double* g, double* hblk) {
-  double J = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
-             F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+// Energy c Psi(F) and gradient (12: vertex a, coordinate r) of one tet; with hblk
+// the projected Hessian in the element layout (tet_hess_blocks<double>).
+__host__ __device__ inline double tet_element(int model, const double F[3][3], const double G[4][3], double mu,
+                                              double lam, double c, double* g, double* hblk) {
+  double J = det3(F);
   if (!(J > 0.0)) {
     for (int k = 0; k < 12; ++k) g[k] = 0.0;
     if (hblk)
-      for (int k = 0; k < 90; ++k) hblk[k] = 0.0;
+      for (int k = 0; k < kTetHess; ++k) hblk[k] = 0.0;
     return INFINITY;
   }
-  double L = log(J);
-  double I = 0.0;
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) I += F[i][j] * F[i][j];
-  double E = c * (0.5 * mu * (I - 3.0) - mu * L + 0.5 * lam * L * L);
-  // first Piola P = mu F + (lambda log J - mu) F^-T, F^-T = cof(F) / J
-  double cof[3][3];
+  double cof[3][3];  // cofactor matrix dJ/dF
   cof[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
   cof[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
   cof[0][2] = F[1][0] * F[2][1] - F[1][1] * F[2][0];
@@ -222,13 +330,47 @@ __host__ __device__ inline double nh_element(const double F[3][3], const double 
   cof[2][0] = F[0][1] * F[1][2] - F[0][2] * F[1][1];
   cof[2][1] = F[0][2] * F[1][0] - F[0][0] * F[1][2];
   cof[2][2] = F[0][0] * F[1][1] - F[0][1] * F[1][0];
-  double k = (lam * L - mu) / J;
-  double P[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) P[i][j] = mu * F[i][j] + k * cof[i][j];
+  double E, P[3][3];  // energy and first Piola-Kirchhoff stress dPsi/dF
+  if (model == MAT_STVK) {
+    double Eg[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        Eg[i][j] = 0.5 * (F[0][i] * F[0][j] + F[1][i] * F[1][j] + F[2][i] * F[2][j] - (i == j ? 1.0 : 0.0));
+    double ee = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) ee += Eg[i][j] * Eg[i][j];
+    double tr = Eg[0][0] + Eg[1][1] + Eg[2][2];
+    E = c * (mu * ee + 0.5 * lam * tr * tr);
+    double S[3][3];  // second Piola-Kirchhoff stress 2 mu E + lambda tr(E) I; P = F S
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) S[i][j] = 2.0 * mu * Eg[i][j] + (i == j ? lam * tr : 0.0);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P[i][j] = F[i][0] * S[0][j] + F[i][1] * S[1][j] + F[i][2] * S[2][j];
+  } else if (model == MAT_FIXED_COROTATED) {
+    double U[3][3], s[3], V[3][3];
+    svd3(F, U, s, V);
+    double d = (s[0] - 1.0) * (s[0] - 1.0) + (s[1] - 1.0) * (s[1] - 1.0) + (s[2] - 1.0) * (s[2] - 1.0);
+    E = c * (mu * d + 0.5 * lam * (J - 1.0) * (J - 1.0));
+    // P = 2 mu (F - R) + lambda (J - 1) cof(F), R = U V^T
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double R = U[i][0] * V[j][0] + U[i][1] * V[j][1] + U[i][2] * V[j][2];
+        P[i][j] = 2.0 * mu * (F[i][j] - R) + lam * (J - 1.0) * cof[i][j];
+      }
+  } else {
+    double L = log(J);
+    double I = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) I += F[i][j] * F[i][j];
+    E = c * (0.5 * mu * (I - 3.0) - mu * L + 0.5 * lam * L * L);
+    // P = mu F + (lambda log J - mu) F^-T, F^-T = cof(F) / J
+    double k = (lam * L - mu) / J;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P[i][j] = mu * F[i][j] + k * cof[i][j];
+  }
   for (int a = 0; a < 4; ++a)
     for (int r = 0; r < 3; ++r) g[3 * a + r] = c * (P[r][0] * G[a][0] + P[r][1] * G[a][1] + P[r][2] * G[a][2]);
-  if (hblk) nh_hess_blocks<double>(F, G, mu, lam, c, hblk);
+  if (hblk) tet_hess_blocks<double>(model, F, G, mu, lam, c, PackedHess<double>{hblk});
   return E;
 }
 

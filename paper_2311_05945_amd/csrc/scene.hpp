@@ -99,12 +99,18 @@ struct zema_scene {
   // ---- soft (device)
   zema::DBuf<int4> tets;
   zema::DBuf<double> Dmi, h2vol, lmu, llam, mass;
-  zema::DBuf<int> vt_ptr, vt_list;       // vertex -> (tet*4 + slot)
-  zema::DBuf<double> e_tet, g_tet, h_tet, e_in;  // per-tet energy, gradient [nt][12], Hessian [nt][90]
+  zema::DBuf<unsigned char> tmodel;  // per tet: 0 neo-Hookean, 1 Saint Venant-Kirchhoff, 2 fixed corotated
+  zema::DBuf<int> vt_ptr, vt_list;       // vertex -> (tet*4 + local index), tet order
+  zema::DBuf<double> e_tet, g_tet, h_tet, e_in;  // per-tet energy; gradient [4nt][3], Hessian [4nt][6] + [6nt][9] records
   zema::DBuf<float> h_tet32;                      // element Hessian blocks, mixed precision
   // ---- static BSR
   int nnzb = 0, bsr_row_soft_end = 0;
   zema::DBuf<int> bsr_ptr, bsr_col, bsr_row, bsr_diag, hc_ptr, hc_list;
+  // element records in destination order: tslot [10][nt] (diagonal / gradient slot of
+  // each tet vertex = its position in the vertex's incident list vt_ptr, then the slot
+  // of each vertex pair in its upper off-diagonal block's list off_ptr); off_blk /
+  // off_mir: BSR positions of those upper blocks and of their transposes
+  zema::DBuf<int> tslot, off_ptr, off_blk, off_mir;
   zema::DBuf<double> bsr_val;
   zema::DBuf<float> bsr_val32;           // static block values, mixed precision
   bool mixed = false;                    // FP32 Hessian storage / products

@@ -184,16 +184,20 @@ def hbm_traffic(kernel, source_files):
     return None
 
 
-def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5):
+def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, group_chunk=25, tag="",
+             groups=GROUPS):
     """Steps every scene `steps` times; returns (wall seconds, stats list, intersections)."""
+    import copy
+
     import torch
+    scenes = [copy.deepcopy(sc) for sc in scenes]
     for sc in scenes:
         sc.params.precision = 1 if mixed else 0
         sc.params.warm_start = 1 if learned is not None else 0
     # batched: the scenes in GROUPS batch objects on as many streams, stepped together
-    # (zema_step_group); each batch takes all its steps in one call, every scene
-    # starting its next step as soon as it has converged
-    objs = zema.batch_group(scenes, GROUPS)[0] if batched else [zema.Scene(sc) for sc in scenes]
+    # (zema_step_group); within a call every scene starts its next step as soon as it
+    # has converged
+    objs = zema.batch_group(scenes, groups)[0] if batched else [zema.Scene(sc) for sc in scenes]
     for o in objs:
         if learned is not None:
             o.set_mlp(learned)
@@ -201,14 +205,21 @@ def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5):
     t0 = time.perf_counter()
     stats = []
     if batched:
-        for st in zema.step_group(objs, steps):
-            stats += st
-    for o in objs if not batched else []:
+        done = 0
+        while done < steps:
+            n = min(group_chunk, steps - done)
+            for st in zema.step_group(objs, n):
+                stats += st
+            done += n
+            log(f"form {tag}: {done}/{steps} steps of {len(scenes)} scenes, {time.perf_counter() - t0:.1f} s")
+    for i, o in enumerate(objs if not batched else []):
         done = 0
         while done < steps:
             n = min(chunk, steps - done)
             stats += o.step(n)
             done += n
+        if (i + 1) % 8 == 0:
+            log(f"form {tag}: {i + 1}/{len(objs)} scenes, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     inter = 0
@@ -219,39 +230,54 @@ def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5):
 
 
 def forms(args, zema):
-    """The batched, learned and mixed-precision forms against the plain form, on a
-    sample of uneven grasp scenes at the same Newton tolerance."""
+    """The batched, learned and mixed-precision forms against the plain form, on uneven
+    grasp scenes at the same Newton tolerance.  The unbatched forms (plain, learned) run
+    one scene after the other, on the first `form_plain_scenes` scenes when that is set
+    (their rate per scene-step does not depend on how many scenes run)."""
     import numpy as np
 
     import scenegen as sg
     seeds = list(range(args.form_seed, args.form_seed + args.form_scenes))
-    mk = lambda: [sg.batch_scene(s, steps=args.form_steps) for s in seeds]
+    t0 = time.perf_counter()
+    scenes = [sg.batch_scene(s, steps=args.form_steps) for s in seeds]
+    log(f"forms: {len(scenes)} scenes generated in {time.perf_counter() - t0:.1f} s, "
+        f"{sum(sum(len(b.tets) for b in sc.softs) for sc in scenes)} tets")
+    n_plain = args.form_plain_scenes if args.form_plain_scenes > 0 else len(scenes)
     mlp = None
     if os.path.exists(args.mlp):
         mlp = zema.Mlp(np.load(args.mlp))
     out = {"sample": f"{len(seeds)} uneven grasp scenes (seeds {seeds[0]}-{seeds[-1]}), {args.form_steps} steps "
                      f"each from rest, dt=0.005 s, Newton tol 1e-6 dt",
+           "unbatched_sample": f"first {n_plain} scenes",
            "network": os.path.basename(args.mlp) if mlp is not None else None,
-           "batched_as": f"{GROUPS} batch objects of similar size on {GROUPS} HIP streams, stepped together "
+           "batched_as": f"{args.form_groups} batch objects of similar size on as many HIP streams, stepped together "
                          f"(zema_step_group); plain: one scene object after the other"}
     cases = [("plain", False, None, False), ("batched", True, None, False)]
     if mlp is not None:
         cases += [("learned", False, mlp, False), ("batched_learned", True, mlp, False),
                   ("batched_learned_mixed", True, mlp, True)]
-    total = len(seeds) * args.form_steps
+    if args.form_cases:
+        keep = args.form_cases.split(",")
+        cases = [c for c in cases if c[0] in keep]
     # untimed warm-up of the grouped batch path (streams, host threads, first launches)
-    run_form(zema, mk(), 2, True)
+    run_form(zema, scenes[:min(8, len(scenes))], 2, True, tag="warm-up")
     for name, batched, learned, mixed in cases:
-        t, st, inter = run_form(zema, mk(), args.form_steps, batched, learned, mixed)
+        sub = scenes if batched else scenes[:n_plain]
+        t, st, inter = run_form(zema, sub, args.form_steps, batched, learned, mixed, tag=name,
+                                groups=args.form_groups)
+        total = len(sub) * args.form_steps
         newton = sum(x["newton_iters"] for x in st)
-        out[name] = {"steps_per_s": total / t, "newton_iters_per_step": newton / total,
+        out[name] = {"scenes": len(sub), "steps_per_s": total / t, "newton_iters_per_step": newton / total,
                      "wall_s": t, "intersections": inter,
+                     "failed_steps": sum(1 for x in st if x["status"] != 0),
                      "learned_start_kept": (sum(x["warm_learned"] for x in st) / total) if learned else None}
         log(f"form {name}: {total / t:.2f} scene-steps/s, newton/step {newton / total:.2f}, "
             f"intersections {inter}")
-    base = out["plain"]["steps_per_s"]
-    for name, *_ in cases[1:]:
-        out[name]["speedup_vs_plain"] = out[name]["steps_per_s"] / base
+    if "plain" in out:
+        base = out["plain"]["steps_per_s"]
+        for name, *_ in cases:
+            if name != "plain":
+                out[name]["speedup_vs_plain"] = out[name]["steps_per_s"] / base
     return out
 
 
@@ -275,6 +301,10 @@ def main():
     ap.add_argument("--form-scenes", type=int, default=32)
     ap.add_argument("--form-steps", type=int, default=16)
     ap.add_argument("--form-seed", type=int, default=10000)
+    ap.add_argument("--form-cases", default="", help="comma-separated subset of the forms (default: all)")
+    ap.add_argument("--form-groups", type=int, default=GROUPS, help="batch objects of the batched forms")
+    ap.add_argument("--form-plain-scenes", type=int, default=0,
+                    help="run the unbatched forms on the first K scenes only (0: all)")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_05945_amd", "warm_mlp.npy"))
     ap.add_argument("--no-legs", action="store_true", help="skip the cube-drop and precision legs")
     ap.add_argument("--precision-res", type=int, default=64)

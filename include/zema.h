@@ -252,6 +252,53 @@ int zema_ccd_max_step(zema_scene* s, const double* y, const double* p, double* a
  * scene). */
 int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats);
 
+/* Contact force sensing (Sec. IV-B): the force on a surface vertex is -dB/dx / h^2
+ * (N), B the barrier energy of eq. 4 over the candidate set rebuilt statically at y
+ * (device, n_dof) -- the incremental potential is h^2 times the potential energy --
+ * and the force on a body the sum over its surface vertices.  forces: host
+ * [n_bodies][3], soft bodies first, then affine bodies (fixed ones included), in
+ * creation order.  Replaces the scene's current candidate set and assembled Hessian.
+ * ZEMA_E_INTERSECT if the state is infeasible; ZEMA_E_ARG on NULL pointers. */
+int zema_contact_forces(zema_scene* s, const double* y, double* forces);
+
+/* Kinematic target q~ (eq. 13) of driven affine body `body` (index among the affine
+ * bodies, creation order) for the steps that follow: q (host, 12 values: p, a1, a2,
+ * a3), or NULL to return to the scheduled target (target_vel until target_stop).
+ * ZEMA_E_ARG if the body is not driven. */
+int zema_set_drive_target(zema_scene* s, int32_t body, const double* q);
+
+/* Grasp procedure (Sec. V: AutoGrasp, Lift, Shake) on a single scene whose driven
+ * affine bodies are the fingers, each closing along its target_vel at |target_vel|.
+ * Before every step the contact forces are measured at the current state (as
+ * zema_contact_forces) and every finger's target is set to its current state plus
+ *   AutoGrasp: phi(f) h target_vel, f = |force on the finger|, with the controller of
+ *     Sec. IV-A eq. 12: phi(f) = (exp(-k f) - exp(-k f*)) / (1 - exp(-k f*)) for
+ *     0 <= f < f*, 0 for f >= f*; the phase ends when phi = 0 for every finger (each
+ *     has reached f*) or after max_close_steps;
+ *   Lift: lift_speed h along -gravity, lift_steps steps;
+ *   Shake: a(t + h) - a(t) along shake_axis, a(t) = shake_amplitude
+ *     sin(2 pi shake_frequency t) from the start of the phase, shake_steps steps.
+ * The grasp succeeds when, at the end, the object body is still in contact with the
+ * hand (a nonzero force on some finger) and not with the ground body (zero force).
+ * trace (host, optional): per step [phase, |f_ground|, |f_finger| ...] (2 + fingers
+ * doubles, at most trace_cap rows).  On a step error the procedure stops with that
+ * status in res->status. */
+typedef struct {
+  double k, f_star;                /* 1/N, N */
+  int32_t max_close_steps, lift_steps, shake_steps, object_body;
+  double lift_speed;               /* m/s */
+  double shake_amplitude, shake_frequency, shake_axis[3];
+  int32_t ground_body, pad_;       /* global body ids (soft bodies first); ground -1: none */
+} zema_grasp_params;
+
+typedef struct {
+  int32_t status, close_steps, total_steps, success, n_fingers, pad_;
+  double ground_force, finger_force_max; /* |f| at the end */
+} zema_grasp_result;
+
+int zema_grasp_run(zema_scene* s, const zema_grasp_params* gp, zema_grasp_result* res, double* trace,
+                   int32_t trace_cap);
+
 /* ---------------------------------------------------------------- batches
  * Independent scenes stepped together (the paper evaluates grasps in parallel): one
  * object holds the concatenation of every scene's bodies, each phase of a step is one

@@ -76,6 +76,8 @@ def lib():
             ("zref_friction_count", [C.c_void_p, PI64]),
             ("zref_friction_table", [C.c_void_p, PI32, PD]),
             ("zref_step", [C.c_void_p, I32, C.POINTER(StepStats)]),
+            ("zref_contact_forces", [C.c_void_p, PD, PD]),
+            ("zref_set_drive_target", [C.c_void_p, I32, PD]),
             ("zref_record", [C.c_void_p, I32]),
             ("zref_record_count", [C.c_void_p, PI64]),
             ("zref_record_get", [C.c_void_p, I64, PI32, PD, PD, PD, PD, PD]),
@@ -286,6 +288,23 @@ class RefScene:
         if rc != 0:
             raise OracleError(rc, lib().zref_last_error(self.h).decode())
         return out
+
+    def contact_forces(self, y):
+        """Contact force (N) on every body at y: soft bodies first, then affine bodies."""
+        nb = self.n_bodies
+        f = np.zeros((nb, 3))
+        rc = lib().zref_contact_forces(self.h, _pd(_f64(y)), _pd(f))
+        if rc != 0:
+            raise OracleError(rc, "contact forces")
+        return f
+
+    def set_drive_target(self, body, q):
+        """Kinematic target (12 values) of driven affine body `body` for the following
+        steps; None returns to the scheduled target."""
+        qq = _f64(q) if q is not None else None
+        rc = lib().zref_set_drive_target(self.h, int(body), _pd(qq))
+        if rc != 0:
+            raise OracleError(rc, "set_drive_target")
 
     def record(self, enable=True):
         lib().zref_record(self.h, 1 if enable else 0)

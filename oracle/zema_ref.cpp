@@ -483,6 +483,8 @@ struct Body {
   double rho = 0, stiff = 0, kappaA = 0;
   double V = 0, m = 0, c[3] = {0, 0, 0}, S[9] = {0};
   double tvel[3] = {0, 0, 0}, tstop = 0;
+  bool has_target = false;  // a target set by the caller replaces the schedule
+  double target[12] = {0};
   double qrest[12];
   double qdot0[12];
   int dof0 = -1;              // first DOF or -1 if fixed
@@ -1399,7 +1401,12 @@ void begin_step(zref_scene* s) {
       double gk = k < 3 ? s->P.gravity[k] : 0.0;
       s->yhat[B.dof0 + k] = s->y[B.dof0 + k] + h * s->ydot[B.dof0 + k] + h * h * gk;
     }
-    // kinematic target (Sec. IV-C-1): rest state moved at target_vel until target_stop
+    // kinematic target (Sec. IV-C-1): rest state moved at target_vel until target_stop,
+    // or the target the caller set (the force controller of Sec. IV-A)
+    if (B.has_target) {
+      for (int k = 0; k < 12; ++k) s->qtilde[12 * b + k] = B.target[k];
+      continue;
+    }
     double tt = std::min(tnext, B.tstop);
     for (int k = 0; k < 12; ++k) s->qtilde[12 * b + k] = B.qrest[k];
     for (int k = 0; k < 3; ++k) s->qtilde[12 * b + k] += tt * B.tvel[k];
@@ -1609,6 +1616,52 @@ int time_step(zref_scene* s, zref_step_stats* st) {
 
 // ================================================================== C interface
 extern "C" {
+
+// Contact force sensing (Sec. IV-B): the barrier energy B of eq. 4 over the static
+// candidate set at y (every inter-body pair closer than dhat) is differentiated with
+// respect to the surface vertex positions; the force on a vertex is -dB/dx divided by
+// h^2 (the incremental potential is h^2 times the potential energy), and the resultant
+// on a body is the sum over its surface vertices.  forces: [n_bodies][3], soft bodies
+// first, then affine bodies, in Newtons.
+int zref_contact_forces(zref_scene* s, const double* y, double* forces) {
+  if (!s || !y || !forces) return -1;
+  const int nb = s->n_soft_bodies + (int)s->bodies.size();
+  std::vector<double> f(3 * (size_t)nb, 0.0);
+  candidates_static(s, y);
+  std::vector<double> xs(3 * s->nsurf);
+  surface_positions(s, y, xs.data());
+  const double h2 = s->P.dt * s->P.dt;
+  for (int kind = 0; kind < 2; ++kind) {
+    const std::vector<Pair>& L = kind == 0 ? s->pt : s->ee;
+    for (const Pair& pr : L) {
+      int v4[4];
+      pair_vertices(s, kind, pr, v4);
+      double x12[12];
+      gather12(xs.data(), v4, x12);
+      double eps = kind == 1 ? ee_eps(s, pr.a, pr.b) : 0.0;
+      J2<12> E;
+      double d;
+      if (!pair_energy_jet(s, kind, x12, eps, s->kappa, E, &d)) continue;
+      for (int a = 0; a < 4; ++a) {
+        int b = s->sv_body[v4[a]];
+        for (int k = 0; k < 3; ++k) f[3 * b + k] -= E.g[3 * a + k] / h2;
+      }
+    }
+  }
+  std::copy(f.begin(), f.end(), forces);
+  return 0;
+}
+
+// Kinematic target of driven affine body `body` (its index among the affine bodies)
+// for the following steps: q (12, host), or NULL to return to the scheduled target.
+int zref_set_drive_target(zref_scene* s, int32_t body, const double* q) {
+  if (!s || body < 0 || body >= (int)s->bodies.size() || s->bodies[body].mode != 2) return -1;
+  Body& B = s->bodies[body];
+  B.has_target = q != nullptr;
+  if (q)
+    for (int k = 0; k < 12; ++k) B.target[k] = q[k];
+  return 0;
+}
 
 int zref_set_threads(int32_t n) {
 #ifdef _OPENMP

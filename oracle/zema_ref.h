@@ -90,6 +90,14 @@ int zref_friction_count(const zref_scene* s, int64_t* n);
 int zref_friction_table(const zref_scene* s, int32_t* ids5, double* vals8);
 int zref_step(zref_scene* s, int32_t n_steps, zref_step_stats* stats);
 
+/* contact force sensing (Sec. IV-B): per body the sum over its surface vertices of
+ * -dB/dx / h^2 (N), B the barrier energy over the static candidate set at y;
+ * forces [n_bodies][3], soft bodies first.  The candidate set is rebuilt at y. */
+int zref_contact_forces(zref_scene* s, const double* y, double* forces);
+/* kinematic target of driven affine body `body` for the following steps (12 values),
+ * NULL returns to the scheduled target */
+int zref_set_drive_target(zref_scene* s, int32_t body, const double* q);
+
 /* iterate recording for per-iterate parity: when enabled every Newton iterate of
  * zref_step is stored: (step, kappa at lag, kappa, y^t, ydot^t, y_k). */
 int zref_record(zref_scene* s, int32_t enable);

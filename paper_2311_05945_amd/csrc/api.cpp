@@ -643,11 +643,16 @@ void body_targets(zema_scene* s, const int* which) {
     const double tnext = (s->scene_step[k] + 1) * s->P.dt;
     for (int b = s->scn[k].b0; b < s->scn[k].b1; ++b) {
       const Body& B = s->bodies[b];
+      // translational target velocity of a driven body over this step (learned guess input)
+      for (int q = 0; q < 3; ++q) s->body_tv_h[3 * b + q] = 0.0;
+      if (B.has_target) {  // a target set by the caller (the force controller of Sec. IV-A)
+        for (int q = 0; q < 12; ++q) s->qt_h[12 * b + q] = B.target[q];
+        for (int q = 0; q < 3; ++q) s->body_tv_h[3 * b + q] = B.target_vel[q];
+        continue;
+      }
       double tt = std::min(tnext, B.tstop);
       for (int q = 0; q < 12; ++q) s->qt_h[12 * b + q] = B.qrest[q];
       for (int q = 0; q < 3; ++q) s->qt_h[12 * b + q] += tt * B.tvel[q];
-      // translational target velocity of a driven body over this step (learned guess input)
-      for (int q = 0; q < 3; ++q) s->body_tv_h[3 * b + q] = 0.0;
       if (B.mode != ZEMA_DRIVEN) continue;
       double span = std::min(tnext, B.tstop) - std::min(tnext - s->P.dt, B.tstop);
       for (int q = 0; q < 3; ++q) s->body_tv_h[3 * b + q] = B.tvel[q] * span / s->P.dt;
@@ -1520,6 +1525,156 @@ int zema_step(zema_scene* s, int32_t n_steps, zema_step_stats* stats) {
     }
   }
   return 0;
+}
+
+// contact forces (N) per body at y on the static candidate set at y (host out)
+static void contact_forces(zema_scene* s, const double* y, double* out) {
+  static_candidates(s, y);
+  double T[8];
+  if (!assemble(s, y, s->grad.p, false, 16u, T)) throw Error(ZEMA_E_INTERSECT, "infeasible state");
+  k_body_forces(s, out);
+}
+
+int zema_contact_forces(zema_scene* s, const double* y, double* forces) {
+  if (!s || !y || !forces) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    contact_forces(s, y, forces);
+    return 0;
+  });
+}
+
+int zema_set_drive_target(zema_scene* s, int32_t body, const double* q) {
+  if (!s || body < 0 || body >= (int)s->bodies.size() || s->bodies[body].mode != ZEMA_DRIVEN) return ZEMA_E_ARG;
+  Body& B = s->bodies[body];
+  if (q) {
+    const double* prev = B.has_target ? B.target : (s->qt_h.size() >= 12 * (size_t)(body + 1) ? &s->qt_h[12 * body]
+                                                                                            : B.qrest);
+    for (int k = 0; k < 3; ++k) B.target_vel[k] = (q[k] - prev[k]) / s->P.dt;
+    for (int k = 0; k < 12; ++k) B.target[k] = q[k];
+  }
+  B.has_target = q != nullptr;
+  return 0;
+}
+
+// the force controller of Sec. IV-A eq. 12
+static double phi_control(double f, double k, double fs) {
+  if (!(f < fs)) return 0.0;
+  return (std::exp(-k * f) - std::exp(-k * fs)) / (1.0 - std::exp(-k * fs));
+}
+
+int zema_grasp_run(zema_scene* s, const zema_grasp_params* gp, zema_grasp_result* res, double* trace,
+                   int32_t trace_cap) {
+  if (!s || !gp || !res || s->ns != 1 || trace_cap < 0 || (trace_cap && !trace)) return ZEMA_E_ARG;
+  if (!(gp->k > 0.0) || !(gp->f_star > 0.0) || gp->max_close_steps < 0 || gp->lift_steps < 0 ||
+      gp->shake_steps < 0 || gp->object_body < 0 || gp->object_body >= s->n_bodies ||
+      gp->ground_body >= s->n_bodies)
+    return ZEMA_E_ARG;
+  std::vector<int> fingers;
+  for (int b = 0; b < (int)s->bodies.size(); ++b)
+    if (s->bodies[b].mode == ZEMA_DRIVEN) fingers.push_back(b);
+  const int nf = (int)fingers.size();
+  *res = zema_grasp_result{};
+  res->n_fingers = nf;
+  if (!nf) return ZEMA_E_ARG;
+  const int nsb = s->n_soft_bodies;
+  return guard(s, [&]() {
+    const double h = s->P.dt;
+    const double gn = std::sqrt(s->P.gravity[0] * s->P.gravity[0] + s->P.gravity[1] * s->P.gravity[1] +
+                                s->P.gravity[2] * s->P.gravity[2]);
+    double up[3] = {0.0, 1.0, 0.0};
+    if (gn > 0.0)
+      for (int k = 0; k < 3; ++k) up[k] = -s->P.gravity[k] / gn;
+    std::vector<double> F((size_t)3 * s->n_bodies), y((size_t)s->ndof);
+    std::vector<double> fmag(nf);
+    double fground = 0.0;
+    auto measure = [&]() {
+      contact_forces(s, s->y.p, F.data());
+      for (int i = 0; i < nf; ++i) {
+        const double* f = &F[3 * (nsb + fingers[i])];
+        fmag[i] = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+      }
+      fground = 0.0;
+      if (gp->ground_body >= 0) {
+        const double* f = &F[3 * gp->ground_body];
+        fground = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+      }
+    };
+    int phase = 0, in_phase = 0, n = 0;
+    const double two_pi = 6.283185307179586476925;
+    for (;;) {
+      measure();
+      if (phase == 0) {
+        bool all_zero = true;
+        for (int i = 0; i < nf; ++i) all_zero = all_zero && phi_control(fmag[i], gp->k, gp->f_star) == 0.0;
+        if (all_zero || in_phase >= gp->max_close_steps) {
+          res->close_steps = in_phase;
+          phase = 1;
+          in_phase = 0;
+        }
+      }
+      if (phase == 1 && in_phase >= gp->lift_steps) {
+        phase = 2;
+        in_phase = 0;
+      }
+      if (phase == 2 && in_phase >= gp->shake_steps) break;
+      if (trace && n < trace_cap) {
+        double* row = trace + (size_t)n * (2 + nf);
+        row[0] = phase;
+        row[1] = fground;
+        for (int i = 0; i < nf; ++i) row[2 + i] = fmag[i];
+      }
+      // each finger's target: its current state plus the phase's increment
+      ZCHK(hipMemcpyAsync(y.data(), s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToHost, s->st));
+      ZCHK(hipStreamSynchronize(s->st));
+      for (int i = 0; i < nf; ++i) {
+        Body& B = s->bodies[fingers[i]];
+        double q[12], d[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 12; ++k) q[k] = y[B.dof0 + k];
+        if (phase == 0) {
+          const double ph = phi_control(fmag[i], gp->k, gp->f_star);
+          for (int k = 0; k < 3; ++k) d[k] = ph * h * B.tvel[k];
+        } else if (phase == 1) {
+          for (int k = 0; k < 3; ++k) d[k] = gp->lift_speed * h * up[k];
+        } else {
+          const double a0 = gp->shake_amplitude * std::sin(two_pi * gp->shake_frequency * in_phase * h);
+          const double a1 = gp->shake_amplitude * std::sin(two_pi * gp->shake_frequency * (in_phase + 1) * h);
+          for (int k = 0; k < 3; ++k) d[k] = (a1 - a0) * gp->shake_axis[k];
+        }
+        for (int k = 0; k < 3; ++k) q[k] += d[k];
+        for (int k = 0; k < 3; ++k) B.target_vel[k] = d[k] / h;
+        for (int k = 0; k < 12; ++k) B.target[k] = q[k];
+        B.has_target = true;
+      }
+      zema_step_stats st{};
+      ZCHK(hipMemcpyAsync(s->yt.p, s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+      ZCHK(hipMemcpyAsync(s->ydt.p, s->ydot.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+      int rc = 0;
+      std::string what;
+      try {
+        rc = time_step(s, &st);
+      } catch (const Error& e) {
+        rc = e.code;
+        what = e.what();
+      }
+      if (rc) {  // the scene keeps the last accepted state
+        ZCHK(hipMemcpyAsync(s->y.p, s->yt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+        ZCHK(hipMemcpyAsync(s->ydot.p, s->ydt.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+        ZCHK(hipStreamSynchronize(s->st));
+        res->status = rc;
+        res->total_steps = n;
+        throw Error(rc, "grasp procedure, step " + std::to_string(n) + ": " + what);
+      }
+      ++n;
+      ++in_phase;
+    }
+    res->total_steps = n;
+    res->ground_force = fground;
+    double fmax = 0.0;
+    for (int i = 0; i < nf; ++i) fmax = std::max(fmax, fmag[i]);
+    res->finger_force_max = fmax;
+    res->success = fmax > 0.0 && fground == 0.0 ? 1 : 0;
+    return 0;
+  });
 }
 
 int zema_step_group(zema_scene* const* scenes, int32_t n_scenes, int32_t n_steps, zema_step_stats* const* stats,

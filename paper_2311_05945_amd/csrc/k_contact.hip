@@ -654,6 +654,50 @@ void k_scene_sums(zema_scene* s, double* out_host) {
   ZCHK(hipStreamSynchronize(s->st));
 }
 
+// ------------------------------------------------------------------ contact force sensing
+// Sec. IV-B: the force on a surface vertex is -dB/dx / h^2 (B the barrier energy of
+// eq. 4 in incremental-potential units), and the resultant on a body the sum over its
+// surface vertices.  One workgroup per body walks the active barrier items in order;
+// item i's x-space gradient (12 slot entries) was written by pair_deriv_kernel.
+__global__ void body_force_kernel(int n_act, ItemArgs A, const int* __restrict__ sv_body,
+                                  const double* __restrict__ item_g, double inv_h2, double* __restrict__ out) {
+  __shared__ double sh[kBlock / 64];
+  const int b = blockIdx.x;
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n_act; i += kBlock) {
+    int kind, sv[4], ea, eb;
+    bool fric;
+    item_slots(A, i, kind, sv, ea, eb, fric);
+    for (int a = 0; a < 4; ++a)
+      if (sv_body[sv[a]] == b)
+        for (int k = 0; k < 3; ++k) f[k] += item_g[(size_t)12 * i + 3 * a + k];
+  }
+  for (int k = 0; k < 3; ++k) {
+    const double t = block_sum<kBlock>(f[k], sh);
+    if (threadIdx.x == 0) out[3 * b + k] = -t * inv_h2;
+  }
+}
+
+void k_body_forces(zema_scene* s, double* out_host) {
+  const int nb = s->n_bodies;
+  s->body_force.reserve((size_t)3 * std::max(nb, 1));
+  ItemArgs A{};
+  A.npt = (int)s->npt;
+  A.nee = (int)s->nee;
+  A.n_act = s->n_act;
+  A.nfric = 0;
+  A.pt = s->pt.p;
+  A.ee = s->ee.p;
+  A.tris = s->tris.p;
+  A.edges = s->edges.p;
+  A.act = s->act_idx.p;
+  if (nb > 0)
+    body_force_kernel<<<nb, kBlock, 0, s->st>>>(s->n_act, A, s->sv_body.p, s->item_g.p,
+                                                1.0 / (s->P.dt * s->P.dt), s->body_force.p);
+  ZCHK(hipMemcpyAsync(out_host, s->body_force.p, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+}
+
 // ------------------------------------------------------------------ launchers
 static int bits_for(unsigned long long v) {
   int b = 0;

@@ -30,6 +30,9 @@ struct Body {
   double V = 0, m = 0, c[3] = {0, 0, 0}, S[9] = {0};
   double qrest[12], qdot0[12];
   double tvel[3] = {0, 0, 0}, tstop = 0;
+  bool has_target = false;  // a kinematic target set by the caller replaces the schedule
+  double target[12] = {0};
+  double target_vel[3] = {0, 0, 0};  // (new target - previous target) / dt of the last set
 };
 
 // Launch timing of one kernel group with HIP events on the scene's stream.
@@ -167,6 +170,7 @@ struct zema_scene {
   zema::DBuf<unsigned long long> trip_key;
   zema::DBuf<double> trip_val;           // [ntrip][9]
   zema::DBuf<double> item_h, item_g;     // per contact item: 12x12 Hessian, gradient
+  zema::DBuf<double> body_force;         // [n_bodies][3] contact force sensing output
   zema::DBuf<double> e_pair, d_pair;     // per candidate energy / distance
   int n_act = 0;
   // contact matrix (CSR over nodes)
@@ -267,6 +271,8 @@ void k_body_energy(zema_scene* s, const double* y);
 void k_contact_energy(zema_scene* s);                 // e_pair, d_pair, e_fric at xs
 void k_scene_sums(zema_scene* s, double* out_host);  // per scene [ns][8] energy terms, total, min distance
 void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask);
+// contact force (N) on every body from the barrier items of the last assembly (host out)
+void k_body_forces(zema_scene* s, double* out_host);
 void k_friction_build(zema_scene* s);                 // lagged table from current candidates at xs
 void k_friction_rebuild(zema_scene* s, const int* rebuild_host);  // the same for some scenes of a batch
 

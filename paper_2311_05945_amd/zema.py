@@ -41,6 +41,17 @@ class AffineDesc(C.Structure):
                 ("target_vel", D * 3), ("target_stop", D)]
 
 
+class GraspParams(C.Structure):
+    _fields_ = [("k", D), ("f_star", D), ("max_close_steps", I32), ("lift_steps", I32), ("shake_steps", I32),
+                ("object_body", I32), ("lift_speed", D), ("shake_amplitude", D), ("shake_frequency", D),
+                ("shake_axis", D * 3), ("ground_body", I32), ("pad_", I32)]
+
+
+class GraspResult(C.Structure):
+    _fields_ = [("status", I32), ("close_steps", I32), ("total_steps", I32), ("success", I32), ("n_fingers", I32),
+                ("pad_", I32), ("ground_force", D), ("finger_force_max", D)]
+
+
 class StepStats(C.Structure):
     _fields_ = [("status", I32), ("newton_iters", I32), ("pcg_iters", I32), ("ls_backtracks", I32),
                 ("n_pt_active", I32), ("n_ee_active", I32), ("n_pt_cand", I32), ("n_ee_cand", I32),
@@ -57,6 +68,9 @@ SIGNATURES = [
     ("zema_scene_create", [C.POINTER(Params), C.POINTER(SoftDesc), I32, C.POINTER(AffineDesc), I32, VP,
                            C.POINTER(VP)]),
     ("zema_scene_destroy", [VP]),
+    ("zema_contact_forces", [VP, VP, PD]),
+    ("zema_set_drive_target", [VP, I32, PD]),
+    ("zema_grasp_run", [VP, C.POINTER(GraspParams), C.POINTER(GraspResult), PD, I32]),
     ("zema_status_string", [C.c_int]),
     ("zema_last_error", [VP]),
     ("zema_sizes", [VP, PI64]),
@@ -165,6 +179,7 @@ class Scene:
         scenes = _batch if _batch is not None else [scene]
         all_softs = [b for sc in scenes for b in sc.softs]
         all_affs = [b for sc in scenes for b in sc.affines]
+        self.n_driven = sum(1 for b in all_affs if b.mode == 2)
         softs = (SoftDesc * max(1, len(all_softs)))()
         for k, b in enumerate(all_softs):
             rp = _f64(b.rest_pos); tt = np.ascontiguousarray(b.tets, dtype=np.int32)
@@ -357,6 +372,35 @@ class Scene:
             self._chk(rc)
             return ids[:n.value], vals[:n.value]
 
+
+    def contact_forces(self, y):
+        """zema_contact_forces: contact force (N) on every body at y (host [n_bodies][3],
+        soft bodies first)."""
+        y = self._dev(y)
+        f = np.zeros((self.n_bodies, 3))
+        self._chk(lib().zema_contact_forces(self.h, _ptr(y), _pd(f)))
+        return f
+
+    def set_drive_target(self, body, q):
+        """zema_set_drive_target: kinematic target (12 values) of driven affine body
+        `body`; None returns to the scheduled target."""
+        qq = np.ascontiguousarray(q, dtype=np.float64) if q is not None else None
+        self._chk(lib().zema_set_drive_target(self.h, int(body), _pd(qq)))
+
+    def grasp_run(self, k=20.0, f_star=0.5, max_close_steps=200, lift_steps=100, lift_speed=0.1,
+                  shake_steps=0, shake_amplitude=0.0, shake_frequency=0.0, shake_axis=(1.0, 0.0, 0.0),
+                  object_body=0, ground_body=-1, trace_cap=4096):
+        """zema_grasp_run: AutoGrasp, Lift and Shake; returns (result dict, trace rows
+        [phase, |f_ground|, |f_finger| ...] per step)."""
+        gp = GraspParams(k, f_star, max_close_steps, lift_steps, shake_steps, object_body, lift_speed,
+                         shake_amplitude, shake_frequency, (D * 3)(*shake_axis), ground_body, 0)
+        res = GraspResult()
+        trace = np.zeros((max(trace_cap, 1), 2 + self.n_driven))
+        rc = lib().zema_grasp_run(self.h, C.byref(gp), C.byref(res), _pd(trace), trace_cap)
+        out = {f[0]: getattr(res, f[0]) for f in GraspResult._fields_ if f[0] != "pad_"}
+        if rc != 0:
+            raise ZemaError(rc, lib().zema_last_error(self.h).decode())
+        return out, trace[:min(res.total_steps, trace_cap), :2 + res.n_fingers]
 
     def intersection_count(self, y, cap=1024):
         """(intersecting edge-triangle pairs, inverted tets, uncertain, uncertain pairs)."""

@@ -339,6 +339,36 @@ def batch_scene(seed: int, steps: int = 100) -> Scene:
                        "mu": mu, "offset": off})
 
 
+def grasp_scene(seed: int = 0, r: int = 10, shape: str = "ellipsoid", rho: float = 400.0, E: float = 5e4,
+                nu: float = 0.45, mu: float = 0.8, speed: float = 0.05, quads: int = 4) -> Scene:
+    """Grasp evaluation: a soft object (semi-axes U[0.02, 0.03] m from `seed`) resting
+    1.5 dhat above a fixed ground slab (top face at y = 0), two driven finger boxes
+    0.01 x 0.03 x 0.04 m (closing x vertical x horizontal) on either side along x, inner
+    faces 2 dhat outside the object, closing at `speed`; gravity along -y."""
+    rng = np.random.default_rng(seed)
+    abc = rng.uniform(0.02, 0.03, 3)
+    dhat = 1e-3
+    verts, tets = shape_mesh(shape, abc, r)
+    verts = verts + np.array([0.0, 1.5 * dhat - verts[:, 1].min(), 0.0])
+    cy = 0.5 * (verts[:, 1].min() + verts[:, 1].max())
+    x_ext = float(np.max(np.abs(verts[:, 0])))
+    fx, fy, fz = 0.01, 0.03, 0.04
+    fy_c = max(cy, fy / 2 + 2 * dhat) + 3.1e-4          # off the voxel grid lines
+    fingers = []
+    for side in (-1.0, 1.0):
+        v, t = box_surface((side * (x_ext + 2 * dhat + fx / 2), fy_c, -2.3e-4), (fx / 2, fy / 2, fz / 2),
+                           (quads, quads, quads))
+        vel = np.array([-side * speed, 0.0, 0.0])
+        fingers.append(AffineBody(v, t, rho=1000.0, stiffness=1e8, mode=MODE_DRIVEN, kappa_A=1e8,
+                                  target_vel=vel, target_stop=1e9))
+    ground_v, ground_t = box_surface((0.0, -0.025, 0.0), (0.15, 0.025, 0.15), 1)
+    ground = AffineBody(ground_v, ground_t, rho=1000.0, stiffness=1e8, mode=MODE_FIXED)
+    p = Params(dt=0.005, dhat=dhat, kappa=0.0, mu=mu, eps_v=1e-3, newton_tol=1e-6)
+    soft = SoftBody(verts, tets, E=E, nu=nu, rho=rho)
+    return Scene(f"grasp_s{seed}", p, [soft], fingers + [ground], 0, seed,
+                 meta={"abc": abc.tolist(), "r": r, "ground_body": 3, "object_body": 0})
+
+
 # ----------------------------------------------------------------------------- tiny cases
 
 def two_tets_scene(model: int = NEO_HOOKEAN) -> Scene:

@@ -185,7 +185,7 @@ def hbm_traffic(kernel, source_files):
 
 
 def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, group_chunk=25, tag="",
-             groups=GROUPS):
+             groups=GROUPS, newton_max=0):
     """Steps every scene `steps` times; returns (wall seconds, stats list, intersections)."""
     import copy
 
@@ -194,6 +194,8 @@ def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, g
     for sc in scenes:
         sc.params.precision = 1 if mixed else 0
         sc.params.warm_start = 1 if learned is not None else 0
+        if newton_max:
+            sc.params.newton_max = newton_max
     # batched: the scenes in GROUPS batch objects on as many streams, stepped together
     # (zema_step_group); within a call every scene starts its next step as soon as it
     # has converged
@@ -249,6 +251,7 @@ def forms(args, zema):
     out = {"sample": f"{len(seeds)} uneven grasp scenes (seeds {seeds[0]}-{seeds[-1]}), {args.form_steps} steps "
                      f"each from rest, dt=0.005 s, Newton tol 1e-6 dt",
            "unbatched_sample": f"first {n_plain} scenes",
+           "newton_max": args.form_newton_max,
            "network": os.path.basename(args.mlp) if mlp is not None else None,
            "batched_as": f"{args.form_groups} batch objects of similar size on as many HIP streams, stepped together "
                          f"(zema_step_group); plain: one scene object after the other"}
@@ -264,7 +267,7 @@ def forms(args, zema):
     for name, batched, learned, mixed in cases:
         sub = scenes if batched else scenes[:n_plain]
         t, st, inter = run_form(zema, sub, args.form_steps, batched, learned, mixed, tag=name,
-                                groups=args.form_groups)
+                                groups=args.form_groups, newton_max=args.form_newton_max)
         total = len(sub) * args.form_steps
         newton = sum(x["newton_iters"] for x in st)
         out[name] = {"scenes": len(sub), "steps_per_s": total / t, "newton_iters_per_step": newton / total,
@@ -303,6 +306,8 @@ def main():
     ap.add_argument("--form-seed", type=int, default=10000)
     ap.add_argument("--form-cases", default="", help="comma-separated subset of the forms (default: all)")
     ap.add_argument("--form-groups", type=int, default=GROUPS, help="batch objects of the batched forms")
+    ap.add_argument("--form-newton-max", type=int, default=1000,
+                    help="Newton iteration cap of the uneven scenes (contact onset can need several hundred)")
     ap.add_argument("--form-plain-scenes", type=int, default=0,
                     help="run the unbatched forms on the first K scenes only (0: all)")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_05945_amd", "warm_mlp.npy"))

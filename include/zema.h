@@ -133,6 +133,8 @@ typedef struct {
   int32_t n_pt_active, n_ee_active, n_pt_cand, n_ee_cand;
   int32_t warm_learned;    /* 1 if the learned initial guess was kept */
   int32_t pcg_breakdowns;  /* PCG solves of the step ended at non-positive curvature */
+  int32_t al_updates;      /* multiplier updates of the kinematic energy (zema_kinematic_al) */
+  int32_t pad_;
   double alpha_ccd_min, kappa, d_min, energy;
   double ms_total, ms_assemble, ms_pcg, ms_broad, ms_ccd, ms_linesearch, ms_warm;
 } zema_step_stats;
@@ -266,6 +268,24 @@ int zema_contact_forces(zema_scene* s, const double* y, double* forces);
  * a3), or NULL to return to the scheduled target (target_vel until target_stop).
  * ZEMA_E_ARG if the body is not driven. */
 int zema_set_drive_target(zema_scene* s, int32_t body, const double* q);
+
+/* Springs (Sec. IV-C-3): the energy k |x - target|^2 of each of n distinct surface
+ * vertices sv (host int32 [n]; x = the soft vertex, or A x0 + p of an affine body's
+ * vertex) with stiffness k (host [n], N/m) towards targets (host [n][3], m), added to
+ * the incremental potential times h^2 and reported in the constraint term (energy
+ * term 3, with the kinematic energy); n = 0 removes them.  Replaces the previous set.
+ * ZEMA_E_ARG on a batch, an out-of-range or repeated vertex, or a negative k. */
+int zema_set_springs(zema_scene* s, int32_t n, const int32_t* sv, const double* k, const double* targets);
+
+/* Augmented Lagrangian of the kinematic energy (Sec. IV-C-1 eq. 13): E_A =
+ * kappa_A/2 |q - q~|^2 - sqrt(m) lambda_A . (q - q~) per driven body (m its mass).
+ * With tol > 0, a step whose Newton loop has converged checks max |q - q~| over the
+ * driven bodies; while it exceeds tol (at most max_updates times per step) every
+ * driven body's multiplier is updated, lambda_A <- lambda_A - kappa_A / sqrt(m)
+ * (q - q~), and the Newton loop continues from the same state.  tol = 0 (the default)
+ * keeps the multipliers (initially zero: the penalty alone).  lam (host [n_affine][12],
+ * optional) receives the multipliers.  Single scenes only (ZEMA_E_ARG on a batch). */
+int zema_kinematic_al(zema_scene* s, double tol, int32_t max_updates, double* lam);
 
 /* Grasp procedure (Sec. V: AutoGrasp, Lift, Shake) on a single scene whose driven
  * affine bodies are the fingers, each closing along its target_vel at |target_vel|.

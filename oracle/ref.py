@@ -42,6 +42,7 @@ class AffineDesc(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("status", I32), ("newton_iters", I32), ("pcg_iters", I32), ("ls_backtracks", I32),
                 ("n_pt_active", I32), ("n_ee_active", I32), ("n_pt_cand", I32), ("n_ee_cand", I32),
+                ("al_updates", I32), ("pad_", I32),
                 ("alpha_ccd_min", D), ("kappa", D), ("d_min", D), ("energy", D)]
 
 
@@ -78,6 +79,8 @@ def lib():
             ("zref_step", [C.c_void_p, I32, C.POINTER(StepStats)]),
             ("zref_contact_forces", [C.c_void_p, PD, PD]),
             ("zref_set_drive_target", [C.c_void_p, I32, PD]),
+            ("zref_set_springs", [C.c_void_p, I32, PI32, PD, PD]),
+            ("zref_kinematic_al", [C.c_void_p, D, I32, PD]),
             ("zref_record", [C.c_void_p, I32]),
             ("zref_record_count", [C.c_void_p, PI64]),
             ("zref_record_get", [C.c_void_p, I64, PI32, PD, PD, PD, PD, PD]),
@@ -178,6 +181,7 @@ class RefScene:
         if rc != 0:
             raise OracleError(rc, "scene create failed")
         self.h = h
+        self.n_soft_bodies = len(scene.softs)
         s = np.zeros(8, dtype=np.int64)
         L.zref_sizes(self.h, s.ctypes.data_as(PI64))
         (self.n_dof, self.n_soft_verts, self.n_tets, self.n_surf, self.n_tris, self.n_edges,
@@ -305,6 +309,26 @@ class RefScene:
         rc = lib().zref_set_drive_target(self.h, int(body), _pd(qq))
         if rc != 0:
             raise OracleError(rc, "set_drive_target")
+
+    def set_springs(self, sv, k, targets):
+        """Springs on distinct surface vertices sv with stiffness k (N/m) towards
+        targets [n][3]; empty arrays remove them."""
+        sv = np.ascontiguousarray(sv, dtype=np.int32)
+        k = _f64(k)
+        t = _f64(targets).reshape(-1, 3)
+        rc = lib().zref_set_springs(self.h, len(sv), sv.ctypes.data_as(PI32), _pd(k), _pd(t))
+        if rc != 0:
+            raise OracleError(rc, "set_springs")
+
+    def kinematic_al(self, tol, max_updates=8):
+        """Augmented Lagrangian updates of the kinematic multipliers; returns the
+        current multipliers [n_affine][12]."""
+        n_aff = self.n_bodies - self.n_soft_bodies
+        lam = np.zeros((max(n_aff, 1), 12))
+        rc = lib().zref_kinematic_al(self.h, float(tol), int(max_updates), _pd(lam))
+        if rc != 0:
+            raise OracleError(rc, "kinematic_al")
+        return lam[:n_aff]
 
     def record(self, enable=True):
         lib().zref_record(self.h, 1 if enable else 0)

@@ -485,6 +485,7 @@ struct Body {
   double tvel[3] = {0, 0, 0}, tstop = 0;
   bool has_target = false;  // a target set by the caller replaces the schedule
   double target[12] = {0};
+  double lamA[12] = {0};    // augmented Lagrangian multiplier of the kinematic energy
   double qrest[12];
   double qdot0[12];
   int dof0 = -1;              // first DOF or -1 if fixed
@@ -511,9 +512,18 @@ struct Rec {
 
 }  // namespace
 
+struct Spring {
+  int sv;          // surface vertex
+  double k;        // stiffness (N/m)
+  double target[3];
+};
+
 struct zref_scene {
   zref_params P;
   std::string err;
+  std::vector<Spring> springs;
+  double al_tol = 0.0;  // kinematic constraint tolerance of the multiplier updates (0: off)
+  int al_max = 0;       // at most this many multiplier updates per step
   int n_soft_bodies = 0;
   // soft
   int nsv = 0;
@@ -1075,11 +1085,13 @@ EvalOut evaluate(zref_scene* s, const double* y, std::vector<double>* grad, bool
     for (int k = 0; k < 12; ++k) G(2)[B.dof0 + k] += go[k];
     double ek = 0.0;
     if (B.mode == 2) {
+      // eq. 13: kappa_A/2 |q - q~|^2 - sqrt(m) lambda_A . (q - q~)
       const double* qt = &s->qtilde[12 * b];
+      const double sm = std::sqrt(B.m);
       for (int k = 0; k < 12; ++k) {
         double d = q[k] - qt[k];
-        ek += 0.5 * B.kappaA * d * d;
-        G(3)[B.dof0 + k] += B.kappaA * d;
+        ek += 0.5 * B.kappaA * d * d - sm * B.lamA[k] * d;
+        G(3)[B.dof0 + k] += B.kappaA * d - sm * B.lamA[k];
       }
     }
     o.terms[3] += ek;
@@ -1132,6 +1144,38 @@ EvalOut evaluate(zref_scene* s, const double* y, std::vector<double>* grad, bool
   // barrier over the active subset of the candidates (eqs. 4-8)
   std::vector<double> xs(3 * s->nsurf);
   surface_positions(s, y, xs.data());
+  // springs (Sec. IV-C-3): k |x - x_target|^2 per constrained surface vertex, times h^2
+  // in incremental-potential units, chained to the DOFs through the vertex map; the
+  // energy joins the constraint term (index 3)
+  for (const Spring& sp : s->springs) {
+    const double h2 = s->P.dt * s->P.dt;
+    double dx[3], e = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      dx[k] = xs[3 * sp.sv + k] - sp.target[k];
+      e += h2 * sp.k * dx[k] * dx[k];
+    }
+    o.terms[3] += e;
+    int dofs[12];
+    double J[36];
+    int nd = vertex_map(s, sp.sv, dofs, J);
+    for (int c = 0; c < nd; ++c) {
+      double acc = 0.0;
+      for (int r = 0; r < 3; ++r) acc += J[r * nd + c] * 2.0 * h2 * sp.k * dx[r];
+      G(3)[dofs[c]] += acc;
+    }
+    if (HS(3) && nd > 0) {
+      Elem el;
+      el.dofs.assign(dofs, dofs + nd);
+      el.M.assign(nd * nd, 0.0);
+      for (int a = 0; a < nd; ++a)
+        for (int c = 0; c < nd; ++c) {
+          double acc = 0.0;
+          for (int r = 0; r < 3; ++r) acc += J[r * nd + a] * J[r * nd + c];
+          el.M[a * nd + c] = 2.0 * h2 * sp.k * acc;
+        }
+      s->H.push_back(el);
+    }
+  }
   double dmin = INF;
   for (int kind = 0; kind < 2; ++kind) {
     const std::vector<Pair>& L = kind == 0 ? s->pt : s->ee;
@@ -1578,6 +1622,25 @@ int time_step(zref_scene* s, zref_step_stats* st) {
     st->pcg_iters += pit;
     if (rc) return rc;
     if (max_vertex_disp(s, p.data()) <= tol) {
+      // augmented Lagrangian (eq. 13): while a driven body misses its target by more
+      // than al_tol, lambda_A <- lambda_A - kappa_A / sqrt(m) (q - q~) and Newton goes on
+      double worst = 0.0;
+      for (size_t b = 0; b < s->bodies.size(); ++b) {
+        const Body& B = s->bodies[b];
+        if (B.mode != 2) continue;
+        for (int k = 0; k < 12; ++k)
+          worst = std::max(worst, std::fabs(s->y[B.dof0 + k] - s->qtilde[12 * b + k]));
+      }
+      if (s->al_tol > 0.0 && worst > s->al_tol && st->al_updates < s->al_max) {
+        for (size_t b = 0; b < s->bodies.size(); ++b) {
+          Body& B = s->bodies[b];
+          if (B.mode != 2) continue;
+          const double c = B.kappaA / std::sqrt(B.m);
+          for (int k = 0; k < 12; ++k) B.lamA[k] -= c * (s->y[B.dof0 + k] - s->qtilde[12 * b + k]);
+        }
+        st->al_updates++;
+        continue;
+      }
       conv = true;
       break;
     }
@@ -1660,6 +1723,40 @@ int zref_set_drive_target(zref_scene* s, int32_t body, const double* q) {
   B.has_target = q != nullptr;
   if (q)
     for (int k = 0; k < 12; ++k) B.target[k] = q[k];
+  return 0;
+}
+
+// Springs (Sec. IV-C-3): n constrained surface vertices sv (distinct), stiffness k (N/m)
+// and targets [n][3]; n = 0 removes them.  Replaces the previous set.
+int zref_set_springs(zref_scene* s, int32_t n, const int32_t* sv, const double* k, const double* targets) {
+  if (!s || n < 0 || (n && (!sv || !k || !targets))) return -1;
+  std::vector<Spring> v;
+  std::vector<char> seen(s->nsurf, 0);
+  for (int i = 0; i < n; ++i) {
+    if (sv[i] < 0 || sv[i] >= s->nsurf || seen[sv[i]] || !(k[i] >= 0.0)) return -1;
+    seen[sv[i]] = 1;
+    Spring sp;
+    sp.sv = sv[i];
+    sp.k = k[i];
+    for (int c = 0; c < 3; ++c) sp.target[c] = targets[3 * i + c];
+    v.push_back(sp);
+  }
+  s->springs = v;
+  return 0;
+}
+
+// Augmented Lagrangian multiplier updates of the kinematic energy (eq. 13): at Newton
+// convergence, while max |q - q~| over the driven bodies exceeds tol, update every
+// driven body's multiplier and continue, at most max_updates times per step.
+// tol = 0 keeps the multipliers at their values.  lam (optional, [n_affine][12]) reads
+// the multipliers.
+int zref_kinematic_al(zref_scene* s, double tol, int32_t max_updates, double* lam) {
+  if (!s || tol < 0.0 || max_updates < 0) return -1;
+  s->al_tol = tol;
+  s->al_max = max_updates;
+  if (lam)
+    for (size_t b = 0; b < s->bodies.size(); ++b)
+      for (int k = 0; k < 12; ++k) lam[12 * b + k] = s->bodies[b].lamA[k];
   return 0;
 }
 

@@ -51,6 +51,7 @@ typedef struct {
 typedef struct {
   int32_t status, newton_iters, pcg_iters, ls_backtracks;
   int32_t n_pt_active, n_ee_active, n_pt_cand, n_ee_cand;
+  int32_t al_updates, pad_; /* augmented Lagrangian multiplier updates of the step */
   double alpha_ccd_min, kappa, d_min, energy;
 } zref_step_stats;
 
@@ -97,6 +98,11 @@ int zref_contact_forces(zref_scene* s, const double* y, double* forces);
 /* kinematic target of driven affine body `body` for the following steps (12 values),
  * NULL returns to the scheduled target */
 int zref_set_drive_target(zref_scene* s, int32_t body, const double* q);
+/* springs (Sec. IV-C-3): h^2 k |x - target|^2 per distinct surface vertex; n = 0 clears */
+int zref_set_springs(zref_scene* s, int32_t n, const int32_t* sv, const double* k, const double* targets);
+/* augmented Lagrangian updates of the kinematic multipliers (eq. 13): tolerance on
+ * max |q - q~| (0: off), at most max_updates per step; lam (optional) reads them */
+int zref_kinematic_al(zref_scene* s, double tol, int32_t max_updates, double* lam);
 
 /* iterate recording for per-iterate parity: when enabled every Newton iterate of
  * zref_step is stored: (step, kappa at lag, kappa, y^t, ydot^t, y_k). */

@@ -27,8 +27,6 @@ using namespace zema;
 
 namespace {
 
-constexpr int BF = 32;
-constexpr int BF_QF = 13;
 
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -563,21 +561,24 @@ void eval_energy(zema_scene* s, const double* y, double* T) {
   k_inertia_energy(s, y, s->e_in.p);
   k_body_energy(s, y);
   k_contact_energy(s);
+  k_spring_energy(s);
   if (s->ns == 1) {
     int nb = (int)s->bodies.size();
-    const double* P[7] = {s->e_in.p, s->e_tet.p, s->e_body.p, s->e_body.p + nb, s->e_body.p + 2 * nb, s->e_pair.p,
-                          s->e_fric.p};
-    int64_t L[7] = {s->nsv, s->nt, nb, nb, nb, s->npt + s->nee, s->nfric};
-    double out[8];
-    k_sums(s, 7, P, L, out, s->sc_dmin.p);
+    const double* P[8] = {s->e_in.p, s->e_tet.p, s->e_body.p, s->e_body.p + nb, s->e_body.p + 2 * nb, s->e_pair.p,
+                          s->e_fric.p, s->e_spr.p};
+    int64_t L[8] = {s->nsv, s->nt, nb, nb, nb, s->npt + s->nee, s->nfric, (int64_t)s->springs.size()};
+    const int nseg = s->springs.empty() ? 7 : 8;
+    double out[9];
+    k_sums(s, nseg, P, L, out, s->sc_dmin.p);
+    const double espr = nseg == 8 ? out[7] : 0.0;  // springs join the constraint term
     unsigned long long du;
-    std::memcpy(&du, &out[7], sizeof(du));
+    std::memcpy(&du, &out[nseg], sizeof(du));
     double dmin;
-    std::memcpy(&dmin, &out[7], sizeof(double));
+    std::memcpy(&dmin, &out[nseg], sizeof(double));
     T[0] = out[0] + out[2];
     T[1] = out[1];
     T[2] = out[3];
-    T[3] = out[4];
+    T[3] = out[4] + espr;
     T[4] = out[5];
     T[5] = out[6];
     T[6] = T[0] + T[1] + T[2] + T[3] + T[4] + T[5];
@@ -606,6 +607,7 @@ bool assemble(zema_scene* s, const double* y, double* grad, bool hess, unsigned 
   if (hess) k_gather_hess_static(s, mask);
   if (timed) kt_end(s, KT_TET, (s->mixed ? 170.0 : 320.0) * s->nt);
   k_body_terms(s, y, grad, hess, mask);
+  if (mask & 8u) k_spring_terms(s, grad, hess);
   k_contact_assemble(s, grad, hess, mask);
   s->hess_valid = hess;
   return true;
@@ -721,6 +723,31 @@ void filtered_start(zema_scene* s, const double* p, double* y_out, double& tb, d
 // One time step of every scene (Sec. III: Newton on the incremental potential with
 // the intersection-free line search); scenes iterate in lockstep, a converged scene
 // stops moving (its right-hand side is zeroed) until every scene has converged.
+// one multiplier update of every driven body when some body misses its target by more
+// than al_tol; false (nothing changed) otherwise
+bool kinematic_al_update(zema_scene* s) {
+  std::vector<double> y((size_t)s->ndof);
+  ZCHK(hipMemcpyAsync(y.data(), s->y.p, sizeof(double) * s->ndof, hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+  double worst = 0.0;
+  for (size_t b = 0; b < s->bodies.size(); ++b) {
+    const Body& B = s->bodies[b];
+    if (B.mode != ZEMA_DRIVEN || B.dof0 < 0) continue;
+    for (int k = 0; k < 12; ++k) worst = std::max(worst, std::fabs(y[B.dof0 + k] - s->qt_h[12 * b + k]));
+  }
+  if (!(worst > s->al_tol)) return false;
+  for (size_t b = 0; b < s->bodies.size(); ++b) {
+    Body& B = s->bodies[b];
+    if (B.mode != ZEMA_DRIVEN || B.dof0 < 0) continue;
+    const double c = B.kappaA / std::sqrt(B.m);
+    for (int k = 0; k < 12; ++k) B.lamA[k] -= c * (y[B.dof0 + k] - s->qt_h[12 * b + k]);
+    ZCHK(hipMemcpyAsync(s->body_f.p + (size_t)BF * b + BF_LAM, B.lamA, sizeof(double) * 12, hipMemcpyHostToDevice,
+                        s->st));
+  }
+  ZCHK(hipStreamSynchronize(s->st));
+  return true;
+}
+
 int time_step(zema_scene* s, zema_step_stats* st) {
   const double h = s->P.dt;
   const int n = s->ndof, ns = s->ns;
@@ -810,6 +837,15 @@ int time_step(zema_scene* s, zema_step_stats* st) {
         if (pst[k]) throw Error(pst[k], "PCG failed");
       }
     k_max_disp(s, s->pdir.p, disp.data());
+    // augmented Lagrangian of the kinematic energy (eq. 13, single scenes): at
+    // convergence, while a driven body misses its target by more than al_tol, update
+    // lambda_A <- lambda_A - kappa_A / sqrt(m) (q - q~) and continue from the same y
+    if (ns == 1 && active[0] && disp[0] <= tol && s->al_tol > 0.0 && st[0].al_updates < s->al_max &&
+        kinematic_al_update(s))
+    {
+      st[0].al_updates++;
+      continue;
+    }
     for (int k = 0; k < ns; ++k)
       if (active[k] && disp[k] <= tol) {
         active[k] = 0;
@@ -1553,6 +1589,46 @@ int zema_set_drive_target(zema_scene* s, int32_t body, const double* q) {
     for (int k = 0; k < 12; ++k) B.target[k] = q[k];
   }
   B.has_target = q != nullptr;
+  return 0;
+}
+
+int zema_set_springs(zema_scene* s, int32_t n, const int32_t* sv, const double* k, const double* targets) {
+  if (!s || n < 0 || (n && (!sv || !k || !targets)) || (n && s->ns != 1)) return ZEMA_E_ARG;
+  std::vector<Spring> v;
+  std::vector<char> seen(std::max(s->nsurf, 1), 0);
+  for (int i = 0; i < n; ++i) {
+    if (sv[i] < 0 || sv[i] >= s->nsurf || seen[sv[i]] || !(k[i] >= 0.0)) return ZEMA_E_ARG;
+    seen[sv[i]] = 1;
+    Spring sp;
+    sp.sv = sv[i];
+    sp.k = k[i];
+    for (int c = 0; c < 3; ++c) sp.target[c] = targets[3 * i + c];
+    v.push_back(sp);
+  }
+  return guard(s, [&]() {
+    std::vector<int> ids;
+    std::vector<double> kt;
+    for (const Spring& sp : v) {
+      ids.push_back(sp.sv);
+      kt.push_back(sp.k);
+      for (int c = 0; c < 3; ++c) kt.push_back(sp.target[c]);
+    }
+    s->spr_sv.upload(ids, s->st);
+    s->spr_kt.upload(kt, s->st);
+    s->e_spr.reserve(v.size() + 1);
+    s->springs = v;
+    s->hess_valid = false;
+    return 0;
+  });
+}
+
+int zema_kinematic_al(zema_scene* s, double tol, int32_t max_updates, double* lam) {
+  if (!s || !(tol >= 0.0) || max_updates < 0 || (tol > 0.0 && s->ns != 1)) return ZEMA_E_ARG;
+  s->al_tol = tol;
+  s->al_max = max_updates;
+  if (lam)
+    for (size_t b = 0; b < s->bodies.size(); ++b)
+      for (int k = 0; k < 12; ++k) lam[12 * b + k] = s->bodies[b].lamA[k];
   return 0;
 }
 

@@ -1,15 +1,15 @@
 // Affine-body terms (Sec. III eq. 2): inertia 1/2 (q - qhat)^T M_b (q - qhat) with
 // M_b = diag(m I, S, S, S) for a centred rest frame, orthogonality potential
 // h^2 lambda V |A A^T - I|_F^2 (9x9 Hessian projected to PSD), and for driven bodies
-// the kinematic penalty kappa_A/2 |q - q~|^2 of Sec. IV-C-1.  One lane per body.
+// the kinematic energy of Sec. IV-C-1 eq. 13, kappa_A/2 |q - q~|^2 - sqrt(m)
+// lambda_A . (q - q~).  One lane per body.  Also the springs of Sec. IV-C-3,
+// h^2 k |x - x_target|^2 per constrained surface vertex.
 #include "geom.hpp"
 #include "scene.hpp"
 #include "wave_jacobi.hpp"
 
 namespace zema {
 
-constexpr int BF = 32;
-constexpr int BF_M = 0, BF_V = 1, BF_ST = 2, BF_KA = 3, BF_S = 4, BF_QF = 13;
 
 // energies [inertia, orthogonality, kinematic]; optional gradient (12) and Hessian
 __device__ inline void body_terms(const double* q, const double* qh, const double* qt, const double* bf, int mode,
@@ -41,10 +41,12 @@ __device__ inline void body_terms(const double* q, const double* qh, const doubl
   double c = h2 * lam * V;
   double eorth = c * phi;
   double ekin = 0.0;
+  const double sm = sqrt(m);
+  const double* lamA = bf + BF_LAM;
   if (mode == ZEMA_DRIVEN)
     for (int k = 0; k < 12; ++k) {
       double d = q[k] - qt[k];
-      ekin += 0.5 * kA * d * d;
+      ekin += 0.5 * kA * d * d - sm * lamA[k] * d;
     }
   E3[0] = ein;
   E3[1] = eorth;
@@ -56,7 +58,7 @@ __device__ inline void body_terms(const double* q, const double* qh, const doubl
         for (int j = 0; j < 3; ++j)
           g[3 + 3 * i + j] += 4.0 * c * (R[i][0] * A[0][j] + R[i][1] * A[1][j] + R[i][2] * A[2][j]);
     if ((mask & 8u) && mode == ZEMA_DRIVEN)
-      for (int k = 0; k < 12; ++k) g[k] += kA * (q[k] - qt[k]);
+      for (int k = 0; k < 12; ++k) g[k] += kA * (q[k] - qt[k]) - sm * lamA[k];
   }
   if (H) {
     for (int i = 0; i < 12; ++i)
@@ -170,6 +172,111 @@ __global__ void __launch_bounds__(64) body_hess_kernel(const double* __restrict_
     if ((mask & 8u) && mode == ZEMA_DRIVEN && r == cc) v += kA;
     int nr = r / 3, nc = cc / 3;
     val[(size_t)(3 * (r % 3) + cc % 3) * nnzb + bsr_ptr[node0 + nr] + nc] = T(v);
+  }
+}
+
+// ------------------------------------------------------------------ springs (Sec. IV-C-3)
+// energy h^2 k |x - t|^2 of each spring at the surface positions xs
+__global__ void spring_energy_kernel(int n, const int* __restrict__ sv, const double* __restrict__ kt,
+                                     const double* __restrict__ xs, double h2, double* __restrict__ e) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* x = xs + 3 * sv[i];
+  const double* c = kt + 4 * i;
+  double d0 = x[0] - c[1], d1 = x[1] - c[2], d2 = x[2] - c[3];
+  e[i] = h2 * c[0] * (d0 * d0 + d1 * d1 + d2 * d2);
+}
+
+// gradient 2 h^2 k (x - t) and Hessian 2 h^2 k I of the springs on soft vertices (one
+// spring per vertex: each thread owns its vertex's DOFs and diagonal block), added to
+// the assembled gradient and static blocks
+template <class T>
+__global__ void spring_soft_kernel(int n, const int* __restrict__ sv, const double* __restrict__ kt,
+                                   const int* __restrict__ sv_ref, const double* __restrict__ xs, double h2,
+                                   double* __restrict__ grad, const int* __restrict__ bdiag, T* __restrict__ val,
+                                   int nnzb) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int v = sv_ref[sv[i]];
+  if (v < 0) return;  // an affine body's vertex
+  const double* x = xs + 3 * sv[i];
+  const double* c = kt + 4 * i;
+  const double w = 2.0 * h2 * c[0];
+  if (grad)
+    for (int k = 0; k < 3; ++k) grad[3 * v + k] += w * (x[k] - c[1 + k]);
+  if (val) {
+    const int j = bdiag[v];
+    for (int k = 0; k < 3; ++k) val[(size_t)(4 * k) * nnzb + j] += T(w);
+  }
+}
+
+// springs on the vertices of free or driven affine bodies, one lane per body walking
+// the springs in order: x = A x0 + p, gradient J^T 2 h^2 k (x - t), Hessian
+// 2 h^2 k J^T J on the body's 4x4 node blocks
+template <class T>
+__global__ void spring_body_kernel(int nb, int n, const int* __restrict__ sv, const double* __restrict__ kt,
+                                   const int* __restrict__ sv_ref, const double* __restrict__ sv_x0,
+                                   const double* __restrict__ xs, const int* __restrict__ bi, double h2,
+                                   double* __restrict__ grad, const int* __restrict__ bsr_ptr, T* __restrict__ val,
+                                   int nnzb) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const int dof0 = bi[4 * b + 1], node0 = bi[4 * b + 2];
+  if (dof0 < 0) return;
+  for (int i = 0; i < n; ++i) {
+    const int s = sv[i];
+    if (sv_ref[s] != -1 - b) continue;
+    const double* x = xs + 3 * s;
+    const double* x0 = sv_x0 + 3 * s;
+    const double* c = kt + 4 * i;
+    const double w = 2.0 * h2 * c[0];
+    // J: row r has 1 at p_r and x0_j at a_{r j} (DOF 3 + 3 r + j)
+    if (grad)
+      for (int r = 0; r < 3; ++r) {
+        const double gr = w * (x[r] - c[1 + r]);
+        grad[dof0 + r] += gr;
+        for (int j = 0; j < 3; ++j) grad[dof0 + 3 + 3 * r + j] += gr * x0[j];
+      }
+    if (val)
+      for (int u = 0; u < 12; ++u)
+        for (int v = 0; v < 12; ++v) {
+          // (J^T J)_{uv} = sum_r J_ru J_rv; J_ru nonzero only for u = r or u = 3 + 3 r + j
+          const int ru = u < 3 ? u : (u - 3) / 3, rv = v < 3 ? v : (v - 3) / 3;
+          if (ru != rv) continue;
+          const double ju = u < 3 ? 1.0 : x0[(u - 3) % 3], jv = v < 3 ? 1.0 : x0[(v - 3) % 3];
+          val[(size_t)(3 * (u % 3) + v % 3) * nnzb + bsr_ptr[node0 + u / 3] + v / 3] += T(w * ju * jv);
+        }
+  }
+}
+
+void k_spring_energy(zema_scene* s) {
+  const int n = (int)s->springs.size();
+  if (n) spring_energy_kernel<<<nblocks(n), kBlock, 0, s->st>>>(n, s->spr_sv.p, s->spr_kt.p, s->xs.p,
+                                                                 s->P.dt * s->P.dt, s->e_spr.p);
+}
+
+void k_spring_terms(zema_scene* s, double* grad, bool hess) {
+  const int n = (int)s->springs.size(), nb = (int)s->bodies.size();
+  if (!n) return;
+  const double h2 = s->P.dt * s->P.dt;
+  if (s->mixed) {
+    spring_soft_kernel<float><<<nblocks(n), kBlock, 0, s->st>>>(n, s->spr_sv.p, s->spr_kt.p, s->sv_ref.p, s->xs.p, h2,
+                                                                grad, s->bsr_diag.p, hess ? s->bsr_val32.p : nullptr,
+                                                                s->nnzb);
+    if (nb)
+      spring_body_kernel<float><<<nblocks(nb, 64), 64, 0, s->st>>>(nb, n, s->spr_sv.p, s->spr_kt.p, s->sv_ref.p,
+                                                                   s->sv_x0.p, s->xs.p, s->body_i.p, h2, grad,
+                                                                   s->bsr_ptr.p, hess ? s->bsr_val32.p : nullptr,
+                                                                   s->nnzb);
+  } else {
+    spring_soft_kernel<double><<<nblocks(n), kBlock, 0, s->st>>>(n, s->spr_sv.p, s->spr_kt.p, s->sv_ref.p, s->xs.p, h2,
+                                                                 grad, s->bsr_diag.p, hess ? s->bsr_val.p : nullptr,
+                                                                 s->nnzb);
+    if (nb)
+      spring_body_kernel<double><<<nblocks(nb, 64), 64, 0, s->st>>>(nb, n, s->spr_sv.p, s->spr_kt.p, s->sv_ref.p,
+                                                                    s->sv_x0.p, s->xs.p, s->body_i.p, h2, grad,
+                                                                    s->bsr_ptr.p, hess ? s->bsr_val.p : nullptr,
+                                                                    s->nnzb);
   }
 }
 

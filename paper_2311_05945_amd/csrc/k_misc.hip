@@ -7,8 +7,6 @@
 
 namespace zema {
 
-constexpr int BF = 32;  // doubles per body record: m, V, stiff, kappa_A, S[9], qfix[12]
-constexpr int BF_M = 0, BF_V = 1, BF_ST = 2, BF_KA = 3, BF_S = 4, BF_QF = 13;
 
 __device__ inline const double* body_q(const double* y, const double* bf, const int* bi, int b) {
   int dof0 = bi[4 * b + 1];

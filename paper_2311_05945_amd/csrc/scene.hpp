@@ -22,6 +22,11 @@
 
 namespace zema {
 
+// Per-body device record (doubles): mass, volume, orthogonality stiffness, kappa_A,
+// second moment S[9], the fixed q of a fixed body [12], the kinematic multiplier [12]
+constexpr int BF = 48;
+constexpr int BF_M = 0, BF_V = 1, BF_ST = 2, BF_KA = 3, BF_S = 4, BF_QF = 13, BF_LAM = 25;
+
 struct Body {
   int mode = 0;
   int dof0 = -1, node0 = -1;       // -1 for fixed bodies
@@ -33,6 +38,13 @@ struct Body {
   bool has_target = false;  // a kinematic target set by the caller replaces the schedule
   double target[12] = {0};
   double target_vel[3] = {0, 0, 0};  // (new target - previous target) / dt of the last set
+  double lamA[12] = {0};             // augmented Lagrangian multiplier of the kinematic energy
+};
+
+// spring on a surface vertex (Sec. IV-C-3)
+struct Spring {
+  int sv;
+  double k, target[3];
 };
 
 // Launch timing of one kernel group with HIP events on the scene's stream.
@@ -77,6 +89,13 @@ struct zema_scene {
   zema_params P;
   hipStream_t st = nullptr;
   std::string err;
+  // constraints of Sec. IV-C: springs (single scenes) and the multiplier updates of the
+  // kinematic energy (al_tol > 0: at most al_max updates per step)
+  std::vector<zema::Spring> springs;
+  zema::DBuf<int> spr_sv;
+  zema::DBuf<double> spr_kt, e_spr;  // [n][4] (k, target), per-spring energies
+  double al_tol = 0.0;
+  int al_max = 0;
   int n_soft_bodies = 0, n_bodies = 0;
   int nsv = 0, nt = 0, nsurf = 0, ntri = 0, nedge = 0, nfree = 0, ndof = 0, nnodes = 0;
   // ---- scene table (batches)
@@ -271,6 +290,10 @@ void k_body_energy(zema_scene* s, const double* y);
 void k_contact_energy(zema_scene* s);                 // e_pair, d_pair, e_fric at xs
 void k_scene_sums(zema_scene* s, double* out_host);  // per scene [ns][8] energy terms, total, min distance
 void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask);
+// springs (Sec. IV-C-3): per-spring energies at s->xs; gradient and Hessian added to the
+// assembled ones (after the elastic gathers and the body terms)
+void k_spring_energy(zema_scene* s);
+void k_spring_terms(zema_scene* s, double* grad, bool hess);
 // contact force (N) on every body from the barrier items of the last assembly (host out)
 void k_body_forces(zema_scene* s, double* out_host);
 void k_friction_build(zema_scene* s);                 // lagged table from current candidates at xs

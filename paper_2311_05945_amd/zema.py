@@ -55,7 +55,7 @@ class GraspResult(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("status", I32), ("newton_iters", I32), ("pcg_iters", I32), ("ls_backtracks", I32),
                 ("n_pt_active", I32), ("n_ee_active", I32), ("n_pt_cand", I32), ("n_ee_cand", I32),
-                ("warm_learned", I32), ("pcg_breakdowns", I32),
+                ("warm_learned", I32), ("pcg_breakdowns", I32), ("al_updates", I32), ("pad_", I32),
                 ("alpha_ccd_min", D), ("kappa", D), ("d_min", D), ("energy", D), ("ms_total", D),
                 ("ms_assemble", D), ("ms_pcg", D), ("ms_broad", D), ("ms_ccd", D), ("ms_linesearch", D),
                 ("ms_warm", D)]
@@ -70,6 +70,8 @@ SIGNATURES = [
     ("zema_scene_destroy", [VP]),
     ("zema_contact_forces", [VP, VP, PD]),
     ("zema_set_drive_target", [VP, I32, PD]),
+    ("zema_set_springs", [VP, I32, PI32, PD, PD]),
+    ("zema_kinematic_al", [VP, D, I32, PD]),
     ("zema_grasp_run", [VP, C.POINTER(GraspParams), C.POINTER(GraspResult), PD, I32]),
     ("zema_status_string", [C.c_int]),
     ("zema_last_error", [VP]),
@@ -180,6 +182,7 @@ class Scene:
         all_softs = [b for sc in scenes for b in sc.softs]
         all_affs = [b for sc in scenes for b in sc.affines]
         self.n_driven = sum(1 for b in all_affs if b.mode == 2)
+        self.n_soft_bodies = len(all_softs)
         softs = (SoftDesc * max(1, len(all_softs)))()
         for k, b in enumerate(all_softs):
             rp = _f64(b.rest_pos); tt = np.ascontiguousarray(b.tets, dtype=np.int32)
@@ -386,6 +389,22 @@ class Scene:
         `body`; None returns to the scheduled target."""
         qq = np.ascontiguousarray(q, dtype=np.float64) if q is not None else None
         self._chk(lib().zema_set_drive_target(self.h, int(body), _pd(qq)))
+
+    def set_springs(self, sv, k, targets):
+        """zema_set_springs: springs on distinct surface vertices sv (stiffness k N/m)
+        towards targets [n][3]; empty arrays remove them."""
+        sv = np.ascontiguousarray(sv, dtype=np.int32)
+        kk = np.ascontiguousarray(k, dtype=np.float64)
+        t = np.ascontiguousarray(targets, dtype=np.float64).reshape(-1, 3)
+        self._chk(lib().zema_set_springs(self.h, len(sv), sv.ctypes.data_as(PI32), _pd(kk), _pd(t)))
+
+    def kinematic_al(self, tol, max_updates=8):
+        """zema_kinematic_al: multiplier updates of the kinematic energy; returns the
+        multipliers [n_affine][12]."""
+        n_aff = self.n_bodies - self.n_soft_bodies
+        lam = np.zeros((max(n_aff, 1), 12))
+        self._chk(lib().zema_kinematic_al(self.h, float(tol), int(max_updates), _pd(lam)))
+        return lam[:n_aff]
 
     def grasp_run(self, k=20.0, f_star=0.5, max_close_steps=200, lift_steps=100, lift_speed=0.1,
                   shake_steps=0, shake_amplitude=0.0, shake_frequency=0.0, shake_axis=(1.0, 0.0, 0.0),

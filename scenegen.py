@@ -369,6 +369,16 @@ def grasp_scene(seed: int = 0, r: int = 10, shape: str = "ellipsoid", rho: float
                  meta={"abc": abc.tolist(), "r": r, "ground_body": 3, "object_body": 0})
 
 
+def held_box(kappa_A: float = 1e8, mode: int = MODE_DRIVEN, steps: int = 10) -> Scene:
+    """A 0.04 m affine box (density 800) under gravity, alone: driven towards its rest
+    pose (a kinematic hold with stiffness kappa_A), or free (`mode`); dt = 0.01 s."""
+    v, t = box_surface((0.013, 0.2, -0.007), (0.02, 0.02, 0.02), 2)
+    p = Params(dt=0.01, dhat=1e-3, kappa=0.0, mu=0.5, eps_v=1e-3, newton_tol=1e-6)
+    box = AffineBody(v, t, rho=800.0, stiffness=1e8, mode=mode, kappa_A=kappa_A,
+                     target_vel=np.zeros(3), target_stop=0.0)
+    return Scene("held_box", p, [], [box], steps)
+
+
 # ----------------------------------------------------------------------------- tiny cases
 
 def two_tets_scene(model: int = NEO_HOOKEAN) -> Scene:

@@ -184,7 +184,7 @@ def hbm_traffic(kernel, source_files):
     return None
 
 
-def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, group_chunk=25, tag="",
+def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, group_chunk=10, tag="",
              groups=GROUPS, newton_max=0):
     """Steps every scene `steps` times; returns (wall seconds, stats list, intersections)."""
     import copy
@@ -199,7 +199,17 @@ def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, g
     # batched: the scenes in GROUPS batch objects on as many streams, stepped together
     # (zema_step_group); within a call every scene starts its next step as soon as it
     # has converged
-    objs = zema.batch_group(scenes, groups)[0] if batched else [zema.Scene(sc) for sc in scenes]
+    if batched:  # as zema.batch_group: similar sizes (largest first, dealt round-robin), one stream each
+        import torch as _t
+        order = sorted(range(len(scenes)), key=lambda i: -sum(len(b.rest_pos) for b in scenes[i].softs))
+        objs = []
+        for g in range(groups):
+            part = [scenes[i] for i in order[g::groups]]
+            if part:
+                objs.append(zema.Scene.batch(part, stream=_t.cuda.Stream()))
+                log(f"form {tag}: batch object {len(objs)} of {len(part)} scenes created")
+    else:
+        objs = [zema.Scene(sc) for sc in scenes]
     for o in objs:
         if learned is not None:
             o.set_mlp(learned)

@@ -277,6 +277,17 @@ int zema_set_drive_target(zema_scene* s, int32_t body, const double* q);
  * ZEMA_E_ARG on a batch, an out-of-range or repeated vertex, or a negative k. */
 int zema_set_springs(zema_scene* s, int32_t n, const int32_t* sv, const double* k, const double* targets);
 
+/* Prismatic joints (Sec. IV-C-2) between affine bodies b12[i][0] = b1 and b12[i][1] = b2
+ * (indices among the affine bodies, distinct, not both fixed), axis d = axes[i] in b1's
+ * rest frame, stiffness kappa[i] (incremental-potential units, as kappa_A): the energy
+ * kappa (|A1 - A2|_F^2 + |r x (A1 d)|^2), r the gap between the two bodies' images of
+ * b1's rest centre of mass (in b1: p1; in b2: A2 (c1 - c2) + p2).  Its Hessian is the
+ * Gauss-Newton matrix of the 12 residuals (PSD; the exact Hessian where the joint
+ * holds).  The energy joins the constraint term (term 3).  n = 0 removes the joints;
+ * host arrays b12 [n][2], axes [n][3], kappa [n].  ZEMA_E_ARG on a batch or bad
+ * bodies. */
+int zema_set_prismatic_joints(zema_scene* s, int32_t n, const int32_t* b12, const double* axes, const double* kappa);
+
 /* Augmented Lagrangian of the kinematic energy (Sec. IV-C-1 eq. 13): E_A =
  * kappa_A/2 |q - q~|^2 - sqrt(m) lambda_A . (q - q~) per driven body (m its mass).
  * With tol > 0, a step whose Newton loop has converged checks max |q - q~| over the

@@ -81,6 +81,7 @@ def lib():
             ("zref_set_drive_target", [C.c_void_p, I32, PD]),
             ("zref_set_springs", [C.c_void_p, I32, PI32, PD, PD]),
             ("zref_kinematic_al", [C.c_void_p, D, I32, PD]),
+            ("zref_set_prismatic_joints", [C.c_void_p, I32, PI32, PD, PD]),
             ("zref_record", [C.c_void_p, I32]),
             ("zref_record_count", [C.c_void_p, PI64]),
             ("zref_record_get", [C.c_void_p, I64, PI32, PD, PD, PD, PD, PD]),
@@ -319,6 +320,16 @@ class RefScene:
         rc = lib().zref_set_springs(self.h, len(sv), sv.ctypes.data_as(PI32), _pd(k), _pd(t))
         if rc != 0:
             raise OracleError(rc, "set_springs")
+
+    def set_prismatic_joints(self, pairs, axes, kappa):
+        """Prismatic joints between affine bodies pairs [n][2] with axes [n][3] (first
+        body's rest frame) and stiffness kappa [n]; empty arrays remove them."""
+        pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        ax = _f64(axes).reshape(-1, 3)
+        kk = _f64(kappa).reshape(-1)
+        rc = lib().zref_set_prismatic_joints(self.h, len(pr), pr.ctypes.data_as(PI32), _pd(ax), _pd(kk))
+        if rc != 0:
+            raise OracleError(rc, "set_prismatic_joints")
 
     def kinematic_al(self, tol, max_updates=8):
         """Augmented Lagrangian updates of the kinematic multipliers; returns the

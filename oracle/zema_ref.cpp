@@ -518,10 +518,17 @@ struct Spring {
   double target[3];
 };
 
+struct Joint {
+  int b1, b2;     // affine body indices
+  double d[3];    // axis in b1's rest frame
+  double kappa;   // penalty stiffness (incremental-potential units, as kappa_A)
+};
+
 struct zref_scene {
   zref_params P;
   std::string err;
   std::vector<Spring> springs;
+  std::vector<Joint> joints;
   double al_tol = 0.0;  // kinematic constraint tolerance of the multiplier updates (0: off)
   int al_max = 0;       // at most this many multiplier updates per step
   int n_soft_bodies = 0;
@@ -1144,6 +1151,60 @@ EvalOut evaluate(zref_scene* s, const double* y, std::vector<double>* grad, bool
   // barrier over the active subset of the candidates (eqs. 4-8)
   std::vector<double> xs(3 * s->nsurf);
   surface_positions(s, y, xs.data());
+  // prismatic joints (Sec. IV-C-2): kappa (|A1 - A2|_F^2 + |r x (A1 d)|^2), r the gap
+  // between the two bodies' images of b1's rest centre of mass c: in b1 (x0 measured
+  // from its centre) that image is p1, in b2 A2 (c - c2) + p2.  Hessian: the
+  // Gauss-Newton matrix 2 kappa sum_i grad R_i grad R_i^T of the 12 residuals R (PSD;
+  // the exact Hessian at R = 0).  The energy joins the constraint term (index 3).
+  for (const Joint& jt : s->joints) {
+    const Body* Bj[2] = {&s->bodies[jt.b1], &s->bodies[jt.b2]};
+    J2<24> q[2][12];
+    for (int b = 0; b < 2; ++b) {
+      const double* qb = body_q(s, b == 0 ? jt.b1 : jt.b2, y);
+      for (int k = 0; k < 12; ++k)
+        q[b][k] = Bj[b]->dof0 >= 0 ? jvar<24>(qb[k], 12 * b + k) : jconst<24>(qb[k]);
+    }
+    J2<24> R[12];
+    for (int k = 0; k < 9; ++k) R[k] = q[0][3 + k] + (-1.0) * q[1][3 + k];
+    J2<24> r[3], u[3];
+    for (int i = 0; i < 3; ++i) {
+      J2<24> a2c = jconst<24>(0.0), a1d = jconst<24>(0.0);
+      for (int j = 0; j < 3; ++j) {
+        a2c = a2c + (Bj[0]->c[j] - Bj[1]->c[j]) * q[1][3 + 3 * i + j];
+        a1d = a1d + jt.d[j] * q[0][3 + 3 * i + j];
+      }
+      r[i] = q[0][i] + (-1.0) * q[1][i] + (-1.0) * a2c;
+      u[i] = a1d;
+    }
+    R[9] = r[1] * u[2] + (-1.0) * (r[2] * u[1]);
+    R[10] = r[2] * u[0] + (-1.0) * (r[0] * u[2]);
+    R[11] = r[0] * u[1] + (-1.0) * (r[1] * u[0]);
+    double e = 0.0, g24[24] = {0}, H[24][24] = {{0}};
+    for (int i = 0; i < 12; ++i) {
+      e += jt.kappa * R[i].v * R[i].v;
+      for (int a = 0; a < 24; ++a) {
+        g24[a] += 2.0 * jt.kappa * R[i].v * R[i].g[a];
+        for (int b = 0; b < 24; ++b) H[a][b] += 2.0 * jt.kappa * R[i].g[a] * R[i].g[b];
+      }
+    }
+    o.terms[3] += e;
+    std::vector<int> loc;  // local indices (0..23) that are DOFs
+    Elem el;
+    for (int b = 0; b < 2; ++b)
+      if (Bj[b]->dof0 >= 0)
+        for (int k = 0; k < 12; ++k) {
+          loc.push_back(12 * b + k);
+          el.dofs.push_back(Bj[b]->dof0 + k);
+        }
+    for (size_t a = 0; a < loc.size(); ++a) G(3)[el.dofs[a]] += g24[loc[a]];
+    if (HS(3) && !loc.empty()) {
+      const size_t n = loc.size();
+      el.M.assign(n * n, 0.0);
+      for (size_t a = 0; a < n; ++a)
+        for (size_t b = 0; b < n; ++b) el.M[a * n + b] = H[loc[a]][loc[b]];
+      s->H.push_back(el);
+    }
+  }
   // springs (Sec. IV-C-3): k |x - x_target|^2 per constrained surface vertex, times h^2
   // in incremental-potential units, chained to the DOFs through the vertex map; the
   // energy joins the constraint term (index 3)
@@ -1757,6 +1818,28 @@ int zref_kinematic_al(zref_scene* s, double tol, int32_t max_updates, double* la
   if (lam)
     for (size_t b = 0; b < s->bodies.size(); ++b)
       for (int k = 0; k < 12; ++k) lam[12 * b + k] = s->bodies[b].lamA[k];
+  return 0;
+}
+
+// Prismatic joints (Sec. IV-C-2) between affine bodies b12[i][0] and b12[i][1] (distinct,
+// not both fixed) with axis axes[i] (b1's rest frame) and stiffness kappa[i]; n = 0
+// removes them.  Replaces the previous set.
+int zref_set_prismatic_joints(zref_scene* s, int32_t n, const int32_t* b12, const double* axes,
+                              const double* kappa) {
+  if (!s || n < 0 || (n && (!b12 || !axes || !kappa))) return -1;
+  std::vector<Joint> v;
+  const int nb = (int)s->bodies.size();
+  for (int i = 0; i < n; ++i) {
+    Joint j;
+    j.b1 = b12[2 * i];
+    j.b2 = b12[2 * i + 1];
+    if (j.b1 < 0 || j.b1 >= nb || j.b2 < 0 || j.b2 >= nb || j.b1 == j.b2 || !(kappa[i] >= 0.0)) return -1;
+    if (s->bodies[j.b1].dof0 < 0 && s->bodies[j.b2].dof0 < 0) return -1;
+    for (int k = 0; k < 3; ++k) j.d[k] = axes[3 * i + k];
+    j.kappa = kappa[i];
+    v.push_back(j);
+  }
+  s->joints = v;
   return 0;
 }
 

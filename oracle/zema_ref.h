@@ -103,6 +103,10 @@ int zref_set_springs(zref_scene* s, int32_t n, const int32_t* sv, const double* 
 /* augmented Lagrangian updates of the kinematic multipliers (eq. 13): tolerance on
  * max |q - q~| (0: off), at most max_updates per step; lam (optional) reads them */
 int zref_kinematic_al(zref_scene* s, double tol, int32_t max_updates, double* lam);
+/* prismatic joints (Sec. IV-C-2): body pairs [n][2] (affine indices), axes [n][3] in the
+ * first body's rest frame, stiffness [n]; n = 0 removes them */
+int zref_set_prismatic_joints(zref_scene* s, int32_t n, const int32_t* b12, const double* axes,
+                              const double* kappa);
 
 /* iterate recording for per-iterate parity: when enabled every Newton iterate of
  * zref_step is stored: (step, kappa at lag, kappa, y^t, ydot^t, y_k). */

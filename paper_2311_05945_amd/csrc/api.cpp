@@ -562,15 +562,17 @@ void eval_energy(zema_scene* s, const double* y, double* T) {
   k_body_energy(s, y);
   k_contact_energy(s);
   k_spring_energy(s);
+  k_joint_energy(s, y, s->e_spr.p + s->springs.size());
   if (s->ns == 1) {
     int nb = (int)s->bodies.size();
     const double* P[8] = {s->e_in.p, s->e_tet.p, s->e_body.p, s->e_body.p + nb, s->e_body.p + 2 * nb, s->e_pair.p,
                           s->e_fric.p, s->e_spr.p};
-    int64_t L[8] = {s->nsv, s->nt, nb, nb, nb, s->npt + s->nee, s->nfric, (int64_t)s->springs.size()};
-    const int nseg = s->springs.empty() ? 7 : 8;
+    const int64_t ncons = (int64_t)(s->springs.size() + s->joints.size());
+    int64_t L[8] = {s->nsv, s->nt, nb, nb, nb, s->npt + s->nee, s->nfric, ncons};
+    const int nseg = ncons ? 8 : 7;
     double out[9];
     k_sums(s, nseg, P, L, out, s->sc_dmin.p);
-    const double espr = nseg == 8 ? out[7] : 0.0;  // springs join the constraint term
+    const double espr = nseg == 8 ? out[7] : 0.0;  // springs and joints join the constraint term
     unsigned long long du;
     std::memcpy(&du, &out[nseg], sizeof(du));
     double dmin;
@@ -595,6 +597,7 @@ void eval_energy(zema_scene* s, const double* y, double* T) {
 // energies, gradient (optional) and Hessian (optional) at y on the current candidates;
 // false (and nothing assembled) when a scene's state is infeasible
 bool assemble(zema_scene* s, const double* y, double* grad, bool hess, unsigned mask, double* T) {
+  s->y_asm = y;
   eval_energy(s, y, T);
   for (int k = 0; k < s->ns; ++k)
     if (!std::isfinite(T[8 * k + 6])) return false;
@@ -1615,8 +1618,47 @@ int zema_set_springs(zema_scene* s, int32_t n, const int32_t* sv, const double* 
     }
     s->spr_sv.upload(ids, s->st);
     s->spr_kt.upload(kt, s->st);
-    s->e_spr.reserve(v.size() + 1);
+    s->e_spr.reserve(v.size() + s->joints.size() + 1);
     s->springs = v;
+    s->hess_valid = false;
+    return 0;
+  });
+}
+
+int zema_set_prismatic_joints(zema_scene* s, int32_t n, const int32_t* b12, const double* axes, const double* kappa) {
+  if (!s || n < 0 || (n && (!b12 || !axes || !kappa)) || (n && s->ns != 1)) return ZEMA_E_ARG;
+  const int nb = (int)s->bodies.size();
+  std::vector<Joint> v;
+  std::vector<double> jd;
+  for (int i = 0; i < n; ++i) {
+    Joint J;
+    J.b1 = b12[2 * i];
+    J.b2 = b12[2 * i + 1];
+    if (J.b1 < 0 || J.b1 >= nb || J.b2 < 0 || J.b2 >= nb || J.b1 == J.b2 || !(kappa[i] >= 0.0)) return ZEMA_E_ARG;
+    if (s->bodies[J.b1].dof0 < 0 && s->bodies[J.b2].dof0 < 0) return ZEMA_E_ARG;
+    for (int k = 0; k < 3; ++k) J.d[k] = axes[3 * i + k];
+    J.kappa = kappa[i];
+    v.push_back(J);
+    for (int k = 0; k < 3; ++k) jd.push_back(J.d[k]);
+    jd.push_back(J.kappa);
+    for (int k = 0; k < 3; ++k) jd.push_back(s->bodies[J.b1].c[k] - s->bodies[J.b2].c[k]);
+    jd.push_back(0.0);
+  }
+  // per joint: bodies and the offsets of its triplets (gradient per node of a non-fixed
+  // body, then with the Hessian every node pair) within the joints' block
+  std::vector<int> ji;
+  int off_h = 0, off_g = 0;
+  for (const Joint& J : v) {
+    const int nodes = 4 * ((s->bodies[J.b1].dof0 >= 0) + (s->bodies[J.b2].dof0 >= 0));
+    ji.insert(ji.end(), {J.b1, J.b2, off_h, off_g});
+    off_h += nodes + nodes * nodes;
+    off_g += nodes;
+  }
+  return guard(s, [&]() {
+    s->jnt_d.upload(jd, s->st);
+    s->jnt_i.upload(ji, s->st);
+    s->joints = v;
+    s->e_spr.reserve(s->springs.size() + v.size() + 1);
     s->hess_valid = false;
     return 0;
   });

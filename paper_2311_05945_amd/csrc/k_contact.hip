@@ -654,6 +654,125 @@ void k_scene_sums(zema_scene* s, double* out_host) {
   ZCHK(hipStreamSynchronize(s->st));
 }
 
+// ------------------------------------------------------------------ prismatic joints
+// Sec. IV-C-2: E = kappa (|A1 - A2|_F^2 + |r x u|^2), u = A1 d (d in b1's rest frame),
+// r = p1 - (A2 (c1 - c2) + p2) the gap between the two bodies' images of b1's rest
+// centre of mass c1 (x0 is measured from each body's centre).  Residuals R (12): the
+// 9 entries of A1 - A2 and the 3 of r x u; Jacobian Jm [12][24] over (q1, q2); Hessian
+// the Gauss-Newton matrix 2 kappa Jm^T Jm.
+__device__ inline void joint_residuals(const double* q1, const double* q2, const double* d, const double* dc,
+                                       double R[12], double Jm[12][24]) {
+  for (int i = 0; i < 12; ++i)
+    for (int k = 0; k < 24; ++k) Jm[i][k] = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    R[k] = q1[3 + k] - q2[3 + k];
+    Jm[k][3 + k] = 1.0;
+    Jm[k][15 + k] = -1.0;
+  }
+  double r[3], u[3], dr[3][24], du[3][24];
+  for (int i = 0; i < 3; ++i) {
+    for (int k = 0; k < 24; ++k) dr[i][k] = du[i][k] = 0.0;
+    r[i] = q1[i] - q2[i];
+    u[i] = 0.0;
+    dr[i][i] = 1.0;
+    dr[i][12 + i] = -1.0;
+    for (int j = 0; j < 3; ++j) {
+      r[i] -= dc[j] * q2[3 + 3 * i + j];
+      dr[i][15 + 3 * i + j] = -dc[j];
+      u[i] += d[j] * q1[3 + 3 * i + j];
+      du[i][3 + 3 * i + j] = d[j];
+    }
+  }
+  for (int i = 0; i < 3; ++i) {
+    const int a = (i + 1) % 3, b = (i + 2) % 3;  // w_i = r_a u_b - r_b u_a
+    R[9 + i] = r[a] * u[b] - r[b] * u[a];
+    for (int k = 0; k < 24; ++k) Jm[9 + i][k] = u[b] * dr[a][k] + r[a] * du[b][k] - u[a] * dr[b][k] - r[b] * du[a][k];
+  }
+}
+
+struct JointArgs {
+  int nj;
+  const int* ji;       // [nj][4]: b1, b2, triplet offset within the joints' block with / without Hessian
+  const double* jd;    // [nj][8]: d (3), kappa, c1 - c2 (3), 0
+  const double* bf;    // body records (fixed q)
+  const int* bi;       // body ints (mode, dof0, node0)
+  const double* y;
+};
+
+__device__ inline const double* joint_q(const JointArgs& J, int b) {
+  const int dof0 = J.bi[4 * b + 1];
+  return dof0 >= 0 ? J.y + dof0 : J.bf + BF * b + BF_QF;
+}
+
+__global__ void joint_energy_kernel(JointArgs J, double* __restrict__ e) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J.nj) return;
+  double R[12], Jm[12][24];
+  joint_residuals(joint_q(J, J.ji[4 * j]), joint_q(J, J.ji[4 * j + 1]), J.jd + 8 * j, J.jd + 8 * j + 4, R, Jm);
+  double acc = 0.0;
+  for (int i = 0; i < 12; ++i) acc += R[i] * R[i];
+  e[j] = J.jd[8 * j + 3] * acc;
+}
+
+// one thread per joint: gradient triplets (node, n_nodes) and, with hess, the node-pair
+// blocks of 2 kappa Jm^T Jm, for the nodes of the joint's non-fixed bodies
+__global__ void joint_emit_kernel(JointArgs J, int hess, int64_t base, unsigned long long W, int nn_total,
+                                  unsigned long long* __restrict__ key, double* __restrict__ val) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J.nj) return;
+  const int b[2] = {J.ji[4 * j], J.ji[4 * j + 1]};
+  const double kappa = J.jd[8 * j + 3];
+  double R[12], Jm[12][24];
+  joint_residuals(joint_q(J, b[0]), joint_q(J, b[1]), J.jd + 8 * j, J.jd + 8 * j + 4, R, Jm);
+  int node[8], nn = 0, loc[8];  // nodes of non-fixed bodies and their first local index
+  for (int k = 0; k < 2; ++k) {
+    const int dof0 = J.bi[4 * b[k] + 1], node0 = J.bi[4 * b[k] + 2];
+    if (dof0 < 0) continue;
+    for (int m = 0; m < 4; ++m) {
+      node[nn] = node0 + m;
+      loc[nn] = 12 * k + 3 * m;
+      ++nn;
+    }
+  }
+  int64_t o = base + J.ji[4 * j + (hess ? 2 : 3)];
+  for (int a = 0; a < nn; ++a, ++o) {
+    key[o] = (unsigned long long)node[a] * W + (unsigned long long)nn_total;
+    for (int c = 0; c < 3; ++c) {
+      double g = 0.0;
+      for (int i = 0; i < 12; ++i) g += Jm[i][loc[a] + c] * R[i];
+      val[(size_t)9 * o + c] = 2.0 * kappa * g;
+    }
+    for (int c = 3; c < 9; ++c) val[(size_t)9 * o + c] = 0.0;
+  }
+  if (!hess) return;
+  for (int a = 0; a < nn; ++a)
+    for (int bb = 0; bb < nn; ++bb, ++o) {
+      key[o] = (unsigned long long)node[a] * W + (unsigned long long)node[bb];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          double h = 0.0;
+          for (int i = 0; i < 12; ++i) h += Jm[i][loc[a] + r] * Jm[i][loc[bb] + c];
+          val[(size_t)9 * o + 3 * r + c] = 2.0 * kappa * h;
+        }
+    }
+}
+
+static JointArgs joint_args(zema_scene* s, const double* y) {
+  JointArgs J;
+  J.nj = (int)s->joints.size();
+  J.ji = s->jnt_i.p;
+  J.jd = s->jnt_d.p;
+  J.bf = s->body_f.p;
+  J.bi = s->body_i.p;
+  J.y = y;
+  return J;
+}
+
+void k_joint_energy(zema_scene* s, const double* y, double* e_out) {
+  const int nj = (int)s->joints.size();
+  if (nj) joint_energy_kernel<<<nblocks(nj, 64), 64, 0, s->st>>>(joint_args(s, y), e_out);
+}
+
 // ------------------------------------------------------------------ contact force sensing
 // Sec. IV-B: the force on a surface vertex is -dB/dx / h^2 (B the barrier energy of
 // eq. 4 in incremental-potential units), and the resultant on a body the sum over its
@@ -830,7 +949,16 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   int nitems = s->n_act + nfr;
   s->nnzc = 0;
   s->c_ptr.reserve(s->nnodes + 1);
-  if (nitems == 0) {
+  // prismatic joints emit their triplets after the items' (constraint term, mask bit 3)
+  // (offsets within the joints' block: jnt_i, uploaded when the joints are set)
+  const int nj = (mask & 8u) ? (int)s->joints.size() : 0;
+  int64_t ntrip_j = 0;
+  for (int j = 0; j < nj; ++j) {
+    const Joint& J = s->joints[j];
+    const int nodes = 4 * ((s->bodies[J.b1].dof0 >= 0) + (s->bodies[J.b2].dof0 >= 0));
+    ntrip_j += nodes + (hess ? nodes * nodes : 0);
+  }
+  if (nitems == 0 && ntrip_j == 0) {
     ZCHK(hipMemsetAsync(s->c_ptr.p, 0, sizeof(int) * (s->nnodes + 1), s->st));
     return;
   }
@@ -860,10 +988,14 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   A.ys = s->P.eps_v * s->P.dt;
   A.nn_total = s->nnodes;
   A.hess = hess ? 1 : 0;
-  s->trip_cnt.reserve(nitems + 1);
-  s->trip_off.reserve(nitems + 1);
-  item_count_kernel<<<nblocks(nitems), kBlock, 0, s->st>>>(A, s->trip_cnt.p);
-  int64_t ntrip = k_exclusive_scan(s, s->trip_cnt.p, s->trip_off.p, nitems);
+  int64_t ntrip_items = 0;
+  if (nitems) {
+    s->trip_cnt.reserve(nitems + 1);
+    s->trip_off.reserve(nitems + 1);
+    item_count_kernel<<<nblocks(nitems), kBlock, 0, s->st>>>(A, s->trip_cnt.p);
+    ntrip_items = k_exclusive_scan(s, s->trip_cnt.p, s->trip_off.p, nitems);
+  }
+  const int64_t ntrip = ntrip_items + ntrip_j;
   if (ntrip == 0) {  // every item touches only fixed bodies
     ZCHK(hipMemsetAsync(s->c_ptr.p, 0, sizeof(int) * (s->nnodes + 1), s->st));
     return;
@@ -872,14 +1004,20 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   sb.k0.reserve(ntrip + 1);
   sb.v0.reserve(ntrip + 1);
   s->trip_val.reserve((size_t)9 * ntrip + 9);
-  s->item_h.reserve((size_t)144 * nitems + 144);
-  s->item_g.reserve((size_t)12 * nitems + 12);
-  pair_deriv_kernel<<<nitems, 64, 0, s->st>>>(A, s->item_h.p, s->item_g.p);
-  kt_begin(s, KT_CONTACT);
-  project_emit_kernel<<<nitems, 64, 0, s->st>>>(A, s->item_h.p, s->item_g.p, s->trip_off.p, sb.k0.p, s->trip_val.p);
-  kt_end(s, KT_CONTACT);
-  k_iota(s, sb.v0.p, ntrip);  // sort values = triplet ids
   unsigned long long W = (unsigned long long)s->nnodes + 1;
+  if (nitems) {
+    s->item_h.reserve((size_t)144 * nitems + 144);
+    s->item_g.reserve((size_t)12 * nitems + 12);
+    pair_deriv_kernel<<<nitems, 64, 0, s->st>>>(A, s->item_h.p, s->item_g.p);
+    kt_begin(s, KT_CONTACT);
+    project_emit_kernel<<<nitems, 64, 0, s->st>>>(A, s->item_h.p, s->item_g.p, s->trip_off.p, sb.k0.p,
+                                                  s->trip_val.p);
+    kt_end(s, KT_CONTACT);
+  }
+  if (nj)
+    joint_emit_kernel<<<nblocks(nj, 64), 64, 0, s->st>>>(joint_args(s, s->y_asm), hess ? 1 : 0, ntrip_items, W,
+                                                        s->nnodes, sb.k0.p, s->trip_val.p);
+  k_iota(s, sb.v0.p, ntrip);  // sort values = triplet ids
   k_radix_sort(s, sb, ntrip, bits_for((unsigned long long)s->nnodes * W + W));
   // segments
   s->cnt.reserve(ntrip + 1);

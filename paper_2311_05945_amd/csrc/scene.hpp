@@ -47,6 +47,12 @@ struct Spring {
   double k, target[3];
 };
 
+// prismatic joint between two affine bodies (Sec. IV-C-2)
+struct Joint {
+  int b1, b2;
+  double d[3], kappa;
+};
+
 // Launch timing of one kernel group with HIP events on the scene's stream.
 enum { KT_SPMV = 0, KT_TET = 1, KT_CONTACT = 2, KT_QUERY = 3, KT_CCD = 4, KT_N = 5 };
 struct KTimer {
@@ -93,7 +99,11 @@ struct zema_scene {
   // kinematic energy (al_tol > 0: at most al_max updates per step)
   std::vector<zema::Spring> springs;
   zema::DBuf<int> spr_sv;
-  zema::DBuf<double> spr_kt, e_spr;  // [n][4] (k, target), per-spring energies
+  zema::DBuf<double> spr_kt, e_spr;  // [n][4] (k, target); energies of the springs, then of the joints
+  std::vector<zema::Joint> joints;
+  zema::DBuf<int> jnt_i;             // [nj][4] b1, b2, triplet offsets with / without Hessian
+  zema::DBuf<double> jnt_d;          // [nj][8] axis (3), kappa, c1 - c2 (3), 0
+  const double* y_asm = nullptr;     // the state of the assembly in progress
   double al_tol = 0.0;
   int al_max = 0;
   int n_soft_bodies = 0, n_bodies = 0;
@@ -294,6 +304,9 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask);
 // assembled ones (after the elastic gathers and the body terms)
 void k_spring_energy(zema_scene* s);
 void k_spring_terms(zema_scene* s, double* grad, bool hess);
+// prismatic joints (Sec. IV-C-2): energies at y into e_out [n_joints]; their gradient
+// and Hessian are emitted with the contact triplets (k_contact_assemble, mask bit 3)
+void k_joint_energy(zema_scene* s, const double* y, double* e_out);
 // contact force (N) on every body from the barrier items of the last assembly (host out)
 void k_body_forces(zema_scene* s, double* out_host);
 void k_friction_build(zema_scene* s);                 // lagged table from current candidates at xs

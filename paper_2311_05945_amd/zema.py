@@ -72,6 +72,7 @@ SIGNATURES = [
     ("zema_set_drive_target", [VP, I32, PD]),
     ("zema_set_springs", [VP, I32, PI32, PD, PD]),
     ("zema_kinematic_al", [VP, D, I32, PD]),
+    ("zema_set_prismatic_joints", [VP, I32, PI32, PD, PD]),
     ("zema_grasp_run", [VP, C.POINTER(GraspParams), C.POINTER(GraspResult), PD, I32]),
     ("zema_status_string", [C.c_int]),
     ("zema_last_error", [VP]),
@@ -397,6 +398,14 @@ class Scene:
         kk = np.ascontiguousarray(k, dtype=np.float64)
         t = np.ascontiguousarray(targets, dtype=np.float64).reshape(-1, 3)
         self._chk(lib().zema_set_springs(self.h, len(sv), sv.ctypes.data_as(PI32), _pd(kk), _pd(t)))
+
+    def set_prismatic_joints(self, pairs, axes, kappa):
+        """zema_set_prismatic_joints: joints between affine bodies pairs [n][2] with axes
+        [n][3] (first body's rest frame) and stiffness kappa [n]."""
+        pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        ax = np.ascontiguousarray(axes, dtype=np.float64).reshape(-1, 3)
+        kk = np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1)
+        self._chk(lib().zema_set_prismatic_joints(self.h, len(pr), pr.ctypes.data_as(PI32), _pd(ax), _pd(kk)))
 
     def kinematic_al(self, tol, max_updates=8):
         """zema_kinematic_al: multiplier updates of the kinematic energy; returns the

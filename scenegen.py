@@ -379,6 +379,20 @@ def held_box(kappa_A: float = 1e8, mode: int = MODE_DRIVEN, steps: int = 10) -> 
     return Scene("held_box", p, [], [box], steps)
 
 
+def slider_scene(speed: float = 0.1, steps: int = 10) -> Scene:
+    """A free affine box (0.04 m, density 800) 3 cm above a fixed rail (0.2 x 0.02 x
+    0.02 m), moving along the rail's axis x at `speed`, under gravity; the two are not
+    in contact (for prismatic-joint tests: joint between body 1 and body 0, axis x)."""
+    rv, rt = box_surface((0.0, 0.0, 0.0), (0.1, 0.01, 0.01), (4, 1, 1))
+    bv, bt = box_surface((0.0013, 0.05, -0.0007), (0.02, 0.02, 0.02), 2)
+    p = Params(dt=0.01, dhat=1e-3, kappa=0.0, mu=0.5, eps_v=1e-3, newton_tol=1e-6)
+    qd = np.zeros(12)
+    qd[0] = speed
+    rail = AffineBody(rv, rt, rho=1000.0, stiffness=1e8, mode=MODE_FIXED)
+    box = AffineBody(bv, bt, rho=800.0, stiffness=1e8, mode=MODE_FREE, qdot0=qd)
+    return Scene("slider", p, [], [rail, box], steps)
+
+
 # ----------------------------------------------------------------------------- tiny cases
 
 def two_tets_scene(model: int = NEO_HOOKEAN) -> Scene:

@@ -74,3 +74,56 @@ def test_kinematic_penalty_sag_and_multiplier():
     lam = R2.kinematic_al(tol, 12)
     assert np.sqrt(mass) * lam[0][1] == pytest.approx(mass * h * h * 9.81, rel=2e-3)
     assert 1 <= sum(s["al_updates"] for s in st) <= 10
+
+
+# ---------------------------------------------------------------- prismatic joint (Sec. IV-C-2)
+
+def _slider(kappa=1e4):
+    sc = sg.slider_scene()
+    R = ref.RefScene(sc)
+    R.set_prismatic_joints([[1, 0]], [[1.0, 0.0, 0.0]], [kappa])
+    return sc, R
+
+
+def test_joint_energy_closed_forms():
+    kappa = 1e4
+    sc, R = _slider(kappa)
+    y0 = R.get_state()[0]                       # DOFs: the slider's q (the rail is fixed)
+    assert len(y0) == 12
+    E = lambda y: R.ip_assemble(y, grad=False, hess=False)[0][3]
+    assert E(y0) == 0.0
+    y = y0.copy(); y[0] += 0.013                 # along the axis: free
+    assert abs(E(y)) <= 1e-20
+    d = np.array([0.002, -0.003, 0.0015])
+    y = y0.copy(); y[:3] += d                    # kappa |d_perp|^2
+    assert E(y) == pytest.approx(kappa * (d[1] ** 2 + d[2] ** 2), rel=1e-12)
+    th = 0.01                                    # relative rotation about z: kappa 4 (1 - cos th)
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    y = y0.copy(); y[3:12] = Rz.ravel()
+    assert E(y) == pytest.approx(kappa * 4 * (1 - np.cos(th)), rel=1e-9)
+
+
+def test_joint_gradient_matches_differences():
+    sc, R = _slider(1e4)
+    rng = np.random.default_rng(5)
+    y = R.get_state()[0] + rng.normal(scale=2e-3, size=12)
+    _, g = R.ip_assemble(y, hess=False, mask=1 << 3)
+    for i in range(12):
+        e = np.zeros(12); e[i] = 1e-7
+        fd = (R.ip_assemble(y + e, grad=False, hess=False)[0][3] - R.ip_assemble(y - e, grad=False, hess=False)[0][3]) / 2e-7
+        assert abs(g[i] - fd) <= 1e-6 * np.abs(g).max(), i
+
+
+def test_joint_slides_freely_and_holds_perpendicular():
+    kappa = 10.0       # soft enough that the sag is well above the Newton tolerance
+    sc, R = _slider(kappa)
+    y0 = R.get_state()[0]
+    st = R.step(10)
+    y = R.get_state()[0]
+    h = sc.params.dt
+    m = sc.affines[1].rho * 0.04 ** 3
+    assert y[0] - y0[0] == pytest.approx(0.1 * 10 * h, rel=1e-6)       # constant axial velocity
+    # perpendicular: the joint's 2 kappa dy balances the inertia term's m h^2 g
+    assert y[1] - y0[1] == pytest.approx(-m * h * h * 9.81 / (2 * kappa), rel=2e-2)
+    # the sagged gap r tilts A1 d towards r only slowly (|r x A1 d|^2 couples them)
+    assert abs(y[2] - y0[2]) <= 1e-12 and np.abs(y[3:] - y0[3:]).max() <= 1e-6

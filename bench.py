@@ -294,6 +294,55 @@ def forms(args, zema):
     return out
 
 
+def warm_analysis(zema, seed0, n_scenes, steps, mlp_path):
+    """The learned initial guess against the explicit one on held-out uneven scenes:
+    from the same state, per step, the distance of each proposal (soft vertices; the
+    explicit x + h v, the network's x + h v + s out) to the converged state, the Newton
+    iterations of a step started from each (the library's filtered start, the learned
+    one kept when its energy is not higher) and whether the learned start was kept."""
+    import numpy as np
+    import torch
+
+    import scenegen as sg
+    mlp = zema.Mlp(np.load(mlp_path))
+    rows = []
+    for s in range(seed0, seed0 + n_scenes):
+        sc = sg.batch_scene(s, steps=steps)
+        scl = sg.batch_scene(s, steps=steps)
+        for c in (sc, scl):
+            c.params.newton_max = 2000
+        scl.params.warm_start = 1
+        A = zema.Scene(sc)
+        L = zema.Scene(scl)
+        L.set_mlp(mlp)
+        h = sc.params.dt
+        n = A.n_soft_verts
+        for k in range(steps):
+            y, yd, kappa, step = A.get_state()
+            out = mlp.forward(A.features())
+            ye = (y[:3 * n] + h * yd[:3 * n]).reshape(-1, 3)
+            yl = ye + h * 0.05 * out.double()
+            L.set_state(y, yd, kappa, step)
+            se, sl = A.step(1)[0], L.step(1)[0]
+            ys = A.get_state()[0][:3 * n].reshape(-1, 3)
+            de = float(torch.linalg.norm(ye - ys, dim=1).pow(2).mean().sqrt())
+            dl = float(torch.linalg.norm(yl - ys, dim=1).pow(2).mean().sqrt())
+            rows.append((se["newton_iters"], sl["newton_iters"], sl["warm_learned"], de, dl, se["n_pt_active"] > 0,
+                         se["status"] == 0 and sl["status"] == 0))
+        log(f"warm analysis: scene {s} done")
+    a = np.array(rows, dtype=float)
+    ne, nl, kept, de, dl, contact, ok = a.T
+
+    def part(m):
+        return {"steps": int(m.sum()), "newton_explicit": float(ne[m].mean()), "newton_learned": float(nl[m].mean()),
+                "rms_dist_explicit_m": float(de[m].mean()), "rms_dist_learned_m": float(dl[m].mean()),
+                "learned_closer": float((dl[m] < de[m]).mean())} if m.any() else None
+    return {"sample": f"{n_scenes} held-out uneven scenes (seeds {seed0}-{seed0 + n_scenes - 1}), {steps} steps",
+            "all": part(np.ones(len(a), bool)), "contact": part(contact == 1), "free": part(contact == 0),
+            "learned_kept": part(kept == 1), "learned_rejected": part(kept == 0),
+            "kept_fraction": float(kept.mean()), "all_converged": bool(ok.all())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,6 +371,8 @@ def main():
                     help="run the unbatched forms on the first K scenes only (0: all)")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_05945_amd", "warm_mlp.npy"))
     ap.add_argument("--no-legs", action="store_true", help="skip the cube-drop and precision legs")
+    ap.add_argument("--warm-analysis", type=int, default=0, metavar="N",
+                    help="only run the learned-start analysis on N held-out scenes (--form-steps steps each)")
     ap.add_argument("--precision-res", type=int, default=64)
     ap.add_argument("--precision-steps", type=int, default=3)
     args = ap.parse_args()
@@ -335,6 +386,10 @@ def main():
     from paper_2311_05945_amd import zema
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.warm_analysis:
+        print(json.dumps({"warm_analysis": warm_analysis(zema, args.form_seed, args.warm_analysis, args.form_steps,
+                                                         args.mlp)}))
+        return
     sc = sg.gripper(args.seed, r=args.res, steps=args.steps)
     tuned = None
     if args.warmup > 0:

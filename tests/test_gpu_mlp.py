@@ -223,3 +223,52 @@ def test_learned_steps_intersection_free(zema):
         y = B.get_state()[0].cpu().numpy()
         assert exact.count_intersections(R.surface_positions(y), tris, edges, vb) == 0
     log(f"learned start kept in {used}/10 steps")
+
+
+def test_learned_start_on_held_out_seeds(zema):
+    """What the trained network gains, on held-out uneven scenes (seeds 10000-10007, 12
+    steps each, from the same state per step): its proposal x + h v + s out is closer to
+    the converged state than the explicit x + h v in most steps (asserted: >= 80%; the
+    RMS distances are logged), both starts converge every step at the same tolerance
+    and end intersection-free.  Newton iterations per step of both are logged and the
+    learned form's are bounded by 1.3x the explicit form's: on these scenes a closer
+    start does not reduce the iteration count (measured 1.09x on 16 scenes x 16 steps;
+    the cause is discussed with the measurements)."""
+    import numpy as np
+    mlp = zema.Mlp(np.load("paper_2311_05945_amd/warm_mlp.npy"))
+    ne = nl = 0
+    closer = total = 0
+    de_sum = dl_sum = 0.0
+    for s in range(10000, 10008):
+        sc, scl = sg.batch_scene(s, steps=12), sg.batch_scene(s, steps=12)
+        for c in (sc, scl):
+            c.params.newton_max = 2000
+        scl.params.warm_start = 1
+        A, L = zema.Scene(sc), zema.Scene(scl)
+        L.set_mlp(mlp)
+        h = sc.params.dt
+        n = A.n_soft_verts
+        for k in range(12):
+            y, yd, kappa, step = A.get_state()
+            out = mlp.forward(A.features())
+            ye = (y[:3 * n] + h * yd[:3 * n]).reshape(-1, 3)
+            yl = ye + h * 0.05 * out.double()
+            L.set_state(y, yd, kappa, step)
+            se, sl = A.step(1)[0], L.step(1)[0]
+            assert se["status"] == 0 and sl["status"] == 0
+            ys = A.get_state()[0][:3 * n].reshape(-1, 3)
+            de = float(torch.linalg.norm(ye - ys, dim=1).pow(2).mean().sqrt())
+            dl = float(torch.linalg.norm(yl - ys, dim=1).pow(2).mean().sqrt())
+            closer += dl < de
+            total += 1
+            de_sum += de
+            dl_sum += dl
+            ne += se["newton_iters"]
+            nl += sl["newton_iters"]
+        for S in (A, L):
+            ni, nv, nu, _ = S.intersection_count(S.get_state()[0], cap=0)
+            assert ni == 0 and nv == 0 and nu == 0
+    log(f"held-out: learned proposal closer in {closer}/{total} steps (RMS {dl_sum / total:.2e} vs "
+        f"{de_sum / total:.2e} m); Newton iterations per step explicit {ne / total:.2f}, learned {nl / total:.2f}")
+    assert closer >= 0.8 * total
+    assert nl <= 1.3 * ne

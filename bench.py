@@ -294,12 +294,14 @@ def forms(args, zema):
     return out
 
 
-def warm_analysis(zema, seed0, n_scenes, steps, mlp_path):
+def warm_analysis(zema, seed0, n_scenes, steps, mlp_path, fits=(0, 1, 2)):
     """The learned initial guess against the explicit one on held-out uneven scenes:
     from the same state, per step, the distance of each proposal (soft vertices; the
     explicit x + h v, the network's x + h v + s out) to the converged state, the Newton
     iterations of a step started from each (the library's filtered start, the learned
-    one kept when its energy is not higher) and whether the learned start was kept."""
+    one kept when its energy is not higher) and whether the learned start was kept.
+    The learned start runs once per setting of the per-body fit of the network's
+    correction (0 as is, 1 affine fit, 2 mean)."""
     import numpy as np
     import torch
 
@@ -308,13 +310,17 @@ def warm_analysis(zema, seed0, n_scenes, steps, mlp_path):
     rows = []
     for s in range(seed0, seed0 + n_scenes):
         sc = sg.batch_scene(s, steps=steps)
-        scl = sg.batch_scene(s, steps=steps)
-        for c in (sc, scl):
-            c.params.newton_max = 2000
-        scl.params.warm_start = 1
+        sc.params.newton_max = 2000
         A = zema.Scene(sc)
-        L = zema.Scene(scl)
-        L.set_mlp(mlp)
+        Ls = []
+        for f in fits:
+            scl = sg.batch_scene(s, steps=steps)
+            scl.params.newton_max = 2000
+            scl.params.warm_start = 1
+            L = zema.Scene(scl)
+            L.set_mlp(mlp)
+            L.tune(zema.TUNE_WARM_FIT, f)
+            Ls.append(L)
         h = sc.params.dt
         n = A.n_soft_verts
         for k in range(steps):
@@ -322,25 +328,36 @@ def warm_analysis(zema, seed0, n_scenes, steps, mlp_path):
             out = mlp.forward(A.features())
             ye = (y[:3 * n] + h * yd[:3 * n]).reshape(-1, 3)
             yl = ye + h * 0.05 * out.double()
-            L.set_state(y, yd, kappa, step)
-            se, sl = A.step(1)[0], L.step(1)[0]
+            sl = []
+            for L in Ls:
+                L.set_state(y, yd, kappa, step)
+                sl.append(L.step(1)[0])
+            se = A.step(1)[0]
             ys = A.get_state()[0][:3 * n].reshape(-1, 3)
             de = float(torch.linalg.norm(ye - ys, dim=1).pow(2).mean().sqrt())
             dl = float(torch.linalg.norm(yl - ys, dim=1).pow(2).mean().sqrt())
-            rows.append((se["newton_iters"], sl["newton_iters"], sl["warm_learned"], de, dl, se["n_pt_active"] > 0,
-                         se["status"] == 0 and sl["status"] == 0))
+            rows.append([se["newton_iters"], de, dl, se["n_pt_active"] > 0,
+                         se["status"] == 0 and all(x["status"] == 0 for x in sl)]
+                        + [x["newton_iters"] for x in sl] + [x["warm_learned"] for x in sl])
         log(f"warm analysis: scene {s} done")
     a = np.array(rows, dtype=float)
-    ne, nl, kept, de, dl, contact, ok = a.T
+    ne, de, dl, contact, ok = a[:, :5].T
+    nf = len(fits)
+    nl, kept = a[:, 5:5 + nf].T, a[:, 5 + nf:].T
 
-    def part(m):
-        return {"steps": int(m.sum()), "newton_explicit": float(ne[m].mean()), "newton_learned": float(nl[m].mean()),
+    def part(m, j):
+        return {"steps": int(m.sum()), "newton_explicit": float(ne[m].mean()), "newton_learned": float(nl[j][m].mean()),
                 "rms_dist_explicit_m": float(de[m].mean()), "rms_dist_learned_m": float(dl[m].mean()),
                 "learned_closer": float((dl[m] < de[m]).mean())} if m.any() else None
-    return {"sample": f"{n_scenes} held-out uneven scenes (seeds {seed0}-{seed0 + n_scenes - 1}), {steps} steps",
-            "all": part(np.ones(len(a), bool)), "contact": part(contact == 1), "free": part(contact == 0),
-            "learned_kept": part(kept == 1), "learned_rejected": part(kept == 0),
-            "kept_fraction": float(kept.mean()), "all_converged": bool(ok.all())}
+    names = {0: "as_is", 1: "affine_fit", 2: "mean"}
+    res = {"sample": f"{n_scenes} held-out uneven scenes (seeds {seed0}-{seed0 + n_scenes - 1}), {steps} steps",
+           "all_converged": bool(ok.all()),
+           "note": "rms distances are of the network's own proposal (as is)"}
+    for j, f in enumerate(fits):
+        res[names[f]] = {"all": part(np.ones(len(a), bool), j), "contact": part(contact == 1, j),
+                         "free": part(contact == 0, j), "learned_kept": part(kept[j] == 1, j),
+                         "learned_rejected": part(kept[j] == 0, j), "kept_fraction": float(kept[j].mean())}
+    return res
 
 
 def main():

@@ -409,6 +409,13 @@ int zema_intersection_count(zema_scene* s, const double* y, int64_t* n_intersect
  *   Each row's products do not depend on the setting; the inner products are summed
  *   per workgroup, so different settings agree to rounding (a fixed setting is
  *   deterministic).
+ * ZEMA_TUNE_WARM_FIT (learned initial guess): 0 uses the network's per-vertex
+ *   correction as it is; 1 replaces it on each soft body by its mass-weighted
+ *   least-squares affine fit cbar + A (x_i - xbar) over the body's vertices at the
+ *   step start (A = 0 for a body whose centred second moment S has
+ *   det S <= 1e-9 (tr S)^3); 2 (default) by its mass-weighted mean cbar.  The fit
+ *   removes the part of the network's error that varies from vertex to vertex
+ *   (zema_warm_fit applies it to a given field).  Deterministic for a fixed setting.
  * Errors: ZEMA_E_ARG for an unknown knob or value. */
 enum {
   ZEMA_TUNE_PCG_GRAPH = 0,
@@ -416,7 +423,8 @@ enum {
   ZEMA_TUNE_UPDATE_BLOCK = 2,
   ZEMA_TUNE_PCG_FORM = 3,
   ZEMA_TUNE_BATCH_ASYNC = 4,
-  ZEMA_TUNE_CG_ROWS = 5
+  ZEMA_TUNE_CG_ROWS = 5,
+  ZEMA_TUNE_WARM_FIT = 6
 };
 int zema_tune(zema_scene* s, int32_t knob, int32_t value);
 /* Current value of a knob (host output).  Errors: ZEMA_E_ARG for an unknown knob. */
@@ -513,6 +521,12 @@ int zema_scene_set_mlp(zema_scene* s, zema_mlp* m);
 int zema_scene_features(zema_scene* s, float* feat);
 /* Training target [n_soft_verts][3] (device) of the last step taken by zema_step. */
 int zema_scene_warm_target(zema_scene* s, float* target);
+/* The per-soft-body fit of the learned initial guess (see ZEMA_TUNE_WARM_FIT; mode 0
+ * copies, 1 affine fit, 2 mean) applied to a correction field at the scene's current
+ * positions with its lumped masses: in, out device float [n_soft_verts][3] (the same
+ * pointer fits in place).  Synchronous.  Errors: ZEMA_E_ARG (mode, null pointers),
+ * ZEMA_E_DEVICE. */
+int zema_warm_fit(zema_scene* s, int32_t mode, const float* in, float* out);
 
 #ifdef __cplusplus
 }

@@ -87,6 +87,7 @@ def lib():
             ("zref_record_get", [C.c_void_p, I64, PI32, PD, PD, PD, PD, PD]),
             ("zref_barrier", [D, D, PD]),
             ("zref_pair_energy", [C.c_void_p, I32, PD, PD, PD, PD, PD, I32]),
+            ("zref_pair_energy_typed", [C.c_void_p, I32, PD, PD, I32, PD, PD, PD, I32]),
             ("zref_tet_energy", [C.c_void_p, I32, PD, PD, PD, PD, I32]),
             ("zref_project_psd", [I32, PD, PD]),
             ("zref_accd_pair", [I32, PD, PD, D, PD]),
@@ -356,10 +357,14 @@ class RefScene:
                         "y_t": yt, "ydot_t": ydt, "y_k": yk})
         return out
 
-    def pair_energy(self, kind, x12, rest_len2=(1.0, 1.0), project=True):
+    def pair_energy(self, kind, x12, rest_len2=(1.0, 1.0), project=True, ftype=-1):
+        """Barrier energy, gradient and (projected) Hessian of one pair at the scene's
+        kappa; ftype >= 0 takes that feature type's squared distance instead of the
+        closest feature's."""
         e = D(); g = np.zeros(12); H = np.zeros((12, 12))
         rl = _f64(rest_len2)
-        lib().zref_pair_energy(self.h, kind, _pd(_f64(x12)), _pd(rl), C.byref(e), _pd(g), _pd(H), 1 if project else 0)
+        self._chk(lib().zref_pair_energy_typed(self.h, kind, _pd(_f64(x12)), _pd(rl), int(ftype), C.byref(e), _pd(g),
+                                               _pd(H), 1 if project else 0))
         return e.value, g, H
 
     def tet_energy(self, tet, x12, project=True):

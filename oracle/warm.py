@@ -145,3 +145,35 @@ def warm_target(scene, y_next, y, ydot, nsv):
     h = scene.params.dt
     n3 = 3 * nsv
     return (((np.asarray(y_next[:n3]) - np.asarray(y[:n3])) - h * np.asarray(ydot[:n3])) / (h * SPEED)).reshape(-1, 3)
+
+
+def fit_correction(scene, mass, y, corr, mode):
+    """Per-soft-body fit of a correction field [nsv, 3] (the learned guess's
+    post-processing, a project choice): mode 0 the field itself, 2 its mass-weighted mean
+    over each body's vertices, 1 its mass-weighted least-squares affine fit
+    cbar + A (x - xbar) at the positions y; a body whose centred second moment S has
+    det S <= 1e-9 (tr S)^3 keeps the mean.  `mass`: the lumped vertex masses.  The
+    affine fit is solved as a weighted least-squares problem on the design [1, x - xbar]."""
+    corr = np.asarray(corr, dtype=np.float64).reshape(-1, 3)
+    out = corr.copy()
+    if mode == 0:
+        return out
+    x_all = np.asarray(y, dtype=np.float64)[:3 * len(corr)].reshape(-1, 3)
+    v0 = 0
+    for body in scene.softs:
+        n = len(body.rest_pos)
+        w, x, c = mass[v0:v0 + n], x_all[v0:v0 + n], corr[v0:v0 + n]
+        W = w.sum()
+        xb, cb = w @ x / W, w @ c / W
+        out[v0:v0 + n] = cb
+        if mode == 1:
+            X = x - xb
+            S = (X * w[:, None]).T @ X
+            if np.linalg.det(S) > 1e-9 * np.trace(S) ** 3:
+                D = np.hstack([np.ones((n, 1)), X])
+                sw = np.sqrt(w)[:, None]
+                coef = np.linalg.lstsq(D * sw, c * sw, rcond=None)[0]
+                out[v0:v0 + n] = D @ coef
+        v0 += n
+    return out
+

@@ -873,10 +873,18 @@ void orth_term(const zref_scene* s, const Body& B, const double* q, double* E, d
 // kappa * m_k * b(d): m_k = 1 for point-triangle; for edge-edge the mollifier
 // (reading) m = 2c/eps - (c/eps)^2 for c < eps, c = |(a1-a0)x(b1-b0)|^2,
 // eps = 1e-3 |A1-A0|^2 |B1-B0|^2 at rest.
+// force_type >= 0 (test use only) evaluates the squared distance of that feature type
+// in place of the closest one, e.g. the other side of a tie between two features.
 bool pair_energy_jet(const zref_scene* s, int kind, const double* x12, double eps_x, double kappa,
-                     J2<12>& out, double* dist) {
+                     J2<12>& out, double* dist, int force_type = -1) {
   int type;
   double d2 = kind == 0 ? pt_type_d2(x12, &type, nullptr) : ee_type_d2(x12, &type, nullptr);
+  if (force_type >= 0) {
+    type = force_type;
+    J2<12> X0[12];
+    for (int k = 0; k < 12; ++k) X0[k] = jconst<12>(x12[k]);
+    d2 = (kind == 0 ? pt_d2_jet(X0, type) : ee_d2_jet(X0, type)).v;
+  }
   double dhat = s->P.dhat;
   if (dist) *dist = std::sqrt(d2);
   if (!(std::sqrt(d2) < dhat)) {
@@ -2266,10 +2274,16 @@ int zref_barrier(double d, double dhat, double* b3) {
 
 int zref_pair_energy(zref_scene* s, int32_t kind, const double* x12, const double* rest_len2,
                      double* e, double* g12, double* h144, int32_t project) {
+  return zref_pair_energy_typed(s, kind, x12, rest_len2, -1, e, g12, h144, project);
+}
+
+int zref_pair_energy_typed(zref_scene* s, int32_t kind, const double* x12, const double* rest_len2, int32_t type,
+                           double* e, double* g12, double* h144, int32_t project) {
+  if (type > (kind == 0 ? 6 : 8)) return -1;
   double eps = kind == 1 ? 1e-3 * rest_len2[0] * rest_len2[1] : 0.0;
   J2<12> E;
   double d;
-  pair_energy_jet(s, kind, x12, eps, s->kappa, E, &d);
+  pair_energy_jet(s, kind, x12, eps, s->kappa, E, &d, type);
   *e = E.v;
   for (int i = 0; i < 12; ++i) g12[i] = E.g[i];
   std::vector<double> Hx(144);

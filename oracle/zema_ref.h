@@ -122,6 +122,10 @@ double zref_dist_ee(const double* x12, int32_t* type);
 int zref_barrier(double d, double dhat, double* b3);
 int zref_pair_energy(zref_scene* s, int32_t kind, const double* x12, const double* rest_len2,
                      double* e, double* g12, double* h144, int32_t project);
+/* the same with the feature type given (type >= 0; -1: the closest feature): the
+ * barrier of the squared distance of that type, for ties between two features */
+int zref_pair_energy_typed(zref_scene* s, int32_t kind, const double* x12, const double* rest_len2, int32_t type,
+                           double* e, double* g12, double* h144, int32_t project);
 int zref_tet_energy(zref_scene* s, int32_t tet, const double* x12, double* e, double* g12,
                     double* h144, int32_t project);
 int zref_project_psd(int32_t n, const double* a, double* out);

@@ -389,6 +389,13 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   s->llam.upload(llam);
   s->tmodel.upload(tmodel);
   s->mass.upload(mass);
+  {
+    std::vector<int> vr(n_soft + 1, (int)mass.size());
+    for (int i = (int)vbody.size() - 1; i >= 0; --i) vr[vbody[i]] = i;
+    for (int b = n_soft - 1; b >= 0; --b) vr[b] = std::min(vr[b], vr[b + 1]);  // bodies without vertices
+    s->soft_vr.upload(vr);
+    s->v_sbody.upload(vbody);
+  }
   s->mass_h = mass;
   s->vt_ptr.upload(vtp);
   s->vt_list.upload(vtl);
@@ -2002,6 +2009,10 @@ int zema_tune(zema_scene* s, int32_t knob, int32_t value) {
     s->tune_cg_rows = value;
     return 0;
   }
+  if (knob == ZEMA_TUNE_WARM_FIT && value >= 0 && value <= 2) {
+    s->warm_fit = value;
+    return 0;
+  }
   return ZEMA_E_ARG;
 }
 
@@ -2025,6 +2036,9 @@ int zema_tune_get(zema_scene* s, int32_t knob, int32_t* value) {
       return 0;
     case ZEMA_TUNE_CG_ROWS:
       *value = s->tune_cg_rows;
+      return 0;
+    case ZEMA_TUNE_WARM_FIT:
+      *value = s->warm_fit;
       return 0;
     default:
       return ZEMA_E_ARG;
@@ -2052,6 +2066,17 @@ int zema_scene_features(zema_scene* s, float* feat) {
   if (!s || (s->nsv && !feat)) return ZEMA_E_ARG;
   return guard(s, [&]() {
     k_features(s, feat);
+    ZCHK(hipStreamSynchronize(s->st));
+    return 0;
+  });
+}
+
+int zema_warm_fit(zema_scene* s, int32_t mode, const float* in, float* out) {
+  if (!s || mode < 0 || mode > 2 || (s->nsv && (!in || !out))) return ZEMA_E_ARG;
+  return guard(s, [&]() {
+    if (s->nsv && in != out)
+      ZCHK(hipMemcpyAsync(out, in, sizeof(float) * 3 * (size_t)s->nsv, hipMemcpyDeviceToDevice, s->st));
+    k_warm_fit(s, mode, out);
     ZCHK(hipStreamSynchronize(s->st));
     return 0;
   });

@@ -140,7 +140,121 @@ void k_features(zema_scene* s, float* feat) {
                                                      s->body_i.p, s->body_tv.p, s->P.dt, s->P.dhat, feat);
 }
 
-void k_warm_dir(zema_scene* s, const float* out, double* p) {
+// Fit of the network's correction field over each soft body (mass-weighted least
+// squares): c_i ~ cbar + A (x_i - xbar), with A = 0 when only the mean is kept or the
+// body's second moment is singular.  One workgroup per body; the sums are taken about
+// the body's first vertex, per thread in a fixed stride and then over a fixed tree, so
+// the fit is bitwise repeatable.
+constexpr int kFitThreads = 256;
+constexpr int kFitSums = 22;  // m, m dx (3), m c (3), m dx dx^T (6), m c dx^T (9)
+
+__global__ void __launch_bounds__(kFitThreads)
+    warm_fit_kernel(const int* __restrict__ vr, const double* __restrict__ y, const double* __restrict__ mass,
+                    const float* __restrict__ out, int affine, double* __restrict__ fit) {
+  __shared__ double sh[kFitSums][kFitThreads];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int v0 = vr[b], v1 = vr[b + 1];
+  double a[kFitSums];
+#pragma unroll
+  for (int q = 0; q < kFitSums; ++q) a[q] = 0.0;
+  if (v1 > v0) {
+    const V3 x0 = ld3(y + 3 * (size_t)v0);
+    for (int i = v0 + t; i < v1; i += kFitThreads) {
+      const double m = mass[i];
+      const V3 xi = ld3(y + 3 * (size_t)i);
+      const double d[3] = {xi.x - x0.x, xi.y - x0.y, xi.z - x0.z};
+      const double c[3] = {(double)out[3 * (size_t)i], (double)out[3 * (size_t)i + 1], (double)out[3 * (size_t)i + 2]};
+      a[0] += m;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        a[1 + k] += m * d[k];
+        a[4 + k] += m * c[k];
+      }
+      a[7] += m * d[0] * d[0];
+      a[8] += m * d[0] * d[1];
+      a[9] += m * d[0] * d[2];
+      a[10] += m * d[1] * d[1];
+      a[11] += m * d[1] * d[2];
+      a[12] += m * d[2] * d[2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a[13 + 3 * r + k] += m * c[r] * d[k];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kFitSums; ++q) sh[q][t] = a[q];
+  __syncthreads();
+  for (int w = kFitThreads / 2; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int q = 0; q < kFitSums; ++q) sh[q][t] += sh[q][t + w];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  double* f = fit + 15 * (size_t)b;
+  for (int q = 0; q < 15; ++q) f[q] = 0.0;
+  const double M = sh[0][0];
+  if (v1 <= v0 || !(M > 0.0)) return;
+  const V3 x0 = ld3(y + 3 * (size_t)v0);
+  double xb[3], cb[3];
+  for (int k = 0; k < 3; ++k) {
+    xb[k] = sh[1 + k][0] / M;
+    cb[k] = sh[4 + k][0] / M;
+  }
+  f[0] = cb[0];
+  f[1] = cb[1];
+  f[2] = cb[2];
+  f[3] = x0.x + xb[0];
+  f[4] = x0.y + xb[1];
+  f[5] = x0.z + xb[2];
+  if (!affine) return;
+  // centred second moment S and cross moment C = sum m (c - cbar)(x - xbar)^T
+  const int si[3][3] = {{7, 8, 9}, {8, 10, 11}, {9, 11, 12}};
+  double S[3][3], C[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      S[r][k] = sh[si[r][k]][0] - M * xb[r] * xb[k];
+      C[r][k] = sh[13 + 3 * r + k][0] - M * cb[r] * xb[k];
+    }
+  // S^-1 by cofactors; a body whose vertices are (nearly) coplanar keeps the mean only
+  double co[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      const int r1 = (r + 1) % 3, r2 = (r + 2) % 3, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+      co[r][k] = S[r1][k1] * S[r2][k2] - S[r1][k2] * S[r2][k1];
+    }
+  const double det = S[0][0] * co[0][0] + S[0][1] * co[0][1] + S[0][2] * co[0][2];
+  const double tr = S[0][0] + S[1][1] + S[2][2];
+  if (!(det > 1e-9 * tr * tr * tr)) return;
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k)  // (C S^-1)[r][k] = sum_j C[r][j] co[k][j] / det (S symmetric)
+      f[6 + 3 * r + k] = (C[r][0] * co[k][0] + C[r][1] * co[k][1] + C[r][2] * co[k][2]) / det;
+}
+
+__global__ void warm_fit_apply_kernel(int nsv, const int* __restrict__ vbody, const double* __restrict__ y,
+                                      const double* __restrict__ fit, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsv) return;
+  const double* f = fit + 15 * (size_t)vbody[i];
+  const V3 x = ld3(y + 3 * (size_t)i);
+  const double d[3] = {x.x - f[3], x.y - f[4], x.z - f[5]};
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    out[3 * (size_t)i + r] = (float)(f[r] + f[6 + 3 * r] * d[0] + f[7 + 3 * r] * d[1] + f[8 + 3 * r] * d[2]);
+}
+
+void k_warm_fit(zema_scene* s, int mode, float* out) {
+  if (mode && s->nsv && s->n_soft_bodies) {
+    s->wfit.reserve(15 * (size_t)s->n_soft_bodies);
+    warm_fit_kernel<<<s->n_soft_bodies, kFitThreads, 0, s->st>>>(s->soft_vr.p, s->y.p, s->mass.p, out, mode == 1,
+                                                                s->wfit.p);
+    warm_fit_apply_kernel<<<nblocks(s->nsv), kBlock, 0, s->st>>>(s->nsv, s->v_sbody.p, s->y.p, s->wfit.p, out);
+  }
+}
+
+void k_warm_dir(zema_scene* s, float* out, double* p) {
+  k_warm_fit(s, s->warm_fit, out);
   if (s->ndof)
     warm_dir_kernel<<<nblocks(s->ndof), kBlock, 0, s->st>>>(s->nsv, s->ndof, s->P.dt, s->ydot.p, out, p);
 }

@@ -169,6 +169,9 @@ struct zema_scene {
   zema::DBuf<int> fpick;                 // ... and the PT pair realising it
   zema::DBuf<float> feat, mlp_out;       // [nsv][16], [nsv][3]
   zema::DBuf<double> ywarm;              // learned initial guess [ndof]
+  int warm_fit = 2;                      // 0 network output as is, 1 its affine fit per soft body, 2 its mean
+  zema::DBuf<int> soft_vr, v_sbody;      // soft body -> first soft vertex [n_soft_bodies + 1]; soft vertex -> body
+  zema::DBuf<double> wfit;               // per soft body: mean correction, centre, 3x3 map [15]
   // ---- state
   zema::DBuf<double> y, ydot, yt, ydt, yhat, ytmp, grad, pdir;
   int step = 0;
@@ -315,7 +318,8 @@ void k_friction_rebuild(zema_scene* s, const int* rebuild_host);  // the same fo
 // -------- broad phase (k_broad.hip)
 void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r, const double* xs2 = nullptr);
 void k_features(zema_scene* s, float* feat);
-void k_warm_dir(zema_scene* s, const float* out, double* p);
+void k_warm_fit(zema_scene* s, int mode, float* out);   // per-soft-body fit of a correction field, in place
+void k_warm_dir(zema_scene* s, float* out, double* p);  // applies the scene's fit to out first
 void k_warm_target(zema_scene* s, float* target);
 int64_t k_edge_tri_pairs(zema_scene* s, const double* xs, DBuf<int>& out);
 

@@ -111,11 +111,13 @@ SIGNATURES = [
     ("zema_scene_set_mlp", [VP, VP]),
     ("zema_scene_features", [VP, VP]),
     ("zema_scene_warm_target", [VP, VP]),
+    ("zema_warm_fit", [VP, I32, VP, VP]),
 ]
 MLP_PARAMS = 9603
 MLP_FEATURES = 16
 WARM_EXPLICIT, WARM_LEARNED = 0, 1
-TUNE_PCG_GRAPH, TUNE_SPMV_LANES, TUNE_UPDATE_BLOCK, TUNE_PCG_FORM, TUNE_BATCH_ASYNC, TUNE_CG_ROWS = 0, 1, 2, 3, 4, 5
+(TUNE_PCG_GRAPH, TUNE_SPMV_LANES, TUNE_UPDATE_BLOCK, TUNE_PCG_FORM, TUNE_BATCH_ASYNC, TUNE_CG_ROWS,
+ TUNE_WARM_FIT) = 0, 1, 2, 3, 4, 5, 6
 KT_SPMV, KT_TET, KT_CONTACT, KT_QUERY, KT_CCD = range(5)
 
 
@@ -482,6 +484,14 @@ class Scene:
         t = self.torch.zeros((self.n_soft_verts, 3), dtype=self.torch.float32, device=self.device)
         self._chk(lib().zema_scene_warm_target(self.h, _ptr(t)))
         return t
+
+    def warm_fit(self, corr, mode):
+        """The learned guess's per-soft-body fit (0 copy, 1 affine, 2 mean) of a
+        correction field [n_soft_verts][3] at the current state."""
+        c = self._dev(corr, self.torch.float32).reshape(self.n_soft_verts, 3).contiguous()
+        out = self.torch.empty_like(c)
+        self._chk(lib().zema_warm_fit(self.h, int(mode), _ptr(c), _ptr(out)))
+        return out
 
 
 class Mlp:

@@ -232,8 +232,10 @@ def test_learned_start_on_held_out_seeds(zema):
     RMS distances are logged), both starts converge every step at the same tolerance
     and end intersection-free.  Newton iterations per step of both are logged and the
     learned form's are bounded by 1.3x the explicit form's: on these scenes a closer
-    start does not reduce the iteration count (measured 1.09x on 16 scenes x 16 steps;
-    the cause is discussed with the measurements)."""
+    start does not reduce the iteration count (measured on 16 scenes x 16 steps: 1.09x
+    with the network's field as it is, 1.04x with its per-body mean, the library's
+    default; the cause is discussed with the measurements).  The closeness is that of
+    the network's own field."""
     import numpy as np
     mlp = zema.Mlp(np.load("paper_2311_05945_amd/warm_mlp.npy"))
     ne = nl = 0
@@ -272,3 +274,38 @@ def test_learned_start_on_held_out_seeds(zema):
         f"{de_sum / total:.2e} m); Newton iterations per step explicit {ne / total:.2f}, learned {nl / total:.2f}")
     assert closer >= 0.8 * total
     assert nl <= 1.3 * ne
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_warm_fit_matches_oracle(zema, mode):
+    """The per-soft-body fit of a correction field (zema_warm_fit, the kernels the
+    learned step runs) against the oracle's weighted least squares, on a scene of two
+    soft bodies (the soft cube and a sheared copy) at a perturbed state, for a random
+    field and for a per-body affine field (reproduced by the affine fit): within
+    1e-5 of the field's largest entry (FP32 output)."""
+    from test_oracle_warm import two_bodies
+    sc = two_bodies()
+    R = ref.RefScene(sc)
+    G = zema.Scene(sc)
+    y, yd, _, _ = R.get_state()
+    n = R.n_soft_verts
+    rng = np.random.default_rng(11 + mode)
+    y = y.copy()
+    y[:3 * n] += rng.normal(scale=2e-3, size=3 * n)
+    G.set_state(y, yd)
+    m = R.lumped_mass()
+    x = y[:3 * n].reshape(-1, 3)
+    n0 = len(sc.softs[0].rest_pos)
+    aff = np.zeros((n, 3), np.float32)
+    for sl in (slice(0, n0), slice(n0, n)):
+        aff[sl] = rng.normal(size=3) + (x[sl] - x[sl].mean(0)) @ rng.normal(size=(3, 3)).T * 10.0
+    for c in (rng.normal(size=(n, 3)).astype(np.float32), aff):
+        got = G.warm_fit(c, mode).cpu().numpy().astype(np.float64)
+        want = warm.fit_correction(sc, m, y, c.astype(np.float64), mode)
+        err = np.abs(got - want).max() / np.abs(c).max()
+        log(f"mode {mode}: fit err {err:.2e} of the field's largest entry")
+        if mode == 0:
+            assert np.array_equal(got, c.astype(np.float64))
+        assert err <= 1e-5
+    assert np.abs(G.warm_fit(aff, 1).cpu().numpy() - aff).max() <= 1e-5 * np.abs(aff).max()
+

@@ -55,20 +55,28 @@ def check_terms(tg, tr, ctx="", floor=0.0):
     assert tg[7] == pytest.approx(tr[7], rel=1e-9, abs=0), f"{ctx} min distance"
 
 
-def check_grad_terms(G, R, y, ctx="", y_t=None):
+def check_grad_terms(G, R, y, ctx="", y_t=None, affine_floor=0.0):
     """Per-term gradients: |g_gpu - g_ref|_inf <= 1e-9 max(|g_term|_inf, 1e-3 S); the total
     gradient to 1e-9 S.  S = max(largest term gradient at y, inertia gradient at the
     step start y^t = |M (y^t - yhat)|_inf, the gravity-and-velocity scale of the step).
 
     The floor matters only where a term's gradient is rounding noise (the elastic
-    gradient of an unstrained body) or where the terms cancel (a converged iterate)."""
+    gradient of an unstrained body) or where the terms cancel (a converged iterate).
+    `affine_floor` is an absolute allowance on the affine DOFs of the total and of the
+    kinematic term, for states where a driven body sits on its target up to rounding."""
+    n3 = 3 * R.n_soft_verts
+
+    def err(d):
+        d = np.abs(d)
+        ea = max(d[n3:].max() - affine_floor, 0.0) if len(d) > n3 else 0.0
+        return max(d[:n3].max() if n3 else 0.0, ea)
     ref_g = [R.ip_assemble(y, hess=False, mask=1 << k)[1] for k in range(6)]
     S = max(np.abs(g).max() for g in ref_g)
     if y_t is not None:
         S = max(S, np.abs(R.ip_assemble(y_t, hess=False, mask=1)[1]).max())
     _, g_all = R.ip_assemble(y, hess=False)
     _, gg_all = G.ip_assemble(y, hess=False)
-    rel_all = np.abs(gg_all.cpu().numpy() - g_all).max() / S
+    rel_all = err(gg_all.cpu().numpy() - g_all) / S
     assert rel_all <= 1e-9, f"{ctx} total gradient err {rel_all:.3e} of the largest term"
     worst = rel_all
     for k in range(6):
@@ -76,17 +84,21 @@ def check_grad_terms(G, R, y, ctx="", y_t=None):
         _, gg = G.ip_assemble(y, hess=False, mask=1 << k)
         gg = gg.cpu().numpy()
         scale = max(np.abs(gr).max(), 1e-3 * S)
-        err = np.abs(gg - gr).max()
+        e = err(gg - gr) if k == 3 else np.abs(gg - gr).max()
         if scale == 0.0:
-            assert err == 0.0, f"{ctx} {TERMS[k]} gradient should vanish"
+            assert e == 0.0, f"{ctx} {TERMS[k]} gradient should vanish"
             continue
-        rel = err / scale
+        rel = e / scale
         worst = max(worst, rel)
         assert rel <= 1e-9, f"{ctx} {TERMS[k]} gradient rel err {rel:.3e}"
     return worst
 
 
-def check_hv(G, R, y, seed, ctx="", masks=(0,) + tuple(1 << k for k in range(6))):
+def check_hv(G, R, y, seed, ctx="", masks=(0,) + tuple(1 << k for k in range(6)), tols=None):
+    """H v of the library against the oracle's for random v, per term mask, within
+    1e-9 of |H v|_inf (or tols[mask] where a caller derives a looser bound from the
+    conditioning of the state)."""
+    tols = tols or {}
     rng = np.random.default_rng(seed)
     worst = 0.0
     for m in masks:
@@ -102,7 +114,7 @@ def check_hv(G, R, y, seed, ctx="", masks=(0,) + tuple(1 << k for k in range(6))
                 continue
             rel = np.abs(hg - hr).max() / scale
             worst = max(worst, rel)
-            assert rel <= 1e-9, f"{ctx} mask {m}: H v rel err {rel:.3e}"
+            assert rel <= tols.get(m, 1e-9), f"{ctx} mask {m}: H v rel err {rel:.3e}"
     return worst
 
 
@@ -277,17 +289,27 @@ def gripper_contact_state(sc, R, squeeze=0.5, noise=3e-5, seed=0):
     return y, yd
 
 
-@pytest.fixture(scope="module")
-def gripper_full():
-    sc = sg.gripper(0)
+def _gripper_at_contact(seed):
+    sc = sg.gripper(seed)
     R = ref.RefScene(sc)
-    y, yd = gripper_contact_state(sc, R)
+    y, yd = gripper_contact_state(sc, R, seed=seed)
     R.set_state(y, yd)
     return sc, R, y, yd
 
 
-def test_gripper_full_size_candidates(zema, gripper_full):
-    sc, R, y, yd = gripper_full
+@pytest.fixture(scope="module")
+def gripper_full():
+    return _gripper_at_contact(0)
+
+
+@pytest.fixture(scope="module", params=[0, 1, 2, 3, 4])
+def gripper_seeded(request):
+    """Gripper scenes of seeds 0-4 (semi-axes drawn per seed), fingers at contact."""
+    return _gripper_at_contact(request.param)
+
+
+def test_gripper_full_size_candidates(zema, gripper_seeded):
+    sc, R, y, yd = gripper_seeded
     G = zema.Scene(sc)
     xs = R.surface_positions(y)
     log(f"gripper: {R.n_tets} tets, {R.n_surf} surface vertices, {R.n_tris} tris, {R.n_edges} edges")
@@ -302,8 +324,8 @@ def test_gripper_full_size_candidates(zema, gripper_full):
     assert np.array_equal(pg.cpu().numpy(), pr) and np.array_equal(eg.cpu().numpy(), er)
 
 
-def test_gripper_full_size_energy_gradient_hv(zema, gripper_full):
-    sc, R, y, yd = gripper_full
+def test_gripper_full_size_energy_gradient_hv(zema, gripper_seeded):
+    sc, R, y, yd = gripper_seeded
     G = zema.Scene(sc)
     G.set_state(y, yd)
     tr, _ = R.ip_assemble(y, hess=False)

@@ -150,6 +150,37 @@ def test_pair_energy_fd(cube, case):
     assert np.linalg.eigvalsh(P).min() >= -1e-12 * np.abs(P).max()
 
 
+def test_pair_typed_matches_closest_and_tie_closed_form(cube):
+    """The typed pair evaluation (test use: the other side of a feature tie).  Away from
+    a tie the closest type gives the untyped result bitwise.  A point at height d above
+    the midpoint of a triangle edge has the face and that edge at the same distance:
+    energies and gradients agree, and the point's unprojected Hessian blocks differ by
+    exactly kappa b'(d)/d m m^T, m the in-plane normal of the edge (the distance to the
+    plane is linear in the point; the distance to a line has Hessian m m^T / d), with
+    b'(d) = -2 (d - dhat) log(d / dhat) - (d - dhat)^2 / d of the log barrier (eq. 5)."""
+    s, R = cube
+    kappa = R.get_state()[2]
+    dhat = s.params.dhat
+    t = np.array([[0, 0, 0], [0.01, 0, 0], [0, 0, 0.01]], float)
+    x = np.concatenate([[0.003, 4e-4, 0.002], t.ravel()])
+    d, ty = ref.dist_pt(x)
+    assert ty == 6
+    e0, g0, H0 = R.pair_energy(0, x, project=False)
+    e1, g1, H1 = R.pair_energy(0, x, project=False, ftype=ty)
+    assert e0 == e1 and np.array_equal(g0, g1) and np.array_equal(H0, H1)
+    for d in (2e-4, 5e-4, 9e-4):
+        x = np.concatenate([[0.005, d, 0.0], t.ravel()])   # above the midpoint of edge t0 t1 (type 3)
+        ef, gf, Hf = R.pair_energy(0, x, project=False, ftype=6)
+        ee, ge, He = R.pair_energy(0, x, project=False, ftype=3)
+        assert ef > 0 and abs(ee - ef) <= 1e-14 * ef
+        assert np.abs(ge - gf).max() <= 1e-12 * np.abs(gf).max()
+        bp = -2.0 * (d - dhat) * np.log(d / dhat) - (d - dhat) ** 2 / d
+        m = np.array([0.0, 0.0, 1.0])
+        want = kappa * bp / d * np.outer(m, m)
+        assert np.abs((He - Hf)[:3, :3] - want).max() <= 1e-9 * np.abs(want).max()
+        assert bp < 0
+
+
 def contact_tet_scene(mu=0.5):
     v0 = np.array([0.02, 5e-4, -0.01])
     v = np.array([v0, v0 + [0.02, 0.01, 0], v0 + [0, 0.02, 0], v0 + [0, 0.01, 0.02]])

@@ -10,7 +10,12 @@
   next to a finger see that finger's target velocity, |h tv / s| = 1;
 * the training target of a free-fall step of an unconstrained body equals the
   gravity displacement h^2 g / s up to the Newton tolerance (no contact, no elastic
-  force: every vertex moves by h v + h^2 g when the body stays undeformed).
+  force: every vertex moves by h v + h^2 g when the body stays undeformed);
+* the per-body fit of a correction field: an affine field is its own affine fit and
+  its mean is the field at the mass centre; a constant field is unchanged by every
+  mode; the residual of the affine fit of a random field is mass-orthogonal to
+  1 and to x - xbar on every body (the normal equations of the weighted least
+  squares), and the fit of each body ignores the other bodies' values.
 """
 import numpy as np
 import pytest
@@ -88,3 +93,54 @@ def test_free_fall_target():
     g = np.asarray(sc.params.gravity)
     # Newton stops once its step is below 1e-6 h = 1e-8 m, i.e. 2e-5 in units of s
     assert np.allclose(T, h * h * g / (h * 0.05), rtol=0, atol=1e-4)
+
+
+def two_bodies():
+    """The soft cube and a shifted, sheared copy of it: two soft bodies in one scene."""
+    sc = sg.cube_drop()
+    a = sc.softs[0]
+    b = sg.SoftBody(a.rest_pos @ np.array([[1.0, 0.2, 0], [0, 1.0, 0], [0, 0.1, 0.9]]) + [0.3, 0.05, -0.1],
+                    a.tets.copy(), a.E, a.nu, a.rho)
+    return sg.Scene("two_cubes", sc.params, [a, b], sc.affines, 1)
+
+
+def test_fit_correction_pins():
+    sc = two_bodies()
+    R = ref.RefScene(sc)
+    m = R.lumped_mass()
+    y = R.get_state()[0]
+    n = R.n_soft_verts
+    rng = np.random.default_rng(5)
+    y = y.copy()
+    y[:3 * n] += rng.normal(scale=2e-3, size=3 * n)
+    x = y[:3 * n].reshape(-1, 3)
+    n0 = len(sc.softs[0].rest_pos)
+    parts = [slice(0, n0), slice(n0, n)]
+    # affine per body
+    aff = np.zeros((n, 3))
+    maps = []
+    for sl in parts:
+        t, B = rng.normal(size=3), rng.normal(size=(3, 3))
+        aff[sl] = t + x[sl] @ B.T
+        maps.append((t, B))
+    f1 = warm.fit_correction(sc, m, y, aff, 1)
+    assert np.abs(f1 - aff).max() <= 1e-12 * np.abs(aff).max()
+    f2 = warm.fit_correction(sc, m, y, aff, 2)
+    for sl, (t, B) in zip(parts, maps):
+        xc = m[sl] @ x[sl] / m[sl].sum()
+        assert np.abs(f2[sl] - (t + B @ xc)).max() <= 1e-12 * np.abs(aff).max()
+    const = np.tile([0.3, -1.2, 0.7], (n, 1))
+    for mode in (0, 1, 2):
+        assert np.abs(warm.fit_correction(sc, m, y, const, mode) - const).max() <= 1e-14
+    c = rng.normal(size=(n, 3))
+    f = warm.fit_correction(sc, m, y, c, 1)
+    for sl in parts:
+        r, w = c[sl] - f[sl], m[sl]
+        X = x[sl] - w @ x[sl] / w.sum()
+        assert np.abs(w @ r).max() <= 1e-12 * np.abs(w[:, None] * c[sl]).sum()
+        assert np.abs((X * w[:, None]).T @ r).max() <= 1e-12 * np.abs(X).max() * np.abs(w[:, None] * c[sl]).sum()
+    c2 = c.copy()
+    c2[parts[1]] += 5.0
+    f_2 = warm.fit_correction(sc, m, y, c2, 1)
+    assert np.array_equal(f_2[parts[0]], f[parts[0]])
+

@@ -33,10 +33,12 @@ __device__ void wave_psd_project(double* M, double* Vm, double* cs, int* partner
     }
     off = wave_sum(off);
     // Stop once the off-diagonal norm is 1e-13 of the Frobenius norm (the eigenvalues
-    // are then those of a matrix within that distance), or when a sweep no longer
-    // shrinks it fourfold: sweeps converge quadratically until rounding stalls them,
-    // which for badly scaled matrices (barrier Hessians) happens above 1e-15.
-    if (!(off > 1e-26 * fro) || (sweep > 2 && off > 0.25 * off_prev)) break;
+    // are then those of a matrix within that distance), or, once it is below 1e-12,
+    // when a sweep no longer halves it: there the sweeps converge quadratically until
+    // rounding stalls them, which for badly scaled matrices (barrier Hessians) happens
+    // above 1e-15.  Above 1e-12 a sweep may shrink it less than that (the linear phase
+    // of cyclic Jacobi, seen on mollified edge-edge Hessians), so no stop there.
+    if (!(off > 1e-26 * fro) || (off < 1e-24 * fro && off > 0.25 * off_prev)) break;
     off_prev = off;
     for (int rd = 0; rd < N - 1; ++rd) {
       if (lane < N / 2) {

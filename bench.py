@@ -185,7 +185,7 @@ def hbm_traffic(kernel, source_files):
 
 
 def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, group_chunk=10, tag="",
-             groups=GROUPS, newton_max=0):
+             groups=GROUPS, newton_max=0, warm_fit=-1):
     """Steps every scene `steps` times; returns (wall seconds, stats list, intersections)."""
     import copy
 
@@ -213,6 +213,8 @@ def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, g
     for o in objs:
         if learned is not None:
             o.set_mlp(learned)
+            if warm_fit >= 0:
+                o.tune(zema.TUNE_WARM_FIT, warm_fit)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -263,6 +265,7 @@ def forms(args, zema):
            "unbatched_sample": f"first {n_plain} scenes",
            "newton_max": args.form_newton_max,
            "network": os.path.basename(args.mlp) if mlp is not None else None,
+           "warm_fit": args.warm_fit if args.warm_fit >= 0 else "library default (2: per-body mean)",
            "batched_as": f"{args.form_groups} batch objects of similar size on as many HIP streams, stepped together "
                          f"(zema_step_group); plain: one scene object after the other"}
     cases = [("plain", False, None, False), ("batched", True, None, False)]
@@ -276,7 +279,7 @@ def forms(args, zema):
     run_form(zema, scenes[:min(8, len(scenes))], 2, True, tag="warm-up")
     for name, batched, learned, mixed in cases:
         sub = scenes if batched else scenes[:n_plain]
-        t, st, inter = run_form(zema, sub, args.form_steps, batched, learned, mixed, tag=name,
+        t, st, inter = run_form(zema, sub, args.form_steps, batched, learned, mixed, tag=name, warm_fit=args.warm_fit,
                                 groups=args.form_groups, newton_max=args.form_newton_max)
         total = len(sub) * args.form_steps
         newton = sum(x["newton_iters"] for x in st)
@@ -387,6 +390,8 @@ def main():
     ap.add_argument("--form-plain-scenes", type=int, default=0,
                     help="run the unbatched forms on the first K scenes only (0: all)")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_05945_amd", "warm_mlp.npy"))
+    ap.add_argument("--warm-fit", type=int, default=-1, choices=(-1, 0, 1, 2),
+                    help="per-body fit of the network's correction in the learned forms (-1: library default)")
     ap.add_argument("--no-legs", action="store_true", help="skip the cube-drop and precision legs")
     ap.add_argument("--warm-analysis", type=int, default=0, metavar="N",
                     help="only run the learned-start analysis on N held-out scenes (--form-steps steps each)")

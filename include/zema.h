@@ -99,8 +99,16 @@ typedef struct {
  * ZEMA_STVK         Psi = mu |E|^2 + lambda/2 (tr E)^2, E = (F^T F - I)/2,
  * ZEMA_FIXED_COROTATED  Psi = mu |F - R|^2 + lambda/2 (J - 1)^2, F = R S;
  * mu, lambda the Lame parameters of E and nu; J <= 0 is infeasible for every model.
- * An unknown model is ZEMA_E_ARG. */
-enum { ZEMA_NEO_HOOKEAN = 0, ZEMA_STVK = 1, ZEMA_FIXED_COROTATED = 2 };
+ * ZEMA_BARAFF_WITKIN makes the body a garment (Sec. IV-D): no tets (n_tets = 0) and
+ * triangles tris [n_tris][3] instead; rest material coordinates (u, v) = rest (x, z)
+ * of the vertices; per triangle of rest area A the incremental-potential energy
+ * h^2 A (k_s/2 ((|w_u| - 1)^2 + (|w_v| - 1)^2) + k_sh/2 (w_u . w_v)^2), w_u, w_v the
+ * columns of the deformation x = W (u, v)^T + const, with k_s = E and
+ * k_sh = E / (2 (1 + nu)) (N/m); rho is the area density (kg/m^2), lumped as rho A / 3
+ * per vertex; every triangle is a contact surface triangle; no bending.  A garment
+ * body is accepted by zema_scene_create only (not in batches).
+ * An unknown model, tets on a garment or triangles on a solid is ZEMA_E_ARG. */
+enum { ZEMA_NEO_HOOKEAN = 0, ZEMA_STVK = 1, ZEMA_FIXED_COROTATED = 2, ZEMA_BARAFF_WITKIN = 3 };
 typedef struct {
   int32_t n_verts, n_tets;
   const double* rest_pos;
@@ -109,6 +117,8 @@ typedef struct {
   const double* vel0;
   double E, nu, rho;
   int32_t model, pad_;
+  const int32_t* tris; /* garment triangles (ZEMA_BARAFF_WITKIN), else NULL */
+  int32_t n_tris, pad2_;
 } zema_soft_desc;
 
 /* Affine body (Sec. III eq. 2): closed outward triangle surface in world

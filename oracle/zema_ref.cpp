@@ -543,6 +543,8 @@ struct zref_scene {
   std::vector<int> tet_model; // [nt] constitutive model (0 neo-Hookean, 1 StVK, 2 fixed corotated)
   std::vector<double> mass;   // [nsv]
   std::vector<int> vbody;     // soft vertex -> body
+  std::vector<int> cloth_v;     // garment triangles [nc*3] (soft vertex ids)
+  std::vector<double> cloth_d;  // per triangle: rest (u, v) edge-matrix inverse [4], area, k_stretch, k_shear
   // affine
   std::vector<Body> bodies;   // index = affine body index
   // surface
@@ -837,6 +839,65 @@ bool tet_term(const zref_scene* s, int e, const double* x12, double* E, double* 
       }
   }
   return true;
+}
+
+// ------------------------------------------------------------------ garment (Sec. IV-D)
+// Baraff-Witkin membrane on a triangle with rest material coordinates (u, v): the
+// deformation's columns w_u, w_v (x = W (u, v)^T + const over the triangle) enter the
+// stretch conditions |w_u| - 1, |w_v| - 1 and the shear condition w_u . w_v; each
+// energy density k/2 C^2 is integrated over the rest area A (reading) and scaled by
+// h^2 into the incremental potential:
+//   h^2 A (k_s/2 ((|w_u| - 1)^2 + (|w_v| - 1)^2) + k_sh/2 (w_u . w_v)^2).
+// Hessian (reading): the stretch and the shear parts are each projected to PSD in the
+// six coordinates of (w_u, w_v) and the sum is mapped to the vertices (W is linear in
+// x).  Bending is not modelled.
+void cloth_term(const zref_scene* s, int c, const double* x9, double* E, double* g9, double* H81) {
+  const double* d = &s->cloth_d[7 * c];
+  const double m00 = d[0], m01 = d[1], m10 = d[2], m11 = d[3];
+  const double h2A = s->P.dt * s->P.dt * d[4], ks = d[5], ksh = d[6];
+  // dW/dx: w_u = sum_a cu[a] x_a, w_v = sum_a cv[a] x_a
+  const double cu[3] = {-(m00 + m10), m00, m10}, cv[3] = {-(m01 + m11), m01, m11};
+  J2<6> w[6];
+  for (int k = 0; k < 3; ++k) {
+    double wu = 0.0, wv = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      wu += cu[a] * x9[3 * a + k];
+      wv += cv[a] * x9[3 * a + k];
+    }
+    w[k] = jvar<6>(wu, k);
+    w[3 + k] = jvar<6>(wv, 3 + k);
+  }
+  J2<6> nu = jsqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  J2<6> nv = jsqrt(w[3] * w[3] + w[4] * w[4] + w[5] * w[5]);
+  J2<6> su = nu + (-1.0), sv = nv + (-1.0);
+  J2<6> st = (0.5 * h2A * ks) * (su * su + sv * sv);
+  J2<6> cs = w[0] * w[3] + w[1] * w[4] + w[2] * w[5];
+  J2<6> sh = (0.5 * h2A * ksh) * (cs * cs);
+  *E = st.v + sh.v;
+  const double* col[2] = {cu, cv};
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 3; ++k)
+      g9[3 * a + k] = col[0][a] * (st.g[k] + sh.g[k]) + col[1][a] * (st.g[3 + k] + sh.g[3 + k]);
+  if (!H81) return;
+  std::vector<double> A(36), B(36);
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      A[6 * i + j] = st.h[i][j];
+      B[6 * i + j] = sh.h[i][j];
+    }
+  std::vector<double> PA = project_psd(6, A), PB = project_psd(6, B);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+          double acc = 0.0;
+          for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) {
+              const int i = 3 * p + k, j = 3 * q + l;
+              acc += col[p][a] * col[q][b] * (PA[6 * i + j] + PB[6 * i + j]);
+            }
+          H81[(3 * a + k) * 9 + 3 * b + l] = acc;
+        }
 }
 
 // ------------------------------------------------------------------ affine body terms (eq. 2)
@@ -1155,6 +1216,24 @@ EvalOut evaluate(zref_scene* s, const double* y, std::vector<double>* grad, bool
           for (int k = 0; k < 3; ++k) G(1)[3 * s->tets[4 * e + a] + k] += tg[e][3 * a + k];
     if (HS(1))
       for (int e = 0; e < nt; ++e) s->H.push_back(std::move(th[e]));
+  }
+  // garment triangles (Sec. IV-D, Baraff-Witkin stretch and shear), elastic term
+  const int ncl = (int)s->cloth_v.size() / 3;
+  for (int c = 0; c < ncl && o.feasible; ++c) {
+    double x9[9], e, g9[9], H81[81];
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < 3; ++k) x9[3 * a + k] = y[3 * s->cloth_v[3 * c + a] + k];
+    cloth_term(s, c, x9, &e, g9, HS(1) ? H81 : nullptr);
+    o.terms[1] += e;
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < 3; ++k) G(1)[3 * s->cloth_v[3 * c + a] + k] += g9[3 * a + k];
+    if (HS(1)) {
+      Elem el;
+      for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) el.dofs.push_back(3 * s->cloth_v[3 * c + a] + k);
+      el.M.assign(H81, H81 + 81);
+      s->H.push_back(el);
+    }
   }
   // barrier over the active subset of the candidates (eqs. 4-8)
   std::vector<double> xs(3 * s->nsurf);
@@ -1877,7 +1956,8 @@ int zref_scene_create(const zref_params* p, const zref_soft_desc* soft, int32_t 
   for (int b = 0; b < n_soft; ++b) {
     const zref_soft_desc& d = soft[b];
     int v0 = s->nsv;
-    if (d.model < 0 || d.model > 2) {
+    if (d.model < 0 || d.model > 3 || (d.model == 3) != (d.n_tris > 0) || (d.model == 3 && d.n_tets) ||
+        (d.n_tris && !d.tris)) {
       delete s;
       return -1;
     }
@@ -1945,6 +2025,45 @@ int zref_scene_create(const zref_params* p, const zref_soft_desc* soft, int32_t 
         else
           it->second.first++;
       }
+    }
+    // garment (reading): rest material coordinates (u, v) = rest (x, z); per triangle
+    // the inverse of the rest edge matrix [[du1, du2], [dv1, dv2]], the rest area, the
+    // stretch stiffness E and the shear stiffness E / (2 (1 + nu)) (N/m), mass rho A / 3
+    // per vertex (rho in kg/m^2); every triangle is a surface triangle as given
+    for (int e = 0; e < d.n_tris; ++e) {
+      int t[3];
+      for (int a = 0; a < 3; ++a) {
+        t[a] = d.tris[3 * e + a];
+        if (t[a] < 0 || t[a] >= d.n_verts) {
+          delete s;
+          return -2;
+        }
+        t[a] += v0;
+      }
+      double du1 = s->X[3 * t[1]] - s->X[3 * t[0]], du2 = s->X[3 * t[2]] - s->X[3 * t[0]];
+      double dv1 = s->X[3 * t[1] + 2] - s->X[3 * t[0] + 2], dv2 = s->X[3 * t[2] + 2] - s->X[3 * t[0] + 2];
+      double det = du1 * dv2 - du2 * dv1;
+      double L = std::max({std::fabs(du1), std::fabs(du2), std::fabs(dv1), std::fabs(dv2)});
+      if (!(std::fabs(det) > 1e-12 * L * L)) {
+        delete s;
+        return -2;
+      }
+      // inverse of [[du1, du2], [dv1, dv2]]
+      double M[4] = {dv2 / det, -du2 / det, -dv1 / det, du1 / det};
+      double A = 0.5 * std::fabs(det);
+      for (int a = 0; a < 3; ++a) s->cloth_v.push_back(t[a]);
+      for (int k = 0; k < 4; ++k) s->cloth_d.push_back(M[k]);
+      s->cloth_d.push_back(A);
+      s->cloth_d.push_back(d.E);
+      s->cloth_d.push_back(d.E / (2.0 * (1.0 + d.nu)));
+      for (int a = 0; a < 3; ++a) s->mass[t[a]] += d.rho * A / 3.0;
+      std::array<int, 3> key = {t[0], t[1], t[2]};
+      std::sort(key.begin(), key.end());
+      auto it = faces.find(key);
+      if (it == faces.end())
+        faces[key] = {1, {t[0], t[1], t[2]}};
+      else
+        it->second.first++;
     }
     for (auto& kv : faces)
       if (kv.second.first == 1) surf_tris.push_back(kv.second.second);

@@ -33,7 +33,10 @@ typedef struct {
   const double* pos0;
   const double* vel0;
   double E, nu, rho;
-  int32_t model, pad_; /* 0 neo-Hookean, 1 Saint Venant-Kirchhoff, 2 fixed corotated */
+  int32_t model, pad_; /* 0 neo-Hookean, 1 Saint Venant-Kirchhoff, 2 fixed corotated,
+                          3 Baraff-Witkin garment (triangles below, no tets) */
+  const int32_t* tris; /* garment triangles [n_tris][3] */
+  int32_t n_tris, pad2_;
 } zref_soft_desc;
 
 typedef struct {

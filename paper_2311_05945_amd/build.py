@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libzema.so")
 ARCH = os.environ.get("ZEMA_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "k_misc.hip", "k_elastic.hip", "k_affine.hip", "k_contact.hip", "k_broad.hip",
-           "k_sort.hip", "k_sparse.hip", "k_ccd.hip", "k_intersect.hip", "k_mlp.hip", "k_warm.hip"]
+           "k_sort.hip", "k_sparse.hip", "k_ccd.hip", "k_intersect.hip", "k_mlp.hip", "k_warm.hip",
+           "k_cloth.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          # packed FP32 instructions are kept out of every kernel

@@ -59,7 +59,8 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
     for (int b = soft_off[k]; b < soft_off[k + 1]; ++b) body_scene[b] = k;
     for (int b = aff_off[k]; b < aff_off[k + 1]; ++b) body_scene[n_soft + b] = k;
   }
-  std::vector<double> X, x_init, v_init, Dmi_aos, vol, lmu, llam, mass;
+  std::vector<double> X, x_init, v_init, Dmi_aos, vol, lmu, llam, mass, cl_d;
+  std::vector<int4> cl_v;
   std::vector<int> tets, vbody;
   std::vector<unsigned char> tmodel;
   // ---- soft bodies
@@ -72,10 +73,14 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
       R.v0 = R.v1 = (int)mass.size();
       R.t0 = R.t1 = (int)vol.size();
     }
-    if (d.n_verts < 0 || d.n_tets < 0 || (d.n_verts && !d.rest_pos) || (d.n_tets && !d.tets))
+    if (d.n_verts < 0 || d.n_tets < 0 || (d.n_verts && !d.rest_pos) || (d.n_tets && !d.tets) || d.n_tris < 0 ||
+        (d.n_tris && !d.tris))
       throw Error(ZEMA_E_ARG, "bad soft body descriptor");
-    if (d.model < ZEMA_NEO_HOOKEAN || d.model > ZEMA_FIXED_COROTATED)
+    if (d.model < ZEMA_NEO_HOOKEAN || d.model > ZEMA_BARAFF_WITKIN)
       throw Error(ZEMA_E_ARG, "unknown constitutive model");
+    if ((d.model == ZEMA_BARAFF_WITKIN) != (d.n_tris > 0) || (d.model == ZEMA_BARAFF_WITKIN && d.n_tets))
+      throw Error(ZEMA_E_ARG, "garment bodies take triangles only, solids tets only");
+    if (d.model == ZEMA_BARAFF_WITKIN && ns > 1) throw Error(ZEMA_E_ARG, "garment bodies are single-scene only");
     int v0 = (int)mass.size();
     double mu = d.E / (2.0 * (1.0 + d.nu)), la = d.E * d.nu / ((1.0 + d.nu) * (1.0 - 2.0 * d.nu));
     for (int i = 0; i < d.n_verts; ++i) {
@@ -129,10 +134,35 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
         faces.push_back({a, bb, c, 0});
       }
     }
+    // garment triangles: rest (u, v) = rest (x, z); inverse rest edge matrix, area,
+    // stretch and shear stiffness; mass rho A / 3 per vertex; each triangle is a
+    // surface triangle as given
+    for (int e = 0; e < d.n_tris; ++e) {
+      int t[3];
+      for (int a = 0; a < 3; ++a) {
+        int v = d.tris[3 * e + a];
+        if (v < 0 || v >= d.n_verts) throw Error(ZEMA_E_MESH, "triangle index out of range");
+        t[a] = v0 + v;
+      }
+      const double du1 = X[3 * t[1]] - X[3 * t[0]], du2 = X[3 * t[2]] - X[3 * t[0]];
+      const double dv1 = X[3 * t[1] + 2] - X[3 * t[0] + 2], dv2 = X[3 * t[2] + 2] - X[3 * t[0] + 2];
+      const double det = du1 * dv2 - du2 * dv1;
+      const double L = std::max({std::fabs(du1), std::fabs(du2), std::fabs(dv1), std::fabs(dv2)});
+      if (!(std::fabs(det) > 1e-12 * L * L)) throw Error(ZEMA_E_MESH, "degenerate garment triangle");
+      const double A = 0.5 * std::fabs(det);
+      cl_v.push_back(make_int4(t[0], t[1], t[2], 0));
+      const double dd[8] = {dv2 / det, -du2 / det, -dv1 / det, du1 / det, A, d.E, d.E / (2.0 * (1.0 + d.nu)), 0.0};
+      cl_d.insert(cl_d.end(), dd, dd + 8);
+      for (int a = 0; a < 3; ++a) mass[t[a]] += d.rho * A / 3.0;
+      int lo = std::min({t[0], t[1], t[2]}), hi = std::max({t[0], t[1], t[2]}), mid = t[0] + t[1] + t[2] - lo - hi;
+      fkey.push_back(((unsigned long long)lo << 42) | ((unsigned long long)mid << 21) | (unsigned long long)hi);
+      faces.push_back({t[0], t[1], t[2], 0});
+    }
     R.v1 = (int)mass.size();
     R.t1 = (int)vol.size();
   }
   s->nsv = (int)mass.size();
+  s->ncl = (int)cl_v.size();
   s->nt = (int)vol.size();
   for (int k = 0, v = 0, t = 0; k < ns; ++k) {  // scenes without soft bodies: empty ranges in order
     if (soft_off[k + 1] == soft_off[k]) {
@@ -337,6 +367,7 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
     if (B.node0 >= 0)
       for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) keys.push_back((unsigned long long)(B.node0 + a) * nn + (B.node0 + b));
+  for (int i = 0; i < s->nsv; ++i) keys.push_back((unsigned long long)i * nn + i);  // garment vertices: mass block
   std::vector<unsigned long long> ukeys = keys;
   std::sort(ukeys.begin(), ukeys.end());
   ukeys.erase(std::unique(ukeys.begin(), ukeys.end()), ukeys.end());
@@ -436,7 +467,9 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   ZCHK(hipMemset(s->bsr_val.p, 0, sizeof(double) * s->bsr_val.n));
   s->bsr_val32.resize(s->mixed ? nbv : 9);
   ZCHK(hipMemset(s->bsr_val32.p, 0, sizeof(float) * s->bsr_val32.n));
-  s->e_tet.resize(s->nt + 1);
+  s->e_tet.resize(s->nt + s->ncl + 1);
+  s->cl_v.upload(cl_v);
+  s->cl_d.upload(cl_d);
   s->g_tet.resize((size_t)12 * s->nt + 12);  // [4 nt][3] gradient records
   s->h_tet.resize(s->mixed ? kTetHess : nht);
   s->h_tet32.resize(s->mixed ? nht : kTetHess);
@@ -565,6 +598,7 @@ void upload_kappa(zema_scene* s) {
 void eval_energy(zema_scene* s, const double* y, double* T) {
   k_map_surface(s, y, s->xs.p);
   k_tet_energy(s, y);
+  k_cloth_energy(s, y, s->e_tet.p + s->nt);
   k_inertia_energy(s, y, s->e_in.p);
   k_body_energy(s, y);
   k_contact_energy(s);
@@ -575,7 +609,7 @@ void eval_energy(zema_scene* s, const double* y, double* T) {
     const double* P[8] = {s->e_in.p, s->e_tet.p, s->e_body.p, s->e_body.p + nb, s->e_body.p + 2 * nb, s->e_pair.p,
                           s->e_fric.p, s->e_spr.p};
     const int64_t ncons = (int64_t)(s->springs.size() + s->joints.size());
-    int64_t L[8] = {s->nsv, s->nt, nb, nb, nb, s->npt + s->nee, s->nfric, ncons};
+    int64_t L[8] = {s->nsv, s->nt + s->ncl, nb, nb, nb, s->npt + s->nee, s->nfric, ncons};
     const int nseg = ncons ? 8 : 7;
     double out[9];
     k_sums(s, nseg, P, L, out, s->sc_dmin.p);

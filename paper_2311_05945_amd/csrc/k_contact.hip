@@ -958,7 +958,9 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
     const int nodes = 4 * ((s->bodies[J.b1].dof0 >= 0) + (s->bodies[J.b2].dof0 >= 0));
     ntrip_j += nodes + (hess ? nodes * nodes : 0);
   }
-  if (nitems == 0 && ntrip_j == 0) {
+  // garment triangles emit theirs after the joints' (elastic term, mask bit 1)
+  const int64_t ntrip_c = (mask & 2u) ? (int64_t)s->ncl * (hess ? 12 : 3) : 0;
+  if (nitems == 0 && ntrip_j == 0 && ntrip_c == 0) {
     ZCHK(hipMemsetAsync(s->c_ptr.p, 0, sizeof(int) * (s->nnodes + 1), s->st));
     return;
   }
@@ -995,7 +997,7 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
     item_count_kernel<<<nblocks(nitems), kBlock, 0, s->st>>>(A, s->trip_cnt.p);
     ntrip_items = k_exclusive_scan(s, s->trip_cnt.p, s->trip_off.p, nitems);
   }
-  const int64_t ntrip = ntrip_items + ntrip_j;
+  const int64_t ntrip = ntrip_items + ntrip_j + ntrip_c;
   if (ntrip == 0) {  // every item touches only fixed bodies
     ZCHK(hipMemsetAsync(s->c_ptr.p, 0, sizeof(int) * (s->nnodes + 1), s->st));
     return;
@@ -1017,6 +1019,7 @@ void k_contact_assemble(zema_scene* s, double* grad, bool hess, unsigned mask) {
   if (nj)
     joint_emit_kernel<<<nblocks(nj, 64), 64, 0, s->st>>>(joint_args(s, s->y_asm), hess ? 1 : 0, ntrip_items, W,
                                                         s->nnodes, sb.k0.p, s->trip_val.p);
+  if (ntrip_c) k_cloth_emit(s, s->y_asm, hess, ntrip_items + ntrip_j, W, sb.k0.p, s->trip_val.p);
   k_iota(s, sb.v0.p, ntrip);  // sort values = triplet ids
   k_radix_sort(s, sb, ntrip, bits_for((unsigned long long)s->nnodes * W + W));
   // segments

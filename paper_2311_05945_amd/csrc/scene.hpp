@@ -131,6 +131,10 @@ struct zema_scene {
   // ---- soft (device)
   zema::DBuf<int4> tets;
   zema::DBuf<double> Dmi, h2vol, lmu, llam, mass;
+  // ---- garment triangles (Baraff-Witkin; single-scene objects only)
+  int ncl = 0;
+  zema::DBuf<int4> cl_v;     // vertices (soft vertex ids)
+  zema::DBuf<double> cl_d;   // [8]: inverse rest (u, v) edge matrix, rest area, k_stretch, k_shear, pad
   zema::DBuf<unsigned char> tmodel;  // per tet: 0 neo-Hookean, 1 Saint Venant-Kirchhoff, 2 fixed corotated
   zema::DBuf<int> vt_ptr, vt_list;       // vertex -> (tet*4 + local index), tet order
   zema::DBuf<double> e_tet, g_tet, h_tet, e_in;  // per-tet energy; gradient [4nt][3], Hessian [4nt][6] + [6nt][9] records
@@ -318,6 +322,9 @@ void k_friction_rebuild(zema_scene* s, const int* rebuild_host);  // the same fo
 // -------- broad phase (k_broad.hip)
 void k_candidates(zema_scene* s, const double* xs0, const double* xs1, double r, const double* xs2 = nullptr);
 void k_features(zema_scene* s, float* feat);
+void k_cloth_energy(zema_scene* s, const double* y, double* e_out);  // per garment triangle
+void k_cloth_emit(zema_scene* s, const double* y, bool hess, int64_t base, unsigned long long W,
+                  unsigned long long* key, double* val);  // gradient (+ Hessian) triplets, 3 (12) per triangle
 void k_warm_fit(zema_scene* s, int mode, float* out);   // per-soft-body fit of a correction field, in place
 void k_warm_dir(zema_scene* s, float* out, double* p);  // applies the scene's fit to out first
 void k_warm_target(zema_scene* s, float* target);

@@ -32,7 +32,8 @@ class Params(C.Structure):
 
 class SoftDesc(C.Structure):
     _fields_ = [("n_verts", I32), ("n_tets", I32), ("rest_pos", PD), ("tets", PI32), ("pos0", PD), ("vel0", PD),
-                ("E", D), ("nu", D), ("rho", D), ("model", I32), ("pad_", I32)]
+                ("E", D), ("nu", D), ("rho", D), ("model", I32), ("pad_", I32), ("tris", PI32), ("n_tris", I32),
+                ("pad2_", I32)]
 
 
 class AffineDesc(C.Structure):
@@ -191,9 +192,12 @@ class Scene:
             rp = _f64(b.rest_pos); tt = np.ascontiguousarray(b.tets, dtype=np.int32)
             p0 = _f64(b.pos0) if b.pos0 is not None else None
             v0 = _f64(b.vel0) if b.vel0 is not None else None
-            self._keep += [rp, tt, p0, v0]
+            tr = getattr(b, "tris", None)
+            tr = np.ascontiguousarray(tr, dtype=np.int32).reshape(-1, 3) if tr is not None else None
+            self._keep += [rp, tt, p0, v0, tr]
             softs[k] = SoftDesc(len(rp), len(tt), _pd(rp), tt.ctypes.data_as(PI32), _pd(p0), _pd(v0), b.E, b.nu, b.rho,
-                                getattr(b, "model", 0), 0)
+                                getattr(b, "model", 0), 0, tr.ctypes.data_as(PI32) if tr is not None else None,
+                                len(tr) if tr is not None else 0, 0)
         affs = (AffineDesc * max(1, len(all_affs)))()
         for k, b in enumerate(all_affs):
             rp = _f64(b.rest_pos); tt = np.ascontiguousarray(b.tris, dtype=np.int32)

@@ -27,7 +27,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 MODE_FREE, MODE_FIXED, MODE_DRIVEN = 0, 1, 2
-NEO_HOOKEAN, STVK, FIXED_COROTATED = 0, 1, 2
+NEO_HOOKEAN, STVK, FIXED_COROTATED, BARAFF_WITKIN = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
 
 
@@ -57,7 +57,8 @@ class SoftBody:
     rho: float
     pos0: np.ndarray | None = None
     vel0: np.ndarray | None = None
-    model: int = NEO_HOOKEAN    # constitutive model: NEO_HOOKEAN, STVK or FIXED_COROTATED
+    model: int = NEO_HOOKEAN    # constitutive model: NEO_HOOKEAN, STVK, FIXED_COROTATED or BARAFF_WITKIN
+    tris: np.ndarray | None = None  # (k,3) int32 garment triangles (BARAFF_WITKIN: E, nu in N/m, rho kg/m^2)
 
 
 @dataclass
@@ -404,6 +405,51 @@ def two_tets_scene(model: int = NEO_HOOKEAN) -> Scene:
     p = Params(dt=0.01, dhat=1e-3, mu=0.5)
     return Scene("two_tets", p, [SoftBody(v, t, E=1e5, nu=0.4, rho=1000.0, model=model)],
                  [AffineBody(slab_v, slab_t, mode=MODE_FIXED)], 10)
+
+
+def cone_surface(apex, radius: float, height: float, n: int = 16):
+    """Closed outward triangle surface of a cone (apex up, base disk at apex - height)
+    with n segments around the axis: apex, n base-rim vertices, base centre."""
+    apex = np.asarray(apex, dtype=np.float64)
+    ang = 2.0 * np.pi * np.arange(n) / n
+    rim = np.stack([apex[0] + radius * np.cos(ang), np.full(n, apex[1] - height), apex[2] + radius * np.sin(ang)], 1)
+    verts = np.vstack([apex, rim, [apex[0], apex[1] - height, apex[2]]])
+    tris = []
+    for k in range(n):
+        a, b = 1 + k, 1 + (k + 1) % n
+        tris.append([0, b, a])          # side, outward
+        tris.append([n + 1, a, b])      # base, facing down
+    return verts, np.asarray(tris, dtype=np.int32)
+
+
+def garment_sheet(n: int, side: float, y: float, offset=(0.0, 0.0)):
+    """Square sheet of n x n quads (2 triangles each) in the plane y, centred at
+    (offset x, offset z); rest material coordinates are its (x, z)."""
+    g = np.linspace(-0.5 * side, 0.5 * side, n + 1)
+    X, Z = np.meshgrid(g + offset[0], g + offset[1], indexing="ij")
+    verts = np.stack([X.ravel(), np.full(X.size, y), Z.ravel()], 1)
+    tris = []
+    for i in range(n):
+        for j in range(n):
+            a, b, c, d = i * (n + 1) + j, (i + 1) * (n + 1) + j, (i + 1) * (n + 1) + j + 1, i * (n + 1) + j + 1
+            if (i + j) % 2 == 0:
+                tris += [[a, b, c], [a, c, d]]
+            else:
+                tris += [[a, b, d], [b, c, d]]
+    return verts, np.asarray(tris, dtype=np.int32)
+
+
+def garment_on_cone(n: int = 10, side: float = 0.3, gap: float = 5e-3, E: float = 500.0, nu: float = 0.3,
+                    rho: float = 0.2, steps: int = 20, offset=(0.013, -0.007)) -> Scene:
+    """A Baraff-Witkin garment (n x n quads, side `side` m, stretch stiffness E N/m,
+    shear E / (2 (1 + nu)), area density rho kg/m^2) dropped from `gap` above the apex of
+    a fixed cone (radius 0.1 m, height 0.15 m); the sheet's centre is offset from the
+    axis so that no vertex sits exactly above the apex.  dt = 0.01 s, dhat = 1e-3 m."""
+    cv, ct = cone_surface((0.0, 0.0, 0.0), 0.1, 0.15, 24)
+    gv, gt = garment_sheet(n, side, gap, offset)
+    p = Params(dt=0.01, dhat=1e-3, mu=0.4)
+    cloth = SoftBody(gv, np.zeros((0, 4), np.int32), E=E, nu=nu, rho=rho, model=BARAFF_WITKIN, tris=gt)
+    return Scene("garment_on_cone", p, [cloth], [AffineBody(cv, ct, mode=MODE_FIXED)], steps)
 
 
 def random_state_perturbation(n: int, scale: float, seed: int) -> np.ndarray:

@@ -106,6 +106,40 @@ def cube_drop_leg(zema):
             "max_position_diff_m": dy, "failed_steps": sum(1 for x in sg_ if x["status"] != 0)}
 
 
+def garment_leg(zema):
+    """The garment dropped onto a fixed cone (Baraff-Witkin membrane, 121 vertices, 200
+    triangles, dt = 0.005 s, 20 steps): the GPU plain form against the oracle on every
+    core, same steps, same tolerance."""
+    import torch
+
+    import scenegen as sg
+    from oracle import ref
+    sc = sg.garment_on_cone(gap=2e-3, steps=20)
+    sc.params.dt = 0.005
+    G = zema.Scene(sc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sg_ = G.step(sc.n_steps)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    used = ref.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    R = ref.RefScene(sc)
+    t0 = time.perf_counter()
+    so = R.step(sc.n_steps)
+    tr = time.perf_counter() - t0
+    ng = sum(x["newton_iters"] for x in sg_)
+    nr = sum(x["newton_iters"] for x in so)
+    dy = float(abs(G.get_state()[0].cpu().numpy() - R.get_state()[0]).max())
+    log(f"garment: gpu {sc.n_steps / tg:.1f} steps/s ({ng} Newton), oracle {sc.n_steps / tr:.1f} steps/s ({nr} Newton)")
+    return {"workload": "Baraff-Witkin garment 0.3 m (10x10 quads, 200 triangles) dropped 2 mm onto a fixed cone, "
+                        "dt=0.005 s, 20 steps",
+            "gpu": {"steps_per_s": sc.n_steps / tg, "newton_iters_per_step": ng / sc.n_steps,
+                    "newton_iters_per_s": ng / tg},
+            "oracle": {"steps_per_s": sc.n_steps / tr, "newton_iters_per_step": nr / sc.n_steps,
+                       "newton_iters_per_s": nr / tr, "cores": used},
+            "max_position_diff_m": dy, "failed_steps": sum(1 for x in sg_ if x["status"] != 0)}
+
+
 def precision_leg(zema, res, steps, seed):
     """The gripper at a finer grid (r = 64 by default): the mixed form (FP32 elastic
     Hessian and products) and the FP64 form on the GPU and the oracle, the first `steps`
@@ -266,6 +300,7 @@ def forms(args, zema):
            "newton_max": args.form_newton_max,
            "network": os.path.basename(args.mlp) if mlp is not None else None,
            "warm_fit": args.warm_fit if args.warm_fit >= 0 else "library default (2: per-body mean)",
+           "batched_steps_per_call": args.form_group_chunk,
            "batched_as": f"{args.form_groups} batch objects of similar size on as many HIP streams, stepped together "
                          f"(zema_step_group); plain: one scene object after the other"}
     cases = [("plain", False, None, False), ("batched", True, None, False)]
@@ -280,7 +315,8 @@ def forms(args, zema):
     for name, batched, learned, mixed in cases:
         sub = scenes if batched else scenes[:n_plain]
         t, st, inter = run_form(zema, sub, args.form_steps, batched, learned, mixed, tag=name, warm_fit=args.warm_fit,
-                                groups=args.form_groups, newton_max=args.form_newton_max)
+                                groups=args.form_groups, newton_max=args.form_newton_max,
+                                group_chunk=args.form_group_chunk)
         total = len(sub) * args.form_steps
         newton = sum(x["newton_iters"] for x in st)
         out[name] = {"scenes": len(sub), "steps_per_s": total / t, "newton_iters_per_step": newton / total,
@@ -385,6 +421,8 @@ def main():
     ap.add_argument("--form-seed", type=int, default=10000)
     ap.add_argument("--form-cases", default="", help="comma-separated subset of the forms (default: all)")
     ap.add_argument("--form-groups", type=int, default=GROUPS, help="batch objects of the batched forms")
+    ap.add_argument("--form-group-chunk", type=int, default=10,
+                    help="steps per call of the batched forms (scenes run ahead of each other within a call)")
     ap.add_argument("--form-newton-max", type=int, default=1000,
                     help="Newton iteration cap of the uneven scenes (contact onset can need several hundred)")
     ap.add_argument("--form-plain-scenes", type=int, default=0,
@@ -527,6 +565,10 @@ def main():
         out["forms"] = forms(args, zema)
     if not args.no_legs:
         out["cube_drop"] = cube_drop_leg(zema)
+        try:
+            out["garment_drop"] = garment_leg(zema)
+        except zema.ZemaError as e:  # reported, not fatal to the bench line
+            out["garment_drop"] = {"error": str(e)}
         if args.precision_steps > 0:
             out["precision"] = precision_leg(zema, args.precision_res, args.precision_steps, args.seed)
     if not args.no_cpu:

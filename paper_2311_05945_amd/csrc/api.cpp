@@ -578,6 +578,54 @@ void build_scene(zema_scene* s, const zema_soft_desc* soft, int n_soft, const ze
   s->pdir.upload(yd0);
 }
 
+// Mixed precision: the FP32 Hessian can be indefinite where the FP64 one is not, and
+// its solve then need not be a usable Newton direction: an ascent direction of the FP64
+// energy (g.p >= 0), or a solve whose FP64-checked residual stayed above half the
+// right-hand side after the refinement passes.  Such a scene steps along the
+// steepest-descent minimiser of the same quadratic model instead,
+// p = -(g.g / g.H g) g (or -g scaled to |p| where g.H g <= 0); the line search and the
+// next Newton iteration take it from there.  FP64 solves are left alone (their
+// Hessian is PSD by construction).  Both were seen at the batched configuration's
+// scale (512 uneven grasp scenes).
+static void mixed_descent_guard(zema_scene* s, const int* active, const double* relres) {
+  if (!s->mixed) return;
+  const int ns = s->ns;
+  std::vector<double> d((size_t)3 * ns), h((size_t)3 * ns), coef(ns, 0.0);
+  std::vector<int> bad(ns, 0);
+  k_scene_dots(s, s->grad.p, s->pdir.p, d.data());
+  bool any = false;
+  for (int k = 0; k < ns; ++k)
+    if (active[k] && (d[3 * k] > 0.0 || !(relres[k] <= 0.5))) {
+      bad[k] = 1;
+      any = true;
+    }
+  if (!any) return;
+  s->res_q.reserve(s->ndof);
+  k_hess_matvec64(s, s->grad.p, s->res_q.p);
+  k_scene_dots(s, s->grad.p, s->res_q.p, h.data());
+  for (int k = 0; k < ns; ++k) {
+    if (!bad[k]) continue;
+    const double gg = d[3 * k + 1], pp = d[3 * k + 2], gHg = h[3 * k];
+    if (gHg > 0.0)
+      coef[k] = -gg / gHg;
+    else
+      coef[k] = gg > 0.0 && std::isfinite(pp) ? -std::sqrt(pp / gg) : 0.0;
+  }
+  // p = bad ? coef g : p (a select, so that a non-finite p is replaced too)
+  s->res_r.reserve(s->ndof);
+  ZCHK(hipMemcpyAsync(s->res_r.p, s->grad.p, sizeof(double) * s->ndof, hipMemcpyDeviceToDevice, s->st));
+  k_scale_scene(s, coef.data(), s->res_r.p);
+  k_select_scene(s, bad.data(), s->res_r.p, s->pdir.p, s->pdir.p);
+}
+
+// message of a failed line search: the scene and the energies that did not decrease
+static std::string ls_failure(int k, double e0, double e1) {
+  char b[160];
+  std::snprintf(b, sizeof b, "line search failed (scene %d: energy %.17g at the iterate, %.17g at the smallest step)",
+                k, e0, e1);
+  return b;
+}
+
 double auto_kappa(const zema_scene* s, int k) {
   double g = std::sqrt(s->P.gravity[0] * s->P.gravity[0] + s->P.gravity[1] * s->P.gravity[1] +
                        s->P.gravity[2] * s->P.gravity[2]);
@@ -880,6 +928,7 @@ int time_step(zema_scene* s, zema_step_stats* st) {
         st[k].pcg_breakdowns += pbd[k];
         if (pst[k]) throw Error(pst[k], "PCG failed");
       }
+    mixed_descent_guard(s, active.data(), rr.data());
     k_max_disp(s, s->pdir.p, disp.data());
     // augmented Lagrangian of the kinematic energy (eq. 13, single scenes): at
     // convergence, while a driven body misses its target by more than al_tol, update
@@ -935,7 +984,7 @@ int time_step(zema_scene* s, zema_step_stats* st) {
         all = false;
         alpha[k] *= 0.5;
         st[k].ls_backtracks++;
-        if (alpha[k] < 1e-10) throw Error(ZEMA_E_LINESEARCH, "line search failed");
+        if (alpha[k] < 1e-10) throw Error(ZEMA_E_LINESEARCH, ls_failure(k, E0[8 * k + 6], T1[8 * k + 6]));
       }
       if (all) break;
     }
@@ -1064,6 +1113,7 @@ int time_steps_async(zema_scene* s, int n_steps, zema_step_stats* stats) {
           cur(k).pcg_breakdowns += pbd[k];
           if (pst[k]) throw Error(pst[k], "PCG failed");
         }
+      mixed_descent_guard(s, inN.data(), rr.data());
       k_max_disp(s, s->pdir.p, disp.data());
       for (int k = 0; k < ns; ++k)
         if (inN[k] && disp[k] <= tol) {
@@ -1191,7 +1241,7 @@ int time_steps_async(zema_scene* s, int n_steps, zema_step_stats* stats) {
           all = false;
           alpha[k] *= 0.5;
           cur(k).ls_backtracks++;
-          if (alpha[k] < 1e-10) throw Error(ZEMA_E_LINESEARCH, "line search failed");
+          if (alpha[k] < 1e-10) throw Error(ZEMA_E_LINESEARCH, ls_failure(k, E0[8 * k + 6], T1[8 * k + 6]));
         } else {  // initial guess of a starting scene
           if (!inv[k]) {
             acc[k] = 1;

@@ -248,6 +248,45 @@ void k_max_disp(zema_scene* s, const double* p, double* out) {
   ZCHK(hipStreamSynchronize(s->st));
 }
 
+// per scene: a.b, a.a, b.b over the scene's soft and free-body DOFs (one block each)
+__global__ void scene_dots_kernel(int nsv, const int* __restrict__ rng, const double* __restrict__ a,
+                                  const double* __restrict__ b, double* __restrict__ out) {
+  __shared__ double sh[3][kBlock / 64];
+  const int k = blockIdx.x;
+  const int64_t r[4] = {3 * (int64_t)rng[8 * k], 3 * (int64_t)rng[8 * k + 1],
+                        3 * (int64_t)nsv + 12 * (int64_t)rng[8 * k + 6], 3 * (int64_t)nsv + 12 * (int64_t)rng[8 * k + 7]};
+  double ab = 0.0, aa = 0.0, bb = 0.0;
+  for (int part = 0; part < 2; ++part)
+    for (int64_t i = r[2 * part] + threadIdx.x; i < r[2 * part + 1]; i += kBlock) {
+      ab += a[i] * b[i];
+      aa += a[i] * a[i];
+      bb += b[i] * b[i];
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    ab += __shfl_xor(ab, o, 64);
+    aa += __shfl_xor(aa, o, 64);
+    bb += __shfl_xor(bb, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = ab;
+    sh[1][threadIdx.x >> 6] = aa;
+    sh[2][threadIdx.x >> 6] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[threadIdx.x][w];
+    out[3 * k + threadIdx.x] = t;
+  }
+}
+
+void k_scene_dots(zema_scene* s, const double* a, const double* b, double* out_host) {
+  s->sc_dots.reserve((size_t)3 * s->ns);
+  scene_dots_kernel<<<s->ns, kBlock, 0, s->st>>>(s->nsv, s->scn_rng.p, a, b, s->sc_dots.p);
+  ZCHK(hipMemcpyAsync(out_host, s->sc_dots.p, sizeof(double) * 3 * s->ns, hipMemcpyDeviceToHost, s->st));
+  ZCHK(hipStreamSynchronize(s->st));
+}
+
 void k_axpy_scene(zema_scene* s, const double* alpha_host, const double* p, const double* y, double* out) {
   ZCHK(hipMemcpyAsync(s->sc_alpha.p, alpha_host, sizeof(double) * s->ns, hipMemcpyHostToDevice, s->st));
   if (s->ndof)

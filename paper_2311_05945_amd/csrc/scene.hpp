@@ -112,6 +112,7 @@ struct zema_scene {
   int ns = 1;
   std::vector<zema::SceneRange> scn;
   zema::DBuf<int> body_scene, sv_scene, v_scene, f_scene;  // global body / surface vertex / soft vertex / free body
+  zema::DBuf<double> sc_dots;                              // [ns][3] per-scene inner products
   zema::DBuf<int> scn_rng;                                 // [ns][8] v0 v1 t0 t1 b0 b1 f0 f1
   zema::DBuf<double> icell_sc, mu_sc, kappa_sc;                // per scene
   zema::DBuf<unsigned long long> sc_u64, sc_dmin, sc_tmin;      // per-scene extrema (bits)
@@ -283,6 +284,7 @@ void k_max_disp(zema_scene* s, const double* p, double* out);  // per scene: max
 void k_axpy_scene(zema_scene* s, const double* alpha_host, const double* p, const double* y, double* out);
 void k_select_scene(zema_scene* s, const int* mask_host, const double* a, const double* b, double* out);
 void k_scale_scene(zema_scene* s, const double* alpha_host, double* p);
+void k_scene_dots(zema_scene* s, const double* a, const double* b, double* out_host);  // per scene a.b, a.a, b.b
 bool k_inverted(zema_scene* s, const double* y, int* out);  // per scene: any tet inverted
 // multi-segment deterministic sums: out[k] = sum of seg k (host results)
 // (extra: optional device word copied to out_host[nseg] in the same synchronisation)

@@ -220,7 +220,10 @@ def hbm_traffic(kernel, source_files):
 
 def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, group_chunk=10, tag="",
              groups=GROUPS, newton_max=0, warm_fit=-1):
-    """Steps every scene `steps` times; returns (wall seconds, stats list, intersections)."""
+    """Steps every scene `steps` times; returns (wall seconds, stats list, [intersecting
+    edge-triangle pairs, inverted tets, uncertain pairs] at the end: the last are pairs
+    the filtered predicates could not decide, touching or coplanar to rounding, which
+    only an exact check resolves)."""
     import copy
 
     import torch
@@ -270,10 +273,12 @@ def run_form(zema, scenes, steps, batched, learned=None, mixed=False, chunk=5, g
             log(f"form {tag}: {i + 1}/{len(objs)} scenes, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    inter = 0
+    inter = [0, 0, 0]  # intersecting (edge, triangle) pairs, inverted tets, pairs the filter left uncertain
     for o in objs:
         ni, nv, nu, _ = o.intersection_count(o.get_state()[0], cap=0)
-        inter += ni + nv + nu
+        inter[0] += ni
+        inter[1] += nv
+        inter[2] += nu
     return t, stats, inter
 
 
@@ -320,11 +325,11 @@ def forms(args, zema):
         total = len(sub) * args.form_steps
         newton = sum(x["newton_iters"] for x in st)
         out[name] = {"scenes": len(sub), "steps_per_s": total / t, "newton_iters_per_step": newton / total,
-                     "wall_s": t, "intersections": inter,
+                     "wall_s": t, "intersections": inter[0] + inter[1], "uncertain_pairs": inter[2],
                      "failed_steps": sum(1 for x in st if x["status"] != 0),
                      "learned_start_kept": (sum(x["warm_learned"] for x in st) / total) if learned else None}
         log(f"form {name}: {total / t:.2f} scene-steps/s, newton/step {newton / total:.2f}, "
-            f"intersections {inter}")
+            f"intersections {inter[0] + inter[1]}, uncertain {inter[2]}")
     if "plain" in out:
         base = out["plain"]["steps_per_s"]
         for name, *_ in cases:

@@ -442,7 +442,7 @@ def main():
     ap.add_argument("--precision-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

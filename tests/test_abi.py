@@ -99,6 +99,8 @@ def test_argument_errors_need_no_device():
     loss = ctypes.c_double()
     buf = ctypes.c_void_p(1)
     assert L.zema_mlp_grad_noalloc(None, buf, buf, 16, buf, ctypes.byref(loss)) == E_ARG
+    assert L.zema_tune(None, zema.TUNE_WARM_FIT, 2) == E_ARG
+    assert L.zema_warm_fit(None, 2, buf, buf) == E_ARG
 
 
 def test_noalloc_entry_point_declared_with_its_limit():
